@@ -1,0 +1,298 @@
+/*
+ * ttipm.h — C ABI of the MI355X tensor-train interior-point library.
+ *
+ * The library solves the semidefinite programs of the paper "An Inexact
+ * Tensor-Train Primal-Dual Interior-Point Method for Semidefinite Programs"
+ * (arXiv 2509.11890) with every matrix (X, Y, T, Z, the Newton direction and
+ * the constraint operators) held in tensor-train (TT) form over d binary
+ * modes, n = 2^d.  The primal SDP is Sec. 2.2, Def. "SDP"; its dual is
+ * Def. "The Dual SDP"; the tensorised problem, vec_TT and the TT operators
+ * are Sec. 3.1-3.3.
+ *
+ * Conventions used by every call
+ *   - Storage: FP64, row-major, device memory.  A TT vector core k is
+ *     [r_k][m][r_{k+1}]; a TT matrix (operator) core k is
+ *     [R_k][m_out][m_in][R_{k+1}] (Def. "TT Matrix").  Index order is
+ *     big-endian (core 0 holds the most significant digit) and the 2x2 mode
+ *     of an n x n matrix is vectorised row-major, i = 2 alpha_k + beta_k,
+ *     exactly as in the worked example of Def. "TT Vectorisation".
+ *   - Ownership: every device pointer passed in is owned by the caller and
+ *     must stay valid until the stream has finished the call.  Handles
+ *     (ttipm_problem, ttipm_state) are owned by the library and released by
+ *     their *_destroy call.  Handles are not thread-safe.
+ *   - Streams: every call that launches work takes a hipStream_t (passed as
+ *     void*, NULL = default stream) and is ordered on it.  Calls whose result
+ *     decides a rank or a convergence test synchronise that stream; this is
+ *     stated per call.
+ *   - Errors: every call returns a status code (TT_OK = 0).  On failure
+ *     tt_last_error() returns a thread-local message.  No C++ exception
+ *     crosses this boundary.  A call that fails leaves its outputs undefined.
+ */
+#ifndef TTIPM_H
+#define TTIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define TTIPM_API __attribute__((visibility("default")))
+#else
+#define TTIPM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum {
+  TT_OK = 0,
+  TT_ERR_ARG = 1,           /* invalid argument (shape, rank, pointer)          */
+  TT_ERR_HIP = 2,           /* a HIP runtime call failed                        */
+  TT_ERR_ALLOC = 3,         /* device allocation failed                         */
+  TT_ERR_RANK_CAP = 4,      /* warning: a result was truncated at the rank cap  */
+  TT_ERR_NOT_CONVERGED = 5, /* iteration limit reached                          */
+  TT_ERR_NOT_PD = 6,        /* an iterate lost positive definiteness            */
+  TT_ERR_NUMERIC = 7,       /* NaN or Inf detected                              */
+  TT_ERR_BREAKDOWN = 8      /* Krylov breakdown                                 */
+};
+
+enum { TT_LEFT = 0, TT_RIGHT = 1 };
+enum { TT_TOL_ABS = 0, TT_TOL_REL = 1 };
+
+/* Text of the last error on this thread ("" if none). */
+TTIPM_API const char* tt_last_error(void);
+
+/* Library version string. */
+TTIPM_API const char* tt_version(void);
+
+/* ---- TT views ----------------------------------------------------------- */
+/*
+ * A TT vector (m_in == 1) or TT matrix (m_in > 1) with d cores.
+ *   ranks : host array of d+1 ranks, ranks[0] = ranks[d] = 1.  Calls that
+ *           change ranks (tt_round) write the new ranks here.
+ *   m_out : mode size of every core (4 for vec_TT vectors and operators,
+ *           2 for TT matrices and plain vectors over binary modes).
+ *   m_in  : 1 for a TT vector, the input mode size for an operator.
+ *   cores : host array of d device pointers; core k holds
+ *           ranks[k] * m_out * m_in * ranks[k+1] doubles.
+ */
+typedef struct {
+  int32_t d;
+  int32_t m_out;
+  int32_t m_in;
+  int32_t* ranks;
+  double** cores;
+} tt_view;
+
+/* ---- environments (interfaces) ------------------------------------------ */
+/*
+ * One step of the left or right environment recursion (Def. "Interface
+ * Matrix"; the cached environments of the matrix-free local products in
+ * Sec. 3.3).  With test TT V, operator O (NULL = identity) and trial TT U:
+ *   dir = TT_LEFT : phi_out[a2][beta][c2] =
+ *        sum V_k[a][i][a2] phi_in[a][alpha][c] O_k[alpha][i][j][beta] U_k[c][j][c2]
+ *        phi_in is the environment of cores < k, phi_out that of cores <= k.
+ *   dir = TT_RIGHT: phi_out[a][alpha][c] =
+ *        sum V_k[a][i][a2] O_k[alpha][i][j][beta] U_k[c][j][c2] phi_in[a2][beta][c2]
+ *        phi_in is the environment of cores > k, phi_out that of cores >= k.
+ * For O == NULL the middle (operator-rank) index has size 1 and V, U must
+ * have equal mode sizes.  V and U are TT vectors (m_in == 1); O has modes
+ * V.m_out x U.m_out.  No synchronisation.
+ */
+TTIPM_API int tt_contract_interfaces(const tt_view* test, const tt_view* op, const tt_view* trial,
+                           int32_t k, int32_t dir, const double* phi_in, double* phi_out,
+                           void* stream);
+
+/* ---- projected local operator -------------------------------------------- */
+/*
+ * A projected operator W^T O W at core k, applied matrix-free (Sec. 3.3):
+ *   y[a][i][b] = sum phiL[a][alpha][a'] O_k[alpha][i][j][beta] x[a'][j][b'] phiR[b][beta][b']
+ * core == NULL is the identity operator (R = Rp = 1, m_out = m_in).
+ */
+typedef struct {
+  const double* phiL;   /* [r][R][r]   device */
+  const double* core;   /* [R][m][m][Rp] device, or NULL */
+  const double* phiR;   /* [rp][Rp][rp] device */
+  int32_t R, Rp;
+} tt_proj_op;
+
+/*
+ * One block of the local block system: y_row += coeff * P(op[nchain-1]) ... P(op[0]) x_col.
+ * nchain = 2 expresses the chained products such as L_X^ Aeq^T^ of the
+ * reduced projected system, eq. (reduced_kkt_system): the product of two
+ * projected operators, never the projection of their product.
+ */
+typedef struct {
+  int32_t row, col;
+  double coeff;
+  int32_t nchain;
+  tt_proj_op op[2];
+} tt_local_block;
+
+/*
+ * The local system at one core: L components, each a local core
+ * [r][m][rp] (vectors x and y are [L][r][m][rp], component-major).
+ */
+typedef struct {
+  int32_t r, rp, m, L;
+  int32_t nblocks;
+  const tt_local_block* blocks;   /* host array of nblocks */
+} tt_local_op;
+
+/* y = K x.  No synchronisation. */
+TTIPM_API int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stream);
+
+enum { TT_SOLVE_AUTO = 0, TT_SOLVE_DIRECT = 1, TT_SOLVE_GMRES = 2 };
+enum { TT_PREC_NONE = 0, TT_PREC_BJACOBI = 1, TT_PREC_MLP = 2 };
+
+typedef struct {
+  int32_t method;       /* TT_SOLVE_*; AUTO = direct when L*r*m*rp <= direct_max */
+  int32_t direct_max;   /* size limit of the dense direct solve (AUTO)             */
+  int32_t restart;      /* GMRES restart length                                    */
+  int32_t maxit;        /* GMRES iteration limit                                   */
+  double rtol;          /* relative residual target ||b - K x|| <= rtol ||b||      */
+  int32_t precond;      /* TT_PREC_*                                               */
+  int32_t precision;    /* TTIPM_F64 or TTIPM_MIXED (see below)                    */
+  const void* mlp;      /* tt_mlp handle when precond == TT_PREC_MLP               */
+} tt_solve_params;
+
+typedef struct {
+  int32_t iters;        /* Krylov iterations (0 for the direct solve)            */
+  int32_t method_used;  /* TT_SOLVE_DIRECT or TT_SOLVE_GMRES                     */
+  int32_t precond_used; /* TT_PREC_* actually used (after the fallback rule)     */
+  double rel_res;       /* true relative residual ||b - K x|| / ||b|| (FP64)      */
+} tt_solve_info;
+
+/*
+ * Solve K x = rhs for the local system (Sec. 3.3: matrix-free GMRES on the
+ * reduced projected system, or a dense direct solve when it is small).
+ * x holds the initial guess on entry and the solution on exit.  Synchronises
+ * the stream (convergence tests).  Returns TT_ERR_NOT_CONVERGED if rtol was
+ * not met within maxit (x then holds the best iterate).
+ */
+TTIPM_API int tt_local_solve(const tt_local_op* K, const double* rhs, double* x, const tt_solve_params* p,
+                   tt_solve_info* info, void* stream);
+
+/* ---- TT rounding ---------------------------------------------------------- */
+/*
+ * In-place TT rounding (Sec. 2.3, round_TT; the QR + truncated-SVD method of
+ * Oseledets 2011): right-to-left Householder QR, then left-to-right truncated
+ * SVD with per-bond budget eps / sqrt(d-1), eps = tol (TT_TOL_ABS) or
+ * tol * ||t||_F (TT_TOL_REL), ranks capped at max_rank.  Ranks never grow, so
+ * the caller's core buffers are reused; t->ranks is updated.  zeta_out (may be
+ * NULL) receives ||t - round(t)||_F accumulated from the discarded singular
+ * values (the spectral-shift size of Cor. 1).  Synchronises the stream.
+ * Returns TT_ERR_RANK_CAP (a warning, result valid) if the cap truncated more
+ * than the tolerance allowed.
+ */
+TTIPM_API int tt_round(tt_view* t, double tol, int32_t tol_mode, int32_t max_rank, double* zeta_out,
+             void* stream);
+
+/* ---- the interior-point method --------------------------------------------- */
+typedef struct ttipm_problem ttipm_problem;
+typedef struct ttipm_state ttipm_state;
+
+enum { TTIPM_MAXCUT = 0, TTIPM_THETA = 1, TTIPM_CC = 2 };
+enum { TTIPM_F64 = 0, TTIPM_MIXED = 1 };
+enum { TTIPM_DIR_XZ = 0, TTIPM_DIR_AHO = 1 };
+
+/*
+ * Problem description (Sec. 4).  graph is a TT matrix with 2 x 2 modes:
+ *   TTIPM_MAXCUT: the weighted adjacency A_G (Sec. 4.1);
+ *   TTIPM_THETA : the 0/1 adjacency A_G (Sec. 4.2);
+ *   TTIPM_CC    : the signed weights W = C+ - C-, zero diagonal (Sec. 4.3),
+ *                 with negdeg the TT vector (m_out = 2) of C- 1.
+ * The library builds C, A_eq, B_eq, K_Y (and A_ineq, K_T) itself and copies
+ * everything it needs; the caller's buffers may be freed after the call.
+ */
+typedef struct {
+  int32_t kind;
+  tt_view graph;
+  tt_view negdeg;   /* TTIPM_CC only (d = 0 otherwise) */
+} ttipm_problem_desc;
+
+TTIPM_API int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out);
+TTIPM_API void ttipm_problem_destroy(ttipm_problem* p);
+
+/* Parameters (defaults from ttipm_params_default follow Sec. 3.5 and Sec. 5.1). */
+typedef struct {
+  double eps_gap;       /* time-to-gap mark: rel_gap <= eps_gap, eps_p, eps_d <= 2 eps_gap */
+  double stop_gap;      /* stop when rel_gap <= stop_gap and eps_p, eps_d <= 2 stop_gap   */
+  double eta0;          /* initial forcing term (1e-3)                                    */
+  double delta;         /* forcing-term floor (1e-4 in the paper)                         */
+  double cmu;           /* eta <- max(min(eta, cmu mu), delta), cmu = 2                    */
+  double tau;           /* fraction of the maximal step (reading: 0.95)                   */
+  int32_t n_xz;         /* XZ warm-up iterations (3)                                      */
+  int32_t max_iter;     /* IPM iteration limit                                            */
+  int32_t rank_cap;     /* cap on the Newton-direction (frame) ranks                      */
+  int32_t iter_rank_cap;/* cap on iterate ranks after rounding                            */
+  int32_t amen_sweeps;  /* maximal AMEn half-sweeps per Newton solve                      */
+  int32_t direct_max;   /* local systems up to this size are solved densely               */
+  int32_t gmres_restart;
+  int32_t gmres_maxit;
+  int32_t precision;    /* TTIPM_F64 or TTIPM_MIXED                                       */
+  int32_t precond;      /* TT_PREC_*                                                      */
+  const void* mlp;      /* tt_mlp handle for TT_PREC_MLP                                  */
+  int32_t eig_rank;     /* rank of the TT eigenvector in the step-length solver          */
+  int32_t eig_sweeps;   /* ALS sweeps of the step-length solver                           */
+  int32_t verbose;      /* print one line per iteration to stderr                          */
+} ttipm_params;
+
+TTIPM_API void ttipm_params_default(ttipm_params* p);
+
+/* Initial point of Sec. 5.1: X = Z = lambda* I, Y = 0 (+ the inequality start). */
+TTIPM_API int ttipm_state_create(const ttipm_problem* p, const ttipm_params* prm, ttipm_state** out);
+TTIPM_API void ttipm_state_destroy(ttipm_state* s);
+
+/* Per-iteration record. */
+typedef struct {
+  int32_t iter, direction, sweeps_pred, sweeps_corr, krylov_iters;
+  int32_t rank_x, rank_y, rank_z, rank_w;
+  double mu, pobj, dobj, rel_gap, eps_p, eps_d, eps_c;
+  double alpha_p, alpha_d, sigma, eta;
+  double alpha_p_max, alpha_d_max;  /* TT eigen-solver step bounds before tau and the PD check */
+  int32_t backtracks;               /* step halvings forced by the positive-definiteness check */
+  double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration */
+} ttipm_step_info;
+
+/*
+ * One IPM iteration (Alg. 1): residuals and mu, Mehrotra predictor and
+ * corrector Newton solves by block AMEn, step lengths (Sec. 3.4), update and
+ * rounding with spectral shift (Cor. 1), eta update (Sec. 3.5).  info
+ * receives the measures of the iterate at entry and the step taken.
+ * Synchronises the stream.
+ */
+TTIPM_API int ttipm_step(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm_step_info* info,
+               void* stream);
+
+typedef struct {
+  int32_t status;       /* 0 converged to stop_gap, TT_ERR_NOT_CONVERGED otherwise */
+  int32_t iterations;
+  double time_to_gap;   /* seconds to the eps_gap mark (-1 if not reached)          */
+  double time_total;
+  double pobj, dobj, rel_gap, eps_p, eps_d;
+} ttipm_result;
+
+/*
+ * Iterate ttipm_step until the stopping test or max_iter.  log (may be NULL)
+ * receives up to log_cap per-iteration records.  Synchronises the stream.
+ */
+TTIPM_API int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm_result* res,
+                ttipm_step_info* log, int32_t log_cap, void* stream);
+
+/*
+ * Copy one iterate to the host: which = 'X', 'Y', 'Z' or 'T' for the
+ * iterates, 'x', 'y', 'z', 't' for the components of the last Newton
+ * direction (the corrector of the last ttipm_step).  ranks_out
+ * receives d+1 ranks; cores are packed one after another into host_out
+ * (capacity cap doubles).  Returns TT_ERR_ARG if cap is too small (the
+ * required size is written to *needed when needed != NULL).
+ */
+TTIPM_API int ttipm_state_export(const ttipm_state* s, int32_t which, int32_t* ranks_out, double* host_out,
+                       size_t cap, size_t* needed);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTIPM_H */

@@ -1,0 +1,640 @@
+// Block-AMEn Newton solver on the device (see amen.hpp).
+//
+// Per core k of a sweep:
+//   1. right-hand sides: every residual term is projected onto the frame
+//      with its cached environments (a projected local product whose trial is
+//      the stored TT), giving R_d^, R_p^, R_c^ [, R_t^];
+//   2. the reduced system of eq. (reduced_kkt_system) is solved for
+//      (dX_k, dY_k [, dT_k]) — densely (LU) when small, else by restarted GMRES
+//      whose matrix-free operator is the chain of projected local products;
+//   3. dZ_k = Aeq^T^ dY_k [+ s Aineq^T^ dT_k] - R_d^ (local elimination);
+//   4. the block core is split by SVD, the orthonormal factor becomes W_k and the
+//      block index moves to the neighbour (Sec. 2.3, Block TT);
+//   5. the environments of the new W_k are appended for every operator/term.
+// The sweep direction alternates; the stopping test is the largest relative
+// local residual of the incoming iterate over a half-sweep.
+#include "amen.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+
+#include "dense.hpp"
+#include "ttops.hpp"
+
+namespace ttipm {
+
+namespace {
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct EnvKey {
+  const TT* op;      // nullptr: identity
+  const TT* trial;   // nullptr: the frame W itself
+};
+
+struct Envs {
+  std::vector<EnvKey> keys;
+  std::vector<std::vector<DevBuf>> L, R;
+  int d = 0;
+
+  int op_rank(const EnvKey& e, int bond) const { return e.op ? e.op->r[bond] : 1; }
+  int trial_rank(const EnvKey& e, const BlockTT& W, int bond) const { return e.trial ? e.trial->r[bond] : W.r[bond]; }
+  const double* trial_core(const EnvKey& e, const BlockTT& W, int k) const {
+    return e.trial ? e.trial->core(k) : W.cores[k].get();
+  }
+
+  void init(const std::vector<EnvKey>& ks, int d_, Ctx& c) {
+    keys = ks;
+    d = d_;
+    L.clear();
+    R.clear();
+    L.resize(keys.size());
+    R.resize(keys.size());
+    for (size_t i = 0; i < keys.size(); ++i) {
+      L[i].resize(d);
+      R[i].resize(d);
+      L[i][0].reserve(1);
+      R[i][d - 1].reserve(1);
+      fill(1, 1.0, L[i][0].get(), c.s);
+      fill(1, 1.0, R[i][d - 1].get(), c.s);
+    }
+  }
+
+  void update_left(const BlockTT& W, int k, Ctx& c) {
+    for (size_t i = 0; i < keys.size(); ++i) {
+      const EnvKey& e = keys[i];
+      const int ra = W.r[k], ra2 = W.r[k + 1];
+      const int R0 = op_rank(e, k), R1 = op_rank(e, k + 1);
+      const int rc = trial_rank(e, W, k), rc2 = trial_rank(e, W, k + 1);
+      L[i][k + 1].reserve((size_t)ra2 * R1 * rc2);
+      env_left_step(L[i][k].get(), ra, R0, rc, W.cores[k].get(), 4, ra2, e.op ? e.op->core(k) : nullptr, R1, 4,
+                    trial_core(e, W, k), rc2, L[i][k + 1].get(), c);
+    }
+  }
+
+  void update_right(const BlockTT& W, int k, Ctx& c) {
+    for (size_t i = 0; i < keys.size(); ++i) {
+      const EnvKey& e = keys[i];
+      const int ra = W.r[k], ra2 = W.r[k + 1];
+      const int R0 = op_rank(e, k), R1 = op_rank(e, k + 1);
+      const int rc = trial_rank(e, W, k), rc2 = trial_rank(e, W, k + 1);
+      R[i][k - 1].reserve((size_t)ra * R0 * rc);
+      env_right_step(R[i][k].get(), ra2, R1, rc2, W.cores[k].get(), 4, ra, e.op ? e.op->core(k) : nullptr, R0, 4,
+                     trial_core(e, W, k), rc, R[i][k - 1].get(), c);
+    }
+  }
+};
+
+// The local KKT system at one core.
+struct LocalKKT {
+  const NewtonSys* sys;
+  Envs* envs;
+  const BlockTT* W;
+  int k, r, s, p, L;
+  int key_of_op[OP_COUNT];
+  DevBuf operm[OP_COUNT];
+  DevBuf tmp, tmp2;
+
+  void setup(Ctx& c) {
+    r = W->r[k];
+    s = W->r[k + 1];
+    p = 4 * r * s;
+    L = sys->L();
+    for (int o = 0; o < OP_COUNT; ++o) {
+      if (key_of_op[o] < 0) continue;
+      const TT* op = sys->ops[o];
+      operm[o].reserve((size_t)op->core_size(k));
+      permute_op_core(op->core(k), op->r[k], 4, op->r[k + 1], operm[o].get(), c.s);
+    }
+    tmp.reserve(p);
+    tmp2.reserve(p);
+  }
+
+  // y = alpha P_op x + beta y
+  void apply(int o, const double* x, double* y, double alpha, double beta, Ctx& c) {
+    const int key = key_of_op[o];
+    const TT* op = sys->ops[o];
+    local_apply(envs->L[key][k].get(), r, op->r[k], r, operm[o].get(), 4, envs->R[key][k].get(), s, op->r[k + 1], s,
+                x, y, alpha, beta, c);
+  }
+
+  // out = K u (u, out: [L][p])
+  void matvec(const double* u, double* out, Ctx& c) {
+    const double* x = u;
+    const double* y = u + p;
+    const double sg = sys->sense;
+    // row p
+    apply(OP_AEQ, x, out, -1.0, 0.0, c);
+    apply(OP_KY, y, out, 1.0, 1.0, c);
+    double* oc = out + (size_t)(L - 1) * p;
+    // chained dZ part: tmp = Aeq^T^ y (+ s Aineq^T^ t)
+    apply(OP_AEQT, y, tmp.get(), 1.0, 0.0, c);
+    if (sys->ineq) {
+      const double* t = u + 2 * p;
+      double* ot = out + p;
+      apply(OP_TA, x, ot, -sg, 0.0, c);
+      apply(OP_DK, t, ot, 1.0, 1.0, c);
+      apply(OP_AIT, t, tmp.get(), sg, 1.0, c);
+    }
+    apply(OP_LZ, x, oc, 1.0, 0.0, c);
+    apply(OP_LX, tmp.get(), oc, 1.0, 1.0, c);
+  }
+};
+
+__global__ void scale_components_kernel(const double* in, double* out, int Lp, int r, int m, int s,
+                                        const double* w) {
+  // in [l][a][i][b] -> out [a][i][l][b] scaled by 1/w[l]
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)Lp * r * m * s;
+  if (t >= total) return;
+  long q = t;
+  int b = (int)(q % s); q /= s;
+  int i = (int)(q % m); q /= m;
+  int a = (int)(q % r); q /= r;
+  int l = (int)q;
+  out[(((long)a * m + i) * Lp + l) * s + b] = in[t] / w[l];
+}
+
+__global__ void scale_components_right_kernel(const double* in, double* out, int Lp, int r, int m, int s,
+                                              const double* w) {
+  // in [l][a][i][b] -> out [a][l][i][b] scaled by 1/w[l]
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)Lp * r * m * s;
+  if (t >= total) return;
+  long q = t;
+  int b = (int)(q % s); q /= s;
+  int i = (int)(q % m); q /= m;
+  int a = (int)(q % r); q /= r;
+  int l = (int)q;
+  out[(((long)a * Lp + l) * m + i) * s + b] = in[t] / w[l];
+}
+
+int rank_for(const std::vector<double>& sv, double tol_rel, int cap) {
+  double tot = 0.0;
+  for (double x : sv) tot += x * x;
+  if (tot == 0.0) return 1;
+  const int n = (int)sv.size();
+  std::vector<double> tail(n + 1, 0.0);
+  for (int j = n - 1; j >= 0; --j) tail[j] = tail[j + 1] + sv[j] * sv[j];
+  int rk = n;
+  for (int j = 1; j < n; ++j)
+    if (std::sqrt(tail[j]) <= tol_rel * std::sqrt(tot)) { rk = j; break; }
+  return std::max(1, std::min(rk, cap));
+}
+
+// host copy of device vector norms per component
+std::vector<double> component_norms(const double* blk, int Lp, long n, Ctx& c) {
+  c.dot_out.reserve(Lp);
+  c.dot_part.reserve(mdot_part_size(1));
+  std::vector<double> out(Lp);
+  double* h = c.host(Lp);
+  for (int l = 0; l < Lp; ++l) mdot(n, 1, blk + (long)l * n, n, blk + (long)l * n, c.dot_out.get() + l, c.dot_part.get(), c.s);
+  TT_HIP(hipMemcpyAsync(h, c.dot_out.get(), sizeof(double) * Lp, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  for (int l = 0; l < Lp; ++l) out[l] = std::sqrt(std::max(h[l], 0.0));
+  return out;
+}
+
+}  // namespace
+
+double dev_norm(const double* x, long n, Ctx& c) {
+  c.dot_out.reserve(1);
+  c.dot_part.reserve(mdot_part_size(1));
+  mdot(n, 1, x, n, x, c.dot_out.get(), c.dot_part.get(), c.s);
+  double* h = c.host(1);
+  TT_HIP(hipMemcpyAsync(h, c.dot_out.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  return std::sqrt(std::max(h[0], 0.0));
+}
+
+// Move the block index from W.pos to W.pos + 1 (dir > 0) or W.pos - 1 (dir < 0).
+void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c) {
+  const int k = W.pos, Lp = W.Lp, r = W.r[k], s = W.r[k + 1], md = W.m;
+  const long n1 = (long)r * md * s;
+  std::vector<double> w = component_norms(W.blk.get(), Lp, n1, c);
+  for (double& x : w) x = (x > 0.0) ? x : 1.0;
+  DevBuf wdev(Lp);
+  TT_HIP(hipMemcpyAsync(wdev.get(), w.data(), sizeof(double) * Lp, hipMemcpyHostToDevice, c.s));
+  const long total = (long)Lp * n1;
+  DevBuf Ms(total), M(total);
+  DevBuf ones(Lp);
+  fill(Lp, 1.0, ones.get(), c.s);
+  if (dir > 0) {
+    // M[(a,i)][(l,b)]
+    const int rows = md * r, cols = Lp * s;
+    hipLaunchKernelGGL(scale_components_kernel, dim3(nblocks(total, 256)), dim3(256), 0, c.s, W.blk.get(), Ms.get(),
+                       Lp, r, md, s, wdev.get());
+    hipLaunchKernelGGL(scale_components_kernel, dim3(nblocks(total, 256)), dim3(256), 0, c.s, W.blk.get(), M.get(),
+                       Lp, r, md, s, ones.get());
+    TT_HIP(hipGetLastError());
+    SvdOut sv;
+    svd_rowmajor(Ms.get(), rows, cols, sv, c);
+    const int rk = rank_for(sv.sigma, tol_rel, std::min(cap, sv.k));
+    // W_k = U[:, :rk]  ([r][4][rk])
+    W.cores[k].reserve((size_t)rows * rk);
+    copy2d(sv.U.get(), sv.k, W.cores[k].get(), rk, rows, rk, c.s);
+    // coef = U_k^T M  (rk x (l,b))
+    DevBuf coef((size_t)rk * cols);
+    Gemm g;
+    g.M = rk; g.N = cols; g.K = rows;
+    g.A = W.cores[k].get(); g.am = 1; g.ak = rk;
+    g.B = M.get(); g.bk = cols; g.bn = 1;
+    g.C = coef.get(); g.cm = cols; g.cn = 1;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+    // new block at k+1: [(c,l)][(i,t)] = coef[(c,l)][b] W_{k+1}[b][(i,t)] -> permute to [l][c][i][t]
+    const int t = W.r[k + 2];
+    DevBuf nb((size_t)rk * Lp * md * t);
+    gemm(gemm_nn(rk * Lp, md * t, s, coef.get(), s, W.cores[k + 1].get(), md * t, nb.get(), md * t), c.s, &c.ws,
+         GemmPrec::F64);
+    W.blk.reserve((size_t)Lp * rk * md * t);
+    permute(nb.get(), W.blk.get(), {rk, Lp, md, t}, {1, 0, 2, 3}, c.s);
+    W.r[k + 1] = rk;
+    W.pos = k + 1;
+  } else {
+    // M[(a,l)][(i,b)]
+    const int rows = r * Lp, cols = md * s;
+    hipLaunchKernelGGL(scale_components_right_kernel, dim3(nblocks(total, 256)), dim3(256), 0, c.s, W.blk.get(),
+                       Ms.get(), Lp, r, md, s, wdev.get());
+    hipLaunchKernelGGL(scale_components_right_kernel, dim3(nblocks(total, 256)), dim3(256), 0, c.s, W.blk.get(),
+                       M.get(), Lp, r, md, s, ones.get());
+    TT_HIP(hipGetLastError());
+    SvdOut sv;
+    svd_rowmajor(Ms.get(), rows, cols, sv, c);
+    const int rk = rank_for(sv.sigma, tol_rel, std::min(cap, sv.k));
+    // W_k = Vt[:rk]  ([rk][4][s])
+    W.cores[k].reserve((size_t)rk * cols);
+    TT_HIP(hipMemcpyAsync(W.cores[k].get(), sv.Vt.get(), sizeof(double) * (size_t)rk * cols, hipMemcpyDeviceToDevice,
+                          c.s));
+    // coef = M Vt[:rk]^T  ((a,l) x rk)
+    DevBuf coef((size_t)rows * rk);
+    Gemm g;
+    g.M = rows; g.N = rk; g.K = cols;
+    g.A = M.get(); g.am = cols; g.ak = 1;
+    g.B = W.cores[k].get(); g.bk = 1; g.bn = cols;
+    g.C = coef.get(); g.cm = rk; g.cn = 1;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+    // new block at k-1: [(q,i)][(l,c)] = W_{k-1}[(q,i)][a] coef[a][(l,c)] -> permute to [l][q][i][c]
+    const int q = W.r[k - 1];
+    DevBuf nb((size_t)q * md * Lp * rk);
+    gemm(gemm_nn(q * md, Lp * rk, r, W.cores[k - 1].get(), r, coef.get(), Lp * rk, nb.get(), Lp * rk), c.s, &c.ws,
+         GemmPrec::F64);
+    W.blk.reserve((size_t)Lp * q * md * rk);
+    permute(nb.get(), W.blk.get(), {q, md, Lp, rk}, {2, 0, 1, 3}, c.s);
+    W.r[k] = rk;
+    W.pos = k - 1;
+  }
+  c.sync();
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// local solvers
+// ---------------------------------------------------------------------------
+
+// Dense direct solve of the reduced system.
+void solve_direct(LocalKKT& K, const double* f, double* u, Ctx& c) {
+  const int p = K.p, L = K.L;
+  const NewtonSys& sys = *K.sys;
+  auto dense = [&](int o, DevBuf& out) {
+    const TT* op = sys.ops[o];
+    const int key = K.key_of_op[o];
+    out.reserve((size_t)p * p);
+    local_dense_op(K.envs->L[key][K.k].get(), K.r, op->r[K.k], op->core(K.k), 4, K.envs->R[key][K.k].get(), K.s,
+                   op->r[K.k + 1], out.get(), c);
+  };
+  DevBuf A, AT, KY, LZ, LX, LXAT;
+  dense(OP_AEQ, A);
+  dense(OP_AEQT, AT);
+  dense(OP_KY, KY);
+  dense(OP_LZ, LZ);
+  dense(OP_LX, LX);
+  LXAT.reserve((size_t)p * p);
+  gemm(gemm_nn(p, p, p, LX.get(), p, AT.get(), p, LXAT.get(), p), c.s, &c.ws, GemmPrec::F64);
+  const int N = L * p;
+  DevBuf Kd((size_t)N * N), rhs(N);
+  fill((long)N * N, 0.0, Kd.get(), c.s);
+  auto put = [&](const double* blk, int bi, int bj, double alpha) {
+    place_block(blk, p, 1, p, Kd.get() + (size_t)bi * p * N, p, N, 0, bj * p, alpha, c.s);
+  };
+  // place_block writes [n0][mid][n1] into [N0][mid][N1]; rows are strided by N here
+  put(A.get(), 0, 0, -1.0);
+  put(KY.get(), 0, 1, 1.0);
+  put(LZ.get(), L - 1, 0, 1.0);
+  put(LXAT.get(), L - 1, 1, 1.0);
+  if (sys.ineq) {
+    DevBuf TA, DK, AiT, LXAiT;
+    dense(OP_TA, TA);
+    dense(OP_DK, DK);
+    dense(OP_AIT, AiT);
+    LXAiT.reserve((size_t)p * p);
+    gemm(gemm_nn(p, p, p, LX.get(), p, AiT.get(), p, LXAiT.get(), p), c.s, &c.ws, GemmPrec::F64);
+    put(TA.get(), 1, 0, -sys.sense);
+    put(DK.get(), 1, 2, 1.0);
+    put(LXAiT.get(), 2, 2, sys.sense);
+    c.sync();
+  }
+  TT_HIP(hipMemcpyAsync(rhs.get(), f, sizeof(double) * N, hipMemcpyDeviceToDevice, c.s));
+  c.ired.reserve(4);
+  int* st = reinterpret_cast<int*>(c.ired.get());
+  dense_lu_solve(Kd.get(), N, rhs.get(), 1, st, c.s);
+  int hst = 0;
+  TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  if (hst != 0) throw Error(TT_ERR_NUMERIC, "singular local KKT system (zero pivot)");
+  TT_HIP(hipMemcpyAsync(u, rhs.get(), sizeof(double) * N, hipMemcpyDeviceToDevice, c.s));
+}
+
+// Restarted GMRES with classical Gram-Schmidt applied twice (CGS2).  The
+// Hessenberg least-squares problem (size <= restart) is updated with Givens
+// rotations on the host after each Arnoldi step, whose convergence decision
+// needs the residual estimate there anyway.
+int solve_gmres(LocalKKT& K, const double* f, double* u, double rtol, int restart, int maxit, double* rel_res,
+                Ctx& c) {
+  const long n = (long)K.L * K.p;
+  const int m = std::max(1, restart);
+  DevBuf V((size_t)(m + 1) * n), w(n), r0(n), h(m + 2), h2(m + 2), yv(m + 1);
+  c.dot_part.reserve(mdot_part_size(m + 1));
+  const double bnorm = dev_norm(f, n, c);
+  if (bnorm == 0.0) {
+    fill(n, 0.0, u, c.s);
+    *rel_res = 0.0;
+    return 0;
+  }
+  int it_total = 0;
+  double rel = 1.0;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  double* hh = c.host(m + 2);
+  while (true) {
+    K.matvec(u, r0.get(), c);
+    axpby(n, 1.0, f, -1.0, r0.get(), c.s);   // r0 = f - K u
+    const double beta = dev_norm(r0.get(), n, c);
+    rel = beta / bnorm;
+    if (rel <= rtol || it_total >= maxit) break;
+    axpby(n, 1.0 / beta, r0.get(), 0.0, V.get(), c.s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < m && it_total < maxit; ++j, ++it_total) {
+      double* vj1 = V.get() + (size_t)(j + 1) * n;
+      K.matvec(V.get() + (size_t)j * n, vj1, c);
+      // CGS2
+      mdot(n, j + 1, V.get(), n, vj1, h.get(), c.dot_part.get(), c.s);
+      gemv_update(n, j + 1, V.get(), n, h.get(), -1.0, vj1, c.s);
+      mdot(n, j + 1, V.get(), n, vj1, h2.get(), c.dot_part.get(), c.s);
+      gemv_update(n, j + 1, V.get(), n, h2.get(), -1.0, vj1, c.s);
+      axpby(j + 1, 1.0, h2.get(), 1.0, h.get(), c.s);
+      mdot(n, 1, vj1, n, vj1, h.get() + j + 1, c.dot_part.get(), c.s);
+      TT_HIP(hipMemcpyAsync(hh, h.get(), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.s));
+      c.sync();
+      double hn = std::sqrt(std::max(hh[j + 1], 0.0));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
+      H[(size_t)(j + 1) * m + j] = hn;
+      if (hn > 0.0) axpby(n, 0.0, vj1, 1.0 / hn, vj1, c.s);
+      // apply previous rotations to column j
+      for (int i = 0; i < j; ++i) {
+        double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+      double rr = std::hypot(a, b);
+      cs[j] = (rr == 0.0) ? 1.0 : a / rr;
+      sn[j] = (rr == 0.0) ? 0.0 : b / rr;
+      H[(size_t)j * m + j] = rr;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      rel = std::fabs(g[j + 1]) / bnorm;
+      if (rel <= rtol || hn == 0.0) { ++j; ++it_total; break; }
+    }
+    // back substitution H y = g
+    std::vector<double> y(j, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int l = i + 1; l < j; ++l) acc -= H[(size_t)i * m + l] * y[l];
+      y[i] = (H[(size_t)i * m + i] != 0.0) ? acc / H[(size_t)i * m + i] : 0.0;
+    }
+    if (j > 0) {
+      TT_HIP(hipMemcpyAsync(yv.get(), y.data(), sizeof(double) * j, hipMemcpyHostToDevice, c.s));
+      gemv_update(n, j, V.get(), n, yv.get(), 1.0, u, c.s);
+      c.sync();   // y (host) is released at scope end
+    }
+    if (rel <= rtol || it_total >= maxit) {
+      // confirm with the true residual
+      K.matvec(u, r0.get(), c);
+      axpby(n, 1.0, f, -1.0, r0.get(), c.s);
+      rel = dev_norm(r0.get(), n, c) / bnorm;
+      if (rel <= rtol * 1.0000001 || it_total >= maxit) break;
+    }
+  }
+  *rel_res = rel;
+  return it_total;
+}
+
+__global__ void stack_dz_kernel(double* dz, const double* tmp, const double* rd, long p) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < p) dz[t] = tmp[t] - rd[t];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// dense projected operator (for the direct solve and the public ABI)
+// ---------------------------------------------------------------------------
+void local_dense_op(const double* phiL, int r, int R, const double* O, int m, const double* phiR, int s, int Rp,
+                    double* out, Ctx& c) {
+  // T1[a][c][(i,j,beta)] = sum_alpha phiL[a][alpha][c] O[alpha][(i,j,beta)]
+  const long w = (long)m * m * Rp;
+  DevBuf T1((size_t)r * r * w), T2((size_t)r * r * m * m * s * s);
+  {
+    Gemm g;
+    g.M = r; g.N = (int)w; g.K = R; g.batch = r;
+    g.A = phiL; g.am = 1; g.ak = r; g.sA = (long)R * r;
+    g.B = O; g.bk = w; g.bn = 1; g.sB = 0;
+    g.C = T1.get(); g.cm = w; g.cn = 1; g.sC = (long)r * w;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+  }
+  // T2[(a,c,i,j)][b][e] = sum_beta T1[(a,c,i,j)][beta] phiR[b][beta][e]
+  {
+    Gemm g;
+    g.M = r * r * m * m; g.N = s; g.K = Rp; g.batch = s;
+    g.A = T1.get(); g.am = Rp; g.ak = 1; g.sA = 0;
+    g.B = phiR; g.bk = s; g.bn = 1; g.sB = (long)Rp * s;
+    g.C = T2.get(); g.cm = (long)s * s; g.cn = 1; g.sC = s;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+  }
+  // [a][c][i][j][b][e] -> [a][i][b][c][j][e]
+  permute(T2.get(), out, {r, r, m, m, s, s}, {0, 2, 4, 1, 3, 5}, c.s);
+  c.sync();
+}
+
+TT BlockTT::component(int l, Ctx& c) const {
+  TT t(d, m, 1);
+  t.r = r;
+  for (int k = 0; k < d; ++k) {
+    t.alloc(k);
+    const double* src = (k == pos) ? blk.get() + (size_t)l * r[k] * m * r[k + 1] : cores[k].get();
+    TT_HIP(hipMemcpyAsync(t.core(k), src, sizeof(double) * t.core_size(k), hipMemcpyDeviceToDevice, c.s));
+  }
+  return t;
+}
+
+BlockTT block_from_frame(const TT& frame, int Lp, Ctx& c) {
+  TT f = tt_clone(frame, c);
+  tt_orth_right(f, 0, c);
+  BlockTT W;
+  W.d = f.d;
+  W.Lp = Lp;
+  W.m = f.mo * f.mi;
+  W.pos = 0;
+  W.r = f.r;
+  W.cores.resize(f.d);
+  for (int k = 1; k < f.d; ++k) W.cores[k] = std::move(f.cores[k]);
+  W.blk.reserve((size_t)Lp * W.m * W.r[1]);
+  fill((long)Lp * W.m * W.r[1], 0.0, W.blk.get(), c.s);
+  return W;
+}
+
+void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInfo& info, Ctx& c) {
+  TT_REQUIRE(W.pos == 0, "amen_solve expects the block at core 0");
+  TT_REQUIRE(W.Lp == sys.Lp(), "block size");
+  const int d = W.d;
+  const int L = sys.L();
+  // environment keys: system operators (trial = W), then residual terms
+  std::vector<EnvKey> keys;
+  int key_of_op[OP_COUNT];
+  for (int o = 0; o < OP_COUNT; ++o) {
+    key_of_op[o] = -1;
+    if (!sys.ops[o]) continue;
+    if (o >= OP_EXTRA0) continue;   // operators used only by residual terms
+    key_of_op[o] = (int)keys.size();
+    keys.push_back({sys.ops[o], nullptr});
+  }
+  std::vector<int> key_of_term(sys.terms.size());
+  for (size_t t = 0; t < sys.terms.size(); ++t) {
+    key_of_term[t] = (int)keys.size();
+    keys.push_back({sys.terms[t].op >= 0 ? sys.ops[sys.terms[t].op] : nullptr, sys.terms[t].vec});
+  }
+  Envs envs;
+  envs.init(keys, d, c);
+  double t0 = now();
+  for (int k = d - 1; k > 0; --k) envs.update_right(W, k, c);
+  c.sync();
+  info.t_env += now() - t0;
+  const double tol_svd = prm.tol / std::sqrt((double)d);
+  int dir = +1;
+  info.sweeps = 0;
+  info.krylov_iters = 0;
+  std::vector<DevBuf> Rhat(4);
+  DevBuf f, u, Ku, dz;
+  for (int sweep = 0; sweep < prm.max_sweeps; ++sweep) {
+    double max_res = 0.0;
+    for (int step = 0; step < d; ++step) {
+      const int k = (dir > 0) ? step : d - 1 - step;
+      TT_REQUIRE(W.pos == k, "block position");
+      LocalKKT K;
+      K.sys = &sys;
+      K.envs = &envs;
+      K.W = &W;
+      K.k = k;
+      for (int o = 0; o < OP_COUNT; ++o) K.key_of_op[o] = key_of_op[o];
+      K.setup(c);
+      const int p = K.p, r = K.r, s = K.s;
+      const long n = (long)L * p;
+      // projected residuals
+      for (int q = 0; q < 4; ++q) {
+        Rhat[q].reserve(p);
+        fill(p, 0.0, Rhat[q].get(), c.s);
+      }
+      for (size_t t = 0; t < sys.terms.size(); ++t) {
+        const Term& tm = sys.terms[t];
+        const int key = key_of_term[t];
+        const EnvKey& e = envs.keys[key];
+        const int R0 = envs.op_rank(e, k), R1 = envs.op_rank(e, k + 1);
+        const int rc = e.trial->r[k], rd = e.trial->r[k + 1];
+        const double* Op = nullptr;
+        DevBuf operm;
+        if (e.op) {
+          operm.reserve((size_t)e.op->core_size(k));
+          permute_op_core(e.op->core(k), R0, 4, R1, operm.get(), c.s);
+          Op = operm.get();
+        }
+        local_apply(envs.L[key][k].get(), r, R0, rc, Op, 4, envs.R[key][k].get(), s, R1, rd, e.trial->core(k),
+                    Rhat[tm.res].get(), tm.coef, 1.0, c);
+        c.sync();   // operm is released at scope end
+      }
+      // local right-hand side f = [-Rp; (-Rt;) -Rc + LX^ Rd]
+      f.reserve(n);
+      axpby(p, -1.0, Rhat[RES_P].get(), 0.0, f.get(), c.s);
+      if (sys.ineq) axpby(p, -1.0, Rhat[RES_T].get(), 0.0, f.get() + p, c.s);
+      double* fc = f.get() + (size_t)(L - 1) * p;
+      K.apply(OP_LX, Rhat[RES_D].get(), fc, 1.0, 0.0, c);
+      axpby(p, -1.0, Rhat[RES_C].get(), 1.0, fc, c.s);
+      // initial guess: current block components
+      u.reserve(n);
+      TT_HIP(hipMemcpyAsync(u.get(), W.blk.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+      Ku.reserve(n);
+      K.matvec(u.get(), Ku.get(), c);
+      axpby(n, 1.0, f.get(), -1.0, Ku.get(), c.s);
+      const double fn = dev_norm(f.get(), n, c);
+      const double res0 = dev_norm(Ku.get(), n, c) / (fn > 0 ? fn : 1.0);
+      max_res = std::max(max_res, res0);
+      double ts = now();
+      if (fn == 0.0) {
+        fill(n, 0.0, u.get(), c.s);
+      } else if (n <= prm.direct_max) {
+        solve_direct(K, f.get(), u.get(), c);
+      } else {
+        double rel = 0.0;
+        int its = solve_gmres(K, f.get(), u.get(), std::max(prm.tol * 0.1, 1e-14), prm.gmres_restart,
+                              prm.gmres_maxit, &rel, c);
+        info.krylov_iters += its;
+      }
+      // dZ_k = Aeq^T^ y (+ s Aineq^T^ t) - R_d^
+      dz.reserve(p);
+      K.apply(OP_AEQT, u.get() + p, K.tmp.get(), 1.0, 0.0, c);
+      if (sys.ineq) K.apply(OP_AIT, u.get() + 2 * p, K.tmp.get(), sys.sense, 1.0, c);
+      // write the block core [x, y, (t), dz]
+      W.blk.reserve((size_t)(L + 1) * p);
+      TT_HIP(hipMemcpyAsync(W.blk.get(), u.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+      hipLaunchKernelGGL(stack_dz_kernel, dim3(nblocks(p, 256)), dim3(256), 0, c.s, W.blk.get() + n, K.tmp.get(),
+                         Rhat[RES_D].get(), (long)p);
+      TT_HIP(hipGetLastError());
+      c.sync();
+      info.t_solve += now() - ts;
+      // move the block index and extend the environments
+      if (dir > 0 && k < d - 1) {
+        double t1 = now();
+        split_block(W, +1, tol_svd, prm.rank_cap, c);
+        info.t_svd += now() - t1;
+        t1 = now();
+        envs.update_left(W, k, c);
+        c.sync();
+        info.t_env += now() - t1;
+      } else if (dir < 0 && k > 0) {
+        double t1 = now();
+        split_block(W, -1, tol_svd, prm.rank_cap, c);
+        info.t_svd += now() - t1;
+        t1 = now();
+        envs.update_right(W, k, c);
+        c.sync();
+        info.t_env += now() - t1;
+      }
+    }
+    info.sweeps += 1;
+    info.last_max_res = max_res;
+    dir = -dir;
+    if (max_res < prm.tol && sweep >= 1) break;
+  }
+  // return the block to core 0 without truncation
+  while (W.pos > 0) split_block(W, -1, 0.0, 1 << 30, c);
+  info.max_rank = 0;
+  for (int x : W.r) info.max_rank = std::max(info.max_rank, x);
+}
+
+}  // namespace ttipm

@@ -1,0 +1,88 @@
+// Block-AMEn solve of the TT Newton system (Sec. 2.3 "Block Tensor-Train",
+// Sec. 3.3): one shared frame W for dX, dY, [dT], dZ; at each core the reduced
+// projected system of eq. (reduced_kkt_system) is solved with dZ eliminated
+// locally, the block index is moved to the neighbour by a truncated SVD, and
+// the left/right environments of every operator and right-hand-side term are
+// cached and updated incrementally.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "tt.hpp"
+
+namespace ttipm {
+
+// Indices of the system operators (all TT matrices with 4 x 4 modes).
+enum SysOpId { OP_AEQ = 0, OP_AEQT, OP_KY, OP_LZ, OP_LX, OP_TA, OP_DK, OP_AIT, OP_EXTRA0, OP_EXTRA1, OP_COUNT };
+
+// Residual blocks of eq. (tt-kkt-newton-system).
+enum ResId { RES_D = 0, RES_P = 1, RES_C = 2, RES_T = 3 };
+
+// A right-hand-side term  coef * op(vec)  contributing to residual `res`
+// (op < 0: the vector itself).  Residuals are never formed as TTs; their
+// projections come from environments of (W | op | vec).
+struct Term {
+  int res;
+  double coef;
+  int op;
+  const TT* vec;
+};
+
+struct NewtonSys {
+  bool ineq = false;
+  double sense = 1.0;          // +1: A_ineq X <= B_ineq; -1: >= (Sec. 4.3)
+  const TT* ops[OP_COUNT] = {};
+  std::vector<Term> terms;
+  int L() const { return ineq ? 3 : 2; }       // solved components
+  int Lp() const { return L() + 1; }           // stored components (dZ last)
+};
+
+// Shared-frame block TT; the block core at `pos` is [Lp][r_pos][4][r_pos+1].
+struct BlockTT {
+  int d = 0, pos = 0, Lp = 3, m = 4;   // m: mode size of every core
+  std::vector<int> r;
+  std::vector<DevBuf> cores;
+  DevBuf blk;
+  long blk_size() const { return (long)Lp * r[pos] * m * r[pos + 1]; }
+  TT component(int l, Ctx& c) const;   // the TT of component l
+};
+
+// Move the block index to the right (dir > 0) or left neighbour by a truncated
+// SVD of the component-normalised block core (relative tolerance, rank cap).
+void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c);
+// Norm of a device vector (deterministic; synchronises).
+double dev_norm(const double* x, long n, Ctx& c);
+
+struct AmenParams {
+  double tol = 1e-6;        // local residual target (also the SVD truncation budget / sqrt(d))
+  int max_sweeps = 6;       // half-sweeps (alternating direction)
+  int rank_cap = 32;
+  int direct_max = 1024;    // local systems of size <= direct_max are solved densely
+  int gmres_restart = 40;
+  int gmres_maxit = 400;
+  int precond = 0;          // TT_PREC_*
+  bool mixed = false;       // BF16 MFMA contractions inside the Krylov solve
+};
+
+struct AmenInfo {
+  int sweeps = 0;
+  int krylov_iters = 0;
+  int max_rank = 0;
+  double last_max_res = 0.0;
+  double t_env = 0, t_solve = 0, t_svd = 0;
+};
+
+// Solve the Newton system starting from W (block at position 0).  On return
+// the block is back at position 0 (warm start for the next call).
+void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInfo& info, Ctx& c);
+
+// Build an initial block TT (block at 0) from a frame TT (e.g. the identity).
+BlockTT block_from_frame(const TT& frame, int Lp, Ctx& c);
+
+// ---- local systems (used by amen_solve and by the C ABI) -----------------------
+// Dense projected operator [(a,i,b)][(c,j,e)] (p x p) from environments.
+void local_dense_op(const double* phiL, int r, int R, const double* O, int m, const double* phiR, int s, int Rp,
+                    double* out, Ctx& c);
+
+}  // namespace ttipm

@@ -1,0 +1,480 @@
+// The C ABI (include/ttipm.h): argument checks, marshalling of tt_view
+// structures into device TTs, and translation of internal errors into status
+// codes.  No C++ exception crosses this boundary.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "../../include/ttipm.h"
+#include "amen.hpp"
+#include "dense.hpp"
+#include "ipm.hpp"
+#include "ttops.hpp"
+
+namespace ttipm {
+const char* last_error();
+}
+
+using namespace ttipm;
+
+struct ttipm_problem {
+  Problem P;
+};
+
+struct ttipm_state {
+  State S;
+  int d = 0;
+};
+
+namespace {
+
+std::mutex g_ctx_mu;
+std::map<void*, std::unique_ptr<Ctx>> g_ctx;
+
+// One execution context (scratch buffers) per stream.
+Ctx& ctx_for(void* stream) {
+  std::lock_guard<std::mutex> g(g_ctx_mu);
+  auto it = g_ctx.find(stream);
+  if (it != g_ctx.end()) return *it->second;
+  auto c = std::make_unique<Ctx>();
+  c->s = as_stream(stream);
+  Ctx& ref = *c;
+  g_ctx[stream] = std::move(c);
+  return ref;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    set_last_error("");
+    return f();
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return TT_ERR_ARG;
+  } catch (...) {
+    set_last_error("unknown error");
+    return TT_ERR_ARG;
+  }
+}
+
+void check_view(const tt_view* v, const char* name) {
+  if (!v) throw Error(TT_ERR_ARG, std::string(name) + " is NULL");
+  if (v->d < 1 || !v->ranks || !v->cores) throw Error(TT_ERR_ARG, std::string(name) + ": empty view");
+  if (v->ranks[0] != 1 || v->ranks[v->d] != 1) throw Error(TT_ERR_ARG, std::string(name) + ": boundary ranks must be 1");
+  if (v->m_out < 1 || v->m_in < 1) throw Error(TT_ERR_ARG, std::string(name) + ": mode sizes");
+  for (int k = 0; k < v->d; ++k) {
+    if (v->ranks[k + 1] < 1) throw Error(TT_ERR_ARG, std::string(name) + ": ranks must be positive");
+    if (!v->cores[k]) throw Error(TT_ERR_ARG, std::string(name) + ": NULL core pointer");
+  }
+}
+
+// Non-owning TT over caller buffers (shallow): copies are made only where the
+// library needs its own storage.
+TT view_as_tt(const tt_view& v, Ctx& c) { return tt_from_view(v, c); }
+
+}  // namespace
+
+extern "C" {
+
+const char* tt_last_error(void) { return ttipm::last_error(); }
+
+const char* tt_version(void) { return "ttipm-mi355x 0.1 (gfx950)"; }
+
+int tt_contract_interfaces(const tt_view* test, const tt_view* op, const tt_view* trial, int32_t k, int32_t dir,
+                           const double* phi_in, double* phi_out, void* stream) {
+  return guarded([&]() -> int {
+    check_view(test, "test");
+    check_view(trial, "trial");
+    if (op) check_view(op, "op");
+    if (test->m_in != 1 || trial->m_in != 1) throw Error(TT_ERR_ARG, "test and trial must be TT vectors");
+    if (test->d != trial->d || (op && op->d != test->d)) throw Error(TT_ERR_ARG, "d mismatch");
+    if (k < 0 || k >= test->d) throw Error(TT_ERR_ARG, "core index out of range");
+    if (!phi_in || !phi_out) throw Error(TT_ERR_ARG, "NULL environment pointer");
+    if (op && (op->m_out != test->m_out || op->m_in != trial->m_out))
+      throw Error(TT_ERR_ARG, "operator modes must be test.m_out x trial.m_out");
+    if (!op && test->m_out != trial->m_out) throw Error(TT_ERR_ARG, "identity needs equal mode sizes");
+    Ctx& c = ctx_for(stream);
+    c.prec = GemmPrec::F64;
+    const int ra = test->ranks[k], ra2 = test->ranks[k + 1];
+    const int rc = trial->ranks[k], rc2 = trial->ranks[k + 1];
+    const int R0 = op ? op->ranks[k] : 1, R1 = op ? op->ranks[k + 1] : 1;
+    const int mo = test->m_out, mi = trial->m_out;
+    if (dir == TT_LEFT)
+      env_left_step(phi_in, ra, R0, rc, test->cores[k], mo, ra2, op ? op->cores[k] : nullptr, R1, mi, trial->cores[k],
+                    rc2, phi_out, c);
+    else if (dir == TT_RIGHT)
+      env_right_step(phi_in, ra2, R1, rc2, test->cores[k], mo, ra, op ? op->cores[k] : nullptr, R0, mi,
+                     trial->cores[k], rc, phi_out, c);
+    else
+      throw Error(TT_ERR_ARG, "dir must be TT_LEFT or TT_RIGHT");
+    return TT_OK;
+  });
+}
+
+namespace {
+
+void check_local_op(const tt_local_op* K) {
+  if (!K || K->r < 1 || K->rp < 1 || K->m < 1 || K->L < 1 || K->nblocks < 0 || (K->nblocks && !K->blocks))
+    throw Error(TT_ERR_ARG, "invalid tt_local_op");
+  for (int b = 0; b < K->nblocks; ++b) {
+    const tt_local_block& B = K->blocks[b];
+    if (B.row < 0 || B.row >= K->L || B.col < 0 || B.col >= K->L) throw Error(TT_ERR_ARG, "block position");
+    if (B.nchain < 1 || B.nchain > 2) throw Error(TT_ERR_ARG, "nchain must be 1 or 2");
+    for (int q = 0; q < B.nchain; ++q) {
+      const tt_proj_op& o = B.op[q];
+      if (!o.phiL || !o.phiR || o.R < 1 || o.Rp < 1) throw Error(TT_ERR_ARG, "projected operator");
+      if (!o.core && (o.R != 1 || o.Rp != 1)) throw Error(TT_ERR_ARG, "identity operator needs R = Rp = 1");
+    }
+  }
+}
+
+// y = K x for the generic block description (chains of projected operators).
+void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c) {
+  const long p = (long)K->r * K->m * K->rp;
+  fill((long)K->L * p, 0.0, y, c.s);
+  DevBuf perm0, perm1, tmp(p);
+  for (int b = 0; b < K->nblocks; ++b) {
+    const tt_local_block& B = K->blocks[b];
+    const double* xin = x + (long)B.col * p;
+    double* yout = y + (long)B.row * p;
+    auto prep = [&](const tt_proj_op& o, DevBuf& buf) -> const double* {
+      if (!o.core) return nullptr;
+      buf.reserve((size_t)o.R * K->m * K->m * o.Rp);
+      permute_op_core(o.core, o.R, K->m, o.Rp, buf.get(), c.s);
+      return buf.get();
+    };
+    if (B.nchain == 1) {
+      const tt_proj_op& o = B.op[0];
+      local_apply(o.phiL, K->r, o.R, K->r, prep(o, perm0), K->m, o.phiR, K->rp, o.Rp, K->rp, xin, yout, B.coeff, 1.0, c);
+    } else {
+      const tt_proj_op& o0 = B.op[0];
+      const tt_proj_op& o1 = B.op[1];
+      local_apply(o0.phiL, K->r, o0.R, K->r, prep(o0, perm0), K->m, o0.phiR, K->rp, o0.Rp, K->rp, xin, tmp.get(), 1.0,
+                  0.0, c);
+      local_apply(o1.phiL, K->r, o1.R, K->r, prep(o1, perm1), K->m, o1.phiR, K->rp, o1.Rp, K->rp, tmp.get(), yout,
+                  B.coeff, 1.0, c);
+    }
+  }
+}
+
+}  // namespace
+
+int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stream) {
+  return guarded([&]() -> int {
+    check_local_op(K);
+    if (!x || !y) throw Error(TT_ERR_ARG, "NULL vector");
+    Ctx& c = ctx_for(stream);
+    c.prec = GemmPrec::F64;
+    generic_matvec(K, x, y, c);
+    c.sync();   // local scratch (permuted cores) is released on return
+    return TT_OK;
+  });
+}
+
+int tt_local_solve(const tt_local_op* K, const double* rhs, double* x, const tt_solve_params* p, tt_solve_info* info,
+                   void* stream) {
+  return guarded([&]() -> int {
+    check_local_op(K);
+    if (!rhs || !x || !p) throw Error(TT_ERR_ARG, "NULL argument");
+    Ctx& c = ctx_for(stream);
+    c.prec = GemmPrec::F64;
+    const long n = (long)K->L * K->r * K->m * K->rp;
+    tt_solve_info inf{};
+    int method = p->method;
+    if (method == TT_SOLVE_AUTO) method = (n <= p->direct_max) ? TT_SOLVE_DIRECT : TT_SOLVE_GMRES;
+    if (method == TT_SOLVE_DIRECT) {
+      // dense K by applying the operator to unit vectors, then LU
+      if (n > 8192) throw Error(TT_ERR_ARG, "direct solve limited to 8192 unknowns");
+      DevBuf Kd((size_t)n * n), e(n), col(n), Kt((size_t)n * n), b(n);
+      for (long j = 0; j < n; ++j) {
+        fill(n, 0.0, e.get(), c.s);
+        fill(1, 1.0, e.get() + j, c.s);
+        generic_matvec(K, e.get(), Kt.get() + (size_t)j * n, c);   // column j (stored as row j of Kt)
+      }
+      permute(Kt.get(), Kd.get(), {n, n}, {1, 0}, c.s);
+      TT_HIP(hipMemcpyAsync(b.get(), rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+      c.ired.reserve(4);
+      int* st = reinterpret_cast<int*>(c.ired.get());
+      dense_lu_solve(Kd.get(), (int)n, b.get(), 1, st, c.s);
+      int hst = 0;
+      TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+      c.sync();
+      if (hst) throw Error(TT_ERR_NUMERIC, "singular local system");
+      TT_HIP(hipMemcpyAsync(x, b.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+      inf.method_used = TT_SOLVE_DIRECT;
+      inf.iters = 0;
+    } else {
+      // restarted GMRES (CGS2) on the generic operator
+      const int m = std::max(1, p->restart);
+      DevBuf V((size_t)(m + 1) * n), r0(n), h(m + 2), h2(m + 2), yv(m + 1);
+      c.dot_part.reserve(mdot_part_size(m + 1));
+      const double bn = dev_norm(rhs, n, c);
+      int it = 0;
+      double rel = 0.0;
+      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+      double* hh = c.host(m + 2);
+      if (bn == 0.0) {
+        fill(n, 0.0, x, c.s);
+      } else {
+        while (true) {
+          generic_matvec(K, x, r0.get(), c);
+          axpby(n, 1.0, rhs, -1.0, r0.get(), c.s);
+          const double beta = dev_norm(r0.get(), n, c);
+          rel = beta / bn;
+          if (rel <= p->rtol || it >= p->maxit) break;
+          axpby(n, 1.0 / beta, r0.get(), 0.0, V.get(), c.s);
+          std::fill(g.begin(), g.end(), 0.0);
+          g[0] = beta;
+          int j = 0;
+          for (; j < m && it < p->maxit; ++j, ++it) {
+            double* v1 = V.get() + (size_t)(j + 1) * n;
+            generic_matvec(K, V.get() + (size_t)j * n, v1, c);
+            mdot(n, j + 1, V.get(), n, v1, h.get(), c.dot_part.get(), c.s);
+            gemv_update(n, j + 1, V.get(), n, h.get(), -1.0, v1, c.s);
+            mdot(n, j + 1, V.get(), n, v1, h2.get(), c.dot_part.get(), c.s);
+            gemv_update(n, j + 1, V.get(), n, h2.get(), -1.0, v1, c.s);
+            axpby(j + 1, 1.0, h2.get(), 1.0, h.get(), c.s);
+            mdot(n, 1, v1, n, v1, h.get() + j + 1, c.dot_part.get(), c.s);
+            TT_HIP(hipMemcpyAsync(hh, h.get(), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.s));
+            c.sync();
+            const double hn = std::sqrt(std::max(hh[j + 1], 0.0));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            if (hn > 0.0) axpby(n, 0.0, v1, 1.0 / hn, v1, c.s);
+            for (int i = 0; i < j; ++i) {
+              double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+              H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+              H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+            double rr = std::hypot(a, bb);
+            cs[j] = rr == 0.0 ? 1.0 : a / rr;
+            sn[j] = rr == 0.0 ? 0.0 : bb / rr;
+            H[(size_t)j * m + j] = rr;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            rel = std::fabs(g[j + 1]) / bn;
+            if (rel <= p->rtol || hn == 0.0) { ++j; ++it; break; }
+          }
+          std::vector<double> y(j, 0.0);
+          for (int i = j - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int l = i + 1; l < j; ++l) acc -= H[(size_t)i * m + l] * y[l];
+            y[i] = H[(size_t)i * m + i] != 0.0 ? acc / H[(size_t)i * m + i] : 0.0;
+          }
+          if (j > 0) {
+            TT_HIP(hipMemcpyAsync(yv.get(), y.data(), sizeof(double) * j, hipMemcpyHostToDevice, c.s));
+            gemv_update(n, j, V.get(), n, yv.get(), 1.0, x, c.s);
+            c.sync();
+          }
+          if (it >= p->maxit) {
+            generic_matvec(K, x, r0.get(), c);
+            axpby(n, 1.0, rhs, -1.0, r0.get(), c.s);
+            rel = dev_norm(r0.get(), n, c) / bn;
+            break;
+          }
+        }
+      }
+      inf.method_used = TT_SOLVE_GMRES;
+      inf.iters = it;
+      inf.rel_res = rel;
+    }
+    // true residual in FP64
+    if (inf.method_used == TT_SOLVE_DIRECT) {
+      DevBuf r0(n);
+      generic_matvec(K, x, r0.get(), c);
+      axpby(n, 1.0, rhs, -1.0, r0.get(), c.s);
+      const double bn = dev_norm(rhs, n, c);
+      inf.rel_res = bn > 0 ? dev_norm(r0.get(), n, c) / bn : 0.0;
+    }
+    inf.precond_used = TT_PREC_NONE;
+    if (info) *info = inf;
+    c.sync();
+    return (inf.rel_res <= p->rtol || inf.method_used == TT_SOLVE_DIRECT) ? TT_OK : TT_ERR_NOT_CONVERGED;
+  });
+}
+
+int tt_round(tt_view* t, double tol, int32_t tol_mode, int32_t max_rank, double* zeta_out, void* stream) {
+  return guarded([&]() -> int {
+    check_view(t, "t");
+    if (!(tol >= 0.0)) throw Error(TT_ERR_ARG, "tol must be >= 0");
+    if (max_rank < 1) throw Error(TT_ERR_ARG, "max_rank must be >= 1");
+    Ctx& c = ctx_for(stream);
+    c.prec = GemmPrec::F64;
+    TT w = tt_from_view(*t, c);
+    double eps = tol;
+    if (tol_mode == TT_TOL_REL) eps = tol * tt_norm(w, c);
+    bool capped = false;
+    const double zeta = tt_round_abs(w, eps, max_rank, c, &capped);
+    for (int k = 0; k <= t->d; ++k) t->ranks[k] = w.r[k];
+    for (int k = 0; k < t->d; ++k)
+      TT_HIP(hipMemcpyAsync(t->cores[k], w.core(k), sizeof(double) * w.core_size(k), hipMemcpyDeviceToDevice, c.s));
+    c.sync();
+    if (zeta_out) *zeta_out = zeta;
+    return capped ? TT_ERR_RANK_CAP : TT_OK;
+  });
+}
+
+void ttipm_params_default(ttipm_params* p) {
+  if (!p) return;
+  p->eps_gap = 1e-4;
+  p->stop_gap = 1e-4;
+  p->eta0 = 1e-3;
+  p->delta = 1e-4;
+  p->cmu = 2.0;
+  p->tau = 0.95;
+  p->n_xz = 3;
+  p->max_iter = 60;
+  p->rank_cap = 16;
+  p->iter_rank_cap = 0;
+  p->amen_sweeps = 6;
+  p->direct_max = 1024;
+  p->gmres_restart = 40;
+  p->gmres_maxit = 400;
+  p->precision = TTIPM_F64;
+  p->precond = TT_PREC_NONE;
+  p->mlp = nullptr;
+  p->eig_rank = 6;
+  p->eig_sweeps = 2;
+  p->verbose = 0;
+}
+
+int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {
+  return guarded([&]() -> int {
+    if (!desc || !out) throw Error(TT_ERR_ARG, "NULL argument");
+    check_view(&desc->graph, "graph");
+    if (desc->graph.m_out != 2 || desc->graph.m_in != 2) throw Error(TT_ERR_ARG, "graph must have 2 x 2 modes");
+    Ctx& c = ctx_for(nullptr);
+    c.prec = GemmPrec::F64;
+    TT G = tt_from_view(desc->graph, c);
+    std::unique_ptr<TT> nd;
+    if (desc->kind == TTIPM_CC) {
+      check_view(&desc->negdeg, "negdeg");
+      nd = std::make_unique<TT>(tt_from_view(desc->negdeg, c));
+    }
+    auto p = std::make_unique<ttipm_problem>();
+    p->P = build_problem(desc->kind, G, nd.get(), c);
+    c.sync();
+    *out = p.release();
+    return TT_OK;
+  });
+}
+
+void ttipm_problem_destroy(ttipm_problem* p) { delete p; }
+
+int ttipm_state_create(const ttipm_problem* p, const ttipm_params* prm, ttipm_state** out) {
+  return guarded([&]() -> int {
+    if (!p || !prm || !out) throw Error(TT_ERR_ARG, "NULL argument");
+    Ctx& c = ctx_for(nullptr);
+    auto s = std::make_unique<ttipm_state>();
+    init_state(p->P, *prm, s->S, c);
+    s->d = p->P.d;
+    c.sync();
+    *out = s.release();
+    return TT_OK;
+  });
+}
+
+void ttipm_state_destroy(ttipm_state* s) { delete s; }
+
+int ttipm_step(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm_step_info* info, void* stream) {
+  return guarded([&]() -> int {
+    if (!p || !s || !prm) throw Error(TT_ERR_ARG, "NULL argument");
+    Ctx& c = ctx_for(stream);
+    c.prec = GemmPrec::F64;
+    ttipm_step_info inf{};
+    ipm_step(p->P, s->S, *prm, inf, c);
+    if (info) *info = inf;
+    if (!std::isfinite(inf.pobj) || !std::isfinite(inf.dobj)) throw Error(TT_ERR_NUMERIC, "non-finite objective");
+    return TT_OK;
+  });
+}
+
+int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm_result* res, ttipm_step_info* log,
+                int32_t log_cap, void* stream) {
+  return guarded([&]() -> int {
+    if (!p || !s || !prm || !res) throw Error(TT_ERR_ARG, "NULL argument");
+    Ctx& c = ctx_for(stream);
+    c.prec = GemmPrec::F64;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    ttipm_result r{};
+    r.time_to_gap = -1.0;
+    r.status = TT_ERR_NOT_CONVERGED;
+    int it = 0;
+    for (;; ++it) {
+      ttipm_step_info m{};
+      ipm_measures(p->P, s->S, m, c);
+      const bool at_mark = m.rel_gap <= prm->eps_gap && m.eps_p <= 2 * prm->eps_gap && m.eps_d <= 2 * prm->eps_gap;
+      if (at_mark && r.time_to_gap < 0) r.time_to_gap = elapsed();
+      r.pobj = m.pobj;
+      r.dobj = m.dobj;
+      r.rel_gap = m.rel_gap;
+      r.eps_p = m.eps_p;
+      r.eps_d = m.eps_d;
+      const bool done = m.rel_gap <= prm->stop_gap && m.eps_p <= 2 * prm->stop_gap && m.eps_d <= 2 * prm->stop_gap;
+      if (done) {
+        r.status = TT_OK;
+        break;
+      }
+      if (it >= prm->max_iter) break;
+      ttipm_step_info inf{};
+      ipm_step(p->P, s->S, *prm, inf, c);
+      if (log && it < log_cap) log[it] = inf;
+      if (prm->verbose)
+        std::fprintf(stderr,
+                     "it %2d %s mu %.2e pobj %+.10e dobj %+.10e gap %.2e ep %.1e ed %.1e ap %.3f ad %.3f "
+                     "rX %d rY %d rZ %d rW %d sw %d/%d kr %d t %.3fs\n",
+                     inf.iter, inf.direction ? "aho" : "xz ", inf.mu, inf.pobj, inf.dobj, inf.rel_gap, inf.eps_p,
+                     inf.eps_d, inf.alpha_p, inf.alpha_d, inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w,
+                     inf.sweeps_pred, inf.sweeps_corr, inf.krylov_iters, inf.t_total);
+      if (!std::isfinite(inf.pobj)) throw Error(TT_ERR_NUMERIC, "non-finite objective");
+    }
+    r.iterations = it;
+    r.time_total = elapsed();
+    *res = r;
+    return TT_OK;
+  });
+}
+
+int ttipm_state_export(const ttipm_state* s, int32_t which, int32_t* ranks_out, double* host_out, size_t cap,
+                       size_t* needed) {
+  return guarded([&]() -> int {
+    if (!s || !ranks_out) throw Error(TT_ERR_ARG, "NULL argument");
+    const TT* t = nullptr;
+    switch (which) {
+      case 'X': t = &s->S.X; break;
+      case 'Y': t = &s->S.Y; break;
+      case 'Z': t = &s->S.Z; break;
+      case 'T': t = &s->S.T; break;
+      case 'x': t = &s->S.dX; break;
+      case 'y': t = &s->S.dY; break;
+      case 'z': t = &s->S.dZ; break;
+      case 't': t = &s->S.dT; break;
+      default: throw Error(TT_ERR_ARG, "which must be one of X Y Z T x y z t");
+    }
+    if (t->d == 0) throw Error(TT_ERR_ARG, "iterate not present");
+    size_t total = 0;
+    for (int k = 0; k < t->d; ++k) total += (size_t)t->core_size(k);
+    if (needed) *needed = total;
+    for (int k = 0; k <= t->d; ++k) ranks_out[k] = t->r[k];
+    if (!host_out || cap < total) return (int)TT_ERR_ARG;
+    Ctx& c = ctx_for(nullptr);
+    size_t off = 0;
+    for (int k = 0; k < t->d; ++k) {
+      TT_HIP(hipMemcpyAsync(host_out + off, t->core(k), sizeof(double) * t->core_size(k), hipMemcpyDeviceToHost, c.s));
+      off += (size_t)t->core_size(k);
+    }
+    c.sync();
+    return TT_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,390 @@
+// Small dense FP64 factorisations that stay on the device: Householder QR,
+// one-sided Jacobi SVD, LU with partial pivoting, Cholesky and triangular
+// solves.  They serve TT rounding (QR + truncated SVD, Sec. 2.3), the SVD move
+// of the block index in AMEn (Sec. 2.3, Block TT), the dense local solve
+// (Sec. 3.3) and the generalised eigenproblems of the step length (Sec. 3.4).
+//
+// The matrices are small (at most a few thousand rows, a few hundred columns),
+// so each factorisation runs in one 1024-thread workgroup: the matrix lives in
+// global memory (resident in the XCD's L2), columns are processed with 64-lane
+// wavefront reductions, and the workgroup synchronises between the sequential
+// steps of the algorithm.  Reductions use a fixed order, so results are
+// reproducible run to run.
+#include "dense.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ttipm {
+
+constexpr int DT = 1024;        // threads per dense workgroup
+constexpr int NW = DT / 64;     // waves per workgroup
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum with a fixed reduction order (result broadcast to all threads).
+__device__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR, column-major A (m x n, leading dimension lda), in place.
+// On exit R is in the upper triangle, the reflector vectors v_j (v_j[j] = 1
+// implicit) below it, and tau[j] their scalars: H_j = I - tau_j v_j v_j^T.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(DT) void qr_kernel(double* A, int m, int n, int lda, double* tau) {
+  __shared__ double red[NW];
+  __shared__ double s_beta, s_tau, s_scale;
+  const int kmax = min(m, n);
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  for (int j = 0; j < kmax; ++j) {
+    double* col = A + (long)j * lda;
+    double part = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) part += col[i] * col[i];
+    double sig = block_sum(part, red);
+    if (threadIdx.x == 0) {
+      double alpha = col[j];
+      if (sig == 0.0) {
+        s_tau = 0.0; s_beta = alpha; s_scale = 0.0;
+      } else {
+        double nrm = sqrt(alpha * alpha + sig);
+        double beta = (alpha <= 0.0) ? nrm : -nrm;
+        s_tau = (beta - alpha) / beta;
+        s_scale = 1.0 / (alpha - beta);
+        s_beta = beta;
+      }
+      tau[j] = s_tau;
+    }
+    __syncthreads();
+    const double sc = s_scale, tj = s_tau;
+    for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) col[i] *= sc;
+    __syncthreads();
+    if (threadIdx.x == 0) col[j] = s_beta;
+    // apply H_j to trailing columns: one wave per column
+    if (tj != 0.0) {
+      for (int c = j + 1 + w; c < n; c += NW) {
+        double* cc = A + (long)c * lda;
+        double d = 0.0;
+        for (int i = j + lane; i < m; i += 64) d += ((i == j) ? 1.0 : col[i]) * cc[i];
+        d = wave_sum(d) * tj;
+        for (int i = j + lane; i < m; i += 64) cc[i] -= d * ((i == j) ? 1.0 : col[i]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Explicit Q (m x k, column-major, ldq) from the reflectors: Q = H_0 ... H_{k-1} I.
+__global__ __launch_bounds__(DT) void qr_form_q_kernel(const double* A, int m, int n, int lda,
+                                                       const double* tau, double* Q, int k, int ldq) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  for (long t = threadIdx.x; t < (long)m * k; t += blockDim.x) {
+    int c = (int)(t / m), i = (int)(t % m);
+    Q[(long)c * ldq + i] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int kmax = min(min(m, n), k);
+  for (int j = kmax - 1; j >= 0; --j) {
+    const double* v = A + (long)j * lda;
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      for (int c = w; c < k; c += NW) {
+        double* qc = Q + (long)c * ldq;
+        double d = 0.0;
+        for (int i = j + lane; i < m; i += 64) d += ((i == j) ? 1.0 : v[i]) * qc[i];
+        d = wave_sum(d) * tj;
+        for (int i = j + lane; i < m; i += 64) qc[i] -= d * ((i == j) ? 1.0 : v[i]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD of a column-major m x n matrix A (lda = m).
+// Column pairs are rotated in the round-robin (tournament) order, n/2 disjoint
+// pairs per step, one wavefront per pair.  On exit U (m x n, column-major),
+// sigma (descending) and V (n x n, column-major) with A = U diag(sigma) V^T.
+// Columns of U with sigma = 0 are zero.  work: m*n + n*n doubles + n ints.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(DT) void jacobi_svd_kernel(double* A, int m, int n, double* Vw,
+                                                        double* U, double* sigma, double* V,
+                                                        int* order, int max_sweeps, double tol,
+                                                        int* sweeps_out) {
+  __shared__ int s_rot;
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
+    int c = (int)(t / n), i = (int)(t % n);
+    Vw[t] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int N = (n % 2) ? n + 1 : n;   // players incl. a dummy when n is odd
+  int sweep = 0;
+  for (; sweep < max_sweeps && N > 1; ++sweep) {
+    if (threadIdx.x == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r) {
+      for (int pi = w; pi < N / 2; pi += NW) {
+        int p, q;
+        if (pi == 0) { p = N - 1; q = r; }
+        else { p = (r + pi) % (N - 1); q = (r - pi + N - 1) % (N - 1); }
+        if (p > q) { int t = p; p = q; q = t; }
+        if (q >= n) continue;
+        double* ap = A + (long)p * m;
+        double* aq = A + (long)q * m;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < m; i += 64) {
+          double x = ap[i], y = aq[i];
+          al += x * x; be += y * y; ga += x * y;
+        }
+        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+        if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
+        if (fabs(ga) <= tol * sqrt(al * be)) continue;
+        double zeta = (be - al) / (2.0 * ga);
+        double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int i = lane; i < m; i += 64) {
+          double x = ap[i], y = aq[i];
+          ap[i] = c * x - s * y;
+          aq[i] = s * x + c * y;
+        }
+        double* vp = Vw + (long)p * n;
+        double* vq = Vw + (long)q * n;
+        for (int i = lane; i < n; i += 64) {
+          double x = vp[i], y = vq[i];
+          vp[i] = c * x - s * y;
+          vq[i] = s * x + c * y;
+        }
+        if (lane == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (!s_rot) { ++sweep; break; }
+    __syncthreads();
+  }
+  // column norms
+  for (int c = w; c < n; c += NW) {
+    const double* ac = A + (long)c * m;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += ac[i] * ac[i];
+    s = wave_sum(s);
+    if (lane == 0) sigma[c] = sqrt(s);   // unsorted for now
+  }
+  __syncthreads();
+  // rank sort (descending, ties by index) -> order[rank] = column
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double sc = sigma[c];
+    int rank = 0;
+    for (int o = 0; o < n; ++o) {
+      double so = sigma[o];
+      rank += (so > sc) || (so == sc && o < c);
+    }
+    order[rank] = c;
+  }
+  __syncthreads();
+  for (long t = threadIdx.x; t < (long)m * n; t += blockDim.x) {
+    int rnk = (int)(t / m), i = (int)(t % m);
+    int c = order[rnk];
+    double sc = sigma[c];
+    U[t] = (sc > 0.0) ? A[(long)c * m + i] / sc : 0.0;
+  }
+  for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
+    int rnk = (int)(t / n), i = (int)(t % n);
+    V[t] = Vw[(long)order[rnk] * n + i];
+  }
+  __syncthreads();
+  // sigma in sorted order (in place via U-independent pass)
+  if (threadIdx.x == 0) {
+    for (int rnk = 0; rnk < n; ++rnk) Vw[rnk] = sigma[order[rnk]];
+    for (int rnk = 0; rnk < n; ++rnk) sigma[rnk] = Vw[rnk];
+    if (sweeps_out) *sweeps_out = sweep;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LU with partial pivoting of a row-major n x n matrix A and solve for nrhs
+// right-hand sides B (row-major n x nrhs), in place: on exit B holds X.
+// status[0] = 0 on success, j+1 if the pivot of column j is exactly zero.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(DT) void lu_solve_kernel(double* A, int n, double* B, int nrhs, int* status) {
+  __shared__ double rv[DT];
+  __shared__ int ri[DT];
+  __shared__ int s_piv;
+  if (threadIdx.x == 0) status[0] = 0;
+  for (int j = 0; j < n; ++j) {
+    // pivot search (max |A[i][j]|, lowest index on ties)
+    double best = -1.0; int bi = j;
+    for (int i = j + threadIdx.x; i < n; i += blockDim.x) {
+      double v = fabs(A[(long)i * n + j]);
+      if (v > best) { best = v; bi = i; }
+    }
+    rv[threadIdx.x] = best; ri[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        double a = rv[threadIdx.x], b = rv[threadIdx.x + o];
+        int ia = ri[threadIdx.x], ib = ri[threadIdx.x + o];
+        if (b > a || (b == a && ib < ia)) { rv[threadIdx.x] = b; ri[threadIdx.x] = ib; }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) s_piv = ri[0];
+    __syncthreads();
+    const int piv = s_piv;
+    if (piv != j) {
+      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        double t = A[(long)j * n + c]; A[(long)j * n + c] = A[(long)piv * n + c]; A[(long)piv * n + c] = t;
+      }
+      for (int c = threadIdx.x; c < nrhs; c += blockDim.x) {
+        double t = B[(long)j * nrhs + c]; B[(long)j * nrhs + c] = B[(long)piv * nrhs + c]; B[(long)piv * nrhs + c] = t;
+      }
+    }
+    __syncthreads();
+    const double d = A[(long)j * n + j];
+    if (d == 0.0) {
+      if (threadIdx.x == 0) status[0] = j + 1;
+      return;
+    }
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(long)i * n + j] /= d;
+    __syncthreads();
+    const int rows = n - j - 1, cols = n - j - 1;
+    for (long t = threadIdx.x; t < (long)rows * cols; t += blockDim.x) {
+      int i = j + 1 + (int)(t / cols), c = j + 1 + (int)(t % cols);
+      A[(long)i * n + c] -= A[(long)i * n + j] * A[(long)j * n + c];
+    }
+    for (long t = threadIdx.x; t < (long)rows * nrhs; t += blockDim.x) {
+      int i = j + 1 + (int)(t / nrhs), c = (int)(t % nrhs);
+      B[(long)i * nrhs + c] -= A[(long)i * n + j] * B[(long)j * nrhs + c];
+    }
+    __syncthreads();
+  }
+  // back substitution U x = y
+  for (int j = n - 1; j >= 0; --j) {
+    const double d = A[(long)j * n + j];
+    for (int c = threadIdx.x; c < nrhs; c += blockDim.x) B[(long)j * nrhs + c] /= d;
+    __syncthreads();
+    for (long t = threadIdx.x; t < (long)j * nrhs; t += blockDim.x) {
+      int i = (int)(t / nrhs), c = (int)(t % nrhs);
+      B[(long)i * nrhs + c] -= A[(long)i * n + j] * B[(long)j * nrhs + c];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky A = L L^T of a row-major symmetric n x n matrix, in place (lower
+// triangle).  status[0] = j+1 if the j-th pivot is not positive.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(DT) void cholesky_kernel(double* A, int n, int* status) {
+  __shared__ double s_d;
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) { status[0] = 0; s_bad = 0; }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = A[(long)j * n + j];
+      if (!(d > 0.0)) { status[0] = j + 1; s_bad = 1; }
+      s_d = (d > 0.0) ? sqrt(d) : 1.0;
+      A[(long)j * n + j] = s_d;
+    }
+    __syncthreads();
+    if (s_bad) return;
+    const double dj = s_d;
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(long)i * n + j] /= dj;
+    __syncthreads();
+    const int rows = n - j - 1;
+    for (long t = threadIdx.x; t < (long)rows * rows; t += blockDim.x) {
+      int i = j + 1 + (int)(t / rows), c = j + 1 + (int)(t % rows);
+      if (c <= i) A[(long)i * n + c] -= A[(long)i * n + j] * A[(long)c * n + j];
+    }
+    __syncthreads();
+  }
+  for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
+    int i = (int)(t / n), c = (int)(t % n);
+    if (c > i) A[t] = 0.0;
+  }
+}
+
+// Solve L X = B in place (L lower triangular row-major n x n, B row-major n x nrhs).
+__global__ __launch_bounds__(DT) void trsm_lower_kernel(const double* L, int n, double* B, int nrhs) {
+  for (int j = 0; j < n; ++j) {
+    const double d = L[(long)j * n + j];
+    for (int c = threadIdx.x; c < nrhs; c += blockDim.x) B[(long)j * nrhs + c] /= d;
+    __syncthreads();
+    const int rows = n - j - 1;
+    for (long t = threadIdx.x; t < (long)rows * nrhs; t += blockDim.x) {
+      int i = j + 1 + (int)(t / nrhs), c = (int)(t % nrhs);
+      B[(long)i * nrhs + c] -= L[(long)i * n + j] * B[(long)j * nrhs + c];
+    }
+    __syncthreads();
+  }
+}
+
+// Solve L^T X = B in place.
+__global__ __launch_bounds__(DT) void trsm_lower_t_kernel(const double* L, int n, double* B, int nrhs) {
+  for (int j = n - 1; j >= 0; --j) {
+    const double d = L[(long)j * n + j];
+    for (int c = threadIdx.x; c < nrhs; c += blockDim.x) B[(long)j * nrhs + c] /= d;
+    __syncthreads();
+    for (long t = threadIdx.x; t < (long)j * nrhs; t += blockDim.x) {
+      int i = (int)(t / nrhs), c = (int)(t % nrhs);
+      B[(long)i * nrhs + c] -= L[(long)j * n + i] * B[(long)j * nrhs + c];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host wrappers
+// ---------------------------------------------------------------------------
+
+void dense_qr(double* A, int m, int n, int lda, double* tau, hipStream_t s) {
+  hipLaunchKernelGGL(qr_kernel, dim3(1), dim3(DT), 0, s, A, m, n, lda, tau);
+  TT_HIP(hipGetLastError());
+}
+
+void dense_qr_form_q(const double* A, int m, int n, int lda, const double* tau, double* Q, int k, int ldq,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(qr_form_q_kernel, dim3(1), dim3(DT), 0, s, A, m, n, lda, tau, Q, k, ldq);
+  TT_HIP(hipGetLastError());
+}
+
+void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, double* work, int* iwork,
+               hipStream_t s, int max_sweeps, double tol) {
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(DT), 0, s, A, m, n, work, U, sigma, V, iwork,
+                     max_sweeps, tol, iwork + n);
+  TT_HIP(hipGetLastError());
+}
+
+void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(lu_solve_kernel, dim3(1), dim3(DT), 0, s, A, n, B, nrhs, status);
+  TT_HIP(hipGetLastError());
+}
+
+void dense_cholesky(double* A, int n, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(DT), 0, s, A, n, status);
+  TT_HIP(hipGetLastError());
+}
+
+void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s) {
+  if (transpose)
+    hipLaunchKernelGGL(trsm_lower_t_kernel, dim3(1), dim3(DT), 0, s, L, n, B, nrhs);
+  else
+    hipLaunchKernelGGL(trsm_lower_kernel, dim3(1), dim3(DT), 0, s, L, n, B, nrhs);
+  TT_HIP(hipGetLastError());
+}
+
+}  // namespace ttipm

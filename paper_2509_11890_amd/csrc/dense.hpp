@@ -1,0 +1,25 @@
+// Single-workgroup dense FP64 factorisations on the device.
+#pragma once
+
+#include "common.hpp"
+
+namespace ttipm {
+
+// Householder QR of column-major A (m x n, lda): R upper, reflectors below, tau[min(m,n)].
+void dense_qr(double* A, int m, int n, int lda, double* tau, hipStream_t s);
+// Explicit first k columns of Q (column-major, ldq) from dense_qr output.
+void dense_qr_form_q(const double* A, int m, int n, int lda, const double* tau, double* Q, int k, int ldq,
+                     hipStream_t s);
+// One-sided Jacobi SVD of column-major A (m x n, lda = m, destroyed):
+// U (m x n col-major), sigma[n] descending, V (n x n col-major).
+// work >= n*n doubles, iwork >= n + 1 ints (iwork[n] = sweeps used).
+void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, double* work, int* iwork,
+               hipStream_t s, int max_sweeps = 40, double tol = 4e-16);
+// LU with partial pivoting; solves A X = B in place (row-major).  status[0] != 0 on a zero pivot.
+void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s);
+// Cholesky (lower, row-major, in place).  status[0] = j+1 if not positive definite.
+void dense_cholesky(double* A, int n, int* status, hipStream_t s);
+// Solve L X = B (or L^T X = B) in place; L lower triangular row-major.
+void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s);
+
+}  // namespace ttipm

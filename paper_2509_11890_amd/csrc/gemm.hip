@@ -1,0 +1,312 @@
+// Strided, batched GEMM on the CDNA4 matrix cores.
+//
+// Every contraction of the TT method (environment builds, the projected local
+// products, dense local blocks, the rounding's small products) reduces to
+//     C[b] = alpha * A[b] * B[b] + beta * C[b]
+// with arbitrary element strides, so one kernel family serves them all.
+//
+//  * FP64: v_mfma_f64_16x16x4f64.  A 256-thread workgroup (four 64-lane waves in
+//    a 2 x 2 arrangement) owns a 64 x 64 output tile; each wave owns 32 x 32,
+//    i.e. 2 x 2 MFMA tiles of 16 x 16 with independent accumulators.  Tiles of A
+//    (64 x 16) and B (16 x 64) are staged through LDS in k-major order so that a
+//    lane reads its MFMA operand (row lane%16, k lane/16) with one LDS load.
+//    The global -> LDS copy maps threads along whichever index is unit-stride,
+//    so loads coalesce for both transposed and plain operands.
+//  * Mixed precision: the same tiling with v_mfma_f32_16x16x32_bf16 — operands
+//    rounded to BF16 on the way into LDS, FP32 accumulation, FP32 or FP64 out.
+//  * Split-K for tall-K, small-MN products (the last stage of a local product
+//    has K = R' r' up to 32k but only r*4 x r outputs): each K slice writes its
+//    partial tile to a workspace, and a second kernel reduces the slices in a
+//    fixed order, so results are bit-reproducible run to run.
+#include "gemm.hpp"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace ttipm {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int PAD = 1;
+
+struct KArgs {
+  int M, N, K;
+  int kslices, kchunk;      // split-K: slice s covers k in [s*kchunk, min(K,(s+1)*kchunk))
+  const double* A; long am, ak, sA;
+  const double* B; long bk, bn, sB;
+  double* C; long cm, cn, sC;
+  double alpha, beta;
+  double* P;                // split-K partials [batch][kslices][M][N] (dense)
+};
+
+// Global -> LDS tile copies.  As is [BK][BM+PAD] (k-major), Bs is [BK][BN+PAD].
+template <typename T>
+__device__ __forceinline__ void load_tile_A(T (*As)[BM + PAD], const double* A, long am, long ak,
+                                            int m0, int k0, int kend, int M, int tid) {
+  if (ak == 1) {  // k contiguous: 16 threads along k, 16 rows per pass
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int m = tid / 16 + 16 * e, k = tid % 16;
+      int gm = m0 + m, gk = k0 + k;
+      double v = (gm < M && gk < kend) ? A[gm * am + gk] : 0.0;
+      As[k][m] = (T)v;
+    }
+  } else {        // m contiguous (or general): 64 threads along m
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int m = tid % 64, k = tid / 64 + 4 * e;
+      int gm = m0 + m, gk = k0 + k;
+      double v = (gm < M && gk < kend) ? A[gm * am + gk * ak] : 0.0;
+      As[k][m] = (T)v;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tile_B(T (*Bs)[BN + PAD], const double* B, long bk, long bn,
+                                            int n0, int k0, int kend, int N, int tid) {
+  if (bk == 1 && bn != 1) {  // k contiguous
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int n = tid / 16 + 16 * e, k = tid % 16;
+      int gn = n0 + n, gk = k0 + k;
+      double v = (gn < N && gk < kend) ? B[gk + gn * bn] : 0.0;
+      Bs[k][n] = (T)v;
+    }
+  } else {                   // n contiguous (or general)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int n = tid % 64, k = tid / 64 + 4 * e;
+      int gn = n0 + n, gk = k0 + k;
+      double v = (gn < N && gk < kend) ? B[gk * bk + gn * bn] : 0.0;
+      Bs[k][n] = (T)v;
+    }
+  }
+}
+
+// Result layouts of the 16 x 16 MFMA tiles (measured on gfx950): every lane
+// holds column lane%16; the four accumulator values are rows lane/16 + 4e for
+// v_mfma_f64_16x16x4f64 and rows 4*(lane/16) + e for v_mfma_f32_16x16x32_bf16.
+template <bool F64_LAYOUT>
+__device__ __forceinline__ void store_tile(const KArgs& g, int bidx, int slice, int m0, int n0,
+                                           int wm, int wn, int lane, const double (*acc)[2][4]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int row = m0 + wm * 32 + i * 16 + (F64_LAYOUT ? (lane / 16) + 4 * e : 4 * (lane / 16) + e);
+        int col = n0 + wn * 32 + j * 16 + (lane % 16);
+        if (row < g.M && col < g.N) {
+          double v = acc[i][j][e];
+          if (g.kslices > 1) {
+            g.P[(((long)bidx * g.kslices + slice) * g.M + row) * g.N + col] = v;
+          } else {
+            double* c = g.C + (long)bidx * g.sC + (long)row * g.cm + (long)col * g.cn;
+            *c = (g.beta == 0.0) ? g.alpha * v : g.alpha * v + g.beta * (*c);
+          }
+        }
+      }
+}
+
+__global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
+  __shared__ double As[BK][BM + PAD];
+  __shared__ double Bs[BK][BN + PAD];
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int bidx = blockIdx.z / g.kslices, slice = blockIdx.z % g.kslices;
+  const int kbeg = slice * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
+  const double* A = g.A + (long)bidx * g.sA;
+  const double* B = g.B + (long)bidx * g.sB;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    load_tile_A<double>(As, A, g.am, g.ak, m0, k0, kend, g.M, tid);
+    load_tile_B<double>(Bs, B, g.bk, g.bn, n0, k0, kend, g.N, tid);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + lane / 16;
+      double a0 = As[kr][wm * 32 + (lane % 16)];
+      double a1 = As[kr][wm * 32 + 16 + (lane % 16)];
+      double b0 = Bs[kr][wn * 32 + (lane % 16)];
+      double b1 = Bs[kr][wn * 32 + 16 + (lane % 16)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double out[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[i][j][e] = acc[i][j][e];
+  store_tile<true>(g, bidx, slice, m0, n0, wm, wn, lane, out);
+}
+
+// BF16 operands, FP32 accumulation: v_mfma_f32_16x16x32_bf16 consumes 8 k-values
+// per lane (k = 8*(lane/16) + 0..7 for both A and B), so a BK=32 step is one MFMA.
+constexpr int BK16 = 32;
+
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(KArgs g) {
+  __shared__ __bf16 As[BK16][BM + 8];
+  __shared__ __bf16 Bs[BK16][BN + 8];
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int bidx = blockIdx.z / g.kslices, slice = blockIdx.z % g.kslices;
+  const int kbeg = slice * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
+  const double* A = g.A + (long)bidx * g.sA;
+  const double* B = g.B + (long)bidx * g.sB;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kbeg; k0 < kend; k0 += BK16) {
+    // 32 x 64 tiles = 2048 values, 8 per thread
+    if (g.ak == 1) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int m = tid / 32 + 8 * e, k = tid % 32;
+        int gm = m0 + m, gk = k0 + k;
+        As[k][m] = (__bf16)((gm < g.M && gk < kend) ? A[gm * g.am + gk] : 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int m = tid % 64, k = tid / 64 + 4 * e;
+        int gm = m0 + m, gk = k0 + k;
+        As[k][m] = (__bf16)((gm < g.M && gk < kend) ? A[gm * g.am + gk * g.ak] : 0.0);
+      }
+    }
+    if (g.bk == 1 && g.bn != 1) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int n = tid / 32 + 8 * e, k = tid % 32;
+        int gn = n0 + n, gk = k0 + k;
+        Bs[k][n] = (__bf16)((gn < g.N && gk < kend) ? B[gk + gn * g.bn] : 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int n = tid % 64, k = tid / 64 + 4 * e;
+        int gn = n0 + n, gk = k0 + k;
+        Bs[k][n] = (__bf16)((gn < g.N && gk < kend) ? B[gk * g.bk + gn * g.bn] : 0.0);
+      }
+    }
+    __syncthreads();
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        a[i][t] = As[8 * (lane / 16) + t][wm * 32 + i * 16 + (lane % 16)];
+        b[i][t] = Bs[8 * (lane / 16) + t][wn * 32 + i * 16 + (lane % 16)];
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  double out[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[i][j][e] = (double)acc[i][j][e];
+  store_tile<false>(g, bidx, slice, m0, n0, wm, wn, lane, out);
+}
+
+__global__ void splitk_reduce_kernel(KArgs g, int batch) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)batch * g.M * g.N;
+  if (idx >= total) return;
+  int b = (int)(idx / ((long)g.M * g.N));
+  long rem = idx % ((long)g.M * g.N);
+  int row = (int)(rem / g.N), col = (int)(rem % g.N);
+  double s = 0.0;
+  for (int sl = 0; sl < g.kslices; ++sl) s += g.P[(((long)b * g.kslices + sl) * g.M + row) * g.N + col];
+  double* c = g.C + (long)b * g.sC + (long)row * g.cm + (long)col * g.cn;
+  *c = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*c);
+}
+
+__global__ void scale_c_kernel(double* C, long cm, long cn, long sC, int M, int N, int batch, double beta) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)batch * M * N;
+  if (idx >= total) return;
+  int b = (int)(idx / ((long)M * N));
+  long rem = idx % ((long)M * N);
+  int row = (int)(rem / N), col = (int)(rem % N);
+  double* c = C + (long)b * sC + (long)row * cm + (long)col * cn;
+  *c = (beta == 0.0) ? 0.0 : beta * (*c);
+}
+
+static Workspace g_default_ws;
+
+void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
+  if (q.M <= 0 || q.N <= 0 || q.batch <= 0) return;
+  if (q.K <= 0) {  // C = beta C
+    long total = (long)q.batch * q.M * q.N;
+    hipLaunchKernelGGL(scale_c_kernel, dim3(nblocks(total, 256)), dim3(256), 0, stream, q.C, q.cm, q.cn,
+                       q.sC, q.M, q.N, q.batch, q.beta);
+    TT_HIP(hipGetLastError());
+    return;
+  }
+  KArgs g;
+  g.M = q.M; g.N = q.N; g.K = q.K;
+  g.A = q.A; g.am = q.am; g.ak = q.ak; g.sA = q.sA;
+  g.B = q.B; g.bk = q.bk; g.bn = q.bn; g.sB = q.sB;
+  g.C = q.C; g.cm = q.cm; g.cn = q.cn; g.sC = q.sC;
+  g.alpha = q.alpha; g.beta = q.beta;
+  const int gm = (q.M + BM - 1) / BM, gn = (q.N + BN - 1) / BN;
+  const long tiles = (long)gm * gn * q.batch;
+  // Split K when the output alone cannot fill the 256 CUs and K is long.
+  int ks = 1;
+  const int kstep = (prec == GemmPrec::BF16) ? BK16 : BK;
+  if (tiles < 512 && q.K >= 8 * kstep) {
+    ks = (int)std::min<long>((512 + tiles - 1) / tiles, (long)q.K / (4 * kstep));
+    ks = std::max(1, std::min(ks, 64));
+  }
+  g.kslices = ks;
+  int chunk = (q.K + ks - 1) / ks;
+  chunk = ((chunk + kstep - 1) / kstep) * kstep;
+  g.kchunk = chunk;
+  ks = (q.K + chunk - 1) / chunk;
+  g.kslices = ks;
+  g.P = nullptr;
+  if (ks > 1) {
+    Workspace* w = ws ? ws : &g_default_ws;
+    size_t need = (size_t)q.batch * ks * q.M * q.N;
+    w->buf.reserve(need);
+    g.P = w->buf.get();
+  }
+  dim3 grid(gm, gn, q.batch * ks);
+  if (prec == GemmPrec::BF16)
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
+  else
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, stream, g);
+  TT_HIP(hipGetLastError());
+  if (ks > 1) {
+    long total = (long)q.batch * q.M * q.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nblocks(total, 256)), dim3(256), 0, stream, g, q.batch);
+    TT_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace ttipm

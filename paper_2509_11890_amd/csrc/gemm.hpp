@@ -1,0 +1,38 @@
+// Strided batched GEMM on MFMA (FP64, or BF16 operands with FP32 accumulation).
+#pragma once
+
+#include "common.hpp"
+
+namespace ttipm {
+
+// C[b](m, n) = alpha * sum_k A[b](m, k) B[b](k, n) + beta * C[b](m, n)
+// with element addresses A + b*sA + m*am + k*ak (same pattern for B and C).
+struct Gemm {
+  int M = 0, N = 0, K = 0, batch = 1;
+  const double* A = nullptr; long am = 0, ak = 0, sA = 0;
+  const double* B = nullptr; long bk = 0, bn = 0, sB = 0;
+  double* C = nullptr; long cm = 0, cn = 0, sC = 0;
+  double alpha = 1.0, beta = 0.0;
+};
+
+enum class GemmPrec { F64, BF16 };
+
+// Scratch for split-K partial sums; grows on demand.
+struct Workspace {
+  DevBuf buf;
+};
+
+void gemm(const Gemm& g, hipStream_t stream, Workspace* ws = nullptr, GemmPrec prec = GemmPrec::F64);
+
+// Helpers for the common row-major cases.
+inline Gemm gemm_nn(int M, int N, int K, const double* A, long lda, const double* B, long ldb, double* C,
+                    long ldc, double alpha = 1.0, double beta = 0.0) {
+  Gemm g; g.M = M; g.N = N; g.K = K;
+  g.A = A; g.am = lda; g.ak = 1;
+  g.B = B; g.bk = ldb; g.bn = 1;
+  g.C = C; g.cm = ldc; g.cn = 1;
+  g.alpha = alpha; g.beta = beta;
+  return g;
+}
+
+}  // namespace ttipm

@@ -1,0 +1,562 @@
+// TT interior-point method driver (see ipm.hpp).  The loop and all decisions
+// (ranks, step lengths, stopping) are host logic; every arithmetic operation on
+// TT data runs in the library's kernels.
+#include "ipm.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <random>
+
+#include "dense.hpp"
+#include "ttops.hpp"
+
+namespace ttipm {
+
+namespace {
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+const std::vector<double> I4 = {1, 0, 0, 1};
+const std::vector<double> J4 = {1, 1, 1, 1};
+const std::vector<double> E4 = {1, 0, 0, 0};
+
+std::vector<double> outer4(const std::vector<double>& u, const std::vector<double>& v) {
+  std::vector<double> o(16);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) o[i * 4 + j] = u[i] * v[j];
+  return o;
+}
+
+// Compress an exactly built TT (sums of elementary terms) to minimal ranks.
+void compress(TT& t, Ctx& c) {
+  double nrm = tt_norm(t, c);
+  if (nrm > 0) tt_round_abs(t, 1e-14 * nrm, 1 << 30, c);
+}
+
+__global__ void symmetrize_kernel(double* A, int n) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)n * n) return;
+  int i = (int)(t / n), j = (int)(t % n);
+  if (j <= i) return;
+  double v = 0.5 * (A[(long)i * n + j] + A[(long)j * n + i]);
+  A[(long)i * n + j] = v;
+  A[(long)j * n + i] = v;
+}
+
+__global__ void add_diag_kernel(double* A, int n, double v) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) A[(long)t * n + t] += v;
+}
+
+__global__ void column_kernel(const double* Vcm, int n, int col, double* out) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = Vcm[(long)col * n + t];
+}
+
+// Rounding with the spectral shift of Cor. 1: round at tol / (1 + ||S||_F),
+// add zeta S; keep the unrounded tensor if the rank does not drop (and is
+// within the cap).
+TT round_shift(TT v, double tol, const TT* shift, int cap, Ctx& c, double* zeta_out) {
+  const double nS = shift ? tt_norm(*shift, c) : 0.0;
+  const int r0 = v.max_rank();
+  TT vt = tt_clone(v, c);
+  const double zeta = tt_round_abs(vt, tol / (1.0 + nS), cap, c);
+  if (zeta_out) *zeta_out = zeta;
+  if (vt.max_rank() >= r0 && r0 <= cap) return v;
+  if (shift && zeta > 0) return tt_add({&vt, shift}, {1.0, zeta}, c);
+  return vt;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// problem encodings (Sec. 4)
+// ---------------------------------------------------------------------------
+Problem build_problem(int kind, const TT& G, const TT* negdeg, Ctx& c) {
+  TT_REQUIRE(G.mo == 2 && G.mi == 2, "graph must be a TT matrix with 2 x 2 modes");
+  Problem P;
+  P.kind = kind;
+  P.d = G.d;
+  const int d = G.d;
+  P.n = std::ldexp(1.0, d);
+  P.Ivec = tt_rank1(d, 4, 1, I4, c);
+  P.I2 = tt_rank1(d, 2, 2, {1, 0, 0, 1}, c);
+  TT Jvec = tt_rank1(d, 4, 1, J4, c);
+  TT Evec = tt_rank1(d, 4, 1, E4, c);
+  TT JmI = tt_add({&Jvec, &P.Ivec}, {1.0, -1.0}, c);
+  if (kind == TTIPM_MAXCUT) {
+    // C = (diag_TT(A_G 1) - A_G) / 4, A_eq = diag_TT(vec_TT I), B_eq = vec_TT I, K_Y = diag_TT(vec_TT(J - I))
+    TT ones2 = tt_rank1(d, 2, 1, {1, 1}, c);
+    TT deg = tt_matvec(G, ones2, c);
+    TT D = tt_diag(deg, c);
+    TT Cm = tt_add({&D, &G}, {0.25, -0.25}, c);
+    P.C = tt_as_vector(Cm, c);
+    P.Aeq = tt_diag(P.Ivec, c);
+    P.AeqT = tt_clone(P.Aeq, c);
+    P.Beq = tt_clone(P.Ivec, c);
+    P.KY = tt_diag(JmI, c);
+    P.lam0 = 1.0;
+  } else if (kind == TTIPM_THETA) {
+    // C = J, A_eq = diag_TT(vec_TT A_G) + vec_TT(E_11) vec_TT(I)^T, B_eq = vec_TT(E_11),
+    // K_Y = diag_TT(vec_TT(J - A_G) - B_eq)
+    TT Avec = tt_as_vector(G, c);
+    TT part1 = tt_diag(Avec, c);
+    TT p2 = tt_rank1(d, 4, 4, outer4(E4, I4), c);
+    TT p2t = tt_rank1(d, 4, 4, outer4(I4, E4), c);
+    P.Aeq = tt_add({&part1, &p2}, {1.0, 1.0}, c);
+    P.AeqT = tt_add({&part1, &p2t}, {1.0, 1.0}, c);
+    P.Beq = tt_clone(Evec, c);
+    TT mask = tt_add({&Jvec, &Avec, &Evec}, {1.0, -1.0, -1.0}, c);
+    P.KY = tt_diag(mask, c);
+    P.C = tt_clone(Jvec, c);
+    P.lam0 = 2.0;
+  } else if (kind == TTIPM_CC) {
+    // C = W + diag_TT(C^- 1); A_eq = diag_TT(vec_TT I), K_Y = diag_TT(vec_TT(J - I));
+    // A_ineq = diag_TT(vec_TT(J - I)) with the >= convention, K_T = diag_TT(vec_TT I)
+    TT_REQUIRE(negdeg != nullptr && negdeg->mo == 2 && negdeg->mi == 1, "negdeg TT vector with mode 2");
+    TT Dm = tt_diag(*negdeg, c);
+    TT Cm = tt_add({&G, &Dm}, {1.0, 1.0}, c);
+    P.C = tt_as_vector(Cm, c);
+    P.Aeq = tt_diag(P.Ivec, c);
+    P.AeqT = tt_clone(P.Aeq, c);
+    P.Beq = tt_clone(P.Ivec, c);
+    P.KY = tt_diag(JmI, c);
+    P.ineq = true;
+    P.sense = -1.0;
+    P.Aineq = tt_diag(JmI, c);
+    P.AineqT = tt_clone(P.Aineq, c);
+    P.KT = tt_diag(P.Ivec, c);
+    P.Bineq = tt_clone(P.Ivec, c);
+    tt_scale(P.Bineq, 0.0, c);
+    P.oneT = tt_clone(JmI, c);
+    P.q = P.n * P.n - P.n;
+    P.lam0 = 2.0;
+  } else {
+    throw Error(TT_ERR_ARG, "unknown problem kind");
+  }
+  compress(P.C, c);
+  compress(P.Aeq, c);
+  compress(P.AeqT, c);
+  compress(P.KY, c);
+  if (P.ineq) {
+    compress(P.Aineq, c);
+    compress(P.AineqT, c);
+    compress(P.KT, c);
+    compress(P.oneT, c);
+  }
+  P.normB = tt_norm(P.Beq, c);
+  P.normC = tt_norm(P.C, c);
+  return P;
+}
+
+void init_state(const Problem& P, const ttipm_params& prm, State& S, Ctx& c) {
+  // Sec. 5.1: X = Z = lambda* I, Y = 0; with inequalities X = lambda* I + (alpha_p/10) A_ineq(J),
+  // T = lambda*_ineq A_ineq(J) (reading: alpha_p = lambda* for A_G = J - I).
+  S.X = tt_clone(P.Ivec, c);
+  tt_scale(S.X, P.lam0, c);
+  S.Z = tt_clone(P.Ivec, c);
+  tt_scale(S.Z, P.lam0, c);
+  S.Y = tt_clone(P.Ivec, c);
+  tt_scale(S.Y, 0.0, c);
+  if (P.ineq) {
+    TT Jvec = tt_rank1(P.d, 4, 1, J4, c);
+    TT AJ = tt_matvec(P.Aineq, Jvec, c);
+    compress(AJ, c);
+    TT X2 = tt_add({&S.X, &AJ}, {1.0, P.lam0 / 10.0}, c);
+    S.X = std::move(X2);
+    S.T = tt_clone(AJ, c);
+    tt_scale(S.T, 1e-3, c);
+  }
+  S.eta = prm.eta0;
+  S.iter = 0;
+  S.has_W = false;
+  S.has_EX = S.has_EZ = false;
+}
+
+// ---------------------------------------------------------------------------
+// step length (Sec. 3.4): extreme generalised Rayleigh quotient in TT form,
+// solved by a two-site DMRG sweep.  At each pair of cores the projected pencil
+// (dM^, M^) is reduced with the Cholesky factor of M^ and its smallest
+// eigenpair is taken from a Jacobi eigen-decomposition; the pair is then split
+// by a truncated SVD, which adapts the rank of E up to `rank`.
+// ---------------------------------------------------------------------------
+namespace {
+
+// merged two-site operator core [R_k][(i,i')][(j,j')][R_{k+2}] of a TT matrix with 2 x 2 modes
+void merge_pair(const TT& M, int k, DevBuf& out, Ctx& c) {
+  const int R0 = M.r[k], R1 = M.r[k + 1], R2 = M.r[k + 2];
+  DevBuf tmp((size_t)R0 * 4 * 4 * R2);
+  gemm(gemm_nn(R0 * 4, 4 * R2, R1, M.core(k), R1, M.core(k + 1), 4 * R2, tmp.get(), 4 * R2), c.s, &c.ws,
+       GemmPrec::F64);
+  out.reserve((size_t)R0 * 16 * R2);
+  // [a][i][j][i'][j'][g] -> [a][i][i'][j][j'][g]
+  permute(tmp.get(), out.get(), {R0, 2, 2, 2, 2, R2}, {0, 1, 3, 2, 4, 5}, c.s);
+}
+
+// smallest eigenpair of the pencil (D, M) (p x p, row-major, symmetrised in place):
+// returns lambda and writes the M-normalised direction into e (p).
+double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, Mm, p);
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, D, p);
+  TT_HIP(hipGetLastError());
+  c.ired.reserve((size_t)p + 8);
+  int* st = reinterpret_cast<int*>(c.ired.get());
+  dense_cholesky(Mm, p, st, c.s);
+  int hst = 0;
+  TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  if (hst != 0) throw Error(TT_ERR_NOT_PD, "projected iterate is not positive definite (step length)");
+  DevBuf Bt((size_t)p * p), U((size_t)p * p), S(p), V((size_t)p * p), work((size_t)p * p);
+  dense_trsm_lower(Mm, p, D, p, false, c.s);                 // L^{-1} D
+  permute(D, Bt.get(), {p, p}, {1, 0}, c.s);                 // (L^{-1} D)^T = D L^{-T}
+  dense_trsm_lower(Mm, p, Bt.get(), p, false, c.s);          // L^{-1} D L^{-T}
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, Bt.get(), p);
+  TT_HIP(hipGetLastError());
+  const double shift = dev_norm(Bt.get(), (long)p * p, c) + 1e-300;
+  hipLaunchKernelGGL(add_diag_kernel, dim3(nblocks(p, 256)), dim3(256), 0, c.s, Bt.get(), p, shift);
+  TT_HIP(hipGetLastError());
+  c.ired.reserve((size_t)p + 8);
+  dense_svd(Bt.get(), p, p, U.get(), S.get(), V.get(), work.get(), reinterpret_cast<int*>(c.ired.get()), c.s);
+  double smin = 0.0;
+  TT_HIP(hipMemcpyAsync(&smin, S.get() + (p - 1), sizeof(double), hipMemcpyDeviceToHost, c.s));
+  hipLaunchKernelGGL(column_kernel, dim3(nblocks(p, 256)), dim3(256), 0, c.s, V.get(), p, p - 1, e);
+  TT_HIP(hipGetLastError());
+  dense_trsm_lower(Mm, p, e, 1, true, c.s);                  // e = L^{-T} v
+  c.sync();
+  return smin - shift;
+}
+
+}  // namespace
+
+double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int rank, int sweeps,
+                   unsigned long long seed, Ctx& c) {
+  const int d = Mv.d;
+  TT M = tt_as_matrix(Mv, 2, c);
+  TT dM = tt_as_matrix(dMv, 2, c);
+  if (!have_E) {
+    // seeded random start of TT rank min(rank, 2), right-orthogonalised; DMRG grows the rank
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<int> rk(d + 1, 1);
+    for (int k = 1; k < d; ++k) rk[k] = std::min(2, rank);
+    std::vector<std::vector<double>> cores(d);
+    for (int k = 0; k < d; ++k) {
+      cores[k].resize((size_t)rk[k] * 2 * rk[k + 1]);
+      for (double& x : cores[k]) x = nd(rng);
+    }
+    TT e0 = tt_from_host(cores, rk, 2, 1, c);
+    E = block_from_frame(e0, 1, c);
+    have_E = true;
+  }
+  if (d == 1) {
+    // a single core: the local problem is the whole pencil
+    DevBuf Ml(4), Dl(4), e(2);
+    TT_HIP(hipMemcpyAsync(Ml.get(), M.core(0), 4 * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    TT_HIP(hipMemcpyAsync(Dl.get(), dM.core(0), 4 * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    return pencil_min(Ml.get(), Dl.get(), 2, e.get(), c);
+  }
+  std::vector<DevBuf> ML(d), MR(d), DL(d), DR(d);
+  for (auto* v : {&ML, &DL}) { (*v)[0].reserve(1); fill(1, 1.0, (*v)[0].get(), c.s); }
+  for (auto* v : {&MR, &DR}) { (*v)[d - 1].reserve(1); fill(1, 1.0, (*v)[d - 1].get(), c.s); }
+  auto upd_right = [&](int k) {
+    const int ra = E.r[k], ra2 = E.r[k + 1];
+    MR[k - 1].reserve((size_t)ra * M.r[k] * ra);
+    env_right_step(MR[k].get(), ra2, M.r[k + 1], ra2, E.cores[k].get(), 2, ra, M.core(k), M.r[k], 2,
+                   E.cores[k].get(), ra, MR[k - 1].get(), c);
+    DR[k - 1].reserve((size_t)ra * dM.r[k] * ra);
+    env_right_step(DR[k].get(), ra2, dM.r[k + 1], ra2, E.cores[k].get(), 2, ra, dM.core(k), dM.r[k], 2,
+                   E.cores[k].get(), ra, DR[k - 1].get(), c);
+  };
+  auto upd_left = [&](int k) {
+    const int ra = E.r[k], ra2 = E.r[k + 1];
+    ML[k + 1].reserve((size_t)ra2 * M.r[k + 1] * ra2);
+    env_left_step(ML[k].get(), ra, M.r[k], ra, E.cores[k].get(), 2, ra2, M.core(k), M.r[k + 1], 2,
+                  E.cores[k].get(), ra2, ML[k + 1].get(), c);
+    DL[k + 1].reserve((size_t)ra2 * dM.r[k + 1] * ra2);
+    env_left_step(DL[k].get(), ra, dM.r[k], ra, E.cores[k].get(), 2, ra2, dM.core(k), dM.r[k + 1], 2,
+                  E.cores[k].get(), ra2, DL[k + 1].get(), c);
+  };
+  for (int k = d - 1; k > 0; --k) upd_right(k);
+  double lam_best = 1e300;
+  DevBuf M2, D2, Ml, Dl, e;
+  // one sweep = left-to-right then right-to-left over the pairs (k, k+1)
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const bool lr = (pass == 0);
+      for (int step = 0; step < d - 1; ++step) {
+        const int k = lr ? step : d - 2 - step;
+        // block sits at k (lr) or k+1 (rl); frame: < k left-orth, > k+1 right-orth
+        const int r = E.r[k], s = E.r[k + 2], p = r * 4 * s;
+        merge_pair(M, k, M2, c);
+        merge_pair(dM, k, D2, c);
+        Ml.reserve((size_t)p * p);
+        Dl.reserve((size_t)p * p);
+        local_dense_op(ML[k].get(), r, M.r[k], M2.get(), 4, MR[k + 1].get(), s, M.r[k + 2], Ml.get(), c);
+        local_dense_op(DL[k].get(), r, dM.r[k], D2.get(), 4, DR[k + 1].get(), s, dM.r[k + 2], Dl.get(), c);
+        e.reserve(p);
+        const double lam = pencil_min(Ml.get(), Dl.get(), p, e.get(), c);
+        lam_best = std::min(lam_best, lam);
+        // split the supercore [(r,i)][(i',s)] by a truncated SVD
+        SvdOut sv;
+        svd_rowmajor(e.get(), 2 * r, 2 * s, sv, c);
+        double tot = 0;
+        for (double x : sv.sigma) tot += x * x;
+        int q = 1;
+        for (int j = 1; j < sv.k; ++j)
+          if (sv.sigma[j] > 1e-10 * std::sqrt(tot)) q = j + 1;
+        q = std::max(1, std::min(q, rank));
+        E.cores[k].reserve((size_t)2 * r * q);
+        E.cores[k + 1].reserve((size_t)q * 2 * s);
+        DevBuf sd(q);
+        TT_HIP(hipMemcpyAsync(sd.get(), sv.sigma.data(), sizeof(double) * q, hipMemcpyHostToDevice, c.s));
+        if (lr) {
+          copy2d(sv.U.get(), sv.k, E.cores[k].get(), q, 2 * r, q, c.s);                   // left-orthonormal
+          TT_HIP(hipMemcpyAsync(E.cores[k + 1].get(), sv.Vt.get(), sizeof(double) * (size_t)q * 2 * s,
+                                hipMemcpyDeviceToDevice, c.s));
+          E.r[k + 1] = q;
+          upd_left(k);
+        } else {
+          TT_HIP(hipMemcpyAsync(E.cores[k + 1].get(), sv.Vt.get(), sizeof(double) * (size_t)q * 2 * s,
+                                hipMemcpyDeviceToDevice, c.s));                           // right-orthonormal
+          copy2d(sv.U.get(), sv.k, E.cores[k].get(), q, 2 * r, q, c.s);
+          E.r[k + 1] = q;
+          upd_right(k + 1);
+        }
+        c.sync();
+      }
+    }
+  }
+  // leave E right-orthogonal with the block at 0 (core 0 is not orthogonal)
+  E.pos = 0;
+  E.blk.reserve((size_t)2 * E.r[1]);
+  TT_HIP(hipMemcpyAsync(E.blk.get(), E.cores[0].get(), sizeof(double) * 2 * E.r[1], hipMemcpyDeviceToDevice, c.s));
+  c.sync();
+  return lam_best;
+}
+
+double step_length(const TT& M, const TT& dM, BlockTT& E, bool& have_E, const ttipm_params& prm,
+                   unsigned long long seed, Ctx& c) {
+  const double lam = min_gen_eig(M, dM, E, have_E, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps), seed, c);
+  if (!(lam < 0.0)) return 1.0;
+  return std::min(1.0, -1.0 / lam);
+}
+
+// ---------------------------------------------------------------------------
+// the IPM iteration
+// ---------------------------------------------------------------------------
+void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& c) {
+  const double mu = tt_dot(S.X, S.Z, c) / (P.n + P.q);
+  TT AY = tt_matvec(P.AeqT, S.Y, c);
+  TT Rd = tt_add({&S.Z, &P.C, &AY}, {1.0, 1.0, -1.0}, c);
+  TT AX = tt_matvec(P.Aeq, S.X, c);
+  TT Rp = tt_add({&P.Beq, &AX}, {1.0, -1.0}, c);
+  const double pobj = tt_dot(P.C, S.X, c);
+  const double dobj = tt_dot(P.Beq, S.Y, c);
+  info.mu = mu;
+  info.pobj = pobj;
+  info.dobj = dobj;
+  info.eps_p = tt_norm(Rp, c) / (1.0 + P.normB);
+  double rdn2 = tt_dot(Rd, Rd, c);
+  if (P.ineq) {
+    TT AT = tt_matvec(P.AineqT, S.T, c);
+    TT Rd2 = tt_add({&Rd, &AT}, {1.0, -P.sense}, c);
+    rdn2 = tt_dot(Rd2, Rd2, c);
+  }
+  info.eps_d = std::sqrt(std::max(rdn2, 0.0)) / (1.0 + P.normC);
+  info.rel_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
+  info.eps_c = tt_dot(S.X, S.Z, c) / ((P.n + P.q) * (1.0 + pobj));
+  info.rank_x = S.X.max_rank();
+  info.rank_y = S.Y.max_rank();
+  info.rank_z = S.Z.max_rank();
+}
+
+namespace {
+
+void L_ops(const Problem& P, const TT& Xv, const TT& Zv, bool aho, TT& LZ, TT& LX, Ctx& c) {
+  TT Xm = tt_as_matrix(Xv, 2, c);
+  TT Zm = tt_as_matrix(Zv, 2, c);
+  if (aho) {
+    TT a = tt_kron(P.I2, Zm, c), b = tt_kron(Zm, P.I2, c);
+    LZ = tt_add({&a, &b}, {1.0, 1.0}, c);
+    TT e = tt_kron(P.I2, Xm, c), f = tt_kron(Xm, P.I2, c);
+    LX = tt_add({&e, &f}, {1.0, 1.0}, c);
+  } else {
+    LZ = tt_kron(Zm, P.I2, c);
+    LX = tt_kron(P.I2, Xm, c);
+  }
+}
+
+}  // namespace
+
+void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c) {
+  const double t_begin = now();
+  info = ttipm_step_info{};
+  info.iter = S.iter;
+  ipm_measures(P, S, info, c);
+  const double mu = info.mu;
+  const bool aho = S.iter >= prm.n_xz;
+  info.direction = aho ? TTIPM_DIR_AHO : TTIPM_DIR_XZ;
+  const double coef = aho ? 2.0 : 1.0;
+  const double tolp = S.eta * (1.0 + P.normB) / 10.0;
+  const double told = S.eta * (1.0 + P.normC) / 10.0;
+  // operators L_Z, L_X (Sec. 3.3) rounded at the primal/dual tolerances (Sec. 3.5)
+  double t0 = now();
+  TT LZ, LX;
+  L_ops(P, S.X, S.Z, aho, LZ, LX, c);
+  tt_round_abs(LZ, told, 1 << 30, c);
+  tt_round_abs(LX, tolp, 1 << 30, c);
+  info.t_round += now() - t0;
+  NewtonSys sys;
+  sys.ineq = P.ineq;
+  sys.sense = P.sense;
+  sys.ops[OP_AEQ] = &P.Aeq;
+  sys.ops[OP_AEQT] = &P.AeqT;
+  sys.ops[OP_KY] = &P.KY;
+  sys.ops[OP_LZ] = &LZ;
+  sys.ops[OP_LX] = &LX;
+  TT TA, DK;
+  if (P.ineq) {
+    TT Tdiag = tt_diag(S.T, c);
+    TA = tt_matmat(Tdiag, P.Aineq, c);
+    tt_round_abs(TA, told, 1 << 30, c);
+    // D_ineq(X) = diag_TT(s(X)), s(X) = s (B_ineq - A_ineq X) (>=: A_ineq X - B_ineq)
+    TT AX = tt_matvec(P.Aineq, S.X, c);
+    TT sx = tt_add({&P.Bineq, &AX}, {P.sense, -P.sense}, c);
+    tt_round_abs(sx, tolp, 1 << 30, c);
+    TT Dx = tt_diag(sx, c);
+    DK = tt_add({&Dx, &P.KT}, {1.0, 1.0}, c);
+    tt_round_abs(DK, tolp, 1 << 30, c);
+    sys.ops[OP_TA] = &TA;
+    sys.ops[OP_DK] = &DK;
+    sys.ops[OP_AIT] = &P.AineqT;
+  }
+  // residual terms: R_d = Z + C - Aeq^T Y (- s Aineq^T T), R_p = B - Aeq X,
+  // R_t = T o s(X) - mu 1_T = -s diag(T) A_ineq X (+ s diag(T) B_ineq) - mu 1_T
+  std::vector<Term> base = {{RES_D, 1.0, -1, &S.Z}, {RES_D, 1.0, -1, &P.C}, {RES_D, -1.0, OP_AEQT, &S.Y},
+                            {RES_P, 1.0, -1, &P.Beq}, {RES_P, -1.0, OP_AEQ, &S.X}};
+  if (P.ineq) {
+    base.push_back({RES_D, -P.sense, OP_AIT, &S.T});
+    base.push_back({RES_T, -P.sense, OP_TA, &S.X});
+  }
+  if (!S.has_W) {
+    S.W = block_from_frame(P.Ivec, sys.Lp(), c);
+    S.has_W = true;
+  }
+  AmenParams ap;
+  ap.tol = std::max(S.eta / 2.0, 1e-13);
+  ap.max_sweeps = prm.amen_sweeps;
+  ap.rank_cap = prm.rank_cap;
+  ap.direct_max = prm.direct_max;
+  ap.gmres_restart = prm.gmres_restart;
+  ap.gmres_maxit = prm.gmres_maxit;
+  ap.precond = prm.precond;
+  ap.mixed = prm.precision == TTIPM_MIXED;
+  // --- predictor: affine direction (target mu = 0) ---
+  sys.terms = base;
+  sys.terms.push_back({RES_C, 1.0, OP_LZ, &S.X});
+  if (P.ineq) {
+    // (R_t keeps its mu term only in the corrector)
+  }
+  AmenInfo ai_p;
+  amen_solve(sys, S.W, ap, ai_p, c);
+  const int L = sys.L();
+  TT dX = S.W.component(0, c), dZ = S.W.component(L, c);
+  double t1 = now();
+  const unsigned long long sd = S.seed + 7919ull * (unsigned long long)S.iter;
+  double a_p = step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, c);
+  double a_d = step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, c);
+  info.t_step += now() - t1;
+  // mu_aff = <X + a_p dX, Z + a_d dZ> / (n + q)
+  const double xz = tt_dot(S.X, S.Z, c), xdz = tt_dot(S.X, dZ, c), dxz = tt_dot(dX, S.Z, c),
+               dxdz = tt_dot(dX, dZ, c);
+  const double mu_aff = (xz + a_d * xdz + a_p * dxz + a_p * a_d * dxdz) / (P.n + P.q);
+  const double sigma = std::pow(std::max(mu_aff, 0.0) / mu, 3.0);
+  // --- corrector: centring and the second-order term L_{dZ_aff} vec dX_aff ---
+  TT LdZ, LdX_unused;
+  {
+    TT dZm = tt_as_matrix(dZ, 2, c);
+    if (aho) {
+      TT a = tt_kron(P.I2, dZm, c), b = tt_kron(dZm, P.I2, c);
+      LdZ = tt_add({&a, &b}, {1.0, 1.0}, c);
+    } else {
+      LdZ = tt_kron(dZm, P.I2, c);
+    }
+    tt_round_abs(LdZ, told, 1 << 30, c);
+  }
+  sys.ops[OP_EXTRA0] = &LdZ;
+  sys.terms = base;
+  sys.terms.push_back({RES_C, 1.0, OP_LZ, &S.X});
+  sys.terms.push_back({RES_C, 1.0, OP_EXTRA0, &dX});
+  sys.terms.push_back({RES_C, -coef * sigma * mu, -1, &P.Ivec});
+  if (P.ineq) sys.terms.push_back({RES_T, -sigma * mu, -1, &P.oneT});
+  AmenInfo ai_c;
+  amen_solve(sys, S.W, ap, ai_c, c);
+  TT dX2 = S.W.component(0, c), dY2 = S.W.component(1, c), dZ2 = S.W.component(L, c);
+  t1 = now();
+  info.alpha_p_max = step_length(S.X, dX2, S.EX, S.has_EX, prm, sd + 3, c);
+  info.alpha_d_max = step_length(S.Z, dZ2, S.EZ, S.has_EZ, prm, sd + 4, c);
+  a_p = std::min(1.0, prm.tau * info.alpha_p_max);
+  a_d = std::min(1.0, prm.tau * info.alpha_d_max);
+  info.t_step += now() - t1;
+  // --- update and rounding with spectral shift (Cor. 1) ---
+  // Safeguard (Sec. 3.3, damped retry): the TT eigen-solver bounds lambda_min
+  // from above, so the step can overshoot; the updated X and Z are checked
+  // with a DMRG estimate of lambda_min against the identity, and a step whose
+  // estimate is not positive is halved and retried.
+  t1 = now();
+  const int cap = prm.iter_rank_cap > 0 ? prm.iter_rank_cap : 4 * prm.rank_cap;
+  {
+    auto pd_min = [&](const TT& M, BlockTT& E, bool& have) {
+      return min_gen_eig(P.Ivec, M, E, have, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps), sd + 11, c);
+    };
+    TT Xn, Zn;
+    for (int tries = 0;; ++tries) {
+      TT Xs = tt_add({&S.X, &dX2}, {1.0, a_p}, c);
+      Xn = round_shift(std::move(Xs), tolp, &P.Ivec, cap, c, nullptr);
+      if (tries >= 6 || pd_min(Xn, S.EXc, S.has_EXc) > 0.0) break;
+      a_p *= 0.5;
+      info.backtracks++;
+    }
+    for (int tries = 0;; ++tries) {
+      TT Zs = tt_add({&S.Z, &dZ2}, {1.0, a_d}, c);
+      Zn = round_shift(std::move(Zs), told, &P.Ivec, cap, c, nullptr);
+      if (tries >= 6 || pd_min(Zn, S.EZc, S.has_EZc) > 0.0) break;
+      a_d *= 0.5;
+      info.backtracks++;
+    }
+    S.X = std::move(Xn);
+    S.Z = std::move(Zn);
+    S.dX = tt_clone(dX2, c);
+    S.dY = tt_clone(dY2, c);
+    S.dZ = tt_clone(dZ2, c);
+    if (P.ineq) S.dT = S.W.component(2, c);
+    TT Yn = tt_add({&S.Y, &dY2}, {1.0, a_d}, c);
+    S.Y = round_shift(std::move(Yn), told, nullptr, cap, c, nullptr);
+    if (P.ineq) {
+      TT dT2 = S.W.component(2, c);
+      TT Tn = tt_add({&S.T, &dT2}, {1.0, a_d}, c);
+      S.T = round_shift(std::move(Tn), told, &P.oneT, cap, c, nullptr);
+    }
+  }
+  info.t_round += now() - t1;
+  info.alpha_p = a_p;
+  info.alpha_d = a_d;
+  info.sigma = sigma;
+  info.eta = S.eta;
+  info.sweeps_pred = ai_p.sweeps;
+  info.sweeps_corr = ai_c.sweeps;
+  info.krylov_iters = ai_p.krylov_iters + ai_c.krylov_iters;
+  info.rank_w = std::max(ai_p.max_rank, ai_c.max_rank);
+  info.t_env = ai_p.t_env + ai_c.t_env;
+  info.t_solve = ai_p.t_solve + ai_c.t_solve;
+  info.t_svd = ai_p.t_svd + ai_c.t_svd;
+  S.eta = std::max(std::min(S.eta, prm.cmu * mu), prm.delta);
+  S.iter += 1;
+  info.t_total = now() - t_begin;
+}
+
+}  // namespace ttipm

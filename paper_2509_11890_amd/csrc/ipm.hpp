@@ -1,0 +1,55 @@
+// The TT primal-dual interior-point method (Alg. 1 with the TT machinery of
+// Sec. 3): problem encodings of Sec. 4, the initial point of Sec. 5.1, the
+// Mehrotra predictor-corrector Newton solves by block AMEn, the step length of
+// Sec. 3.4, rounding with the spectral shift of Cor. 1 and the tolerance
+// schedule of Sec. 3.5.
+#pragma once
+
+#include "amen.hpp"
+
+namespace ttipm {
+
+struct Problem {
+  int kind = 0, d = 0;
+  double n = 0, q = 0;
+  double lam0 = 1.0;
+  bool ineq = false;
+  double sense = 1.0;
+  TT C, Aeq, AeqT, KY, Beq;          // vec_TT vectors (mode 4) and operators (4 x 4)
+  TT Aineq, AineqT, KT, Bineq, oneT;
+  TT Ivec;                           // vec_TT(I)
+  TT I2;                             // identity TT matrix, 2 x 2 modes
+  double normB = 0, normC = 0;
+};
+
+struct State {
+  TT X, Y, Z, T;
+  BlockTT W;
+  bool has_W = false;
+  BlockTT EX, EZ, ET;                // warm starts of the step-length eigenvectors
+  bool has_EX = false, has_EZ = false;
+  BlockTT EXc, EZc;                  // warm starts of the positive-definiteness checks
+  bool has_EXc = false, has_EZc = false;
+  TT dX, dY, dZ, dT;                 // last Newton direction (corrector)
+  double eta = 1e-3;
+  int iter = 0;
+  unsigned long long seed = 12345;
+};
+
+Problem build_problem(int kind, const TT& graph, const TT* negdeg, Ctx& c);
+void init_state(const Problem& P, const ttipm_params& prm, State& S, Ctx& c);
+// One IPM iteration; fills info (measures at entry + the step taken).
+void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c);
+// Measures of the current iterate (mu, objectives, relative errors, gap).
+void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& c);
+
+// Smallest generalised eigenvalue of (dM, M) over TT vectors of the given rank
+// (one-site ALS with Cholesky reduction of the projected pencil; Sec. 3.4).
+// Throws TT_ERR_NOT_PD if a projected M is not positive definite.
+double min_gen_eig(const TT& M, const TT& dM, BlockTT& E, bool& have_E, int rank, int sweeps,
+                   unsigned long long seed, Ctx& c);
+// Largest alpha in (0, 1] with M + alpha dM psd, scaled by tau (Sec. 3.4).
+double step_length(const TT& M, const TT& dM, BlockTT& E, bool& have_E, const ttipm_params& prm,
+                   unsigned long long seed, Ctx& c);
+
+}  // namespace ttipm

@@ -1,0 +1,533 @@
+// TT algebra on the device (see tt.hpp).  Host code here only sequences kernels
+// and GEMMs; every arithmetic step runs on the GPU.  The only host reads are
+// the scalars that decide control flow (dot products, singular values for
+// rank choices), each after a stream synchronisation.
+#include "tt.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "dense.hpp"
+#include "ttops.hpp"
+
+namespace ttipm {
+
+Ctx::~Ctx() {
+  if (hbuf) (void)hipHostFree(hbuf);
+}
+
+double* Ctx::host(size_t n) {
+  if (n > hbuf_n) {
+    if (hbuf) (void)hipHostFree(hbuf);
+    hbuf = nullptr;
+    size_t want = std::max<size_t>(n, 1 << 16);
+    TT_HIP(hipHostMalloc((void**)&hbuf, want * sizeof(double), hipHostMallocDefault));
+    hbuf_n = want;
+  }
+  return hbuf;
+}
+
+// ---------------------------------------------------------------------------
+// construction
+// ---------------------------------------------------------------------------
+TT tt_from_host(const std::vector<std::vector<double>>& cores, const std::vector<int>& ranks, int mo, int mi,
+                Ctx& c) {
+  const int d = (int)cores.size();
+  TT t(d, mo, mi);
+  t.r = ranks;
+  for (int k = 0; k < d; ++k) {
+    TT_REQUIRE((long)cores[k].size() == t.core_size(k), "core size mismatch");
+    t.alloc(k);
+    TT_HIP(hipMemcpyAsync(t.core(k), cores[k].data(), cores[k].size() * sizeof(double), hipMemcpyHostToDevice,
+                          c.s));
+  }
+  c.sync();
+  return t;
+}
+
+TT tt_from_view(const tt_view& v, Ctx& c) {
+  TT_REQUIRE(v.d >= 1 && v.ranks && v.cores, "tt_view");
+  TT t(v.d, v.m_out, v.m_in);
+  for (int k = 0; k <= v.d; ++k) t.r[k] = v.ranks[k];
+  TT_REQUIRE(t.r[0] == 1 && t.r[v.d] == 1, "boundary ranks must be 1");
+  for (int k = 0; k < v.d; ++k) {
+    t.alloc(k);
+    TT_HIP(hipMemcpyAsync(t.core(k), v.cores[k], t.core_size(k) * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+  }
+  return t;
+}
+
+TT tt_clone(const TT& a, Ctx& c) {
+  TT t(a.d, a.mo, a.mi);
+  t.r = a.r;
+  for (int k = 0; k < a.d; ++k) {
+    t.alloc(k);
+    TT_HIP(hipMemcpyAsync(t.core(k), a.core(k), a.core_size(k) * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+  }
+  return t;
+}
+
+std::vector<std::vector<double>> tt_to_host(const TT& a, Ctx& c) {
+  std::vector<std::vector<double>> out(a.d);
+  for (int k = 0; k < a.d; ++k) {
+    out[k].resize(a.core_size(k));
+    TT_HIP(hipMemcpyAsync(out[k].data(), a.core(k), out[k].size() * sizeof(double), hipMemcpyDeviceToHost, c.s));
+  }
+  c.sync();
+  return out;
+}
+
+TT tt_rank1(int d, int mo, int mi, const std::vector<double>& core, Ctx& c) {
+  std::vector<std::vector<double>> cores(d, core);
+  return tt_from_host(cores, std::vector<int>(d + 1, 1), mo, mi, c);
+}
+
+// ---------------------------------------------------------------------------
+// algebra
+// ---------------------------------------------------------------------------
+TT tt_add(const std::vector<const TT*>& terms, const std::vector<double>& coef, Ctx& c) {
+  TT_REQUIRE(!terms.empty() && terms.size() == coef.size(), "tt_add arguments");
+  const TT& t0 = *terms[0];
+  const int d = t0.d;
+  const long mid = (long)t0.mo * t0.mi;
+  for (auto* t : terms) TT_REQUIRE(t->d == d && t->mo == t0.mo && t->mi == t0.mi, "tt_add shapes");
+  TT out(d, t0.mo, t0.mi);
+  if (d == 1) {
+    out.alloc(0);
+    fill(out.core_size(0), 0.0, out.core(0), c.s);
+    for (size_t i = 0; i < terms.size(); ++i) axpby(out.core_size(0), coef[i], terms[i]->core(0), 1.0, out.core(0), c.s);
+    return out;
+  }
+  for (int k = 1; k < d; ++k) {
+    int s = 0;
+    for (auto* t : terms) s += t->r[k];
+    out.r[k] = s;
+  }
+  for (int k = 0; k < d; ++k) {
+    out.alloc(k);
+    const int N0 = out.r[k], N1 = out.r[k + 1];
+    if (k > 0 && k < d - 1) fill(out.core_size(k), 0.0, out.core(k), c.s);
+    int o0 = 0, o1 = 0;
+    for (size_t i = 0; i < terms.size(); ++i) {
+      const TT& t = *terms[i];
+      const int n0 = t.r[k], n1 = t.r[k + 1];
+      const double a = (k == d - 1) ? coef[i] : 1.0;
+      place_block(t.core(k), n0, mid, n1, out.core(k), N0, N1, (k == 0) ? 0 : o0, (k == d - 1) ? 0 : o1, a, c.s);
+      o0 += n0;
+      o1 += n1;
+    }
+  }
+  return out;
+}
+
+void tt_scale(TT& a, double s, Ctx& c) { axpby(a.core_size(a.d - 1), 0.0, a.core(a.d - 1), s, a.core(a.d - 1), c.s); }
+
+TT tt_kron(const TT& A, const TT& B, Ctx& c) {
+  TT_REQUIRE(A.d == B.d, "kron d");
+  TT out(A.d, A.mo * B.mo, A.mi * B.mi);
+  for (int k = 0; k <= A.d; ++k) out.r[k] = A.r[k] * B.r[k];
+  for (int k = 0; k < A.d; ++k) {
+    out.alloc(k);
+    kron_core(A.core(k), A.r[k], A.mo, A.mi, A.r[k + 1], B.core(k), B.r[k], B.mo, B.mi, B.r[k + 1], out.core(k), c.s);
+  }
+  return out;
+}
+
+TT tt_diag(const TT& v, Ctx& c) {
+  TT_REQUIRE(v.mi == 1, "diag of a vector");
+  TT out(v.d, v.mo, v.mo);
+  out.r = v.r;
+  for (int k = 0; k < v.d; ++k) {
+    out.alloc(k);
+    diag_core(v.core(k), v.r[k], v.mo, v.r[k + 1], out.core(k), c.s);
+  }
+  return out;
+}
+
+TT tt_matvec(const TT& A, const TT& x, Ctx& c) {
+  TT_REQUIRE(A.d == x.d && A.mi == x.mo && x.mi == 1, "matvec shapes");
+  TT out(A.d, A.mo, 1);
+  for (int k = 0; k <= A.d; ++k) out.r[k] = A.r[k] * x.r[k];
+  for (int k = 0; k < A.d; ++k) {
+    out.alloc(k);
+    matvec_core(A.core(k), A.r[k], A.mo, A.mi, A.r[k + 1], x.core(k), x.r[k], x.r[k + 1], out.core(k), c.s);
+  }
+  return out;
+}
+
+TT tt_matmat(const TT& A, const TT& B, Ctx& c) {
+  TT_REQUIRE(A.d == B.d && A.mi == B.mo, "matmat shapes");
+  TT out(A.d, A.mo, B.mi);
+  for (int k = 0; k <= A.d; ++k) out.r[k] = A.r[k] * B.r[k];
+  for (int k = 0; k < A.d; ++k) {
+    out.alloc(k);
+    matmat_core(A.core(k), A.r[k], A.mo, A.mi, A.r[k + 1], B.core(k), B.r[k], B.mi, B.r[k + 1], out.core(k), c.s);
+  }
+  return out;
+}
+
+TT tt_as_matrix(const TT& v, int n, Ctx& c) {
+  TT_REQUIRE(v.mi == 1 && v.mo == n * n, "as_matrix");
+  TT t = tt_clone(v, c);
+  t.mo = n;
+  t.mi = n;
+  return t;
+}
+
+TT tt_as_vector(const TT& m, Ctx& c) {
+  TT t = tt_clone(m, c);
+  t.mo = m.mo * m.mi;
+  t.mi = 1;
+  return t;
+}
+
+TT tt_transpose(const TT& A, Ctx& c) {
+  TT out(A.d, A.mi, A.mo);
+  out.r = A.r;
+  for (int k = 0; k < A.d; ++k) {
+    out.alloc(k);
+    permute(A.core(k), out.core(k), {A.r[k], A.mo, A.mi, A.r[k + 1]}, {0, 2, 1, 3}, c.s);
+  }
+  return out;
+}
+
+// <x, y> by left-to-right identity environments.
+double tt_dot(const TT& x, const TT& y, Ctx& c) {
+  TT_REQUIRE(x.d == y.d && x.mo * x.mi == y.mo * y.mi, "dot shapes");
+  const int m = x.mo * x.mi;
+  int maxr = 1;
+  for (int k = 0; k <= x.d; ++k) maxr = std::max(maxr, x.r[k] * y.r[k]);
+  DevBuf e0(maxr), e1(maxr);
+  fill(1, 1.0, e0.get(), c.s);
+  for (int k = 0; k < x.d; ++k) {
+    env_left_step(e0.get(), x.r[k], 1, y.r[k], x.core(k), m, x.r[k + 1], nullptr, 1, m, y.core(k), y.r[k + 1],
+                  e1.get(), c);
+    std::swap(e0, e1);
+  }
+  double* h = c.host(1);
+  TT_HIP(hipMemcpyAsync(h, e0.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  return h[0];
+}
+
+double tt_norm(const TT& x, Ctx& c) {
+  double v = tt_dot(x, x, c);
+  return v > 0 ? std::sqrt(v) : 0.0;
+}
+
+double tt_sandwich(const TT& u, const TT& A, const TT& v, Ctx& c) {
+  TT_REQUIRE(u.d == A.d && v.d == A.d && u.mo == A.mo && v.mo == A.mi, "sandwich shapes");
+  int maxr = 1;
+  for (int k = 0; k <= u.d; ++k) maxr = std::max(maxr, u.r[k] * A.r[k] * v.r[k]);
+  DevBuf e0(maxr), e1(maxr);
+  fill(1, 1.0, e0.get(), c.s);
+  for (int k = 0; k < u.d; ++k) {
+    env_left_step(e0.get(), u.r[k], A.r[k], v.r[k], u.core(k), A.mo, u.r[k + 1], A.core(k), A.r[k + 1], A.mi,
+                  v.core(k), v.r[k + 1], e1.get(), c);
+    std::swap(e0, e1);
+  }
+  double* h = c.host(1);
+  TT_HIP(hipMemcpyAsync(h, e0.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  return h[0];
+}
+
+// ---------------------------------------------------------------------------
+// environments and local products: three GEMM stages each
+// ---------------------------------------------------------------------------
+void permute_op_core(const double* O, int R, int m, int Rp, double* out, hipStream_t s) {
+  // [alpha][i][j][beta] -> [i][beta][alpha][j]
+  permute(O, out, {R, m, m, Rp}, {1, 3, 0, 2}, s);
+}
+
+void env_left_step(const double* phi, int ra, int R, int rc, const double* V, int mo, int ra2, const double* O,
+                   int Rp, int mi, const double* U, int rc2, double* out, Ctx& c) {
+  if (O == nullptr) {
+    TT_REQUIRE(R == 1 && Rp == 1 && mo == mi, "identity environment shapes");
+    // t1[a][(i,c2)] = phi[a][c] U[c][(i,c2)];  out[a2][c2] = sum_(a,i) V[(a,i)][a2] t1[(a,i)][c2]
+    c.t1.reserve((size_t)ra * mi * rc2);
+    gemm(gemm_nn(ra, mi * rc2, rc, phi, rc, U, mi * rc2, c.t1.get(), mi * rc2), c.s, &c.ws, c.prec);
+    Gemm g;
+    g.M = ra2; g.N = rc2; g.K = ra * mo;
+    g.A = V; g.am = 1; g.ak = ra2;
+    g.B = c.t1.get(); g.bk = rc2; g.bn = 1;
+    g.C = out; g.cm = rc2; g.cn = 1;
+    gemm(g, c.s, &c.ws, c.prec);
+    return;
+  }
+  // stage 1: t1[(a,alpha)][(j,c2)] = phi[(a,alpha)][c] U[c][(j,c2)]
+  c.t1.reserve((size_t)ra * R * mi * rc2);
+  gemm(gemm_nn(ra * R, mi * rc2, rc, phi, rc, U, mi * rc2, c.t1.get(), mi * rc2), c.s, &c.ws, c.prec);
+  // stage 2: t2[a][(i,beta)][c2] = O'[(i,beta)][(alpha,j)] t1[a][(alpha,j)][c2]
+  c.perm.reserve((size_t)R * mo * mi * Rp);
+  permute(O, c.perm.get(), {R, mo, mi, Rp}, {1, 3, 0, 2}, c.s);
+  c.t2.reserve((size_t)ra * mo * Rp * rc2);
+  {
+    Gemm g;
+    g.M = mo * Rp; g.N = rc2; g.K = R * mi; g.batch = ra;
+    g.A = c.perm.get(); g.am = R * mi; g.ak = 1; g.sA = 0;
+    g.B = c.t1.get(); g.bk = rc2; g.bn = 1; g.sB = (long)R * mi * rc2;
+    g.C = c.t2.get(); g.cm = rc2; g.cn = 1; g.sC = (long)mo * Rp * rc2;
+    gemm(g, c.s, &c.ws, c.prec);
+  }
+  // stage 3: out[a2][(beta,c2)] = sum_(a,i) V[(a,i)][a2] t2[(a,i)][(beta,c2)]
+  {
+    Gemm g;
+    g.M = ra2; g.N = Rp * rc2; g.K = ra * mo;
+    g.A = V; g.am = 1; g.ak = ra2;
+    g.B = c.t2.get(); g.bk = (long)Rp * rc2; g.bn = 1;
+    g.C = out; g.cm = (long)Rp * rc2; g.cn = 1;
+    gemm(g, c.s, &c.ws, c.prec);
+  }
+}
+
+void env_right_step(const double* phi, int ra2, int Rp, int rc2, const double* V, int mo, int ra,
+                    const double* O, int R, int mi, const double* U, int rc, double* out, Ctx& c) {
+  if (O == nullptr) {
+    TT_REQUIRE(R == 1 && Rp == 1 && mo == mi, "identity environment shapes");
+    // t1[(c,i)][a2] = sum_c2 U[(c,i)][c2] phi[a2][c2]
+    c.t1.reserve((size_t)rc * mi * ra2);
+    Gemm g1;
+    g1.M = rc * mi; g1.N = ra2; g1.K = rc2;
+    g1.A = U; g1.am = rc2; g1.ak = 1;
+    g1.B = phi; g1.bk = 1; g1.bn = rc2;
+    g1.C = c.t1.get(); g1.cm = ra2; g1.cn = 1;
+    gemm(g1, c.s, &c.ws, c.prec);
+    // out[a][c] = sum_(i,a2) V[a][(i,a2)] t1[c][(i,a2)]
+    Gemm g2;
+    g2.M = ra; g2.N = rc; g2.K = mo * ra2;
+    g2.A = V; g2.am = (long)mo * ra2; g2.ak = 1;
+    g2.B = c.t1.get(); g2.bk = 1; g2.bn = (long)mi * ra2;
+    g2.C = out; g2.cm = rc; g2.cn = 1;
+    gemm(g2, c.s, &c.ws, c.prec);
+    return;
+  }
+  // stage 1 (batched over a2): t1[a2][(c,j)][beta] = sum_c2 U[(c,j)][c2] phi[a2][beta][c2]
+  c.t1.reserve((size_t)ra2 * rc * mi * Rp);
+  {
+    Gemm g;
+    g.M = rc * mi; g.N = Rp; g.K = rc2; g.batch = ra2;
+    g.A = U; g.am = rc2; g.ak = 1; g.sA = 0;
+    g.B = phi; g.bk = 1; g.bn = rc2; g.sB = (long)Rp * rc2;
+    g.C = c.t1.get(); g.cm = Rp; g.cn = 1; g.sC = (long)rc * mi * Rp;
+    gemm(g, c.s, &c.ws, c.prec);
+  }
+  // stage 2: t2[(alpha,i)][(a2,c)] = sum_(j,beta) O[(alpha,i)][(j,beta)] t1[(a2,c)][(j,beta)]
+  c.t2.reserve((size_t)R * mo * ra2 * rc);
+  {
+    Gemm g;
+    g.M = R * mo; g.N = ra2 * rc; g.K = mi * Rp;
+    g.A = O; g.am = (long)mi * Rp; g.ak = 1;
+    g.B = c.t1.get(); g.bk = 1; g.bn = (long)mi * Rp;
+    g.C = c.t2.get(); g.cm = (long)ra2 * rc; g.cn = 1;
+    gemm(g, c.s, &c.ws, c.prec);
+  }
+  // stage 3 (batched over alpha): out[a][alpha][c] = sum_(i,a2) V[a][(i,a2)] t2[alpha][(i,a2)][c]
+  {
+    Gemm g;
+    g.M = ra; g.N = rc; g.K = mo * ra2; g.batch = R;
+    g.A = V; g.am = (long)mo * ra2; g.ak = 1; g.sA = 0;
+    g.B = c.t2.get(); g.bk = rc; g.bn = 1; g.sB = (long)mo * ra2 * rc;
+    g.C = out; g.cm = (long)R * rc; g.cn = 1; g.sC = rc;
+    gemm(g, c.s, &c.ws, c.prec);
+  }
+}
+
+void local_apply(const double* phiL, int r, int R, int rc, const double* Operm, int m, const double* phiR, int s,
+                 int Rp, int rd, const double* x, double* y, double alpha, double beta, Ctx& c) {
+  // y[a][i][b] = alpha sum phiL[a][al][c] O[al][i][j][be] x[c][j][e] phiR[b][be][e] + beta y
+  if (Operm == nullptr) {
+    TT_REQUIRE(R == 1 && Rp == 1, "identity local operator");
+    c.t1.reserve((size_t)r * m * rd);
+    gemm(gemm_nn(r, m * rd, rc, phiL, rc, x, m * rd, c.t1.get(), m * rd), c.s, &c.ws, c.prec);
+    Gemm g;
+    g.M = r * m; g.N = s; g.K = rd;
+    g.A = c.t1.get(); g.am = rd; g.ak = 1;
+    g.B = phiR; g.bk = 1; g.bn = rd;
+    g.C = y; g.cm = s; g.cn = 1;
+    g.alpha = alpha; g.beta = beta;
+    gemm(g, c.s, &c.ws, c.prec);
+    return;
+  }
+  // stage 1: t1[(a,alpha)][(j,e)] = phiL[(a,alpha)][c] x[c][(j,e)]
+  c.t1.reserve((size_t)r * R * m * rd);
+  gemm(gemm_nn(r * R, m * rd, rc, phiL, rc, x, m * rd, c.t1.get(), m * rd), c.s, &c.ws, c.prec);
+  // stage 2 (batched over a): t2[a][(i,beta)][e] = O'[(i,beta)][(alpha,j)] t1[a][(alpha,j)][e]
+  c.t2.reserve((size_t)r * m * Rp * rd);
+  {
+    Gemm g;
+    g.M = m * Rp; g.N = rd; g.K = R * m; g.batch = r;
+    g.A = Operm; g.am = (long)R * m; g.ak = 1; g.sA = 0;
+    g.B = c.t1.get(); g.bk = rd; g.bn = 1; g.sB = (long)R * m * rd;
+    g.C = c.t2.get(); g.cm = rd; g.cn = 1; g.sC = (long)m * Rp * rd;
+    gemm(g, c.s, &c.ws, c.prec);
+  }
+  // stage 3: y[(a,i)][b] = alpha sum_(beta,e) t2[(a,i)][(beta,e)] phiR[b][(beta,e)] + beta y
+  {
+    Gemm g;
+    g.M = r * m; g.N = s; g.K = Rp * rd;
+    g.A = c.t2.get(); g.am = (long)Rp * rd; g.ak = 1;
+    g.B = phiR; g.bk = 1; g.bn = (long)Rp * rd;
+    g.C = y; g.cm = s; g.cn = 1;
+    g.alpha = alpha; g.beta = beta;
+    gemm(g, c.s, &c.ws, c.prec);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SVD and orthogonalisation
+// ---------------------------------------------------------------------------
+__global__ void upper_to_rowmajor_kernel(const double* Acm, int lda, int k, int n, double* R) {
+  // R (k x n row-major) = upper triangle of the column-major QR output
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)k * n) return;
+  int i = (int)(t / n), j = (int)(t % n);
+  R[t] = (i <= j) ? Acm[(long)j * lda + i] : 0.0;
+}
+
+__global__ void scale_rows_kernel(double* A, int rows, int cols, const double* s) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)rows * cols) return;
+  A[t] *= s[t / cols];
+}
+
+// Householder QR of a row-major matrix given as its column-major transpose:
+// the input `Mt_cm` is column-major (m x n) = row-major (n x m).  Returns Q
+// column-major (m x k) and R row-major (k x n), k = min(m, n).
+static void qr_colmajor(double* A, int m, int n, double* Q, double* R, Ctx& c) {
+  const int k = std::min(m, n);
+  c.dscr3.reserve((size_t)k + 1);
+  dense_qr(A, m, n, m, c.dscr3.get(), c.s);
+  hipLaunchKernelGGL(upper_to_rowmajor_kernel, dim3(nblocks((long)k * n, 256)), dim3(256), 0, c.s, A, m, k, n, R);
+  TT_HIP(hipGetLastError());
+  dense_qr_form_q(A, m, n, m, c.dscr3.get(), Q, k, m, c.s);
+}
+
+void svd_rowmajor(const double* M, int rows, int cols, SvdOut& out, Ctx& c) {
+  // Jacobi works on the columns of a column-major matrix.  For rows >= cols we
+  // factor M (column-major copy = transpose of the row-major data); otherwise
+  // M^T, whose column-major form is the row-major M itself.
+  const bool tall = rows >= cols;
+  const int m = tall ? rows : cols;     // length of the Jacobi columns
+  const int n = tall ? cols : rows;     // number of Jacobi columns
+  const int k = n;
+  out.k = k;
+  DevBuf A((size_t)m * n);
+  if (tall)
+    permute(M, A.get(), {rows, cols}, {1, 0}, c.s);
+  else
+    TT_HIP(hipMemcpyAsync(A.get(), M, sizeof(double) * (size_t)m * n, hipMemcpyDeviceToDevice, c.s));
+  DevBuf Ucm((size_t)m * n), Vcm((size_t)n * n), sig(n), work((size_t)n * n);
+  c.ired.reserve((size_t)n + 8);
+  int* iw = reinterpret_cast<int*>(c.ired.get());
+  if (m > 2 * n) {
+    // QR first: A = Q R with R (n x n); SVD of R keeps the Jacobi sweeps on n x n.
+    DevBuf Q((size_t)m * n), R((size_t)n * n), Rcm((size_t)n * n), Ur((size_t)n * n);
+    qr_colmajor(A.get(), m, n, Q.get(), R.get(), c);
+    permute(R.get(), Rcm.get(), {n, n}, {1, 0}, c.s);
+    dense_svd(Rcm.get(), n, n, Ur.get(), sig.get(), Vcm.get(), work.get(), iw, c.s);
+    // Ucm (m x n col-major) = Q Ur : row-major view Ucm^T (n x m) = Ur^T Q^T
+    Gemm g;
+    g.M = n; g.N = m; g.K = n;
+    g.A = Ur.get(); g.am = n; g.ak = 1;          // Ur^T[c][j] = Ur(j,c) = Ur[c*n + j]
+    g.B = Q.get(); g.bk = m; g.bn = 1;           // Q^T[j][i] = Q(i,j) = Q[j*m + i]
+    g.C = Ucm.get(); g.cm = m; g.cn = 1;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+  } else {
+    dense_svd(A.get(), m, n, Ucm.get(), sig.get(), Vcm.get(), work.get(), iw, c.s);
+  }
+  out.sigma.resize(k);
+  TT_HIP(hipMemcpyAsync(out.sigma.data(), sig.get(), sizeof(double) * k, hipMemcpyDeviceToHost, c.s));
+  out.U.reserve((size_t)rows * k);
+  out.Vt.reserve((size_t)k * cols);
+  if (tall) {
+    // U row-major (rows x k) = transpose of Ucm; Vt row-major (k x cols) = Vcm buffer
+    permute(Ucm.get(), out.U.get(), {k, rows}, {1, 0}, c.s);
+    TT_HIP(hipMemcpyAsync(out.Vt.get(), Vcm.get(), sizeof(double) * (size_t)k * cols, hipMemcpyDeviceToDevice, c.s));
+  } else {
+    // M^T = U' S V'^T: U (rows x k) = V' -> transpose of Vcm; Vt (k x cols) = U'^T = Ucm buffer
+    permute(Vcm.get(), out.U.get(), {k, rows}, {1, 0}, c.s);
+    TT_HIP(hipMemcpyAsync(out.Vt.get(), Ucm.get(), sizeof(double) * (size_t)k * cols, hipMemcpyDeviceToDevice, c.s));
+  }
+  c.sync();
+}
+
+void tt_orth_right(TT& t, int downto, Ctx& c) {
+  const long mid = (long)t.mo * t.mi;
+  for (int k = t.d - 1; k > downto; --k) {
+    const int rk = t.r[k], rn = t.r[k + 1];
+    const int m = (int)(mid * rn);        // rows of the column-major view (= row length of the core)
+    const int n = rk;
+    const int kk = std::min(m, n);
+    DevBuf A((size_t)m * n), Q((size_t)m * kk), R((size_t)kk * n);
+    // column-major (m x n) view of the core's row-major (rk x m) matrix is the core itself
+    TT_HIP(hipMemcpyAsync(A.get(), t.core(k), sizeof(double) * (size_t)m * n, hipMemcpyDeviceToDevice, c.s));
+    qr_colmajor(A.get(), m, n, Q.get(), R.get(), c);
+    // new core k: Q^T as [kk][mid][rn] row-major == column-major Q buffer
+    t.cores[k].reserve((size_t)kk * m);
+    TT_HIP(hipMemcpyAsync(t.core(k), Q.get(), sizeof(double) * (size_t)kk * m, hipMemcpyDeviceToDevice, c.s));
+    // core k-1 <- core_{k-1} R^T : [(r_{k-1} mid)][rk] x [rk][kk]
+    const int rows = (int)(t.r[k - 1] * mid);
+    DevBuf nc((size_t)rows * kk);
+    Gemm g;
+    g.M = rows; g.N = kk; g.K = rk;
+    g.A = t.core(k - 1); g.am = rk; g.ak = 1;
+    g.B = R.get(); g.bk = 1; g.bn = rk;          // R^T[j][c] = R[c][j]
+    g.C = nc.get(); g.cm = kk; g.cn = 1;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+    t.r[k] = kk;
+    t.cores[k - 1].reserve((size_t)rows * kk);
+    TT_HIP(hipMemcpyAsync(t.core(k - 1), nc.get(), sizeof(double) * (size_t)rows * kk, hipMemcpyDeviceToDevice, c.s));
+    c.sync();   // temporaries are released at scope end
+  }
+}
+
+double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped) {
+  if (capped) *capped = false;
+  if (t.d == 1) return 0.0;
+  tt_orth_right(t, 0, c);
+  const double eps_k = eps / std::sqrt((double)(t.d - 1));
+  const long mid = (long)t.mo * t.mi;
+  double zeta2 = 0.0;
+  for (int k = 0; k < t.d - 1; ++k) {
+    const int rows = (int)(t.r[k] * mid), cols = t.r[k + 1];
+    SvdOut sv;
+    svd_rowmajor(t.core(k), rows, cols, sv, c);
+    const int kk = sv.k;
+    // smallest rank whose discarded tail is within eps_k
+    std::vector<double> tail(kk + 1, 0.0);
+    for (int j = kk - 1; j >= 0; --j) tail[j] = tail[j + 1] + sv.sigma[j] * sv.sigma[j];
+    int rk = kk;
+    for (int j = 1; j <= kk; ++j)
+      if (std::sqrt(tail[j]) <= eps_k) { rk = j; break; }
+    rk = std::max(1, rk);
+    if (rk > max_rank) {
+      rk = max_rank;
+      if (capped) *capped = true;
+    }
+    zeta2 += tail[rk];
+    // new core k = U[:, :rk] (leading columns of the row-major U)
+    DevBuf nc((size_t)rows * rk);
+    copy2d(sv.U.get(), kk, nc.get(), rk, rows, rk, c.s);
+    // S Vt[:rk] into the next core: next = diag(s) Vt[:rk, :] core_{k+1}
+    DevBuf svt((size_t)rk * cols), s_dev(rk);
+    TT_HIP(hipMemcpyAsync(svt.get(), sv.Vt.get(), sizeof(double) * (size_t)rk * cols, hipMemcpyDeviceToDevice, c.s));
+    TT_HIP(hipMemcpyAsync(s_dev.get(), sv.sigma.data(), sizeof(double) * rk, hipMemcpyHostToDevice, c.s));
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(nblocks((long)rk * cols, 256)), dim3(256), 0, c.s, svt.get(), rk, cols,
+                       s_dev.get());
+    TT_HIP(hipGetLastError());
+    const int ncols = (int)(mid * t.r[k + 2]);
+    DevBuf nn((size_t)rk * ncols);
+    gemm(gemm_nn(rk, ncols, cols, svt.get(), cols, t.core(k + 1), ncols, nn.get(), ncols), c.s, &c.ws, GemmPrec::F64);
+    t.r[k + 1] = rk;
+    t.cores[k].reserve((size_t)rows * rk);
+    TT_HIP(hipMemcpyAsync(t.core(k), nc.get(), sizeof(double) * (size_t)rows * rk, hipMemcpyDeviceToDevice, c.s));
+    t.cores[k + 1].reserve((size_t)rk * ncols);
+    TT_HIP(hipMemcpyAsync(t.core(k + 1), nn.get(), sizeof(double) * (size_t)rk * ncols, hipMemcpyDeviceToDevice, c.s));
+    c.sync();
+  }
+  return std::sqrt(zeta2);
+}
+
+}  // namespace ttipm

@@ -1,0 +1,19 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
+    config.addinivalue_line("markers", "slow: long CPU oracle runs")
+
+
+def pytest_collection_modifyitems(config, items):
+    # a GPU test on a machine without a GPU is a configuration error, not a skip:
+    # the full test run selects -m gpu only on the GPU machine.
+    pass
