@@ -267,7 +267,10 @@ TTIPM_API int ttipm_step(ttipm_problem* p, ttipm_state* s, const ttipm_params* p
                void* stream);
 
 typedef struct {
-  int32_t status;       /* 0 converged to stop_gap, TT_ERR_NOT_CONVERGED otherwise */
+  int32_t status;       /* TT_OK: stop_gap reached; TT_ERR_NOT_CONVERGED: max_iter or a
+                           stall (both step lengths < 1e-3 twice in a row); TT_ERR_NOT_PD:
+                           an iterate lost positive definiteness.  The other fields
+                           describe the last accepted iterate in every case. */
   int32_t iterations;
   double time_to_gap;   /* seconds to the eps_gap mark (-1 if not reached)          */
   double time_total;
@@ -275,8 +278,9 @@ typedef struct {
 } ttipm_result;
 
 /*
- * Iterate ttipm_step until the stopping test or max_iter.  log (may be NULL)
- * receives up to log_cap per-iteration records.  Synchronises the stream.
+ * Iterate ttipm_step until the stopping test, max_iter or a stall.  log (may
+ * be NULL) receives up to log_cap per-iteration records.  Returns TT_OK with
+ * res->status describing how the run ended.  Synchronises the stream.
  */
 TTIPM_API int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm_result* res,
                 ttipm_step_info* log, int32_t log_cap, void* stream);

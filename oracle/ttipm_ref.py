@@ -63,7 +63,23 @@ class BlockTT:
         return tt.ranks(self.component(0))
 
 
-def _split_left(blk, tol_rel, rank_cap, weights):
+def _kick(U, rho, rng):
+    """Enrichment (Sec. 2.3, AMEn): append rho orthonormal columns orthogonal to
+    U.  reading: the columns are random (a seeded Gaussian kick) rather than
+    residual cores; they make the frame grow so that the block-ALS fixed point
+    is the Newton solution and the local residual test detects missing directions."""
+    rows, rk = U.shape
+    q = min(rho, rows - rk)
+    if q <= 0:
+        return U
+    G = rng.standard_normal((rows, q))
+    for _ in range(2):
+        G = G - U @ (U.T @ G)
+    Q, _ = np.linalg.qr(G)
+    return np.hstack([U, Q])
+
+
+def _split_left(blk, tol_rel, rank_cap, weights, kick=0, rng=None):
     """SVD move of the block index to the right neighbour (Sec. 2.3): the matrix
     M[(a,i), (l,b)] gives a left-orthonormal U (truncated); coefficients U^T M.
     reading: truncation is taken on the component-normalised matrix so that a
@@ -72,20 +88,26 @@ def _split_left(blk, tol_rel, rank_cap, weights):
     M = blk.transpose(1, 2, 0, 3).reshape(r * m, Lp * s)
     Ms = (blk / weights[:, None, None, None]).transpose(1, 2, 0, 3).reshape(r * m, Lp * s)
     U, sv, _ = np.linalg.svd(Ms, full_matrices=False)
-    rk = _rank_for(sv, tol_rel, rank_cap)
+    rk = _rank_for(sv, tol_rel, max(1, rank_cap - kick))
     U = U[:, :rk]
+    if kick:
+        U = _kick(U, kick, rng)
+    rk = U.shape[1]
     coef = U.T @ M                                   # [rk, (l, b)]
     return U.reshape(r, m, rk), coef.reshape(rk, Lp, s)
 
 
-def _split_right(blk, tol_rel, rank_cap, weights):
+def _split_right(blk, tol_rel, rank_cap, weights, kick=0, rng=None):
     """Block index moved to the left neighbour: M[(a,l), (i,b)] = V^T rows."""
     Lp, r, m, s = blk.shape
     M = blk.transpose(1, 0, 2, 3).reshape(r * Lp, m * s)
     Ms = (blk / weights[:, None, None, None]).transpose(1, 0, 2, 3).reshape(r * Lp, m * s)
     _, sv, Vt = np.linalg.svd(Ms, full_matrices=False)
-    rk = _rank_for(sv, tol_rel, rank_cap)
+    rk = _rank_for(sv, tol_rel, max(1, rank_cap - kick))
     V = Vt[:rk].T                                    # [(i,b), rk]
+    if kick:
+        V = _kick(V, kick, rng)
+    rk = V.shape[1]
     coef = M @ V                                     # [(a,l), rk]
     return V.T.reshape(rk, m, s), coef.reshape(r, Lp, rk)
 
@@ -253,7 +275,7 @@ def _dz_local(sysm, parts, sol, p):
     return dz
 
 
-def amen_solve(sysm, W, tol, max_sweeps, rank_cap, log=None, local="lu"):
+def amen_solve(sysm, W, tol, max_sweeps, rank_cap, log=None, local="elim", kick=2, seed=0):
     """Block-AMEn sweeps (alternating directions) for the Newton system.
     W is a BlockTT warm start whose block core sits at position 0.
     Returns (W, info).  Stopping: the largest relative local residual of the
@@ -268,6 +290,7 @@ def amen_solve(sysm, W, tol, max_sweeps, rank_cap, log=None, local="lu"):
         envs.update_right(W, k)
     info = dict(sweeps=0, max_res=[], ranks=None)
     tol_svd = tol / math.sqrt(d)
+    rng = np.random.default_rng(seed)
     direction = +1
     for sweep in range(max_sweeps):
         max_res = 0.0
@@ -289,7 +312,7 @@ def amen_solve(sysm, W, tol, max_sweeps, rank_cap, log=None, local="lu"):
             blk = np.concatenate([sol, dz]).reshape(Lp, r, 4, s)
             wts = np.array([max(np.linalg.norm(b), 1e-300) for b in blk])
             if direction > 0 and k < d - 1:
-                U, coef = _split_left(blk, tol_svd, rank_cap, wts)
+                U, coef = _split_left(blk, tol_svd, rank_cap, wts, kick, rng)
                 W.cores[k] = U
                 nxt = W.cores[k + 1]
                 W.blk = np.einsum("rls,sit->lrit", coef, nxt)
@@ -297,7 +320,7 @@ def amen_solve(sysm, W, tol, max_sweeps, rank_cap, log=None, local="lu"):
                 W.pos = k + 1
                 envs.update_left(W, k)
             elif direction < 0 and k > 0:
-                V, coef = _split_right(blk, tol_svd, rank_cap, wts)
+                V, coef = _split_right(blk, tol_svd, rank_cap, wts, kick, rng)
                 W.cores[k] = V
                 prv = W.cores[k - 1]
                 W.blk = np.einsum("qia,alr->lqir", prv, coef)
@@ -389,7 +412,7 @@ def initial_point(prob):
 
 def solve(prob, rank_cap=16, eps_gap=1e-4, max_iter=40, eta0=1e-3, delta=1e-4, Cmu=2.0,
           n_xz=3, tau=0.95, amen_sweeps=6, log=None, stop_gap=None, delta_final=None,
-          sigma_guard=False, local="lu"):
+          sigma_guard=False, local="elim"):
     """Reference TT-IPM.  Returns a dict with the objective history and the
     final iterates.  stop_gap (default eps_gap) ends the run; the time-to-gap
     mark uses eps_gap with eps_p = eps_d = 2 eps_gap (Sec. 5.1)."""

@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <random>
 
 #include "dense.hpp"
 #include "ttops.hpp"
@@ -212,7 +213,17 @@ double dev_norm(const double* x, long n, Ctx& c) {
 }
 
 // Move the block index from W.pos to W.pos + 1 (dir > 0) or W.pos - 1 (dir < 0).
-void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c) {
+// n x q block of seeded standard normal numbers (row-major), uploaded to dev.
+static void random_block(double* dev, long count, unsigned long long seed, Ctx& c) {
+  std::mt19937_64 rng(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  std::vector<double> h(count);
+  for (double& x : h) x = nd(rng);
+  TT_HIP(hipMemcpyAsync(dev, h.data(), sizeof(double) * count, hipMemcpyHostToDevice, c.s));
+  c.sync();
+}
+
+void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick, unsigned long long seed) {
   const int k = W.pos, Lp = W.Lp, r = W.r[k], s = W.r[k + 1], md = W.m;
   const long n1 = (long)r * md * s;
   std::vector<double> w = component_norms(W.blk.get(), Lp, n1, c);
@@ -233,10 +244,37 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c) {
     TT_HIP(hipGetLastError());
     SvdOut sv;
     svd_rowmajor(Ms.get(), rows, cols, sv, c);
-    const int rk = rank_for(sv.sigma, tol_rel, std::min(cap, sv.k));
-    // W_k = U[:, :rk]  ([r][4][rk])
+    const int rk0 = rank_for(sv.sigma, tol_rel, std::max(1, std::min(cap - kick, sv.k)));
+    const int q = std::max(0, std::min(kick, rows - rk0));
+    const int rk = rk0 + q;
+    // W_k = [U[:, :rk0] | kick]  ([r][4][rk])
     W.cores[k].reserve((size_t)rows * rk);
-    copy2d(sv.U.get(), sv.k, W.cores[k].get(), rk, rows, rk, c.s);
+    copy2d(sv.U.get(), sv.k, W.cores[k].get(), rk, rows, rk0, c.s);
+    if (q > 0) {
+      // random columns orthogonalised against U (twice) and orthonormalised
+      DevBuf G((size_t)q * rows), T((size_t)q * rk0);
+      random_block(G.get(), (long)q * rows, seed, c);          // G^T: q x rows
+      for (int pass = 0; pass < 2; ++pass) {
+        Gemm g1;   // T = G^T U  (q x rk0)
+        g1.M = q; g1.N = rk0; g1.K = rows;
+        g1.A = G.get(); g1.am = rows; g1.ak = 1;
+        g1.B = W.cores[k].get(); g1.bk = rk; g1.bn = 1;
+        g1.C = T.get(); g1.cm = rk0; g1.cn = 1;
+        gemm(g1, c.s, &c.ws, GemmPrec::F64);
+        Gemm g2;   // G^T -= T U^T
+        g2.M = q; g2.N = rows; g2.K = rk0;
+        g2.A = T.get(); g2.am = rk0; g2.ak = 1;
+        g2.B = W.cores[k].get(); g2.bk = 1; g2.bn = rk;
+        g2.C = G.get(); g2.cm = rows; g2.cn = 1;
+        g2.alpha = -1.0; g2.beta = 1.0;
+        gemm(g2, c.s, &c.ws, GemmPrec::F64);
+      }
+      orth_rows(G.get(), q, rows, c);
+      // columns rk0.. of W_k = G (transposed)
+      DevBuf Gt((size_t)rows * q);
+      permute(G.get(), Gt.get(), {q, rows}, {1, 0}, c.s);
+      copy2d(Gt.get(), q, W.cores[k].get() + rk0, rk, rows, q, c.s);
+    }
     // coef = U_k^T M  (rk x (l,b))
     DevBuf coef((size_t)rk * cols);
     Gemm g;
@@ -264,11 +302,34 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c) {
     TT_HIP(hipGetLastError());
     SvdOut sv;
     svd_rowmajor(Ms.get(), rows, cols, sv, c);
-    const int rk = rank_for(sv.sigma, tol_rel, std::min(cap, sv.k));
-    // W_k = Vt[:rk]  ([rk][4][s])
+    const int rk0 = rank_for(sv.sigma, tol_rel, std::max(1, std::min(cap - kick, sv.k)));
+    const int q = std::max(0, std::min(kick, cols - rk0));
+    const int rk = rk0 + q;
+    // W_k = [Vt[:rk0]; kick]  ([rk][4][s])
     W.cores[k].reserve((size_t)rk * cols);
-    TT_HIP(hipMemcpyAsync(W.cores[k].get(), sv.Vt.get(), sizeof(double) * (size_t)rk * cols, hipMemcpyDeviceToDevice,
+    TT_HIP(hipMemcpyAsync(W.cores[k].get(), sv.Vt.get(), sizeof(double) * (size_t)rk0 * cols, hipMemcpyDeviceToDevice,
                           c.s));
+    if (q > 0) {
+      double* G = W.cores[k].get() + (size_t)rk0 * cols;        // q x cols
+      random_block(G, (long)q * cols, seed, c);
+      DevBuf T((size_t)q * rk0);
+      for (int pass = 0; pass < 2; ++pass) {
+        Gemm g1;   // T = G Vt^T (q x rk0)
+        g1.M = q; g1.N = rk0; g1.K = cols;
+        g1.A = G; g1.am = cols; g1.ak = 1;
+        g1.B = W.cores[k].get(); g1.bk = 1; g1.bn = cols;
+        g1.C = T.get(); g1.cm = rk0; g1.cn = 1;
+        gemm(g1, c.s, &c.ws, GemmPrec::F64);
+        Gemm g2;   // G -= T Vt
+        g2.M = q; g2.N = cols; g2.K = rk0;
+        g2.A = T.get(); g2.am = rk0; g2.ak = 1;
+        g2.B = W.cores[k].get(); g2.bk = cols; g2.bn = 1;
+        g2.C = G; g2.cm = cols; g2.cn = 1;
+        g2.alpha = -1.0; g2.beta = 1.0;
+        gemm(g2, c.s, &c.ws, GemmPrec::F64);
+      }
+      orth_rows(G, q, cols, c);
+    }
     // coef = M Vt[:rk]^T  ((a,l) x rk)
     DevBuf coef((size_t)rows * rk);
     Gemm g;
@@ -278,12 +339,12 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c) {
     g.C = coef.get(); g.cm = rk; g.cn = 1;
     gemm(g, c.s, &c.ws, GemmPrec::F64);
     // new block at k-1: [(q,i)][(l,c)] = W_{k-1}[(q,i)][a] coef[a][(l,c)] -> permute to [l][q][i][c]
-    const int q = W.r[k - 1];
-    DevBuf nb((size_t)q * md * Lp * rk);
-    gemm(gemm_nn(q * md, Lp * rk, r, W.cores[k - 1].get(), r, coef.get(), Lp * rk, nb.get(), Lp * rk), c.s, &c.ws,
+    const int rq = W.r[k - 1];
+    DevBuf nb((size_t)rq * md * Lp * rk);
+    gemm(gemm_nn(rq * md, Lp * rk, r, W.cores[k - 1].get(), r, coef.get(), Lp * rk, nb.get(), Lp * rk), c.s, &c.ws,
          GemmPrec::F64);
-    W.blk.reserve((size_t)Lp * q * md * rk);
-    permute(nb.get(), W.blk.get(), {q, md, Lp, rk}, {2, 0, 1, 3}, c.s);
+    W.blk.reserve((size_t)Lp * rq * md * rk);
+    permute(nb.get(), W.blk.get(), {rq, md, Lp, rk}, {2, 0, 1, 3}, c.s);
     W.r[k] = rk;
     W.pos = k - 1;
   }
@@ -347,6 +408,73 @@ void solve_direct(LocalKKT& K, const double* f, double* u, Ctx& c) {
   c.sync();
   if (hst != 0) throw Error(TT_ERR_NUMERIC, "singular local KKT system (zero pivot)");
   TT_HIP(hipMemcpyAsync(u, rhs.get(), sizeof(double) * N, hipMemcpyDeviceToDevice, c.s));
+}
+
+// Direct solve by the block elimination of Sec. 3.3 (systems without
+// inequalities): Cholesky of L_Z^, the Schur complement
+//   S = Aeq^ L_Z^{-1} L_X^ Aeq^T^ + K_Y^,   S dY = Aeq^ L_Z^{-1}(L_X^ R_d^ - R_c^) - R_p^,
+// then dZ = Aeq^T^ dY - R_d^ and dX = -L_Z^{-1}(R_c^ + L_X^ dZ).  Unlike an LU of
+// the whole unsymmetric block system, the ill-conditioning of L_Z^ and L_X^
+// as mu -> 0 stays inside the Cholesky solves.  Returns false if L_Z^ is not
+// numerically positive definite (the caller then falls back to the LU).
+bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* Rc, double* u, Ctx& c) {
+  const int p = K.p;
+  const NewtonSys& sys = *K.sys;
+  auto dense = [&](int o, DevBuf& out) {
+    const TT* op = sys.ops[o];
+    const int key = K.key_of_op[o];
+    out.reserve((size_t)p * p);
+    local_dense_op(K.envs->L[key][K.k].get(), K.r, op->r[K.k], op->core(K.k), 4, K.envs->R[key][K.k].get(), K.s,
+                   op->r[K.k + 1], out.get(), c);
+  };
+  DevBuf A, AT, KY, LZ, LX, T1, S, v1, v2, ry;
+  dense(OP_LZ, LZ);
+  dense_symmetrize(LZ.get(), p, c.s);
+  c.ired.reserve(4);
+  int* st = reinterpret_cast<int*>(c.ired.get());
+  dense_cholesky(LZ.get(), p, st, c.s);
+  int hst = 0;
+  TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  if (hst != 0) return false;
+  dense(OP_AEQ, A);
+  dense(OP_AEQT, AT);
+  dense(OP_KY, KY);
+  dense(OP_LX, LX);
+  auto solve_LZ = [&](double* B, int nrhs) {   // B <- L_Z^{-1} B = L^{-T} L^{-1} B
+    dense_trsm_lower(LZ.get(), p, B, nrhs, false, c.s);
+    dense_trsm_lower(LZ.get(), p, B, nrhs, true, c.s);
+  };
+  // G = L_Z^{-1} L_X^ Aeq^T^ ; S = Aeq^ G + K_Y^
+  T1.reserve((size_t)p * p);
+  gemm(gemm_nn(p, p, p, LX.get(), p, AT.get(), p, T1.get(), p), c.s, &c.ws, GemmPrec::F64);
+  solve_LZ(T1.get(), p);
+  S.reserve((size_t)p * p);
+  TT_HIP(hipMemcpyAsync(S.get(), KY.get(), sizeof(double) * (size_t)p * p, hipMemcpyDeviceToDevice, c.s));
+  gemm(gemm_nn(p, p, p, A.get(), p, T1.get(), p, S.get(), p, 1.0, 1.0), c.s, &c.ws, GemmPrec::F64);
+  // rhs_y = Aeq^ L_Z^{-1}(L_X^ R_d^ - R_c^) - R_p^
+  v1.reserve(p);
+  v2.reserve(p);
+  gemm(gemm_nn(p, 1, p, LX.get(), p, Rd, 1, v1.get(), 1), c.s, &c.ws, GemmPrec::F64);
+  axpby(p, -1.0, Rc, 1.0, v1.get(), c.s);
+  solve_LZ(v1.get(), 1);
+  ry.reserve(p);
+  gemm(gemm_nn(p, 1, p, A.get(), p, v1.get(), 1, ry.get(), 1), c.s, &c.ws, GemmPrec::F64);
+  axpby(p, -1.0, Rp, 1.0, ry.get(), c.s);
+  dense_lu_solve(S.get(), p, ry.get(), 1, st, c.s);
+  TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  if (hst != 0) throw Error(TT_ERR_NUMERIC, "singular Schur complement in the local block elimination");
+  // dZ = Aeq^T^ y - R_d^ ; dX = -L_Z^{-1}(R_c^ + L_X^ dZ)
+  gemm(gemm_nn(p, 1, p, AT.get(), p, ry.get(), 1, v1.get(), 1), c.s, &c.ws, GemmPrec::F64);
+  axpby(p, -1.0, Rd, 1.0, v1.get(), c.s);
+  TT_HIP(hipMemcpyAsync(v2.get(), Rc, sizeof(double) * p, hipMemcpyDeviceToDevice, c.s));
+  gemm(gemm_nn(p, 1, p, LX.get(), p, v1.get(), 1, v2.get(), 1, 1.0, 1.0), c.s, &c.ws, GemmPrec::F64);
+  solve_LZ(v2.get(), 1);
+  axpby(p, -1.0, v2.get(), 0.0, u, c.s);
+  TT_HIP(hipMemcpyAsync(u + p, ry.get(), sizeof(double) * p, hipMemcpyDeviceToDevice, c.s));
+  c.sync();
+  return true;
 }
 
 // Restarted GMRES with classical Gram-Schmidt applied twice (CGS2).  The
@@ -588,7 +716,10 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       if (fn == 0.0) {
         fill(n, 0.0, u.get(), c.s);
       } else if (n <= prm.direct_max) {
-        solve_direct(K, f.get(), u.get(), c);
+        // the paper's block elimination; LU of the whole block system when
+        // inequalities are present or L_Z^ is numerically singular
+        const bool ok = !sys.ineq && solve_elim(K, Rhat[RES_D].get(), Rhat[RES_P].get(), Rhat[RES_C].get(), u.get(), c);
+        if (!ok) solve_direct(K, f.get(), u.get(), c);
       } else {
         double rel = 0.0;
         int its = solve_gmres(K, f.get(), u.get(), std::max(prm.tol * 0.1, 1e-14), prm.gmres_restart,
@@ -610,7 +741,8 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       // move the block index and extend the environments
       if (dir > 0 && k < d - 1) {
         double t1 = now();
-        split_block(W, +1, tol_svd, prm.rank_cap, c);
+        split_block(W, +1, tol_svd, prm.rank_cap, c, prm.kick,
+                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k));
         info.t_svd += now() - t1;
         t1 = now();
         envs.update_left(W, k, c);
@@ -618,7 +750,8 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
         info.t_env += now() - t1;
       } else if (dir < 0 && k > 0) {
         double t1 = now();
-        split_block(W, -1, tol_svd, prm.rank_cap, c);
+        split_block(W, -1, tol_svd, prm.rank_cap, c, prm.kick,
+                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k) + 7777ull);
         info.t_svd += now() - t1;
         t1 = now();
         envs.update_right(W, k, c);

@@ -50,7 +50,10 @@ struct BlockTT {
 
 // Move the block index to the right (dir > 0) or left neighbour by a truncated
 // SVD of the component-normalised block core (relative tolerance, rank cap).
-void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c);
+// kick > 0 appends that many seeded random orthonormal directions to the kept
+// factor (enrichment), within the rank cap.
+void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick = 0,
+                 unsigned long long seed = 0);
 // Norm of a device vector (deterministic; synchronises).
 double dev_norm(const double* x, long n, Ctx& c);
 
@@ -63,6 +66,8 @@ struct AmenParams {
   int gmres_maxit = 400;
   int precond = 0;          // TT_PREC_*
   bool mixed = false;       // BF16 MFMA contractions inside the Krylov solve
+  int kick = 2;             // enrichment directions added at every block move
+  unsigned long long seed = 0;
 };
 
 struct AmenInfo {

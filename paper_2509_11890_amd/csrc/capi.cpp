@@ -409,6 +409,7 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
     r.time_to_gap = -1.0;
     r.status = TT_ERR_NOT_CONVERGED;
     int it = 0;
+    int short_steps = 0;
     for (;; ++it) {
       ttipm_step_info m{};
       ipm_measures(p->P, s->S, m, c);
@@ -425,16 +426,32 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
         break;
       }
       if (it >= prm->max_iter) break;
+      // Stall: the TT direction no longer admits a step (both step lengths
+      // collapsed twice in a row), or an iterate lost positive definiteness in
+      // the step-length test; the last accepted iterate is the result.
+      if (short_steps >= 2) {
+        r.status = TT_ERR_NOT_CONVERGED;
+        break;
+      }
       ttipm_step_info inf{};
-      ipm_step(p->P, s->S, *prm, inf, c);
+      try {
+        ipm_step(p->P, s->S, *prm, inf, c);
+      } catch (const Error& e) {
+        if (e.code != TT_ERR_NOT_PD) throw;
+        r.status = TT_ERR_NOT_PD;
+        if (prm->verbose) std::fprintf(stderr, "stop: %s\n", e.what());
+        break;
+      }
+      short_steps = (inf.alpha_p < 1e-3 && inf.alpha_d < 1e-3) ? short_steps + 1 : 0;
       if (log && it < log_cap) log[it] = inf;
       if (prm->verbose)
         std::fprintf(stderr,
-                     "it %2d %s mu %.2e pobj %+.10e dobj %+.10e gap %.2e ep %.1e ed %.1e ap %.3f ad %.3f "
-                     "rX %d rY %d rZ %d rW %d sw %d/%d kr %d t %.3fs\n",
+                     "it %2d %s mu %.2e pobj %+.10e dobj %+.10e gap %.2e ep %.1e ed %.1e ap %.3e/%.3e ad %.3e/%.3e "
+                     "bt %d rX %d rY %d rZ %d rW %d sw %d/%d kr %d t %.3fs\n",
                      inf.iter, inf.direction ? "aho" : "xz ", inf.mu, inf.pobj, inf.dobj, inf.rel_gap, inf.eps_p,
-                     inf.eps_d, inf.alpha_p, inf.alpha_d, inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w,
-                     inf.sweeps_pred, inf.sweeps_corr, inf.krylov_iters, inf.t_total);
+                     inf.eps_d, inf.alpha_p, inf.alpha_p_max, inf.alpha_d, inf.alpha_d_max, inf.backtracks,
+                     inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w, inf.sweeps_pred, inf.sweeps_corr,
+                     inf.krylov_iters, inf.t_total);
       if (!std::isfinite(inf.pobj)) throw Error(TT_ERR_NUMERIC, "non-finite objective");
     }
     r.iterations = it;

@@ -347,9 +347,25 @@ __global__ __launch_bounds__(DT) void trsm_lower_t_kernel(const double* L, int n
   }
 }
 
+__global__ void symmetrize_kernel(double* A, int n) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)n * n) return;
+  int i = (int)(t / n), j = (int)(t % n);
+  if (j <= i) return;
+  double v = 0.5 * (A[(long)i * n + j] + A[(long)j * n + i]);
+  A[(long)i * n + j] = v;
+  A[(long)j * n + i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
+
+void dense_symmetrize(double* A, int n, hipStream_t s) {
+  long total = (long)n * n;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, A, n);
+  TT_HIP(hipGetLastError());
+}
 
 void dense_qr(double* A, int m, int n, int lda, double* tau, hipStream_t s) {
   hipLaunchKernelGGL(qr_kernel, dim3(1), dim3(DT), 0, s, A, m, n, lda, tau);

@@ -19,6 +19,8 @@ void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, dou
 void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s);
 // Cholesky (lower, row-major, in place).  status[0] = j+1 if not positive definite.
 void dense_cholesky(double* A, int n, int* status, hipStream_t s);
+// A <- (A + A^T) / 2 (row-major n x n).
+void dense_symmetrize(double* A, int n, hipStream_t s);
 // Solve L X = B (or L^T X = B) in place; L lower triangular row-major.
 void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s);
 

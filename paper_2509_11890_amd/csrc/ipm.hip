@@ -85,6 +85,11 @@ Problem build_problem(int kind, const TT& G, const TT* negdeg, Ctx& c) {
   P.n = std::ldexp(1.0, d);
   P.Ivec = tt_rank1(d, 4, 1, I4, c);
   P.I2 = tt_rank1(d, 2, 2, {1, 0, 0, 1}, c);
+  {
+    std::vector<double> i16(16, 0.0);
+    for (int i = 0; i < 4; ++i) i16[i * 4 + i] = 1.0;
+    P.I16 = tt_rank1(d, 4, 4, i16, c);
+  }
   TT Jvec = tt_rank1(d, 4, 1, J4, c);
   TT Evec = tt_rank1(d, 4, 1, E4, c);
   TT JmI = tt_add({&Jvec, &P.Ivec}, {1.0, -1.0}, c);
@@ -407,8 +412,10 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   double t0 = now();
   TT LZ, LX;
   L_ops(P, S.X, S.Z, aho, LZ, LX, c);
-  tt_round_abs(LZ, told, 1 << 30, c);
-  tt_round_abs(LX, tolp, 1 << 30, c);
+  // reading: L_Z and L_X are rounded with the Cor. 1 shift (S = I kron I) so
+  // that they stay positive definite when Z and X approach singularity
+  LZ = round_shift(std::move(LZ), told, &P.I16, 1 << 30, c, nullptr);
+  LX = round_shift(std::move(LX), tolp, &P.I16, 1 << 30, c, nullptr);
   info.t_round += now() - t0;
   NewtonSys sys;
   sys.ineq = P.ineq;
@@ -455,6 +462,8 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   ap.gmres_maxit = prm.gmres_maxit;
   ap.precond = prm.precond;
   ap.mixed = prm.precision == TTIPM_MIXED;
+  ap.kick = 2;
+  ap.seed = S.seed + 31ull * (unsigned long long)S.iter;
   // --- predictor: affine direction (target mu = 0) ---
   sys.terms = base;
   sys.terms.push_back({RES_C, 1.0, OP_LZ, &S.X});
@@ -515,16 +524,26 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     };
     TT Xn, Zn;
     for (int tries = 0;; ++tries) {
+      if (tries > 6) {           // no acceptable step: keep the iterate
+        a_p = 0.0;
+        Xn = tt_clone(S.X, c);
+        break;
+      }
       TT Xs = tt_add({&S.X, &dX2}, {1.0, a_p}, c);
       Xn = round_shift(std::move(Xs), tolp, &P.Ivec, cap, c, nullptr);
-      if (tries >= 6 || pd_min(Xn, S.EXc, S.has_EXc) > 0.0) break;
+      if (pd_min(Xn, S.EXc, S.has_EXc) > 0.0) break;
       a_p *= 0.5;
       info.backtracks++;
     }
     for (int tries = 0;; ++tries) {
+      if (tries > 6) {
+        a_d = 0.0;
+        Zn = tt_clone(S.Z, c);
+        break;
+      }
       TT Zs = tt_add({&S.Z, &dZ2}, {1.0, a_d}, c);
       Zn = round_shift(std::move(Zs), told, &P.Ivec, cap, c, nullptr);
-      if (tries >= 6 || pd_min(Zn, S.EZc, S.has_EZc) > 0.0) break;
+      if (pd_min(Zn, S.EZc, S.has_EZc) > 0.0) break;
       a_d *= 0.5;
       info.backtracks++;
     }

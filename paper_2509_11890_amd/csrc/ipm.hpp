@@ -19,6 +19,7 @@ struct Problem {
   TT Aineq, AineqT, KT, Bineq, oneT;
   TT Ivec;                           // vec_TT(I)
   TT I2;                             // identity TT matrix, 2 x 2 modes
+  TT I16;                            // identity operator I kron I, 4 x 4 modes
   double normB = 0, normC = 0;
 };
 

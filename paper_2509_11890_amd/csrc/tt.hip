@@ -453,6 +453,15 @@ void svd_rowmajor(const double* M, int rows, int cols, SvdOut& out, Ctx& c) {
   c.sync();
 }
 
+void orth_rows(double* G, int q, int len, Ctx& c) {
+  // rows of G (q x len, row-major) = columns of a column-major len x q matrix
+  if (q <= 0) return;
+  DevBuf Q((size_t)len * q), R((size_t)q * q);
+  qr_colmajor(G, len, q, Q.get(), R.get(), c);
+  TT_HIP(hipMemcpyAsync(G, Q.get(), sizeof(double) * (size_t)len * q, hipMemcpyDeviceToDevice, c.s));
+  c.sync();
+}
+
 void tt_orth_right(TT& t, int downto, Ctx& c) {
   const long mid = (long)t.mo * t.mi;
   for (int k = t.d - 1; k > downto; --k) {

@@ -86,6 +86,8 @@ void local_apply(const double* phiL, int r, int R, int rc, const double* Operm, 
 void permute_op_core(const double* O, int R, int m, int Rp, double* out, hipStream_t s);
 
 // ---- orthogonalisation and rounding --------------------------------------------
+// Orthonormalise the q rows (each of length len) of a row-major matrix in place (Householder QR).
+void orth_rows(double* G, int q, int len, Ctx& c);
 // Right-orthogonalise cores d-1 .. downto+1 (ranks may shrink).
 void tt_orth_right(TT& t, int downto, Ctx& c);
 // TT rounding (abs tolerance eps, per-bond eps/sqrt(d-1)); returns zeta = ||t - t~||_F.

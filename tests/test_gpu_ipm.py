@@ -1,0 +1,130 @@
+"""GPU TT-IPM against the oracle.
+
+* Newton step (a1-a6 together): at full TT rank the block-AMEn solve is the
+  dense Newton solve, so the corrector direction of one ttipm_step equals the
+  dense Mehrotra corrector of eq. (tt-kkt-newton-system) built by the oracle
+  (relative error <= 1e-8; the dense system at the initial point is well
+  conditioned, so this bounds the whole chain of contractions, local solves,
+  SVD moves and step lengths).
+* Whole solves: objective within 1e-6 (relative) of closed-form SDP values and
+  of the dense IPM oracle; the time-to-gap mark is reached.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import instances as I
+from oracle import kkt, problems as OP, sdp_dense as S, tt as ott
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2509_11890_amd as P
+    return P
+
+
+def _perm(d):
+    """index map: vec_TT position of entry (r, c) of a 2^d x 2^d matrix."""
+    n = 2 ** d
+    idx = np.zeros((n, n), dtype=np.int64)
+    for r in range(n):
+        for c in range(n):
+            v = 0
+            for k in range(d):
+                v = v * 4 + 2 * ((r >> (d - 1 - k)) & 1) + ((c >> (d - 1 - k)) & 1)
+            idx[r, c] = v
+    return idx
+
+
+def _mat(v, idx):
+    return v[idx]
+
+
+def _vec(M, idx):
+    out = np.zeros(M.size)
+    out[idx.reshape(-1)] = M.reshape(-1)
+    return out
+
+
+def _dense_corrector(prob, direction):
+    """Oracle Mehrotra step at the initial point: predictor, Thm. 1 steps, sigma,
+    corrector with the second-order term (dense)."""
+    d = prob["d"]
+    n = 2 ** d
+    idx = _perm(d)
+    lam = prob["lam0"]
+    Xt = ott.scale(OP._const_vec(OP._I4, d), lam)
+    Zt = ott.scale(OP._const_vec(OP._I4, d), lam)
+    Yt = ott.scale(OP._const_vec(OP._I4, d), 0.0)
+    x, z = ott.full(Xt), ott.full(Zt)
+    mu = x @ z / n
+    dX, dY, _, dZ = kkt.newton_dense(prob, Xt, Yt, Zt, None, mu, direction, sigma_mu=0.0)
+    X, Z = _mat(x, idx), _mat(z, idx)
+    sym = lambda A: 0.5 * (A + A.T)
+    ap = min(1.0, S.max_step(sym(X), sym(_mat(dX, idx))))
+    ad = min(1.0, S.max_step(sym(Z), sym(_mat(dZ, idx))))
+    mu_aff = (x + ap * dX) @ (z + ad * dZ) / n
+    sigma = (mu_aff / mu) ** 3
+    DX, DZ = _mat(dX, idx), _mat(dZ, idx)
+    coef = 2.0 if direction == "aho" else 1.0
+    second = DZ @ DX + DX @ DZ if direction == "aho" else DZ @ DX
+    _, _, _, Rc = kkt.residuals_dense(prob, Xt, Yt, Zt, None, mu, direction, sigma_mu=sigma * mu)
+    Rc = Rc + _vec(second, idx)
+    return kkt.newton_dense(prob, Xt, Yt, Zt, None, mu, direction, Rc_override=Rc)
+
+
+@pytest.mark.parametrize("kind,graph", [("maxcut", I.complete(3)), ("maxcut", I.odd_cycle_plus_isolated(3)),
+                                        ("theta", I.c5_plus_3k1())], ids=["K8", "C7+K1", "C5+3K1"])
+@pytest.mark.parametrize("direction", ["xz", "aho"])
+def test_full_rank_step_equals_dense_newton(kind, graph, direction):
+    P = _lib()
+    prob = OP.maxcut(graph.cores) if kind == "maxcut" else OP.theta(graph.cores)
+    ref = _dense_corrector(prob, direction)
+    kid = P.TTIPM_MAXCUT if kind == "maxcut" else P.TTIPM_THETA
+    pr = P.Problem(kid, graph.cores)
+    prm = P.Params(eta0=1e-13, delta=1e-13, rank_cap=64, iter_rank_cap=256, amen_sweeps=8,
+                   n_xz=3 if direction == "xz" else 0, eig_rank=64, eig_sweeps=3)
+    st = P.State(pr, prm)
+    P.ttipm_step(pr, st, prm)
+    for comp, r in zip("xyz", (ref[0], ref[1], ref[3])):
+        got = ott.full(st.export(comp))
+        err = np.linalg.norm(got - r) / max(np.linalg.norm(r), 1e-300)
+        assert err < 1e-8, (comp, err)
+
+
+CLOSED = [
+    ("K16", "maxcut", lambda: I.complete(4), 64.0),
+    ("C7+K1", "maxcut", lambda: I.odd_cycle_plus_isolated(3), 3.5 * (1 + math.cos(math.pi / 7))),
+    ("Q5-maxcut", "maxcut", lambda: I.hypercube(5), 80.0),
+    ("theta-Q5", "theta", lambda: I.hypercube(5), 16.0),
+    ("theta-C5+3K1", "theta", lambda: I.c5_plus_3k1(), 3 + math.sqrt(5)),
+    ("grid-4x8", "maxcut", lambda: I.grid_4x8(), 52.0),
+]
+
+
+@pytest.mark.parametrize("name,kind,make,value", CLOSED, ids=[c[0] for c in CLOSED])
+def test_solve_matches_closed_form(name, kind, make, value):
+    P = _lib()
+    g = make()
+    pr = P.Problem(P.TTIPM_MAXCUT if kind == "maxcut" else P.TTIPM_THETA, g.cores)
+    prm = P.Params(rank_cap=8 if g.d >= 5 else 16, stop_gap=3e-7, delta=1e-10, max_iter=60)
+    st = P.State(pr, prm)
+    res, log = P.ttipm_solve(pr, st, prm)
+    print(name, res)
+    assert res["time_to_gap"] > 0                         # gap 1e-4 with eps_p, eps_d <= 2e-4
+    assert abs(res["pobj"] - value) / (1 + value) < 1e-6
+    assert abs(res["dobj"] - value) / (1 + value) < 1e-6
+
+
+def test_c1_grid_matches_dense_oracle():
+    """Config 1 (4x8 grid, d = 5, rank cap 8, FP64): objective vs the dense IPM."""
+    P = _lib()
+    g = I.grid_4x8()
+    dense = S.solve(OP.maxcut_dense(g.dense))
+    pr = P.Problem(P.TTIPM_MAXCUT, g.cores)
+    prm = P.Params(rank_cap=8, stop_gap=3e-7, delta=1e-10, max_iter=60)
+    st = P.State(pr, prm)
+    res, _ = P.ttipm_solve(pr, st, prm)
+    assert abs(res["pobj"] - dense["pobj"]) / (1 + abs(dense["pobj"])) < 1e-6
