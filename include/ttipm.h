@@ -143,7 +143,11 @@ typedef struct {
 /* y = K x.  No synchronisation. */
 TTIPM_API int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stream);
 
-enum { TT_SOLVE_AUTO = 0, TT_SOLVE_DIRECT = 1, TT_SOLVE_GMRES = 2 };
+/* DIRECT: blocked LU with partial pivoting of the assembled dense K.
+ * CHOLESKY: blocked Cholesky of the symmetric part of the assembled K, for
+ * symmetric positive definite local operators; TT_ERR_NUMERIC if a pivot is
+ * not positive. */
+enum { TT_SOLVE_AUTO = 0, TT_SOLVE_DIRECT = 1, TT_SOLVE_GMRES = 2, TT_SOLVE_CHOLESKY = 3 };
 enum { TT_PREC_NONE = 0, TT_PREC_BJACOBI = 1, TT_PREC_MLP = 2 };
 
 typedef struct {
@@ -159,7 +163,7 @@ typedef struct {
 
 typedef struct {
   int32_t iters;        /* Krylov iterations (0 for the direct solve)            */
-  int32_t method_used;  /* TT_SOLVE_DIRECT or TT_SOLVE_GMRES                     */
+  int32_t method_used;  /* TT_SOLVE_DIRECT, TT_SOLVE_GMRES or TT_SOLVE_CHOLESKY  */
   int32_t precond_used; /* TT_PREC_* actually used (after the fallback rule)     */
   double rel_res;       /* true relative residual ||b - K x|| / ||b|| (FP64)      */
 } tt_solve_info;
@@ -167,7 +171,8 @@ typedef struct {
 /*
  * Solve K x = rhs for the local system (Sec. 3.3: matrix-free GMRES on the
  * reduced projected system, or a dense direct solve when it is small).
- * x holds the initial guess on entry and the solution on exit.  Synchronises
+ * x holds the initial guess on entry and the solution on exit (x must not
+ * alias rhs).  Synchronises
  * the stream (convergence tests).  Returns TT_ERR_NOT_CONVERGED if rtol was
  * not met within maxit (x then holds the best iterate).
  */
@@ -215,6 +220,27 @@ typedef struct {
 TTIPM_API int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out);
 TTIPM_API void ttipm_problem_destroy(ttipm_problem* p);
 
+/* Kernel timing.  While profiling is on, every period-th launch of the
+ * instrumented kernels (the FP64 and BF16 MFMA GEMMs, the Jacobi SVD, the LU
+ * panel) is bracketed by HIP events recorded on its launch stream.
+ * tt_profile_stop synchronises on those events, turns profiling off and writes
+ * up to cap records (one per instrumented kernel) into out; *count receives
+ * the number of instrumented kernels.  flops and bytes are the algorithmic
+ * counts of the timed launches (GEMM: 2 M N K flops; operands and result read
+ * or written once), so flops / time is the achieved rate of those launches.
+ * Profiling is process-wide and not meant to overlap with another profiled run. */
+typedef struct {
+  char name[48];
+  int64_t launches;     /* launches while profiling was on                        */
+  int64_t timed;        /* launches bracketed by events                           */
+  double time_ms;       /* summed event time of the timed launches                */
+  double flops;         /* algorithmic flops of the timed launches                */
+  double bytes;         /* algorithmic bytes of the timed launches                */
+} tt_kernel_stat;
+
+TTIPM_API int tt_profile_start(int32_t period);
+TTIPM_API int tt_profile_stop(tt_kernel_stat* out, int32_t cap, int32_t* count);
+
 /* Parameters (defaults from ttipm_params_default follow Sec. 3.5 and Sec. 5.1). */
 typedef struct {
   double eps_gap;       /* time-to-gap mark: rel_gap <= eps_gap, eps_p, eps_d <= 2 eps_gap */
@@ -237,6 +263,9 @@ typedef struct {
   int32_t eig_rank;     /* rank of the TT eigenvector in the step-length solver          */
   int32_t eig_sweeps;   /* ALS sweeps of the step-length solver                           */
   int32_t verbose;      /* print one line per iteration to stderr                          */
+  int32_t kick;         /* seeded random enrichment columns per AMEn core move (0)         */
+  int32_t seed;         /* seed of the enrichment and step-length start vectors            */
+  int32_t kick_sweeps;  /* enrichment only in the first kick_sweeps half-sweeps of a solve */
 } ttipm_params;
 
 TTIPM_API void ttipm_params_default(ttipm_params* p);

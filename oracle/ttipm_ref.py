@@ -63,13 +63,14 @@ class BlockTT:
         return tt.ranks(self.component(0))
 
 
-def _kick(U, rho, rng):
+def _kick(U, rho, rng, cap=1 << 30):
     """Enrichment (Sec. 2.3, AMEn): append rho orthonormal columns orthogonal to
     U.  reading: the columns are random (a seeded Gaussian kick) rather than
     residual cores; they make the frame grow so that the block-ALS fixed point
-    is the Newton solution and the local residual test detects missing directions."""
+    is the Newton solution and the local residual test detects missing
+    directions.  They only fill the capacity left under the rank cap."""
     rows, rk = U.shape
-    q = min(rho, rows - rk)
+    q = min(rho, rows - rk, cap - rk)
     if q <= 0:
         return U
     G = rng.standard_normal((rows, q))
@@ -88,10 +89,10 @@ def _split_left(blk, tol_rel, rank_cap, weights, kick=0, rng=None):
     M = blk.transpose(1, 2, 0, 3).reshape(r * m, Lp * s)
     Ms = (blk / weights[:, None, None, None]).transpose(1, 2, 0, 3).reshape(r * m, Lp * s)
     U, sv, _ = np.linalg.svd(Ms, full_matrices=False)
-    rk = _rank_for(sv, tol_rel, max(1, rank_cap - kick))
+    rk = _rank_for(sv, tol_rel, max(1, rank_cap))
     U = U[:, :rk]
     if kick:
-        U = _kick(U, kick, rng)
+        U = _kick(U, kick, rng, rank_cap)
     rk = U.shape[1]
     coef = U.T @ M                                   # [rk, (l, b)]
     return U.reshape(r, m, rk), coef.reshape(rk, Lp, s)
@@ -103,13 +104,24 @@ def _split_right(blk, tol_rel, rank_cap, weights, kick=0, rng=None):
     M = blk.transpose(1, 0, 2, 3).reshape(r * Lp, m * s)
     Ms = (blk / weights[:, None, None, None]).transpose(1, 0, 2, 3).reshape(r * Lp, m * s)
     _, sv, Vt = np.linalg.svd(Ms, full_matrices=False)
-    rk = _rank_for(sv, tol_rel, max(1, rank_cap - kick))
+    rk = _rank_for(sv, tol_rel, max(1, rank_cap))
     V = Vt[:rk].T                                    # [(i,b), rk]
     if kick:
-        V = _kick(V, kick, rng)
+        V = _kick(V, kick, rng, rank_cap)
     rk = V.shape[1]
     coef = M @ V                                     # [(a,l), rk]
     return V.T.reshape(rk, m, s), coef.reshape(r, Lp, rk)
+
+
+def _weights(blk):
+    """Per-component norms used to normalise the block before its SVD; a
+    component at rounding level relative to the largest keeps the largest
+    weight (normalising pure rounding noise would inflate the rank)."""
+    w = np.array([np.linalg.norm(b) for b in blk])
+    wmax = w.max()
+    if wmax == 0.0:
+        return np.ones_like(w)
+    return np.where(w > 1e-8 * wmax, w, wmax)
 
 
 def _rank_for(sv, tol_rel, cap):
@@ -310,7 +322,7 @@ def amen_solve(sysm, W, tol, max_sweeps, rank_cap, log=None, local="elim", kick=
                 sol = np.linalg.solve(K, f)
                 dz = _dz_local(sysm, parts, sol, p)
             blk = np.concatenate([sol, dz]).reshape(Lp, r, 4, s)
-            wts = np.array([max(np.linalg.norm(b), 1e-300) for b in blk])
+            wts = _weights(blk)
             if direction > 0 and k < d - 1:
                 U, coef = _split_left(blk, tol_svd, rank_cap, wts, kick, rng)
                 W.cores[k] = U
@@ -341,7 +353,7 @@ def amen_solve(sysm, W, tol, max_sweeps, rank_cap, log=None, local="elim", kick=
         envs_dummy = None
         while W.pos > 0:
             k = W.pos
-            wts = np.array([max(np.linalg.norm(b), 1e-300) for b in W.blk])
+            wts = _weights(W.blk)
             V, coef = _split_right(W.blk, 0.0, 1 << 30, wts)
             W.cores[k] = V
             W.blk = np.einsum("qia,alr->lqir", W.cores[k - 1], coef)

@@ -38,7 +38,7 @@ TT_OK, TT_ERR_ARG, TT_ERR_HIP, TT_ERR_ALLOC, TT_ERR_RANK_CAP = 0, 1, 2, 3, 4
 TT_ERR_NOT_CONVERGED, TT_ERR_NOT_PD, TT_ERR_NUMERIC, TT_ERR_BREAKDOWN = 5, 6, 7, 8
 TT_LEFT, TT_RIGHT = 0, 1
 TT_TOL_ABS, TT_TOL_REL = 0, 1
-TT_SOLVE_AUTO, TT_SOLVE_DIRECT, TT_SOLVE_GMRES = 0, 1, 2
+TT_SOLVE_AUTO, TT_SOLVE_DIRECT, TT_SOLVE_GMRES, TT_SOLVE_CHOLESKY = 0, 1, 2, 3
 TT_PREC_NONE, TT_PREC_BJACOBI, TT_PREC_MLP = 0, 1, 2
 TTIPM_MAXCUT, TTIPM_THETA, TTIPM_CC = 0, 1, 2
 TTIPM_F64, TTIPM_MIXED = 0, 1
@@ -86,7 +86,8 @@ class ttipm_params(C.Structure):
                 ("iter_rank_cap", C.c_int32), ("amen_sweeps", C.c_int32), ("direct_max", C.c_int32),
                 ("gmres_restart", C.c_int32), ("gmres_maxit", C.c_int32), ("precision", C.c_int32),
                 ("precond", C.c_int32), ("mlp", C.c_void_p), ("eig_rank", C.c_int32),
-                ("eig_sweeps", C.c_int32), ("verbose", C.c_int32)]
+                ("eig_sweeps", C.c_int32), ("verbose", C.c_int32), ("kick", C.c_int32), ("seed", C.c_int32),
+                ("kick_sweeps", C.c_int32)]
 
 
 class ttipm_step_info(C.Structure):
@@ -135,8 +136,32 @@ lib.ttipm_state_export.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTE
                                    C.c_size_t, C.POINTER(C.c_size_t)]
 
 
+class tt_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("timed", C.c_int64),
+                ("time_ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+lib.tt_profile_start.argtypes = [C.c_int32]
+lib.tt_profile_stop.argtypes = [C.POINTER(tt_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
+
+
 def version():
     return lib.tt_version().decode()
+
+
+def profile_start(period=1):
+    """Start HIP-event timing of every period-th launch of the instrumented kernels."""
+    _check(lib.tt_profile_start(int(period)))
+
+
+def profile_stop():
+    """Stop kernel timing; returns {kernel name: dict(launches, timed, time_ms, flops, bytes)}."""
+    cap = 16
+    arr = (tt_kernel_stat * cap)()
+    n = C.c_int32(0)
+    _check(lib.tt_profile_stop(arr, cap, C.byref(n)))
+    return {arr[i].name.decode(): dict(launches=arr[i].launches, timed=arr[i].timed, time_ms=arr[i].time_ms,
+                                       flops=arr[i].flops, bytes=arr[i].bytes) for i in range(min(n.value, cap))}
 
 
 def _check(code, allow=()):

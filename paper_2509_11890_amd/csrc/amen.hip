@@ -14,6 +14,7 @@
 // The sweep direction alternates; the stopping test is the largest relative
 // local residual of the incoming iterate over a half-sweep.
 #include "amen.hpp"
+#include "blocked.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -226,8 +227,14 @@ static void random_block(double* dev, long count, unsigned long long seed, Ctx& 
 void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick, unsigned long long seed) {
   const int k = W.pos, Lp = W.Lp, r = W.r[k], s = W.r[k + 1], md = W.m;
   const long n1 = (long)r * md * s;
+  // Components are normalised before the SVD so that a small component is not
+  // truncated away next to a large one; a component at rounding level (e.g. a
+  // Newton block whose right-hand side vanishes) keeps the largest weight, so
+  // that its noise is not amplified into spurious rank.
   std::vector<double> w = component_norms(W.blk.get(), Lp, n1, c);
-  for (double& x : w) x = (x > 0.0) ? x : 1.0;
+  double wmax = 0.0;
+  for (double x : w) wmax = std::max(wmax, x);
+  for (double& x : w) x = (wmax == 0.0) ? 1.0 : (x > 1e-8 * wmax ? x : wmax);
   DevBuf wdev(Lp);
   TT_HIP(hipMemcpyAsync(wdev.get(), w.data(), sizeof(double) * Lp, hipMemcpyHostToDevice, c.s));
   const long total = (long)Lp * n1;
@@ -244,8 +251,10 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     TT_HIP(hipGetLastError());
     SvdOut sv;
     svd_rowmajor(Ms.get(), rows, cols, sv, c);
-    const int rk0 = rank_for(sv.sigma, tol_rel, std::max(1, std::min(cap - kick, sv.k)));
-    const int q = std::max(0, std::min(kick, rows - rk0));
+    // Enrichment fills only the capacity the rank cap leaves: once the cap
+    // binds, the truncated SVD directions are kept in full.
+    const int rk0 = rank_for(sv.sigma, tol_rel, std::max(1, std::min(cap, sv.k)));
+    const int q = std::max(0, std::min({kick, rows - rk0, cap - rk0}));
     const int rk = rk0 + q;
     // W_k = [U[:, :rk0] | kick]  ([r][4][rk])
     W.cores[k].reserve((size_t)rows * rk);
@@ -302,8 +311,8 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     TT_HIP(hipGetLastError());
     SvdOut sv;
     svd_rowmajor(Ms.get(), rows, cols, sv, c);
-    const int rk0 = rank_for(sv.sigma, tol_rel, std::max(1, std::min(cap - kick, sv.k)));
-    const int q = std::max(0, std::min(kick, cols - rk0));
+    const int rk0 = rank_for(sv.sigma, tol_rel, std::max(1, std::min(cap, sv.k)));
+    const int q = std::max(0, std::min({kick, cols - rk0, cap - rk0}));
     const int rk = rk0 + q;
     // W_k = [Vt[:rk0]; kick]  ([rk][4][s])
     W.cores[k].reserve((size_t)rk * cols);
@@ -352,6 +361,9 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
 }
 
 namespace {
+
+// frames above this size use the blocked dense factorisations
+constexpr int kBlockedMin = 192;
 
 // ---------------------------------------------------------------------------
 // local solvers
@@ -402,9 +414,15 @@ void solve_direct(LocalKKT& K, const double* f, double* u, Ctx& c) {
   TT_HIP(hipMemcpyAsync(rhs.get(), f, sizeof(double) * N, hipMemcpyDeviceToDevice, c.s));
   c.ired.reserve(4);
   int* st = reinterpret_cast<int*>(c.ired.get());
-  dense_lu_solve(Kd.get(), N, rhs.get(), 1, st, c.s);
   int hst = 0;
-  TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+  if (N > kBlockedMin) {
+    BlockedFactors fk;
+    hst = lu_blocked(Kd.get(), N, fk, c);
+    if (hst == 0) lu_solve_blocked(Kd.get(), N, fk, rhs.get(), 1, c);
+  } else {
+    dense_lu_solve(Kd.get(), N, rhs.get(), 1, st, c.s);
+    TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+  }
   c.sync();
   if (hst != 0) throw Error(TT_ERR_NUMERIC, "singular local KKT system (zero pivot)");
   TT_HIP(hipMemcpyAsync(u, rhs.get(), sizeof(double) * N, hipMemcpyDeviceToDevice, c.s));
@@ -432,18 +450,31 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
   dense_symmetrize(LZ.get(), p, c.s);
   c.ired.reserve(4);
   int* st = reinterpret_cast<int*>(c.ired.get());
-  dense_cholesky(LZ.get(), p, st, c.s);
+  // Large frames go through the blocked (GEMM-based) factorisations; small
+  // ones through the single-workgroup kernels, which have less launch overhead.
+  const bool blocked = p > kBlockedMin;
+  BlockedFactors fz, fs;
   int hst = 0;
-  TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
-  c.sync();
+  if (blocked) {
+    hst = chol_blocked(LZ.get(), p, fz, c);
+  } else {
+    dense_cholesky(LZ.get(), p, st, c.s);
+    TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+    c.sync();
+  }
   if (hst != 0) return false;
   dense(OP_AEQ, A);
   dense(OP_AEQT, AT);
   dense(OP_KY, KY);
   dense(OP_LX, LX);
   auto solve_LZ = [&](double* B, int nrhs) {   // B <- L_Z^{-1} B = L^{-T} L^{-1} B
-    dense_trsm_lower(LZ.get(), p, B, nrhs, false, c.s);
-    dense_trsm_lower(LZ.get(), p, B, nrhs, true, c.s);
+    if (blocked) {
+      trsm_blocked(LZ.get(), p, fz, B, nrhs, false, c);
+      trsm_blocked(LZ.get(), p, fz, B, nrhs, true, c);
+    } else {
+      dense_trsm_lower(LZ.get(), p, B, nrhs, false, c.s);
+      dense_trsm_lower(LZ.get(), p, B, nrhs, true, c.s);
+    }
   };
   // G = L_Z^{-1} L_X^ Aeq^T^ ; S = Aeq^ G + K_Y^
   T1.reserve((size_t)p * p);
@@ -461,9 +492,14 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
   ry.reserve(p);
   gemm(gemm_nn(p, 1, p, A.get(), p, v1.get(), 1, ry.get(), 1), c.s, &c.ws, GemmPrec::F64);
   axpby(p, -1.0, Rp, 1.0, ry.get(), c.s);
-  dense_lu_solve(S.get(), p, ry.get(), 1, st, c.s);
-  TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
-  c.sync();
+  if (blocked) {
+    hst = lu_blocked(S.get(), p, fs, c);
+    if (hst == 0) lu_solve_blocked(S.get(), p, fs, ry.get(), 1, c);
+  } else {
+    dense_lu_solve(S.get(), p, ry.get(), 1, st, c.s);
+    TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+    c.sync();
+  }
   if (hst != 0) throw Error(TT_ERR_NUMERIC, "singular Schur complement in the local block elimination");
   // dZ = Aeq^T^ y - R_d^ ; dX = -L_Z^{-1}(R_c^ + L_X^ dZ)
   gemm(gemm_nn(p, 1, p, AT.get(), p, ry.get(), 1, v1.get(), 1), c.s, &c.ws, GemmPrec::F64);
@@ -741,7 +777,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       // move the block index and extend the environments
       if (dir > 0 && k < d - 1) {
         double t1 = now();
-        split_block(W, +1, tol_svd, prm.rank_cap, c, prm.kick,
+        split_block(W, +1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
                     prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k));
         info.t_svd += now() - t1;
         t1 = now();
@@ -750,7 +786,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
         info.t_env += now() - t1;
       } else if (dir < 0 && k > 0) {
         double t1 = now();
-        split_block(W, -1, tol_svd, prm.rank_cap, c, prm.kick,
+        split_block(W, -1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
                     prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k) + 7777ull);
         info.t_svd += now() - t1;
         t1 = now();
@@ -761,6 +797,11 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
     }
     info.sweeps += 1;
     info.last_max_res = max_res;
+    if (prm.verbose >= 2) {
+      std::fprintf(stderr, "    amen sweep %d dir %+d max_res %.3e tol %.3e ranks", sweep, dir, max_res, prm.tol);
+      for (int x : W.r) std::fprintf(stderr, " %d", x);
+      std::fprintf(stderr, "\n");
+    }
     dir = -dir;
     if (max_res < prm.tol && sweep >= 1) break;
   }

@@ -68,6 +68,8 @@ struct AmenParams {
   bool mixed = false;       // BF16 MFMA contractions inside the Krylov solve
   int kick = 2;             // enrichment directions added at every block move
   unsigned long long seed = 0;
+  int verbose = 0;          // >= 2: one line per sweep to stderr
+  int kick_sweeps = 1 << 30; // enrichment only in the first kick_sweeps half-sweeps
 };
 
 struct AmenInfo {

@@ -10,6 +10,7 @@
 
 #include "../../include/ttipm.h"
 #include "amen.hpp"
+#include "blocked.hpp"
 #include "dense.hpp"
 #include "ipm.hpp"
 #include "ttops.hpp"
@@ -85,6 +86,23 @@ extern "C" {
 const char* tt_last_error(void) { return ttipm::last_error(); }
 
 const char* tt_version(void) { return "ttipm-mi355x 0.1 (gfx950)"; }
+
+int tt_profile_start(int32_t period) {
+  return guarded([&]() -> int {
+    if (period < 1) throw Error(TT_ERR_ARG, "period must be >= 1");
+    prof_start(period);
+    return TT_OK;
+  });
+}
+
+int tt_profile_stop(tt_kernel_stat* out, int32_t cap, int32_t* count) {
+  return guarded([&]() -> int {
+    if (cap > 0 && !out) throw Error(TT_ERR_ARG, "out is NULL");
+    const int n = prof_stop(out, cap < 0 ? 0 : cap);
+    if (count) *count = n;
+    return TT_OK;
+  });
+}
 
 int tt_contract_interfaces(const tt_view* test, const tt_view* op, const tt_view* trial, int32_t k, int32_t dir,
                            const double* phi_in, double* phi_out, void* stream) {
@@ -182,32 +200,37 @@ int tt_local_solve(const tt_local_op* K, const double* rhs, double* x, const tt_
   return guarded([&]() -> int {
     check_local_op(K);
     if (!rhs || !x || !p) throw Error(TT_ERR_ARG, "NULL argument");
+    if (rhs == x) throw Error(TT_ERR_ARG, "rhs and x must not alias");
+    if (p->method < TT_SOLVE_AUTO || p->method > TT_SOLVE_CHOLESKY) throw Error(TT_ERR_ARG, "unknown solve method");
     Ctx& c = ctx_for(stream);
     c.prec = GemmPrec::F64;
     const long n = (long)K->L * K->r * K->m * K->rp;
     tt_solve_info inf{};
     int method = p->method;
     if (method == TT_SOLVE_AUTO) method = (n <= p->direct_max) ? TT_SOLVE_DIRECT : TT_SOLVE_GMRES;
-    if (method == TT_SOLVE_DIRECT) {
-      // dense K by applying the operator to unit vectors, then LU
+    if (method == TT_SOLVE_DIRECT || method == TT_SOLVE_CHOLESKY) {
+      // dense K by applying the operator to unit vectors, then a blocked factorisation
       if (n > 8192) throw Error(TT_ERR_ARG, "direct solve limited to 8192 unknowns");
-      DevBuf Kd((size_t)n * n), e(n), col(n), Kt((size_t)n * n), b(n);
+      DevBuf Kd((size_t)n * n), e(n), Kt((size_t)n * n);
       for (long j = 0; j < n; ++j) {
         fill(n, 0.0, e.get(), c.s);
         fill(1, 1.0, e.get() + j, c.s);
         generic_matvec(K, e.get(), Kt.get() + (size_t)j * n, c);   // column j (stored as row j of Kt)
       }
       permute(Kt.get(), Kd.get(), {n, n}, {1, 0}, c.s);
-      TT_HIP(hipMemcpyAsync(b.get(), rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
-      c.ired.reserve(4);
-      int* st = reinterpret_cast<int*>(c.ired.get());
-      dense_lu_solve(Kd.get(), (int)n, b.get(), 1, st, c.s);
-      int hst = 0;
-      TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+      TT_HIP(hipMemcpyAsync(x, rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+      BlockedFactors f;
+      if (method == TT_SOLVE_CHOLESKY) {
+        dense_symmetrize(Kd.get(), (int)n, c.s);
+        if (chol_blocked(Kd.get(), (int)n, f, c)) throw Error(TT_ERR_NUMERIC, "local system not positive definite");
+        trsm_blocked(Kd.get(), (int)n, f, x, 1, false, c);
+        trsm_blocked(Kd.get(), (int)n, f, x, 1, true, c);
+      } else {
+        if (lu_blocked(Kd.get(), (int)n, f, c)) throw Error(TT_ERR_NUMERIC, "singular local system");
+        lu_solve_blocked(Kd.get(), (int)n, f, x, 1, c);
+      }
       c.sync();
-      if (hst) throw Error(TT_ERR_NUMERIC, "singular local system");
-      TT_HIP(hipMemcpyAsync(x, b.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
-      inf.method_used = TT_SOLVE_DIRECT;
+      inf.method_used = method;
       inf.iters = 0;
     } else {
       // restarted GMRES (CGS2) on the generic operator
@@ -287,7 +310,7 @@ int tt_local_solve(const tt_local_op* K, const double* rhs, double* x, const tt_
       inf.rel_res = rel;
     }
     // true residual in FP64
-    if (inf.method_used == TT_SOLVE_DIRECT) {
+    if (inf.method_used != TT_SOLVE_GMRES) {
       DevBuf r0(n);
       generic_matvec(K, x, r0.get(), c);
       axpby(n, 1.0, rhs, -1.0, r0.get(), c.s);
@@ -297,7 +320,7 @@ int tt_local_solve(const tt_local_op* K, const double* rhs, double* x, const tt_
     inf.precond_used = TT_PREC_NONE;
     if (info) *info = inf;
     c.sync();
-    return (inf.rel_res <= p->rtol || inf.method_used == TT_SOLVE_DIRECT) ? TT_OK : TT_ERR_NOT_CONVERGED;
+    return (inf.rel_res <= p->rtol || inf.method_used != TT_SOLVE_GMRES) ? TT_OK : TT_ERR_NOT_CONVERGED;
   });
 }
 
@@ -344,6 +367,9 @@ void ttipm_params_default(ttipm_params* p) {
   p->eig_rank = 6;
   p->eig_sweeps = 2;
   p->verbose = 0;
+  p->kick = 0;
+  p->seed = 12345;
+  p->kick_sweeps = 1 << 30;
 }
 
 int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {
@@ -447,11 +473,11 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
       if (prm->verbose)
         std::fprintf(stderr,
                      "it %2d %s mu %.2e pobj %+.10e dobj %+.10e gap %.2e ep %.1e ed %.1e ap %.3e/%.3e ad %.3e/%.3e "
-                     "bt %d rX %d rY %d rZ %d rW %d sw %d/%d kr %d t %.3fs\n",
+                     "bt %d rX %d rY %d rZ %d rW %d sw %d/%d kr %d sig %.2e eta %.1e t %.3fs\n",
                      inf.iter, inf.direction ? "aho" : "xz ", inf.mu, inf.pobj, inf.dobj, inf.rel_gap, inf.eps_p,
                      inf.eps_d, inf.alpha_p, inf.alpha_p_max, inf.alpha_d, inf.alpha_d_max, inf.backtracks,
                      inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w, inf.sweeps_pred, inf.sweeps_corr,
-                     inf.krylov_iters, inf.t_total);
+                     inf.krylov_iters, inf.sigma, inf.eta, inf.t_total);
       if (!std::isfinite(inf.pobj)) throw Error(TT_ERR_NUMERIC, "non-finite objective");
     }
     r.iterations = it;

@@ -66,6 +66,97 @@ void pool_free(void* p, size_t bytes) {
 
 size_t pool_bytes_in_use() { return pool().in_use; }
 
+namespace {
+const char* const kProfNames[PK_COUNT] = {"gemm_f64_kernel", "gemm_bf16_kernel", "jacobi_svd_kernel",
+                                          "panel_lu_kernel"};
+struct ProfRec {
+  hipEvent_t a, b;
+  int kernel;
+  double flops, bytes;
+};
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  int period = 1;
+  long launches[PK_COUNT] = {};
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> spare;
+};
+Prof& prof() {
+  static Prof* p = new Prof();
+  return *p;
+}
+hipEvent_t prof_event(Prof& P) {
+  if (!P.spare.empty()) {
+    hipEvent_t e = P.spare.back();
+    P.spare.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  TT_HIP(hipEventCreate(&e));
+  return e;
+}
+}  // namespace
+
+int prof_begin(int kernel, hipStream_t s, double flops, double bytes) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  if (!P.on) return -1;
+  const long n = P.launches[kernel]++;
+  if (n % P.period) return -1;
+  ProfRec r{prof_event(P), prof_event(P), kernel, flops, bytes};
+  TT_HIP(hipEventRecord(r.a, s));
+  P.recs.push_back(r);
+  return (int)P.recs.size() - 1;
+}
+
+void prof_end(int token, hipStream_t s) {
+  if (token < 0) return;
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  TT_HIP(hipEventRecord(P.recs[token].b, s));
+}
+
+void prof_start(int period) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  for (ProfRec& r : P.recs) {
+    P.spare.push_back(r.a);
+    P.spare.push_back(r.b);
+  }
+  P.recs.clear();
+  for (long& x : P.launches) x = 0;
+  P.period = period > 0 ? period : 1;
+  P.on = true;
+}
+
+int prof_stop(tt_kernel_stat* out, int cap) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.on = false;
+  tt_kernel_stat st[PK_COUNT] = {};
+  for (int k = 0; k < PK_COUNT; ++k) {
+    std::snprintf(st[k].name, sizeof(st[k].name), "%s", kProfNames[k]);
+    st[k].launches = P.launches[k];
+  }
+  for (ProfRec& r : P.recs) {
+    TT_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    TT_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    tt_kernel_stat& x = st[r.kernel];
+    x.timed += 1;
+    x.time_ms += ms;
+    x.flops += r.flops;
+    x.bytes += r.bytes;
+    P.spare.push_back(r.a);
+    P.spare.push_back(r.b);
+  }
+  P.recs.clear();
+  const int n = cap < PK_COUNT ? cap : PK_COUNT;
+  for (int k = 0; k < n; ++k) out[k] = st[k];
+  return PK_COUNT;
+}
+
 void pool_trim() {
   Pool& P = pool();
   std::lock_guard<std::mutex> g(P.mu);

@@ -82,6 +82,16 @@ class DevBuf {
 
 inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// Event timing of selected kernels (tt_profile_start / tt_profile_stop).  While
+// profiling is on, every period-th launch of an instrumented kernel is
+// bracketed by HIP events recorded on the launch stream; its algorithmic flops
+// and bytes are recorded with it.
+enum ProfKernel { PK_GEMM_F64 = 0, PK_GEMM_BF16, PK_JACOBI_SVD, PK_PANEL_LU, PK_COUNT };
+int prof_begin(int kernel, hipStream_t s, double flops, double bytes);   // -1 when not timed
+void prof_end(int token, hipStream_t s);
+void prof_start(int period);
+int prof_stop(tt_kernel_stat* out, int cap);
+
 // Number of blocks for n items with b threads per block (at least 1).
 inline unsigned nblocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
 

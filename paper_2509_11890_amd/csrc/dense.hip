@@ -119,11 +119,9 @@ __global__ __launch_bounds__(DT) void qr_form_q_kernel(const double* A, int m, i
 // sigma (descending) and V (n x n, column-major) with A = U diag(sigma) V^T.
 // Columns of U with sigma = 0 are zero.  work: m*n + n*n doubles + n ints.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(DT) void jacobi_svd_kernel(double* A, int m, int n, double* Vw,
-                                                        double* U, double* sigma, double* V,
-                                                        int* order, int max_sweeps, double tol,
-                                                        int* sweeps_out) {
-  __shared__ int s_rot;
+__device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double* Vw, double* U, double* sigma,
+                                                double* V, int* order, int max_sweeps, double tol, int* sweeps_out,
+                                                int& s_rot) {
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
     int c = (int)(t / n), i = (int)(t % n);
@@ -212,6 +210,28 @@ __global__ __launch_bounds__(DT) void jacobi_svd_kernel(double* A, int m, int n,
     for (int rnk = 0; rnk < n; ++rnk) sigma[rnk] = Vw[rnk];
     if (sweeps_out) *sweeps_out = sweep;
   }
+}
+
+__global__ __launch_bounds__(DT) void jacobi_svd_kernel(double* A, int m, int n, double* Vw, double* U,
+                                                        double* sigma, double* V, int* order, int max_sweeps,
+                                                        double tol, int* sweeps_out) {
+  __shared__ int s_rot;
+  jacobi_svd_body(A, m, n, Vw, U, sigma, V, order, max_sweeps, tol, sweeps_out, s_rot);
+}
+
+// The same sweeps with A and the rotation accumulator resident in LDS (dynamic
+// shared memory of (m*n + n*n) doubles): every column access of a rotation is
+// then an LDS access instead of an L2 round trip, which is what bounds the
+// latency-bound sweeps for the small matrices of the TT splits and roundings.
+__global__ __launch_bounds__(DT) void jacobi_svd_lds_kernel(const double* Ag, int m, int n, double* U,
+                                                            double* sigma, double* V, int* order, int max_sweeps,
+                                                            double tol, int* sweeps_out) {
+  extern __shared__ double lds[];
+  __shared__ int s_rot;
+  double* As = lds;
+  double* Vs = lds + (long)m * n;
+  for (long t = threadIdx.x; t < (long)m * n; t += blockDim.x) As[t] = Ag[t];
+  jacobi_svd_body(As, m, n, Vs, U, sigma, V, order, max_sweeps, tol, sweeps_out, s_rot);
 }
 
 // ---------------------------------------------------------------------------
@@ -378,10 +398,41 @@ void dense_qr_form_q(const double* A, int m, int n, int lda, const double* tau, 
   TT_HIP(hipGetLastError());
 }
 
+// Dynamic LDS available to the Jacobi kernel: the device's per-workgroup limit
+// (queried once) minus the kernel's static shared memory, opted in with
+// hipFuncSetAttribute when above the 64 KiB default.
+static size_t jacobi_lds_limit() {
+  static size_t limit = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+      (void)hipGetLastError();
+      return (size_t)0;
+    }
+    size_t lim = (size_t)v - 256;
+    if (lim > 65536 - 256 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_lds_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
+      (void)hipGetLastError();
+      lim = 65536 - 256;
+    }
+    return lim;
+  }();
+  return limit;
+}
+
 void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, double* work, int* iwork,
                hipStream_t s, int max_sweeps, double tol) {
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(DT), 0, s, A, m, n, work, U, sigma, V, iwork,
-                     max_sweeps, tol, iwork + n);
+  const int tok = prof_begin(PK_JACOBI_SVD, s, 0.0, 8.0 * ((double)m * n * 2 + (double)n * n + n));
+  const size_t lds_bytes = sizeof(double) * ((size_t)m * n + (size_t)n * n);
+  if (lds_bytes <= jacobi_lds_limit()) {
+    hipLaunchKernelGGL(jacobi_svd_lds_kernel, dim3(1), dim3(DT), lds_bytes, s, A, m, n, U, sigma, V, iwork,
+                       max_sweeps, tol, iwork + n);
+  } else {
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(DT), 0, s, A, m, n, work, U, sigma, V, iwork,
+                       max_sweeps, tol, iwork + n);
+  }
+  prof_end(tok, s);
   TT_HIP(hipGetLastError());
 }
 

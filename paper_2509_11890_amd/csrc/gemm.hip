@@ -297,10 +297,14 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
     g.P = w->buf.get();
   }
   dim3 grid(gm, gn, q.batch * ks);
+  const double flops = 2.0 * q.M * q.N * (double)q.K * q.batch;
+  const double bytes = 8.0 * q.batch * ((double)q.M * q.K + (double)q.K * q.N + (double)q.M * q.N * (q.beta != 0.0 ? 2 : 1));
+  const int tok = prof_begin(prec == GemmPrec::BF16 ? PK_GEMM_BF16 : PK_GEMM_F64, stream, flops, bytes);
   if (prec == GemmPrec::BF16)
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
   else
     hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, stream, g);
+  prof_end(tok, stream);
   TT_HIP(hipGetLastError());
   if (ks > 1) {
     long total = (long)q.batch * q.M * q.N;

@@ -161,6 +161,7 @@ Problem build_problem(int kind, const TT& G, const TT* negdeg, Ctx& c) {
 void init_state(const Problem& P, const ttipm_params& prm, State& S, Ctx& c) {
   // Sec. 5.1: X = Z = lambda* I, Y = 0; with inequalities X = lambda* I + (alpha_p/10) A_ineq(J),
   // T = lambda*_ineq A_ineq(J) (reading: alpha_p = lambda* for A_G = J - I).
+  S.seed = (unsigned long long)(unsigned)prm.seed;
   S.X = tt_clone(P.Ivec, c);
   tt_scale(S.X, P.lam0, c);
   S.Z = tt_clone(P.Ivec, c);
@@ -462,7 +463,9 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   ap.gmres_maxit = prm.gmres_maxit;
   ap.precond = prm.precond;
   ap.mixed = prm.precision == TTIPM_MIXED;
-  ap.kick = 2;
+  ap.kick = std::max(0, prm.kick);
+  ap.verbose = prm.verbose;
+  ap.kick_sweeps = std::max(0, prm.kick_sweeps);
   ap.seed = S.seed + 31ull * (unsigned long long)S.iter;
   // --- predictor: affine direction (target mu = 0) ---
   sys.terms = base;

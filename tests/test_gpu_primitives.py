@@ -194,3 +194,46 @@ def test_local_solve_matches_dense_lu(method):
     torch.cuda.synchronize()
     assert info["rel_res"] < 1e-12
     assert _rel(x.cpu().numpy(), x_ref) < 1e-10
+
+
+def _random_local_op(P, rng, r, rp, m, L, spd):
+    """A random well-conditioned L-block local operator and its dense matrix."""
+    p = r * m * rp
+    ident = (np.eye(r)[:, None, :], None, np.eye(rp)[:, None, :])
+    op = (rng.standard_normal((r, 2, r)) * 0.1, rng.standard_normal((2, m, m, 3)),
+          rng.standard_normal((rp, 3, rp)) * 0.1)
+    Dm = ott.local_dense(*op)
+    if spd:   # K = 2 I + B^T B with B the projected operator (L = 1); chains apply left to right
+        opT = (np.transpose(op[0], (2, 1, 0)), np.transpose(op[1], (0, 2, 1, 3)), np.transpose(op[2], (2, 1, 0)))
+        assert np.allclose(ott.local_dense(*opT), Dm.T)
+        blocks = [(0, 0, 2.0, [ident]), (0, 0, 1.0, [op, opT])]
+        return blocks, 2.0 * np.eye(p) + Dm.T @ Dm
+    blocks = [(0, 0, 1.0, [ident]), (1, 1, 1.0, [ident]), (0, 1, 1.0, [op]), (1, 0, -1.0, [op])]
+    Kd = np.eye(L * p)
+    Kd[:p, p:] += Dm
+    Kd[p:, :p] -= Dm
+    return blocks, Kd
+
+
+@pytest.mark.parametrize("r,rp,method", [(8, 10, "direct"), (5, 13, "direct"), (9, 11, "cholesky"),
+                                          (2, 3, "cholesky")])
+def test_local_direct_solve_blocked_sizes(r, rp, method):
+    """Blocked LU / Cholesky across several 64-wide panels with a ragged tail."""
+    P = _lib()
+    rng = np.random.default_rng(r * 100 + rp)
+    m = 4
+    spd = method == "cholesky"
+    L = 1 if spd else 2
+    blocks, Kd = _random_local_op(P, rng, r, rp, m, L, spd)
+    if spd:
+        assert np.allclose(Kd, Kd.T) and np.linalg.eigvalsh(Kd).min() > 1.0
+    b = rng.standard_normal(Kd.shape[0])
+    x_ref = np.linalg.solve(Kd, b)
+    pblocks = [P.LocalBlock(row, col, coef, [P.ProjOp(_cuda(a), None if c is None else _cuda(c), _cuda(bb))
+                                             for a, c, bb in chain]) for row, col, coef, chain in blocks]
+    K = P.LocalOp(r, rp, L, pblocks)
+    x = torch.zeros(Kd.shape[0], dtype=torch.float64, device="cuda")
+    info = P.local_solve(K, _cuda(b), x, method=P.TT_SOLVE_CHOLESKY if spd else P.TT_SOLVE_DIRECT)
+    torch.cuda.synchronize()
+    assert info["rel_res"] < 1e-12
+    assert _rel(x.cpu().numpy(), x_ref) < 1e-10
