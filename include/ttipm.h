@@ -138,9 +138,11 @@ typedef struct {
   int32_t r, rp, m, L;
   int32_t nblocks;
   const tt_local_block* blocks;   /* host array of nblocks */
+  int32_t precision;              /* TTIPM_F64: FP64 MFMA contractions; TTIPM_MIXED: BF16
+                                     operands with FP32 accumulation (vectors stay FP64) */
 } tt_local_op;
 
-/* y = K x.  No synchronisation. */
+/* y = K x in the precision of K->precision. */
 TTIPM_API int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stream);
 
 /* DIRECT: blocked LU with partial pivoting of the assembled dense K.
@@ -159,6 +161,7 @@ typedef struct {
   int32_t precond;      /* TT_PREC_*                                               */
   int32_t precision;    /* TTIPM_F64 or TTIPM_MIXED (see below)                    */
   const void* mlp;      /* tt_mlp handle when precond == TT_PREC_MLP               */
+  float context[4];     /* context features of the MLP preconditioner (see tt_mlp) */
 } tt_solve_params;
 
 typedef struct {
@@ -171,6 +174,12 @@ typedef struct {
 /*
  * Solve K x = rhs for the local system (Sec. 3.3: matrix-free GMRES on the
  * reduced projected system, or a dense direct solve when it is small).
+ * With p->precision == TTIPM_MIXED the Arnoldi products use BF16-operand
+ * contractions and every restart recomputes the true residual rhs - K x in
+ * FP64 (GMRES as the inner solver of an iterative refinement), so rel_res is
+ * an FP64 residual.  The direct methods always run in FP64.
+ * p->precond: TT_PREC_BJACOBI applies the inverse of the (a, b) diagonal
+ * blocks of K (L*m x L*m each) as a right preconditioner.
  * x holds the initial guess on entry and the solution on exit (x must not
  * alias rhs).  Synchronises
  * the stream (convergence tests).  Returns TT_ERR_NOT_CONVERGED if rtol was
@@ -220,6 +229,53 @@ typedef struct {
 TTIPM_API int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out);
 TTIPM_API void ttipm_problem_destroy(ttipm_problem* p);
 
+/* ---- learned block preconditioner ---------------------------------------- */
+/*
+ * A two-hidden-layer ReLU network (FP32) predicting, for each diagonal block
+ * (a, b) of a local system (n = L*m unknowns per block), a correction C_b of
+ * the block-Jacobi inverse: M_b = B_b^{-1} + C_b / s_b, s_b = ||B_b||_F.  Its
+ * input is the block normalised by s_b (n*n values, row-major) followed by
+ * four context scalars (the IPM passes log10(mu), k/d, r/64, s/64), so
+ * in_dim = n*n + 4 and out_dim = n*n.  The output layer starts at zero: an
+ * untrained network is exactly the block-Jacobi preconditioner.
+ * Training data are probe pairs of local systems: for a seeded Gaussian probe
+ * x of the whole system and y = K x, the block residual r_b = x_b - B_b^{-1} y_b
+ * and y_b; the loss is (1/N) sum_blocks sum_p w_p || r_b - C_b y_b / s_b ||^2
+ * with w_p = (number of blocks) / ||x||^2, the block part of ||x - M K x||^2.
+ * Parameters are flat FP32 in the order W1 [h][in], b1 [h], W2 [h][h], b2 [h],
+ * W3 [out][h], b3 [out].  Handles are not thread-safe.
+ */
+typedef struct tt_mlp tt_mlp;
+
+typedef struct {
+  int32_t N, P, n;      /* blocks, probes per block, unknowns per block             */
+  const float* F;       /* [N][n*n + 4] features (device)                           */
+  const float* R;       /* [N][P][n] block-Jacobi residuals (device)                */
+  const float* Y;       /* [N][P][n] probe images y_b (device)                      */
+  const float* S;       /* [N] block norms (device)                                 */
+  const float* W;       /* [N][P] probe weights (device)                            */
+} tt_mlp_batch;
+
+TTIPM_API int tt_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, int32_t seed, tt_mlp** out);
+TTIPM_API void tt_mlp_destroy(tt_mlp* m);
+TTIPM_API int64_t tt_mlp_num_params(const tt_mlp* m);
+/* host copies of the flat parameter vector (count must equal tt_mlp_num_params) */
+TTIPM_API int tt_mlp_get_params(const tt_mlp* m, float* host, int64_t count);
+TTIPM_API int tt_mlp_set_params(tt_mlp* m, const float* host, int64_t count);
+/* loss of a batch and its gradient (host, flat, num_params floats; may be NULL) */
+TTIPM_API int tt_mlp_loss_grad(tt_mlp* m, const tt_mlp_batch* b, double* loss, float* grad_host, void* stream);
+/* Append the blocks of local system K to the handle's dataset (at most cap
+ * blocks in total): features with the given context, nprobe seeded probes. */
+TTIPM_API int tt_mlp_collect(tt_mlp* m, const tt_local_op* K, const float* context, int32_t nprobe, int32_t seed,
+                             int64_t cap, void* stream);
+TTIPM_API int tt_mlp_dataset_size(const tt_mlp* m, int64_t* n_blocks);
+/* Adam on shuffled mini-batches of data (NULL = the collected dataset);
+ * loss_hist (host, epochs doubles, may be NULL) receives the mean loss per epoch. */
+TTIPM_API int tt_mlp_train(tt_mlp* m, const tt_mlp_batch* data, int32_t epochs, int32_t batch, float lr, int32_t seed,
+                           double* loss_hist, void* stream);
+/* loss of data (NULL = the collected dataset) without updating the network */
+TTIPM_API int tt_mlp_eval(tt_mlp* m, const tt_mlp_batch* data, double* loss, void* stream);
+
 /* Kernel timing.  While profiling is on, every period-th launch of the
  * instrumented kernels (the FP64 and BF16 MFMA GEMMs, the Jacobi SVD, the LU
  * panel) is bracketed by HIP events recorded on its launch stream.
@@ -259,13 +315,17 @@ typedef struct {
   int32_t gmres_maxit;
   int32_t precision;    /* TTIPM_F64 or TTIPM_MIXED                                       */
   int32_t precond;      /* TT_PREC_*                                                      */
-  const void* mlp;      /* tt_mlp handle for TT_PREC_MLP                                  */
+  const void* mlp;      /* tt_mlp handle for TT_PREC_MLP (and the collect_probes dataset)  */
   int32_t eig_rank;     /* rank of the TT eigenvector in the step-length solver          */
   int32_t eig_sweeps;   /* ALS sweeps of the step-length solver                           */
   int32_t verbose;      /* print one line per iteration to stderr                          */
-  int32_t kick;         /* seeded random enrichment columns per AMEn core move (0)         */
+  int32_t kick;         /* seeded random enrichment columns per AMEn core move (2); off once
+                           a Newton frame has been truncated by rank_cap                 */
   int32_t seed;         /* seed of the enrichment and step-length start vectors            */
   int32_t kick_sweeps;  /* enrichment only in the first kick_sweeps half-sweeps of a solve */
+  int32_t collect_probes; /* > 0 and mlp set: every local system of the AMEn solves adds its
+                           blocks with this many probes to the mlp handle's dataset        */
+  int64_t collect_cap;  /* dataset size limit (blocks) for collect_probes                 */
 } ttipm_params;
 
 TTIPM_API void ttipm_params_default(ttipm_params* p);
@@ -280,8 +340,11 @@ typedef struct {
   int32_t rank_x, rank_y, rank_z, rank_w;
   double mu, pobj, dobj, rel_gap, eps_p, eps_d, eps_c;
   double alpha_p, alpha_d, sigma, eta;
-  double alpha_p_max, alpha_d_max;  /* TT eigen-solver step bounds before tau and the PD check */
+  double alpha_p_max, alpha_d_max;  /* Thm. 1 step bounds from the TT eigen-solver, before tau and
+                                       the PD check (1e6 when the direction has no bound) */
   int32_t backtracks;               /* step halvings forced by the positive-definiteness check */
+  int32_t mlp_used, mlp_fallbacks;  /* local solves with the MLP preconditioner kept / replaced by
+                                       block Jacobi under the fallback rule */
   double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration */
 } ttipm_step_info;
 

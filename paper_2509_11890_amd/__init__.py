@@ -10,5 +10,5 @@ from .binding import (  # noqa: F401
     TTIPM_MAXCUT, TTIPM_THETA, TTIPM_CC, TTIPM_F64, TTIPM_MIXED,
     TT_SOLVE_AUTO, TT_SOLVE_DIRECT, TT_SOLVE_GMRES, TT_SOLVE_CHOLESKY, TT_PREC_NONE, TT_PREC_BJACOBI, TT_PREC_MLP,
     contract_interfaces, local_matvec, local_solve, tt_round, ProjOp, LocalBlock, LocalOp,
-    Params, Problem, State, ttipm_step, ttipm_solve, version, profile_start, profile_stop,
+    Params, Problem, State, ttipm_step, ttipm_solve, version, profile_start, profile_stop, MLP,
 )

@@ -61,13 +61,13 @@ class tt_local_block(C.Structure):
 
 class tt_local_op(C.Structure):
     _fields_ = [("r", C.c_int32), ("rp", C.c_int32), ("m", C.c_int32), ("L", C.c_int32),
-                ("nblocks", C.c_int32), ("blocks", C.POINTER(tt_local_block))]
+                ("nblocks", C.c_int32), ("blocks", C.POINTER(tt_local_block)), ("precision", C.c_int32)]
 
 
 class tt_solve_params(C.Structure):
     _fields_ = [("method", C.c_int32), ("direct_max", C.c_int32), ("restart", C.c_int32),
                 ("maxit", C.c_int32), ("rtol", C.c_double), ("precond", C.c_int32),
-                ("precision", C.c_int32), ("mlp", C.c_void_p)]
+                ("precision", C.c_int32), ("mlp", C.c_void_p), ("context", C.c_float * 4)]
 
 
 class tt_solve_info(C.Structure):
@@ -87,7 +87,7 @@ class ttipm_params(C.Structure):
                 ("gmres_restart", C.c_int32), ("gmres_maxit", C.c_int32), ("precision", C.c_int32),
                 ("precond", C.c_int32), ("mlp", C.c_void_p), ("eig_rank", C.c_int32),
                 ("eig_sweeps", C.c_int32), ("verbose", C.c_int32), ("kick", C.c_int32), ("seed", C.c_int32),
-                ("kick_sweeps", C.c_int32)]
+                ("kick_sweeps", C.c_int32), ("collect_probes", C.c_int32), ("collect_cap", C.c_int64)]
 
 
 class ttipm_step_info(C.Structure):
@@ -96,7 +96,7 @@ class ttipm_step_info(C.Structure):
                [(n, C.c_double) for n in ("mu", "pobj", "dobj", "rel_gap", "eps_p", "eps_d", "eps_c",
                                           "alpha_p", "alpha_d", "sigma", "eta", "alpha_p_max",
                                           "alpha_d_max")] + \
-               [("backtracks", C.c_int32)] + \
+               [("backtracks", C.c_int32), ("mlp_used", C.c_int32), ("mlp_fallbacks", C.c_int32)] + \
                [(n, C.c_double) for n in ("t_env", "t_solve", "t_svd", "t_step", "t_round", "t_total")]
 
     def as_dict(self):
@@ -228,7 +228,7 @@ class LocalBlock:
 class LocalOp:
     """tt_local_op from python blocks (each a chain of one or two ProjOp)."""
 
-    def __init__(self, r, rp, L, blocks, m=4):
+    def __init__(self, r, rp, L, blocks, m=4, precision=0):
         self.blocks = blocks
         arr = (tt_local_block * max(1, len(blocks)))()
         for i, b in enumerate(blocks):
@@ -239,7 +239,7 @@ class LocalOp:
                                           _dev(o.phiR).value, o.R, o.Rp)
         self.arr = arr
         self.op = tt_local_op(int(r), int(rp), int(m), int(L), len(blocks),
-                              C.cast(arr, C.POINTER(tt_local_block)))
+                              C.cast(arr, C.POINTER(tt_local_block)), int(precision))
 
 
 def local_matvec(K: LocalOp, x, y):
@@ -247,8 +247,9 @@ def local_matvec(K: LocalOp, x, y):
 
 
 def local_solve(K: LocalOp, rhs, x, method=TT_SOLVE_AUTO, rtol=1e-12, restart=40, maxit=1000,
-                direct_max=1024, precond=TT_PREC_NONE):
-    prm = tt_solve_params(method, direct_max, restart, maxit, rtol, precond, TTIPM_F64, None)
+                direct_max=1024, precond=TT_PREC_NONE, precision=TTIPM_F64, mlp=None, context=(0, 0, 0, 0)):
+    prm = tt_solve_params(method, direct_max, restart, maxit, rtol, precond, precision,
+                          mlp.h if mlp is not None else None, (C.c_float * 4)(*context))
     info = tt_solve_info()
     code = lib.tt_local_solve(C.byref(K.op), _dev(rhs), _dev(x), C.byref(prm), C.byref(info), _stream())
     _check(code, allow=(TT_ERR_NOT_CONVERGED,))
@@ -350,3 +351,96 @@ def ttipm_solve(problem: Problem, state: State, params: Params, log_cap=200):
     _check(lib.ttipm_solve(problem.h, state.h, C.byref(params.p), C.byref(res), log, log_cap, _stream()))
     n = min(res.iterations, log_cap)
     return res.as_dict(), [log[i].as_dict() for i in range(n)]
+
+
+# ---- learned block preconditioner ----------------------------------------------
+class tt_mlp_batch(C.Structure):
+    _fields_ = [("N", C.c_int32), ("P", C.c_int32), ("n", C.c_int32), ("F", C.c_void_p), ("R", C.c_void_p),
+                ("Y", C.c_void_p), ("S", C.c_void_p), ("W", C.c_void_p)]
+
+
+lib.tt_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
+lib.tt_mlp_destroy.argtypes = [C.c_void_p]
+lib.tt_mlp_destroy.restype = None
+lib.tt_mlp_num_params.argtypes = [C.c_void_p]
+lib.tt_mlp_num_params.restype = C.c_int64
+lib.tt_mlp_get_params.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64]
+lib.tt_mlp_set_params.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64]
+lib.tt_mlp_loss_grad.argtypes = [C.c_void_p, C.POINTER(tt_mlp_batch), C.POINTER(C.c_double), C.POINTER(C.c_float),
+                                 C.c_void_p]
+lib.tt_mlp_collect.argtypes = [C.c_void_p, C.POINTER(tt_local_op), C.POINTER(C.c_float), C.c_int32, C.c_int32,
+                               C.c_int64, C.c_void_p]
+lib.tt_mlp_dataset_size.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+lib.tt_mlp_train.argtypes = [C.c_void_p, C.POINTER(tt_mlp_batch), C.c_int32, C.c_int32, C.c_float, C.c_int32,
+                             C.POINTER(C.c_double), C.c_void_p]
+lib.tt_mlp_eval.argtypes = [C.c_void_p, C.POINTER(tt_mlp_batch), C.POINTER(C.c_double), C.c_void_p]
+
+
+class MLP:
+    """Handle of the learned block preconditioner (tt_mlp)."""
+
+    def __init__(self, block_n, hidden=256, seed=0):
+        self.n = int(block_n)
+        self.in_dim = self.n * self.n + 4
+        self.out_dim = self.n * self.n
+        self.h = C.c_void_p()
+        _check(lib.tt_mlp_create(self.in_dim, int(hidden), self.out_dim, int(seed), C.byref(self.h)))
+        self.hidden = int(hidden)
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib.tt_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    @property
+    def num_params(self):
+        return int(lib.tt_mlp_num_params(self.h))
+
+    def get_params(self):
+        import numpy as np
+        buf = (C.c_float * self.num_params)()
+        _check(lib.tt_mlp_get_params(self.h, buf, self.num_params))
+        return np.frombuffer(buf, dtype=np.float32).copy()
+
+    def set_params(self, vec):
+        import numpy as np
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        assert v.size == self.num_params
+        _check(lib.tt_mlp_set_params(self.h, v.ctypes.data_as(C.POINTER(C.c_float)), v.size))
+
+    @staticmethod
+    def _batch(F, R, Y, S, W):
+        N, P, n = R.shape
+        b = tt_mlp_batch(N, P, n, _dev(F).value, _dev(R).value, _dev(Y).value, _dev(S).value, _dev(W).value)
+        return b
+
+    def loss_grad(self, F, R, Y, S, W):
+        """Device float32 tensors F [N][n*n+4], R/Y [N][P][n], S [N], W [N][P] -> (loss, grad numpy)."""
+        import numpy as np
+        b = self._batch(F, R, Y, S, W)
+        loss = C.c_double(0.0)
+        g = (C.c_float * self.num_params)()
+        _check(lib.tt_mlp_loss_grad(self.h, C.byref(b), C.byref(loss), g, _stream()))
+        return loss.value, np.frombuffer(g, dtype=np.float32).copy()
+
+    def collect(self, K, nprobe=8, seed=0, cap=1 << 22, context=(0, 0, 0, 0)):
+        ctx = (C.c_float * 4)(*context)
+        _check(lib.tt_mlp_collect(self.h, C.byref(K.op), ctx, int(nprobe), int(seed), int(cap), _stream()))
+
+    @property
+    def dataset_size(self):
+        n = C.c_int64(0)
+        _check(lib.tt_mlp_dataset_size(self.h, C.byref(n)))
+        return n.value
+
+    def train(self, epochs=20, batch=1024, lr=1e-3, seed=0, data=None):
+        hist = (C.c_double * max(1, epochs))()
+        b = C.byref(self._batch(*data)) if data is not None else None
+        _check(lib.tt_mlp_train(self.h, b, int(epochs), int(batch), float(lr), int(seed), hist, _stream()))
+        return list(hist)[:epochs]
+
+    def eval(self, data=None):
+        b = C.byref(self._batch(*data)) if data is not None else None
+        loss = C.c_double(0.0)
+        _check(lib.tt_mlp_eval(self.h, b, C.byref(loss), _stream()))
+        return loss.value

@@ -15,6 +15,8 @@
 // local residual of the incoming iterate over a half-sweep.
 #include "amen.hpp"
 #include "blocked.hpp"
+#include "krylov.hpp"
+#include "mlp.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -224,7 +226,8 @@ static void random_block(double* dev, long count, unsigned long long seed, Ctx& 
   c.sync();
 }
 
-void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick, unsigned long long seed) {
+bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick, unsigned long long seed) {
+  bool capped = false;
   const int k = W.pos, Lp = W.Lp, r = W.r[k], s = W.r[k + 1], md = W.m;
   const long n1 = (long)r * md * s;
   // Components are normalised before the SVD so that a small component is not
@@ -253,7 +256,9 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     svd_rowmajor(Ms.get(), rows, cols, sv, c);
     // Enrichment fills only the capacity the rank cap leaves: once the cap
     // binds, the truncated SVD directions are kept in full.
-    const int rk0 = rank_for(sv.sigma, tol_rel, std::max(1, std::min(cap, sv.k)));
+    const int rk_tol = rank_for(sv.sigma, tol_rel, sv.k);
+    const int rk0 = std::max(1, std::min(rk_tol, cap));
+    capped = rk_tol > cap;
     const int q = std::max(0, std::min({kick, rows - rk0, cap - rk0}));
     const int rk = rk0 + q;
     // W_k = [U[:, :rk0] | kick]  ([r][4][rk])
@@ -311,7 +316,9 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     TT_HIP(hipGetLastError());
     SvdOut sv;
     svd_rowmajor(Ms.get(), rows, cols, sv, c);
-    const int rk0 = rank_for(sv.sigma, tol_rel, std::max(1, std::min(cap, sv.k)));
+    const int rk_tol = rank_for(sv.sigma, tol_rel, sv.k);
+    const int rk0 = std::max(1, std::min(rk_tol, cap));
+    capped = rk_tol > cap;
     const int q = std::max(0, std::min({kick, cols - rk0, cap - rk0}));
     const int rk = rk0 + q;
     // W_k = [Vt[:rk0]; kick]  ([rk][4][s])
@@ -358,6 +365,7 @@ void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     W.pos = k - 1;
   }
   c.sync();
+  return capped;
 }
 
 namespace {
@@ -513,91 +521,107 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
   return true;
 }
 
-// Restarted GMRES with classical Gram-Schmidt applied twice (CGS2).  The
-// Hessenberg least-squares problem (size <= restart) is updated with Givens
-// rotations on the host after each Arnoldi step, whose convergence decision
-// needs the residual estimate there anyway.
-int solve_gmres(LocalKKT& K, const double* f, double* u, double rtol, int restart, int maxit, double* rel_res,
-                Ctx& c) {
+// Raw (not inverted) block-Jacobi blocks of the reduced local system.
+void build_block_jacobi(LocalKKT& K, BlockJacobi& bj, Ctx& c) {
+  const NewtonSys& sys = *K.sys;
+  auto op = [&](int o) {
+    const TT* t = sys.ops[o];
+    const int key = K.key_of_op[o];
+    return BlockJacobi::Op{K.envs->L[key][K.k].get(), t->core(K.k), K.envs->R[key][K.k].get(), t->r[K.k],
+                           t->r[K.k + 1]};
+  };
+  const int L = K.L;
+  const double sg = sys.sense;
+  bj.init(K.r, K.s, 4, L, c);
+  BlockJacobi::Op o1 = op(OP_AEQ);
+  bj.add(0, 0, -1.0, &o1, 1, c);
+  o1 = op(OP_KY);
+  bj.add(0, 1, 1.0, &o1, 1, c);
+  o1 = op(OP_LZ);
+  bj.add(L - 1, 0, 1.0, &o1, 1, c);
+  BlockJacobi::Op ch[2] = {op(OP_AEQT), op(OP_LX)};
+  bj.add(L - 1, 1, 1.0, ch, 2, c);
+  if (sys.ineq) {
+    o1 = op(OP_TA);
+    bj.add(1, 0, -sg, &o1, 1, c);
+    o1 = op(OP_DK);
+    bj.add(1, 2, 1.0, &o1, 1, c);
+    BlockJacobi::Op ch2[2] = {op(OP_AIT), op(OP_LX)};
+    bj.add(L - 1, 2, sg, ch2, 2, c);
+  }
+}
+
+void mlp_context(const LocalKKT& K, const AmenParams& prm, float ctx[4]) {
+  ctx[0] = (float)std::log10(std::max(prm.mu, 1e-300));
+  ctx[1] = (float)K.k / (float)std::max(1, K.W->d);
+  ctx[2] = (float)K.r / 64.f;
+  ctx[3] = (float)K.s / 64.f;
+}
+
+// Matrix-free local solve by restarted GMRES (krylov.hip): optionally right
+// preconditioned by the block-Jacobi inverse of the (a, b) diagonal blocks of
+// the reduced system, or by the learned correction of it (MLP), and in mixed
+// mode with BF16-operand Arnoldi products and FP64 residual refinement at
+// every restart.  Fallback rule of the MLP preconditioner: at each core the
+// first solve of an AMEn call uses block Jacobi and records its iteration
+// count; later solves try the MLP with that count as the iteration budget and
+// redo the solve with block Jacobi when it is not met.
+int solve_gmres(LocalKKT& K, const double* f, double* u, const AmenParams& prm, std::vector<int>& bj_ref,
+                AmenInfo& info, double* rel_res, Ctx& c) {
   const long n = (long)K.L * K.p;
-  const int m = std::max(1, restart);
-  DevBuf V((size_t)(m + 1) * n), w(n), r0(n), h(m + 2), h2(m + 2), yv(m + 1);
-  c.dot_part.reserve(mdot_part_size(m + 1));
-  const double bnorm = dev_norm(f, n, c);
-  if (bnorm == 0.0) {
-    fill(n, 0.0, u, c.s);
-    *rel_res = 0.0;
-    return 0;
+  KrylovOps ops;
+  ops.matvec = [&](const double* x, double* y, bool low) {
+    c.prec = low ? GemmPrec::BF16 : GemmPrec::F64;
+    K.matvec(x, y, c);
+    c.prec = GemmPrec::F64;
+  };
+  KrylovParams kp;
+  kp.rtol = std::max(prm.tol * 0.1, 1e-14);
+  kp.restart = prm.gmres_restart;
+  kp.maxit = prm.gmres_maxit;
+  kp.mixed = prm.mixed;
+  KrylovInfo ki;
+  if (prm.precond == TT_PREC_NONE) {
+    gmres_solve(n, ops, f, u, kp, ki, c);
+    *rel_res = ki.rel_res;
+    return ki.iters;
   }
-  int it_total = 0;
-  double rel = 1.0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
-  double* hh = c.host(m + 2);
-  while (true) {
-    K.matvec(u, r0.get(), c);
-    axpby(n, 1.0, f, -1.0, r0.get(), c.s);   // r0 = f - K u
-    const double beta = dev_norm(r0.get(), n, c);
-    rel = beta / bnorm;
-    if (rel <= rtol || it_total >= maxit) break;
-    axpby(n, 1.0 / beta, r0.get(), 0.0, V.get(), c.s);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int j = 0;
-    for (; j < m && it_total < maxit; ++j, ++it_total) {
-      double* vj1 = V.get() + (size_t)(j + 1) * n;
-      K.matvec(V.get() + (size_t)j * n, vj1, c);
-      // CGS2
-      mdot(n, j + 1, V.get(), n, vj1, h.get(), c.dot_part.get(), c.s);
-      gemv_update(n, j + 1, V.get(), n, h.get(), -1.0, vj1, c.s);
-      mdot(n, j + 1, V.get(), n, vj1, h2.get(), c.dot_part.get(), c.s);
-      gemv_update(n, j + 1, V.get(), n, h2.get(), -1.0, vj1, c.s);
-      axpby(j + 1, 1.0, h2.get(), 1.0, h.get(), c.s);
-      mdot(n, 1, vj1, n, vj1, h.get() + j + 1, c.dot_part.get(), c.s);
-      TT_HIP(hipMemcpyAsync(hh, h.get(), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.s));
-      c.sync();
-      double hn = std::sqrt(std::max(hh[j + 1], 0.0));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
-      H[(size_t)(j + 1) * m + j] = hn;
-      if (hn > 0.0) axpby(n, 0.0, vj1, 1.0 / hn, vj1, c.s);
-      // apply previous rotations to column j
-      for (int i = 0; i < j; ++i) {
-        double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-      }
-      double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
-      double rr = std::hypot(a, b);
-      cs[j] = (rr == 0.0) ? 1.0 : a / rr;
-      sn[j] = (rr == 0.0) ? 0.0 : b / rr;
-      H[(size_t)j * m + j] = rr;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      rel = std::fabs(g[j + 1]) / bnorm;
-      if (rel <= rtol || hn == 0.0) { ++j; ++it_total; break; }
+  BlockJacobi raw, bj;
+  build_block_jacobi(K, raw, c);
+  bj.copy_from(raw, c);
+  bj.invert(c);
+  ops.precond = [&](const double* x, double* y) { bj.apply(x, y, c); };
+  const bool try_mlp = prm.precond == TT_PREC_MLP && prm.mlp && bj_ref[K.k] > 0;
+  if (try_mlp) {
+    DevBuf u0(n);
+    TT_HIP(hipMemcpyAsync(u0.get(), u, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+    BlockJacobi ml;
+    ml.copy_from(bj, c);
+    float ctx[4];
+    mlp_context(K, prm, ctx);
+    mlp_correct_blocks(*prm.mlp, raw, ml, ctx, c);
+    KrylovOps mops = ops;
+    mops.precond = [&](const double* x, double* y) { ml.apply(x, y, c); };
+    KrylovParams mp = kp;
+    mp.maxit = std::min(kp.maxit, bj_ref[K.k]);
+    gmres_solve(n, mops, f, u, mp, ki, c);
+    if (ki.rel_res <= kp.rtol) {
+      info.mlp_used++;
+      *rel_res = ki.rel_res;
+      return ki.iters;
     }
-    // back substitution H y = g
-    std::vector<double> y(j, 0.0);
-    for (int i = j - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int l = i + 1; l < j; ++l) acc -= H[(size_t)i * m + l] * y[l];
-      y[i] = (H[(size_t)i * m + i] != 0.0) ? acc / H[(size_t)i * m + i] : 0.0;
-    }
-    if (j > 0) {
-      TT_HIP(hipMemcpyAsync(yv.get(), y.data(), sizeof(double) * j, hipMemcpyHostToDevice, c.s));
-      gemv_update(n, j, V.get(), n, yv.get(), 1.0, u, c.s);
-      c.sync();   // y (host) is released at scope end
-    }
-    if (rel <= rtol || it_total >= maxit) {
-      // confirm with the true residual
-      K.matvec(u, r0.get(), c);
-      axpby(n, 1.0, f, -1.0, r0.get(), c.s);
-      rel = dev_norm(r0.get(), n, c) / bnorm;
-      if (rel <= rtol * 1.0000001 || it_total >= maxit) break;
-    }
+    info.mlp_fallbacks++;
+    TT_HIP(hipMemcpyAsync(u, u0.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+    const int spent = ki.iters;
+    gmres_solve(n, ops, f, u, kp, ki, c);
+    bj_ref[K.k] = std::max(1, ki.iters);
+    *rel_res = ki.rel_res;
+    return ki.iters + spent;
   }
-  *rel_res = rel;
-  return it_total;
+  gmres_solve(n, ops, f, u, kp, ki, c);
+  bj_ref[K.k] = std::max(1, ki.iters);
+  *rel_res = ki.rel_res;
+  return ki.iters;
 }
 
 __global__ void stack_dz_kernel(double* dz, const double* tmp, const double* rd, long p) {
@@ -696,6 +720,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   info.krylov_iters = 0;
   std::vector<DevBuf> Rhat(4);
   DevBuf f, u, Ku, dz;
+  std::vector<int> bj_ref(d, 0);   // block-Jacobi Krylov counts per core (MLP fallback budget)
   for (int sweep = 0; sweep < prm.max_sweeps; ++sweep) {
     double max_res = 0.0;
     for (int step = 0; step < d; ++step) {
@@ -748,6 +773,20 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       const double fn = dev_norm(f.get(), n, c);
       const double res0 = dev_norm(Ku.get(), n, c) / (fn > 0 ? fn : 1.0);
       max_res = std::max(max_res, res0);
+      if (prm.mlp && prm.collect_probes > 0 && prm.mlp->ds_N < prm.collect_cap && fn > 0.0) {
+        // the local systems the solver emits, as training data of the learned preconditioner
+        BlockJacobi raw, inv;
+        build_block_jacobi(K, raw, c);
+        inv.copy_from(raw, c);
+        inv.invert(c);
+        float ctx[4];
+        mlp_context(K, prm, ctx);
+        FBuf F, Rr, Y, S, Wt;
+        mlp_block_data(raw, inv, [&](const double* x, double* y) { K.matvec(x, y, c); }, ctx, prm.collect_probes,
+                       prm.seed * 7ull + (unsigned long long)(sweep * 131 + k), F, Rr, Y, S, Wt, c);
+        const MlpBatch mb{K.r * K.s, prm.collect_probes, L * 4, F.get(), Rr.get(), Y.get(), S.get(), Wt.get()};
+        if (prm.mlp->out == mb.n * mb.n) prm.mlp->append(mb, prm.collect_cap, c);
+      }
       double ts = now();
       if (fn == 0.0) {
         fill(n, 0.0, u.get(), c.s);
@@ -758,8 +797,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
         if (!ok) solve_direct(K, f.get(), u.get(), c);
       } else {
         double rel = 0.0;
-        int its = solve_gmres(K, f.get(), u.get(), std::max(prm.tol * 0.1, 1e-14), prm.gmres_restart,
-                              prm.gmres_maxit, &rel, c);
+        int its = solve_gmres(K, f.get(), u.get(), prm, bj_ref, info, &rel, c);
         info.krylov_iters += its;
       }
       // dZ_k = Aeq^T^ y (+ s Aineq^T^ t) - R_d^
@@ -777,7 +815,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       // move the block index and extend the environments
       if (dir > 0 && k < d - 1) {
         double t1 = now();
-        split_block(W, +1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
+        info.capped |= split_block(W, +1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
                     prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k));
         info.t_svd += now() - t1;
         t1 = now();
@@ -786,7 +824,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
         info.t_env += now() - t1;
       } else if (dir < 0 && k > 0) {
         double t1 = now();
-        split_block(W, -1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
+        info.capped |= split_block(W, -1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
                     prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k) + 7777ull);
         info.t_svd += now() - t1;
         t1 = now();

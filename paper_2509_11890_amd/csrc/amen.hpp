@@ -52,7 +52,7 @@ struct BlockTT {
 // SVD of the component-normalised block core (relative tolerance, rank cap).
 // kick > 0 appends that many seeded random orthonormal directions to the kept
 // factor (enrichment), within the rank cap.
-void split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick = 0,
+bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick = 0,
                  unsigned long long seed = 0);
 // Norm of a device vector (deterministic; synchronises).
 double dev_norm(const double* x, long n, Ctx& c);
@@ -70,6 +70,10 @@ struct AmenParams {
   unsigned long long seed = 0;
   int verbose = 0;          // >= 2: one line per sweep to stderr
   int kick_sweeps = 1 << 30; // enrichment only in the first kick_sweeps half-sweeps
+  struct Mlp* mlp = nullptr;  // learned preconditioner (precond == TT_PREC_MLP) and dataset sink
+  int collect_probes = 0;    // > 0: add every local system's blocks to mlp's dataset
+  long collect_cap = 0;
+  double mu = 1.0;           // barrier parameter (a context feature of the MLP)
 };
 
 struct AmenInfo {
@@ -77,6 +81,8 @@ struct AmenInfo {
   int krylov_iters = 0;
   int max_rank = 0;
   double last_max_res = 0.0;
+  bool capped = false;      // some split was limited by the rank cap (not by the tolerance)
+  int mlp_used = 0, mlp_fallbacks = 0;
   double t_env = 0, t_solve = 0, t_svd = 0;
 };
 

@@ -11,6 +11,8 @@
 #include "../../include/ttipm.h"
 #include "amen.hpp"
 #include "blocked.hpp"
+#include "krylov.hpp"
+#include "mlp.hpp"
 #include "dense.hpp"
 #include "ipm.hpp"
 #include "ttops.hpp"
@@ -140,6 +142,7 @@ namespace {
 void check_local_op(const tt_local_op* K) {
   if (!K || K->r < 1 || K->rp < 1 || K->m < 1 || K->L < 1 || K->nblocks < 0 || (K->nblocks && !K->blocks))
     throw Error(TT_ERR_ARG, "invalid tt_local_op");
+  if (K->precision != TTIPM_F64 && K->precision != TTIPM_MIXED) throw Error(TT_ERR_ARG, "tt_local_op precision");
   for (int b = 0; b < K->nblocks; ++b) {
     const tt_local_block& B = K->blocks[b];
     if (B.row < 0 || B.row >= K->L || B.col < 0 || B.col >= K->L) throw Error(TT_ERR_ARG, "block position");
@@ -188,8 +191,9 @@ int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stre
     check_local_op(K);
     if (!x || !y) throw Error(TT_ERR_ARG, "NULL vector");
     Ctx& c = ctx_for(stream);
-    c.prec = GemmPrec::F64;
+    c.prec = K->precision == TTIPM_MIXED ? GemmPrec::BF16 : GemmPrec::F64;
     generic_matvec(K, x, y, c);
+    c.prec = GemmPrec::F64;
     c.sync();   // local scratch (permuted cores) is released on return
     return TT_OK;
   });
@@ -233,81 +237,69 @@ int tt_local_solve(const tt_local_op* K, const double* rhs, double* x, const tt_
       inf.method_used = method;
       inf.iters = 0;
     } else {
-      // restarted GMRES (CGS2) on the generic operator
-      const int m = std::max(1, p->restart);
-      DevBuf V((size_t)(m + 1) * n), r0(n), h(m + 2), h2(m + 2), yv(m + 1);
-      c.dot_part.reserve(mdot_part_size(m + 1));
-      const double bn = dev_norm(rhs, n, c);
-      int it = 0;
-      double rel = 0.0;
-      std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
-      double* hh = c.host(m + 2);
-      if (bn == 0.0) {
-        fill(n, 0.0, x, c.s);
-      } else {
-        while (true) {
-          generic_matvec(K, x, r0.get(), c);
-          axpby(n, 1.0, rhs, -1.0, r0.get(), c.s);
-          const double beta = dev_norm(r0.get(), n, c);
-          rel = beta / bn;
-          if (rel <= p->rtol || it >= p->maxit) break;
-          axpby(n, 1.0 / beta, r0.get(), 0.0, V.get(), c.s);
-          std::fill(g.begin(), g.end(), 0.0);
-          g[0] = beta;
-          int j = 0;
-          for (; j < m && it < p->maxit; ++j, ++it) {
-            double* v1 = V.get() + (size_t)(j + 1) * n;
-            generic_matvec(K, V.get() + (size_t)j * n, v1, c);
-            mdot(n, j + 1, V.get(), n, v1, h.get(), c.dot_part.get(), c.s);
-            gemv_update(n, j + 1, V.get(), n, h.get(), -1.0, v1, c.s);
-            mdot(n, j + 1, V.get(), n, v1, h2.get(), c.dot_part.get(), c.s);
-            gemv_update(n, j + 1, V.get(), n, h2.get(), -1.0, v1, c.s);
-            axpby(j + 1, 1.0, h2.get(), 1.0, h.get(), c.s);
-            mdot(n, 1, v1, n, v1, h.get() + j + 1, c.dot_part.get(), c.s);
-            TT_HIP(hipMemcpyAsync(hh, h.get(), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.s));
-            c.sync();
-            const double hn = std::sqrt(std::max(hh[j + 1], 0.0));
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
-            H[(size_t)(j + 1) * m + j] = hn;
-            if (hn > 0.0) axpby(n, 0.0, v1, 1.0 / hn, v1, c.s);
-            for (int i = 0; i < j; ++i) {
-              double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
-              H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
-              H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
-            }
-            double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
-            double rr = std::hypot(a, bb);
-            cs[j] = rr == 0.0 ? 1.0 : a / rr;
-            sn[j] = rr == 0.0 ? 0.0 : bb / rr;
-            H[(size_t)j * m + j] = rr;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            rel = std::fabs(g[j + 1]) / bn;
-            if (rel <= p->rtol || hn == 0.0) { ++j; ++it; break; }
-          }
-          std::vector<double> y(j, 0.0);
-          for (int i = j - 1; i >= 0; --i) {
-            double acc = g[i];
-            for (int l = i + 1; l < j; ++l) acc -= H[(size_t)i * m + l] * y[l];
-            y[i] = H[(size_t)i * m + i] != 0.0 ? acc / H[(size_t)i * m + i] : 0.0;
-          }
-          if (j > 0) {
-            TT_HIP(hipMemcpyAsync(yv.get(), y.data(), sizeof(double) * j, hipMemcpyHostToDevice, c.s));
-            gemv_update(n, j, V.get(), n, yv.get(), 1.0, x, c.s);
-            c.sync();
-          }
-          if (it >= p->maxit) {
-            generic_matvec(K, x, r0.get(), c);
-            axpby(n, 1.0, rhs, -1.0, r0.get(), c.s);
-            rel = dev_norm(r0.get(), n, c) / bn;
-            break;
-          }
+      // restarted GMRES (CGS2), right-preconditioned; mixed: BF16 Arnoldi products, FP64 refinement
+      const bool mixed = p->precision == TTIPM_MIXED;
+      BlockJacobi bj;
+      KrylovOps ops;
+      ops.matvec = [&](const double* xv, double* yv, bool low) {
+        c.prec = low ? GemmPrec::BF16 : GemmPrec::F64;
+        generic_matvec(K, xv, yv, c);
+        c.prec = GemmPrec::F64;
+      };
+      inf.precond_used = TT_PREC_NONE;
+      KrylovParams kp;
+      kp.rtol = p->rtol;
+      kp.restart = std::max(1, p->restart);
+      kp.maxit = std::max(0, p->maxit);
+      kp.mixed = mixed;
+      KrylovInfo ki;
+      if (p->precond == TT_PREC_BJACOBI || p->precond == TT_PREC_MLP) {
+        if (p->precond == TT_PREC_MLP && !p->mlp) throw Error(TT_ERR_ARG, "TT_PREC_MLP needs an mlp handle");
+        BlockJacobi raw;
+        raw.init(K->r, K->rp, K->m, K->L, c);
+        for (int b = 0; b < K->nblocks; ++b) {
+          const tt_local_block& B = K->blocks[b];
+          BlockJacobi::Op ch[2];
+          for (int q = 0; q < B.nchain; ++q) ch[q] = {B.op[q].phiL, B.op[q].core, B.op[q].phiR, B.op[q].R, B.op[q].Rp};
+          raw.add(B.row, B.col, B.coeff, ch, B.nchain, c);
         }
+        bj.copy_from(raw, c);
+        bj.invert(c);
+        ops.precond = [&](const double* xv, double* yv) { bj.apply(xv, yv, c); };
+        if (p->precond == TT_PREC_MLP) {
+          // Fallback rule: the MLP preconditioner is kept only if it needs no
+          // more Krylov iterations and reaches no worse a residual than block
+          // Jacobi from the same initial guess.
+          DevBuf x0(n), xb(n);
+          TT_HIP(hipMemcpyAsync(x0.get(), x, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+          TT_HIP(hipMemcpyAsync(xb.get(), x, sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+          KrylovInfo kb;
+          gmres_solve(n, ops, rhs, xb.get(), kp, kb, c);
+          BlockJacobi ml;
+          ml.copy_from(bj, c);
+          mlp_correct_blocks(const_cast<tt_mlp*>(static_cast<const tt_mlp*>(p->mlp))->net, raw, ml, p->context, c);
+          KrylovOps mops = ops;
+          mops.precond = [&](const double* xv, double* yv) { ml.apply(xv, yv, c); };
+          gmres_solve(n, mops, rhs, x, kp, ki, c);
+          const bool mlp_ok = ki.iters <= kb.iters && ki.rel_res <= std::max(kb.rel_res, p->rtol);
+          if (mlp_ok) {
+            inf.precond_used = TT_PREC_MLP;
+          } else {
+            TT_HIP(hipMemcpyAsync(x, xb.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
+            ki = kb;
+            inf.precond_used = TT_PREC_BJACOBI;
+          }
+          c.sync();
+        } else {
+          gmres_solve(n, ops, rhs, x, kp, ki, c);
+          inf.precond_used = TT_PREC_BJACOBI;
+        }
+      } else {
+        gmres_solve(n, ops, rhs, x, kp, ki, c);
       }
       inf.method_used = TT_SOLVE_GMRES;
-      inf.iters = it;
-      inf.rel_res = rel;
+      inf.iters = ki.iters;
+      inf.rel_res = ki.rel_res;
     }
     // true residual in FP64
     if (inf.method_used != TT_SOLVE_GMRES) {
@@ -317,7 +309,6 @@ int tt_local_solve(const tt_local_op* K, const double* rhs, double* x, const tt_
       const double bn = dev_norm(rhs, n, c);
       inf.rel_res = bn > 0 ? dev_norm(r0.get(), n, c) / bn : 0.0;
     }
-    inf.precond_used = TT_PREC_NONE;
     if (info) *info = inf;
     c.sync();
     return (inf.rel_res <= p->rtol || inf.method_used != TT_SOLVE_GMRES) ? TT_OK : TT_ERR_NOT_CONVERGED;
@@ -367,9 +358,11 @@ void ttipm_params_default(ttipm_params* p) {
   p->eig_rank = 6;
   p->eig_sweeps = 2;
   p->verbose = 0;
-  p->kick = 0;
+  p->kick = 2;
   p->seed = 12345;
   p->kick_sweeps = 1 << 30;
+  p->collect_probes = 0;
+  p->collect_cap = 1 << 20;
 }
 
 int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {
@@ -516,6 +509,136 @@ int ttipm_state_export(const ttipm_state* s, int32_t which, int32_t* ranks_out, 
       off += (size_t)t->core_size(k);
     }
     c.sync();
+    return TT_OK;
+  });
+}
+
+int tt_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, int32_t seed, tt_mlp** out) {
+  return guarded([&]() -> int {
+    if (!out) throw Error(TT_ERR_ARG, "out is NULL");
+    if (in_dim < 1 || hidden < 1 || out_dim < 1) throw Error(TT_ERR_ARG, "network dimensions");
+    auto m = std::make_unique<tt_mlp>();
+    Ctx& c = ctx_for(nullptr);
+    m->net.init(in_dim, hidden, out_dim, (unsigned long long)(unsigned)seed, c);
+    *out = m.release();
+    return TT_OK;
+  });
+}
+
+void tt_mlp_destroy(tt_mlp* m) { delete m; }
+
+int64_t tt_mlp_num_params(const tt_mlp* m) { return m ? (int64_t)m->net.nparams : 0; }
+
+int tt_mlp_get_params(const tt_mlp* m, float* host, int64_t count) {
+  return guarded([&]() -> int {
+    if (!m || !host || count != m->net.nparams) throw Error(TT_ERR_ARG, "parameter buffer");
+    Ctx& c = ctx_for(nullptr);
+    TT_HIP(hipMemcpyAsync(host, m->net.params.get(), sizeof(float) * count, hipMemcpyDeviceToHost, c.s));
+    c.sync();
+    return TT_OK;
+  });
+}
+
+int tt_mlp_set_params(tt_mlp* m, const float* host, int64_t count) {
+  return guarded([&]() -> int {
+    if (!m || !host || count != m->net.nparams) throw Error(TT_ERR_ARG, "parameter buffer");
+    Ctx& c = ctx_for(nullptr);
+    TT_HIP(hipMemcpyAsync(m->net.params.get(), host, sizeof(float) * count, hipMemcpyHostToDevice, c.s));
+    c.sync();
+    return TT_OK;
+  });
+}
+
+static MlpBatch as_batch(const tt_mlp_batch* b, const tt_mlp* m) {
+  MlpBatch mb;
+  if (b) {
+    if (b->N < 1 || b->P < 1 || b->n < 1 || !b->F || !b->R || !b->Y || !b->S || !b->W)
+      throw Error(TT_ERR_ARG, "invalid tt_mlp_batch");
+    mb = MlpBatch{b->N, b->P, b->n, b->F, b->R, b->Y, b->S, b->W};
+  } else {
+    const Mlp& net = m->net;
+    if (net.ds_N < 1) throw Error(TT_ERR_ARG, "the collected dataset is empty");
+    mb = MlpBatch{(int)net.ds_N, net.ds_P, net.ds_n, net.dsF.get(), net.dsR.get(), net.dsY.get(), net.dsS.get(),
+                  net.dsW.get()};
+  }
+  if (mb.n * mb.n != m->net.out || mb.n * mb.n + 4 != m->net.in)
+    throw Error(TT_ERR_ARG, "batch block size does not match the network (in = n*n + 4, out = n*n)");
+  return mb;
+}
+
+int tt_mlp_loss_grad(tt_mlp* m, const tt_mlp_batch* b, double* loss, float* grad_host, void* stream) {
+  return guarded([&]() -> int {
+    if (!m) throw Error(TT_ERR_ARG, "mlp is NULL");
+    Ctx& c = ctx_for(stream);
+    const MlpBatch mb = as_batch(b, m);
+    const double l = m->net.loss_grad(mb, c);
+    if (loss) *loss = l;
+    if (grad_host) {
+      TT_HIP(hipMemcpyAsync(grad_host, m->net.grad.get(), sizeof(float) * m->net.nparams, hipMemcpyDeviceToHost, c.s));
+      c.sync();
+    }
+    return TT_OK;
+  });
+}
+
+int tt_mlp_collect(tt_mlp* m, const tt_local_op* K, const float* context, int32_t nprobe, int32_t seed, int64_t cap,
+                   void* stream) {
+  return guarded([&]() -> int {
+    if (!m) throw Error(TT_ERR_ARG, "mlp is NULL");
+    check_local_op(K);
+    if (nprobe < 1) throw Error(TT_ERR_ARG, "nprobe must be >= 1");
+    Ctx& c = ctx_for(stream);
+    c.prec = GemmPrec::F64;
+    const int n = K->L * K->m;
+    if (n * n != m->net.out || n * n + 4 != m->net.in) throw Error(TT_ERR_ARG, "block size does not match the network");
+    BlockJacobi raw, inv;
+    raw.init(K->r, K->rp, K->m, K->L, c);
+    for (int b = 0; b < K->nblocks; ++b) {
+      const tt_local_block& B = K->blocks[b];
+      BlockJacobi::Op ch[2];
+      for (int q = 0; q < B.nchain; ++q) ch[q] = {B.op[q].phiL, B.op[q].core, B.op[q].phiR, B.op[q].R, B.op[q].Rp};
+      raw.add(B.row, B.col, B.coeff, ch, B.nchain, c);
+    }
+    inv.copy_from(raw, c);
+    inv.invert(c);
+    float ctx[4] = {0.f, 0.f, 0.f, 0.f};
+    if (context) for (int q = 0; q < 4; ++q) ctx[q] = context[q];
+    FBuf F, R, Y, S, W;
+    mlp_block_data(raw, inv, [&](const double* xv, double* yv) { generic_matvec(K, xv, yv, c); }, ctx, nprobe,
+                   (unsigned long long)(unsigned)seed, F, R, Y, S, W, c);
+    const MlpBatch mb{K->r * K->rp, nprobe, n, F.get(), R.get(), Y.get(), S.get(), W.get()};
+    m->net.append(mb, cap, c);
+    return TT_OK;
+  });
+}
+
+int tt_mlp_dataset_size(const tt_mlp* m, int64_t* n_blocks) {
+  return guarded([&]() -> int {
+    if (!m || !n_blocks) throw Error(TT_ERR_ARG, "NULL argument");
+    *n_blocks = m->net.ds_N;
+    return TT_OK;
+  });
+}
+
+int tt_mlp_train(tt_mlp* m, const tt_mlp_batch* data, int32_t epochs, int32_t batch, float lr, int32_t seed,
+                 double* loss_hist, void* stream) {
+  return guarded([&]() -> int {
+    if (!m) throw Error(TT_ERR_ARG, "mlp is NULL");
+    if (epochs < 0 || batch < 1 || !(lr > 0.f)) throw Error(TT_ERR_ARG, "training parameters");
+    Ctx& c = ctx_for(stream);
+    const MlpBatch mb = as_batch(data, m);
+    std::vector<double> hist;
+    mlp_train(m->net, mb, epochs, batch, lr, (unsigned long long)(unsigned)seed, hist, c);
+    if (loss_hist) for (int e = 0; e < epochs; ++e) loss_hist[e] = hist[e];
+    return TT_OK;
+  });
+}
+
+int tt_mlp_eval(tt_mlp* m, const tt_mlp_batch* data, double* loss, void* stream) {
+  return guarded([&]() -> int {
+    if (!m || !loss) throw Error(TT_ERR_ARG, "NULL argument");
+    Ctx& c = ctx_for(stream);
+    *loss = m->net.loss_grad(as_batch(data, m), c);
     return TT_OK;
   });
 }

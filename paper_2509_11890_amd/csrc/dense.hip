@@ -129,12 +129,16 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
   }
   __syncthreads();
   const int N = (n % 2) ? n + 1 : n;   // players incl. a dummy when n is odd
+  // 16-lane groups rotate one column pair each (64 pairs in flight per step);
+  // a group is active or idle as a whole, so its shuffles stay inside it.
+  const int gl = threadIdx.x % 16, gid = threadIdx.x / 16;
+  constexpr int NG = DT / 16;
   int sweep = 0;
   for (; sweep < max_sweeps && N > 1; ++sweep) {
     if (threadIdx.x == 0) s_rot = 0;
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
-      for (int pi = w; pi < N / 2; pi += NW) {
+      for (int pi = gid; pi < N / 2; pi += NG) {
         int p, q;
         if (pi == 0) { p = N - 1; q = r; }
         else { p = (r + pi) % (N - 1); q = (r - pi + N - 1) % (N - 1); }
@@ -143,29 +147,34 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
         double* ap = A + (long)p * m;
         double* aq = A + (long)q * m;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += 16) {
           double x = ap[i], y = aq[i];
           al += x * x; be += y * y; ga += x * y;
         }
-        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o);
+          be += __shfl_xor(be, o);
+          ga += __shfl_xor(ga, o);
+        }
         if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
         if (fabs(ga) <= tol * sqrt(al * be)) continue;
         double zeta = (be - al) / (2.0 * ga);
         double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += 16) {
           double x = ap[i], y = aq[i];
           ap[i] = c * x - s * y;
           aq[i] = s * x + c * y;
         }
         double* vp = Vw + (long)p * n;
         double* vq = Vw + (long)q * n;
-        for (int i = lane; i < n; i += 64) {
+        for (int i = gl; i < n; i += 16) {
           double x = vp[i], y = vq[i];
           vp[i] = c * x - s * y;
           vq[i] = s * x + c * y;
         }
-        if (lane == 0) s_rot = 1;
+        if (gl == 0) s_rot = 1;
       }
       __syncthreads();
     }
@@ -398,6 +407,212 @@ void dense_qr_form_q(const double* A, int m, int n, int lda, const double* tau, 
   TT_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Smallest eigenpair of a symmetric p x p row-major matrix B: Lanczos with full
+// (two-pass) reorthogonalisation, restarted from the Ritz vector.  The
+// tridiagonal T_k is solved for its smallest eigenvalue by multisection of the
+// Sturm count (every thread tests one point, so each round shrinks the
+// bracket by the workgroup size) and for its eigenvector by inverse iteration
+// with the positive definite shift theta - delta.  Q (global) holds the
+// Lanczos basis, p x (kmax + 1).  A Lanczos breakdown (invariant subspace)
+// continues with a deterministic pseudo-random vector orthogonal to the basis,
+// so an eigenvector orthogonal to the start vector is not missed.
+// ---------------------------------------------------------------------------
+constexpr int LZ_MAX = 256;
+
+__device__ __forceinline__ double lz_pseudo(int i, int j) {
+  double x = sin(12.9898 * (i + 1) + 78.233 * (j + 1)) * 43758.5453;
+  return x - floor(x) - 0.5;
+}
+
+// number of eigenvalues of the symmetric tridiagonal (a, b) below x
+__device__ int lz_sturm(const double* a, const double* b, int k, double x) {
+  int cnt = 0;
+  double dd = 1.0;
+  for (int i = 0; i < k; ++i) {
+    const double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
+    dd = a[i] - x - ((i > 0) ? bb / dd : 0.0);
+    if (dd == 0.0) dd = -1e-300;
+    if (dd < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p, int kmax, int restarts, double tol,
+                                                         double* Q, double* v, double* lam_out) {
+  __shared__ double al[LZ_MAX], be[LZ_MAX], y[LZ_MAX], h[LZ_MAX];
+  __shared__ double red[NW];
+  __shared__ double s_theta, s_lo, s_hi, s_bnorm;
+  __shared__ int s_first;
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  // start vector
+  for (int i = tid; i < p; i += DT) v[i] = 1.0 + 0.25 * lz_pseudo(i, 0);
+  __syncthreads();
+  // Frobenius norm of B (scale for tolerances)
+  {
+    double part = 0.0;
+    for (long t = tid; t < (long)p * p; t += DT) part += B[t] * B[t];
+    const double f = block_sum(part, red);
+    if (tid == 0) s_bnorm = sqrt(f) + 1e-300;
+  }
+  __syncthreads();
+  double theta = 0.0;
+  for (int rs = 0; rs <= restarts; ++rs) {
+    // q_0 = v / |v|
+    double part = 0.0;
+    for (int i = tid; i < p; i += DT) part += v[i] * v[i];
+    const double nv = sqrt(block_sum(part, red));
+    for (int i = tid; i < p; i += DT) Q[i] = v[i] / nv;
+    __syncthreads();
+    int k = 0;
+    for (int j = 0; j < kmax; ++j) {
+      double* qj = Q + (long)j * p;
+      double* wv = Q + (long)(j + 1) * p;
+      // w = B q_j, one wave per row
+      for (int i = w; i < p; i += NW) {
+        const double* row = B + (long)i * p;
+        double acc = 0.0;
+        for (int c = lane; c < p; c += 64) acc += row[c] * qj[c];
+        acc = wave_sum(acc);
+        if (lane == 0) wv[i] = acc;
+      }
+      __syncthreads();
+      // two passes of classical Gram-Schmidt against q_0 .. q_j
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int t = w; t <= j; t += NW) {
+          const double* qt = Q + (long)t * p;
+          double acc = 0.0;
+          for (int i = lane; i < p; i += 64) acc += qt[i] * wv[i];
+          acc = wave_sum(acc);
+          if (lane == 0) h[t] = acc;
+        }
+        __syncthreads();
+        if (pass == 0 && tid == 0) al[j] = h[j];
+        for (int i = tid; i < p; i += DT) {
+          double acc = wv[i];
+          for (int t = 0; t <= j; ++t) acc -= Q[(long)t * p + i] * h[t];
+          wv[i] = acc;
+        }
+        __syncthreads();
+      }
+      part = 0.0;
+      for (int i = tid; i < p; i += DT) part += wv[i] * wv[i];
+      double bj = sqrt(block_sum(part, red));
+      k = j + 1;
+      if (k >= p) { if (tid == 0) be[j] = 0.0; __syncthreads(); break; }
+      if (bj <= 1e-13 * s_bnorm) {
+        // invariant subspace: continue with a pseudo-random vector orthogonal to the basis
+        for (int i = tid; i < p; i += DT) wv[i] = lz_pseudo(i, j + 1 + 7919 * rs);
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int t = w; t <= j; t += NW) {
+            const double* qt = Q + (long)t * p;
+            double acc = 0.0;
+            for (int i = lane; i < p; i += 64) acc += qt[i] * wv[i];
+            acc = wave_sum(acc);
+            if (lane == 0) h[t] = acc;
+          }
+          __syncthreads();
+          for (int i = tid; i < p; i += DT) {
+            double acc = wv[i];
+            for (int t = 0; t <= j; ++t) acc -= Q[(long)t * p + i] * h[t];
+            wv[i] = acc;
+          }
+          __syncthreads();
+        }
+        part = 0.0;
+        for (int i = tid; i < p; i += DT) part += wv[i] * wv[i];
+        const double nr = sqrt(block_sum(part, red));
+        for (int i = tid; i < p; i += DT) wv[i] /= nr;
+        if (tid == 0) be[j] = 0.0;
+      } else {
+        for (int i = tid; i < p; i += DT) wv[i] /= bj;
+        if (tid == 0) be[j] = bj;
+      }
+      __syncthreads();
+    }
+    // smallest eigenvalue of T_k by multisection of the Sturm count
+    if (tid == 0) {
+      double lo = 1e300, hi = -1e300;
+      for (int i = 0; i < k; ++i) {
+        const double r = ((i > 0) ? fabs(be[i - 1]) : 0.0) + ((i + 1 < k) ? fabs(be[i]) : 0.0);
+        lo = fmin(lo, al[i] - r);
+        hi = fmax(hi, al[i] + r);
+      }
+      s_lo = lo - 1e-300;
+      s_hi = hi + 1e-300;
+    }
+    __syncthreads();
+    for (int round = 0; round < 8; ++round) {
+      const double lo = s_lo, hi = s_hi;
+      if (!(hi - lo > 1e-15 * (fabs(lo) + fabs(hi)) + 1e-300)) break;
+      if (tid == 0) s_first = DT;
+      __syncthreads();
+      const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(DT + 1);
+      if (lz_sturm(al, be, k, x) >= 1) atomicMin(&s_first, tid);
+      __syncthreads();
+      if (tid == 0) {
+        const int f = s_first;
+        const double xf = (f < DT) ? lo + (hi - lo) * (double)(f + 1) / (double)(DT + 1) : hi;
+        const double xp = (f > 0) ? lo + (hi - lo) * (double)f / (double)(DT + 1) : lo;
+        s_lo = xp;
+        s_hi = xf;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      theta = 0.5 * (s_lo + s_hi);
+      s_theta = theta;
+      // inverse iteration on T - (theta - delta) I (positive definite)
+      double tn = 0.0;
+      for (int i = 0; i < k; ++i) tn = fmax(tn, fabs(al[i]) + ((i > 0) ? fabs(be[i - 1]) : 0.0) + fabs(be[i]));
+      const double sh = theta - (1e-12 * tn + 1e-300);
+      for (int i = 0; i < k; ++i) y[i] = 1.0;
+      for (int it = 0; it < 3; ++it) {
+        // LDL^T of the tridiagonal T - sh I, then solve in place (h holds D, reuse be for L)
+        double dprev = al[0] - sh;
+        h[0] = dprev;
+        for (int i = 1; i < k; ++i) {
+          const double l = be[i - 1] / dprev;
+          dprev = al[i] - sh - l * be[i - 1];
+          if (dprev == 0.0) dprev = 1e-300;
+          h[i] = dprev;
+        }
+        for (int i = 1; i < k; ++i) y[i] -= (be[i - 1] / h[i - 1]) * y[i - 1];
+        for (int i = 0; i < k; ++i) y[i] /= h[i];
+        for (int i = k - 2; i >= 0; --i) y[i] -= (be[i] / h[i]) * y[i + 1];
+        double nn = 0.0;
+        for (int i = 0; i < k; ++i) nn += y[i] * y[i];
+        nn = sqrt(nn) + 1e-300;
+        for (int i = 0; i < k; ++i) y[i] /= nn;
+      }
+    }
+    __syncthreads();
+    theta = s_theta;
+    // Ritz vector v = Q_k y and its residual |B v - theta v|
+    for (int i = tid; i < p; i += DT) {
+      double acc = 0.0;
+      for (int t = 0; t < k; ++t) acc += Q[(long)t * p + i] * y[t];
+      v[i] = acc;
+    }
+    __syncthreads();
+    part = 0.0;
+    for (int i = w; i < p; i += NW) {
+      const double* row = B + (long)i * p;
+      double acc = 0.0;
+      for (int c = lane; c < p; c += 64) acc += row[c] * v[c];
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        const double r = acc - theta * v[i];
+        part += r * r;
+      }
+    }
+    const double res = sqrt(block_sum(part, red));
+    if (res <= tol * s_bnorm || k >= p) break;
+  }
+  if (tid == 0) lam_out[0] = theta;
+}
+
 // Dynamic LDS available to the Jacobi kernel: the device's per-workgroup limit
 // (queried once) minus the kernel's static shared memory, opted in with
 // hipFuncSetAttribute when above the 64 KiB default.
@@ -433,6 +648,13 @@ void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, dou
                        max_sweeps, tol, iwork + n);
   }
   prof_end(tok, s);
+  TT_HIP(hipGetLastError());
+}
+
+void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* work, hipStream_t s, int kmax,
+                       int restarts, double tol) {
+  kmax = std::max(1, std::min({kmax, p, LZ_MAX - 1}));
+  hipLaunchKernelGGL(lanczos_min_kernel, dim3(1), dim3(DT), 0, s, B, p, kmax, restarts, tol, work, v, lam);
   TT_HIP(hipGetLastError());
 }
 

@@ -15,6 +15,11 @@ void dense_qr_form_q(const double* A, int m, int n, int lda, const double* tau, 
 // work >= n*n doubles, iwork >= n + 1 ints (iwork[n] = sweeps used).
 void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, double* work, int* iwork,
                hipStream_t s, int max_sweeps = 40, double tol = 4e-16);
+// Smallest eigenpair of a symmetric row-major p x p matrix B (restarted Lanczos
+// with full reorthogonalisation): v (p, unit norm), lam (1 double, device).
+// work >= p * (min(kmax, p) + 1) doubles.
+void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* work, hipStream_t s,
+                       int kmax = 128, int restarts = 8, double tol = 1e-12);
 // LU with partial pivoting; solves A X = B in place (row-major).  status[0] != 0 on a zero pivot.
 void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s);
 // Cholesky (lower, row-major, in place).  status[0] = j+1 if not positive definite.

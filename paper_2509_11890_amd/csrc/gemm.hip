@@ -113,47 +113,120 @@ __device__ __forceinline__ void store_tile(const KArgs& g, int bidx, int slice, 
       }
 }
 
+// FP64 kernel, templated on the MFMA tiles per wave (WM x WN of 16 x 16): the
+// workgroup tile is (32 WM) x (32 WN).  The next k-tile is fetched into
+// registers while the current one is consumed from LDS (two LDS buffers, one
+// barrier per k-step), so global latency overlaps the MFMA work.  Workgroups
+// are dispatched round-robin over the eight XCDs; tiles are renumbered so that
+// each XCD works on a contiguous run of output tiles (shared A row panels and
+// B column panels stay in that XCD's L2).
+template <int WM, int WN>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
-  __shared__ double As[BK][BM + PAD];
-  __shared__ double Bs[BK][BN + PAD];
+  constexpr int TM = 32 * WM, TN = 32 * WN;
+  constexpr int NA = TM * BK / 256, NB = BK * TN / 256;
+  __shared__ double As[2][BK][TM + PAD];
+  __shared__ double Bs[2][BK][TN + PAD];
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  // XCD-aware renumbering of the (m, n) tile grid
+  const int gmt = gridDim.x, gnt = gridDim.y;
+  const int tiles = gmt * gnt;
+  const int lin = blockIdx.y * gmt + blockIdx.x;
+  int t = lin;
+  if (tiles >= 16) {
+    const int per = (tiles + 7) / 8;
+    const int cand = (lin % 8) * per + lin / 8;
+    // keep the map a bijection when tiles is not a multiple of 8
+    t = (tiles % 8 == 0) ? cand : lin;
+  }
+  const int tm = t / gnt, tn = t % gnt;
+  const int m0 = tm * TM, n0 = tn * TN;
   const int bidx = blockIdx.z / g.kslices, slice = blockIdx.z % g.kslices;
   const int kbeg = slice * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
   const double* A = g.A + (long)bidx * g.sA;
   const double* B = g.B + (long)bidx * g.sB;
-  f64x4 acc[2][2];
+  const bool a_kc = (g.ak == 1), b_kc = (g.bk == 1 && g.bn != 1);
+  double ra[NA], rb[NB];
+  auto fetch = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int e = 0; e < NA; ++e) {
+      const int q = tid + 256 * e;
+      const int m = a_kc ? q / BK : q % TM, k = a_kc ? q % BK : q / TM;
+      const int gm = m0 + m, gk = k0 + k;
+      ra[e] = (gm < g.M && gk < kend) ? A[(long)gm * g.am + (long)gk * g.ak] : 0.0;
+    }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < NB; ++e) {
+      const int q = tid + 256 * e;
+      const int n = b_kc ? q / BK : q % TN, k = b_kc ? q % BK : q / TN;
+      const int gn = n0 + n, gk = k0 + k;
+      rb[e] = (gn < g.N && gk < kend) ? B[(long)gk * g.bk + (long)gn * g.bn] : 0.0;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int q = tid + 256 * e;
+      const int m = a_kc ? q / BK : q % TM, k = a_kc ? q % BK : q / TM;
+      As[buf][k][m] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int q = tid + 256 * e;
+      const int n = b_kc ? q / BK : q % TN, k = b_kc ? q % BK : q / TN;
+      Bs[buf][k][n] = rb[e];
+    }
+  };
+  f64x4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  int buf = 0;
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    load_tile_A<double>(As, A, g.am, g.ak, m0, k0, kend, g.M, tid);
-    load_tile_B<double>(Bs, B, g.bk, g.bn, n0, k0, kend, g.N, tid);
-    __syncthreads();
+    const bool more = k0 + BK < kend;
+    if (more) fetch(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lane / 16;
-      double a0 = As[kr][wm * 32 + (lane % 16)];
-      double a1 = As[kr][wm * 32 + 16 + (lane % 16)];
-      double b0 = Bs[kr][wn * 32 + (lane % 16)];
-      double b1 = Bs[kr][wn * 32 + 16 + (lane % 16)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      double a[WM], b[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[i] = As[buf][kr][wm * (16 * WM) + i * 16 + (lane % 16)];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[j] = Bs[buf][kr][wn * (16 * WN) + j * 16 + (lane % 16)];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
-  double out[2][2][4];
+  // epilogue: f64 MFMA result rows lane/16 + 4e, column lane%16
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) out[i][j][e] = acc[i][j][e];
-  store_tile<true>(g, bidx, slice, m0, n0, wm, wn, lane, out);
+      for (int e = 0; e < 4; ++e) {
+        const int row = m0 + wm * (16 * WM) + i * 16 + (lane / 16) + 4 * e;
+        const int col = n0 + wn * (16 * WN) + j * 16 + (lane % 16);
+        if (row < g.M && col < g.N) {
+          const double v = acc[i][j][e];
+          if (g.kslices > 1) {
+            g.P[(((long)bidx * g.kslices + slice) * g.M + row) * g.N + col] = v;
+          } else {
+            double* c = g.C + (long)bidx * g.sC + (long)row * g.cm + (long)col * g.cn;
+            *c = (g.beta == 0.0) ? g.alpha * v : g.alpha * v + g.beta * (*c);
+          }
+        }
+      }
 }
 
 // BF16 operands, FP32 accumulation: v_mfma_f32_16x16x32_bf16 consumes 8 k-values
@@ -274,7 +347,15 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   g.B = q.B; g.bk = q.bk; g.bn = q.bn; g.sB = q.sB;
   g.C = q.C; g.cm = q.cm; g.cn = q.cn; g.sC = q.sC;
   g.alpha = q.alpha; g.beta = q.beta;
-  const int gm = (q.M + BM - 1) / BM, gn = (q.N + BN - 1) / BN;
+  // FP64 tile shape: 128 x 128 for large outputs, 128 x 64 / 64 x 128 for
+  // skinny ones, 64 x 64 otherwise (BF16 always uses 64 x 64).
+  int TMs = BM, TNs = BN;
+  if (prec == GemmPrec::F64) {
+    if (q.M >= 128 && q.N >= 128) { TMs = 128; TNs = 128; }
+    else if (q.M >= 128) { TMs = 128; TNs = 64; }
+    else if (q.N >= 128) { TMs = 64; TNs = 128; }
+  }
+  const int gm = (q.M + TMs - 1) / TMs, gn = (q.N + TNs - 1) / TNs;
   const long tiles = (long)gm * gn * q.batch;
   // Split K when the output alone cannot fill the 256 CUs and K is long.
   int ks = 1;
@@ -302,8 +383,14 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   const int tok = prof_begin(prec == GemmPrec::BF16 ? PK_GEMM_BF16 : PK_GEMM_F64, stream, flops, bytes);
   if (prec == GemmPrec::BF16)
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
+  else if (TMs == 128 && TNs == 128)
+    hipLaunchKernelGGL((gemm_f64_kernel<4, 4>), grid, dim3(256), 0, stream, g);
+  else if (TMs == 128)
+    hipLaunchKernelGGL((gemm_f64_kernel<4, 2>), grid, dim3(256), 0, stream, g);
+  else if (TNs == 128)
+    hipLaunchKernelGGL((gemm_f64_kernel<2, 4>), grid, dim3(256), 0, stream, g);
   else
-    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, stream, g);
+    hipLaunchKernelGGL((gemm_f64_kernel<2, 2>), grid, dim3(256), 0, stream, g);
   prof_end(tok, stream);
   TT_HIP(hipGetLastError());
   if (ks > 1) {

@@ -2,6 +2,7 @@
 // (ranks, step lengths, stopping) are host logic; every arithmetic operation on
 // TT data runs in the library's kernels.
 #include "ipm.hpp"
+#include "mlp.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -45,16 +46,6 @@ __global__ void symmetrize_kernel(double* A, int n) {
   double v = 0.5 * (A[(long)i * n + j] + A[(long)j * n + i]);
   A[(long)i * n + j] = v;
   A[(long)j * n + i] = v;
-}
-
-__global__ void add_diag_kernel(double* A, int n, double v) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) A[(long)t * n + t] += v;
-}
-
-__global__ void column_kernel(const double* Vcm, int n, int col, double* out) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) out[t] = Vcm[(long)col * n + t];
 }
 
 // Rounding with the spectral shift of Cor. 1: round at tol / (1 + ||S||_F),
@@ -216,24 +207,19 @@ double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c) {
   TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
   c.sync();
   if (hst != 0) throw Error(TT_ERR_NOT_PD, "projected iterate is not positive definite (step length)");
-  DevBuf Bt((size_t)p * p), U((size_t)p * p), S(p), V((size_t)p * p), work((size_t)p * p);
+  DevBuf Bt((size_t)p * p), work((size_t)p * (std::min(p, 128) + 1)), lam(1);
   dense_trsm_lower(Mm, p, D, p, false, c.s);                 // L^{-1} D
   permute(D, Bt.get(), {p, p}, {1, 0}, c.s);                 // (L^{-1} D)^T = D L^{-T}
   dense_trsm_lower(Mm, p, Bt.get(), p, false, c.s);          // L^{-1} D L^{-T}
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, Bt.get(), p);
   TT_HIP(hipGetLastError());
-  const double shift = dev_norm(Bt.get(), (long)p * p, c) + 1e-300;
-  hipLaunchKernelGGL(add_diag_kernel, dim3(nblocks(p, 256)), dim3(256), 0, c.s, Bt.get(), p, shift);
-  TT_HIP(hipGetLastError());
-  c.ired.reserve((size_t)p + 8);
-  dense_svd(Bt.get(), p, p, U.get(), S.get(), V.get(), work.get(), reinterpret_cast<int*>(c.ired.get()), c.s);
-  double smin = 0.0;
-  TT_HIP(hipMemcpyAsync(&smin, S.get() + (p - 1), sizeof(double), hipMemcpyDeviceToHost, c.s));
-  hipLaunchKernelGGL(column_kernel, dim3(nblocks(p, 256)), dim3(256), 0, c.s, V.get(), p, p - 1, e);
-  TT_HIP(hipGetLastError());
-  dense_trsm_lower(Mm, p, e, 1, true, c.s);                  // e = L^{-T} v
+  // smallest eigenpair of the reduced pencil (Lanczos), then e = L^{-T} v
+  dense_sym_min_eig(Bt.get(), p, e, lam.get(), work.get(), c.s, 128);
+  dense_trsm_lower(Mm, p, e, 1, true, c.s);
+  double lmin = 0.0;
+  TT_HIP(hipMemcpyAsync(&lmin, lam.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
   c.sync();
-  return smin - shift;
+  return lmin;
 }
 
 }  // namespace
@@ -344,11 +330,15 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
   return lam_best;
 }
 
+constexpr double kNoBound = 1e6;
+
 double step_length(const TT& M, const TT& dM, BlockTT& E, bool& have_E, const ttipm_params& prm,
                    unsigned long long seed, Ctx& c) {
   const double lam = min_gen_eig(M, dM, E, have_E, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps), seed, c);
-  if (!(lam < 0.0)) return 1.0;
-  return std::min(1.0, -1.0 / lam);
+  // Thm. 1: the largest alpha with M + alpha dM positive definite is -1/lambda_min
+  // when lambda_min < 0 and unbounded otherwise (reported as kNoBound).
+  if (!(lam < 0.0)) return kNoBound;
+  return std::min(kNoBound, -1.0 / lam);
 }
 
 // ---------------------------------------------------------------------------
@@ -463,9 +453,16 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   ap.gmres_maxit = prm.gmres_maxit;
   ap.precond = prm.precond;
   ap.mixed = prm.precision == TTIPM_MIXED;
-  ap.kick = std::max(0, prm.kick);
+  // Random enrichment lets the frame ranks grow past a block-ALS fixed point;
+  // once a Newton frame has been truncated by the rank cap the ranks cannot
+  // grow any more, and enrichment is switched off for the rest of the solve.
+  ap.kick = S.frame_capped ? 0 : std::max(0, prm.kick);
   ap.verbose = prm.verbose;
   ap.kick_sweeps = std::max(0, prm.kick_sweeps);
+  ap.mlp = prm.mlp ? &const_cast<tt_mlp*>(static_cast<const tt_mlp*>(prm.mlp))->net : nullptr;
+  ap.collect_probes = std::max(0, prm.collect_probes);
+  ap.collect_cap = (long)prm.collect_cap;
+  ap.mu = std::max(tt_dot(S.X, S.Z, c) / (P.n + P.q), 1e-300);
   ap.seed = S.seed + 31ull * (unsigned long long)S.iter;
   // --- predictor: affine direction (target mu = 0) ---
   sys.terms = base;
@@ -475,12 +472,14 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   }
   AmenInfo ai_p;
   amen_solve(sys, S.W, ap, ai_p, c);
+  S.frame_capped |= ai_p.capped;
   const int L = sys.L();
   TT dX = S.W.component(0, c), dZ = S.W.component(L, c);
   double t1 = now();
   const unsigned long long sd = S.seed + 7919ull * (unsigned long long)S.iter;
-  double a_p = step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, c);
-  double a_d = step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, c);
+  // affine (predictor) steps: the full Thm. 1 step, clipped to 1
+  double a_p = std::min(1.0, step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, c));
+  double a_d = std::min(1.0, step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, c));
   info.t_step += now() - t1;
   // mu_aff = <X + a_p dX, Z + a_d dZ> / (n + q)
   const double xz = tt_dot(S.X, S.Z, c), xdz = tt_dot(S.X, dZ, c), dxz = tt_dot(dX, S.Z, c),
@@ -507,6 +506,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   if (P.ineq) sys.terms.push_back({RES_T, -sigma * mu, -1, &P.oneT});
   AmenInfo ai_c;
   amen_solve(sys, S.W, ap, ai_c, c);
+  S.frame_capped |= ai_c.capped;
   TT dX2 = S.W.component(0, c), dY2 = S.W.component(1, c), dZ2 = S.W.component(L, c);
   t1 = now();
   info.alpha_p_max = step_length(S.X, dX2, S.EX, S.has_EX, prm, sd + 3, c);
@@ -572,6 +572,8 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   info.sweeps_pred = ai_p.sweeps;
   info.sweeps_corr = ai_c.sweeps;
   info.krylov_iters = ai_p.krylov_iters + ai_c.krylov_iters;
+  info.mlp_used = ai_p.mlp_used + ai_c.mlp_used;
+  info.mlp_fallbacks = ai_p.mlp_fallbacks + ai_c.mlp_fallbacks;
   info.rank_w = std::max(ai_p.max_rank, ai_c.max_rank);
   info.t_env = ai_p.t_env + ai_c.t_env;
   info.t_solve = ai_p.t_solve + ai_c.t_solve;

@@ -34,6 +34,7 @@ struct State {
   TT dX, dY, dZ, dT;                 // last Newton direction (corrector)
   double eta = 1e-3;
   int iter = 0;
+  bool frame_capped = false;         // a Newton frame has reached the rank cap: enrichment is off
   unsigned long long seed = 12345;
 };
 
