@@ -34,8 +34,8 @@ HBM = 8.0e12
 
 WORKLOADS = {
     # name: (instance config, frame rank cap, iterate rank cap)
-    "maxcut_kron_d10": ("maxcut_kron_d10", 32, 128),
-    "maxcut_grid_d5": ("maxcut_grid_d5", 8, 64),
+    "maxcut_kron_d10": ("maxcut_kron_d10", 32, 32),
+    "maxcut_grid_d5": ("maxcut_grid_d5", 8, 8),
 }
 
 
@@ -43,14 +43,19 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="maxcut_kron_d10", choices=sorted(WORKLOADS))
     ap.add_argument("--rank-cap", type=int, default=None, help="override the frame rank cap")
     ap.add_argument("--iter-rank-cap", type=int, default=None, help="override the iterate rank cap")
-    ap.add_argument("--max-iter", type=int, default=60)
+    ap.add_argument("--max-iter", type=int, default=6,
+                    help="IPM iteration limit of a step (the step ends earlier at the gap mark)")
     ap.add_argument("--profile-period", type=int, default=4,
                     help="event-time every n-th launch of the instrumented kernels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip the mixed / learned comparison")
+    ap.add_argument("--contraction-only", action="store_true",
+                    help="only the local-contraction microbenchmarks (and a 256 MiB device copy used to calibrate "
+                         "the HBM byte counters)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -77,6 +82,66 @@ def contraction_rate(P, torch, r, R, reps=50, warm=5):
     flops = 16.0 * r ** 3 * R + 32.0 * r ** 2 * R ** 2
     return {"r": r, "R": R, "dtype": "f64", "us_per_matvec": t * 1e6, "gflop_per_matvec": flops / 1e9,
             "tflops": flops / t / 1e12, "frac_of_peak": flops / t / PEAK["f64"]}
+
+
+def contraction_rate_bf16(P, torch, r, R, reps=50, warm=5):
+    """Same projected matvec with BF16 operands / FP32 accumulation (tt_local_op.precision)."""
+    g = torch.Generator(device="cpu").manual_seed(r * 1000 + R)
+    rnd = lambda *s: torch.randn(*s, generator=g, dtype=torch.float64).cuda()
+    m = 4
+    op = P.ProjOp(rnd(r, R, r), rnd(R, m, m, R), rnd(r, R, r))
+    K = P.LocalOp(r, r, 1, [P.LocalBlock(0, 0, 1.0, [op])], precision=P.TTIPM_MIXED)
+    x = rnd(r * m * r)
+    y = torch.empty_like(x)
+    for _ in range(warm):
+        P.local_matvec(K, x, y)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        P.local_matvec(K, x, y)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    flops = 16.0 * r ** 3 * R + 32.0 * r ** 2 * R ** 2
+    return {"r": r, "R": R, "dtype": "bf16-in/f32-acc", "us_per_matvec": t * 1e6, "gflop_per_matvec": flops / 1e9,
+            "tflops": flops / t / 1e12, "frac_of_peak": flops / t / PEAK["bf16"]}
+
+
+def precision_variants(P, I):
+    """Time-to-gap of the 4x8 grid MaxCut (n = 32, value 52) with the plain FP64
+    direct local solves and with GMRES local solves (block Jacobi, mixed BF16 +
+    FP64 refinement, mixed + learned preconditioner trained on the local systems
+    of one FP64 run of the same instance)."""
+    g = I.grid_4x8()
+    prob = P.Problem(P.TTIPM_MAXCUT, g.cores)
+    out = {}
+
+    def run(name, **kw):
+        prm = P.Params(rank_cap=8, iter_rank_cap=8, stop_gap=1e-4, eps_gap=1e-4, max_iter=100, **kw)
+        st = P.State(prob, prm)
+        t0 = time.perf_counter()
+        res, log = P.ttipm_solve(prob, st, prm)
+        out[name] = {"time_to_gap_s": res["time_to_gap"], "wall_s": time.perf_counter() - t0,
+                     "iterations": res["iterations"], "rel_gap": res["rel_gap"],
+                     "obj_err_vs_closed_form": abs(res["pobj"] - 52.0) / 53.0,
+                     "krylov_iters": int(sum(l["krylov_iters"] for l in log)),
+                     "mlp_used": int(sum(l["mlp_used"] for l in log)),
+                     "mlp_fallbacks": int(sum(l["mlp_fallbacks"] for l in log))}
+
+    run("f64_direct")
+    run("f64_gmres_bjacobi", direct_max=64, precond=P.TT_PREC_BJACOBI, gmres_restart=40, gmres_maxit=800)
+    run("mixed_gmres_bjacobi", direct_max=64, precond=P.TT_PREC_BJACOBI, precision=P.TTIPM_MIXED,
+        gmres_restart=40, gmres_maxit=800)
+    net = P.MLP(8, hidden=256, seed=0)
+    run("collect", direct_max=64, precond=P.TT_PREC_BJACOBI, gmres_restart=40, gmres_maxit=800, mlp=net.h.value,
+        collect_probes=8, collect_cap=200000)
+    hist = net.train(epochs=30, batch=512, lr=1e-3, seed=1)
+    out.pop("collect")
+    run("mixed_gmres_mlp", direct_max=64, precond=P.TT_PREC_MLP, precision=P.TTIPM_MIXED, gmres_restart=40,
+        gmres_maxit=800, mlp=net.h.value)
+    out["mlp_training"] = {"blocks": net.dataset_size, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    return out
 
 
 def cpu_baseline(graph, budget_s=60.0):
@@ -110,6 +175,19 @@ def main():
     import instances as I
     import paper_2509_11890_amd as P
 
+    if args.contraction_only:
+        torch.cuda.set_device(0)
+        rows = []
+        for r, R in ((32, 64), (64, 128), (128, 256)):
+            rows.append(contraction_rate(P, torch, r, R))
+            rows.append(contraction_rate_bf16(P, torch, r, R))
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"local_contraction": rows, "copy_bytes": 2 * src.numel() * 8}), flush=True)
+        return
+
     cfg_name, cap, icap = WORKLOADS[args.workload]
     cap = args.rank_cap or cap
     icap = args.iter_rank_cap or icap
@@ -126,6 +204,9 @@ def main():
         res, log = P.ttipm_solve(prob, st, prm)
         return res, log
 
+    # load the kernels and fill the allocator once (one IPM iteration, untimed)
+    warm = P.Params(rank_cap=cap, iter_rank_cap=icap, stop_gap=1e-4, eps_gap=1e-4, max_iter=1, direct_max=8192)
+    P.ttipm_solve(prob, P.State(prob, warm), warm)
     for w in range(args.warmup):
         res, _ = one_solve()
         print(f"warmup {w}: {res['iterations']} iterations, gap {res['rel_gap']:.2e}, "
@@ -170,6 +251,8 @@ def main():
                     for k, v in kstats.items()}
 
     contraction = [contraction_rate(P, torch, r, R) for r, R in ((cap, 2 * cap), (64, 128))]
+    contraction += [contraction_rate_bf16(P, torch, r, R) for r, R in ((cap, 2 * cap), (64, 128))]
+    variants = None if args.no_variants else precision_variants(P, I)
 
     cpu = None
     if not args.no_cpu and graph.dense is not None:
@@ -209,6 +292,7 @@ def main():
         "kernel_time_s_per_step": kernel_share,
         "roofline": roof,
         "local_contraction": contraction,
+        "precision_variants_grid_d5": variants,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -142,7 +142,8 @@ typedef struct {
                                      operands with FP32 accumulation (vectors stay FP64) */
 } tt_local_op;
 
-/* y = K x in the precision of K->precision. */
+/* y = K x in the precision of K->precision.  No synchronisation: the work is
+ * enqueued on the stream (scratch is owned by the per-stream context). */
 TTIPM_API int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stream);
 
 /* DIRECT: blocked LU with partial pivoting of the assembled dense K.
@@ -234,9 +235,9 @@ TTIPM_API void ttipm_problem_destroy(ttipm_problem* p);
  * A two-hidden-layer ReLU network (FP32) predicting, for each diagonal block
  * (a, b) of a local system (n = L*m unknowns per block), a correction C_b of
  * the block-Jacobi inverse: M_b = B_b^{-1} + C_b / s_b, s_b = ||B_b||_F.  Its
- * input is the block normalised by s_b (n*n values, row-major) followed by
- * four context scalars (the IPM passes log10(mu), k/d, r/64, s/64), so
- * in_dim = n*n + 4 and out_dim = n*n.  The output layer starts at zero: an
+ * input is the block normalised by s_b (n*n values, row-major), log10(s_b)
+ * and four context scalars (the IPM passes log10(mu), k/d, r/64, s/64), so
+ * in_dim = n*n + 5 and out_dim = n*n.  The output layer starts at zero: an
  * untrained network is exactly the block-Jacobi preconditioner.
  * Training data are probe pairs of local systems: for a seeded Gaussian probe
  * x of the whole system and y = K x, the block residual r_b = x_b - B_b^{-1} y_b
@@ -249,7 +250,7 @@ typedef struct tt_mlp tt_mlp;
 
 typedef struct {
   int32_t N, P, n;      /* blocks, probes per block, unknowns per block             */
-  const float* F;       /* [N][n*n + 4] features (device)                           */
+  const float* F;       /* [N][n*n + 5] features (device)                           */
   const float* R;       /* [N][P][n] block-Jacobi residuals (device)                */
   const float* Y;       /* [N][P][n] probe images y_b (device)                      */
   const float* S;       /* [N] block norms (device)                                 */

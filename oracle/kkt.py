@@ -67,16 +67,19 @@ def residuals_dense(prob, X, Y, Z, T, mu, direction, sigma_mu=None):
         t = f(T)
         Rd = Rd - s * (AiT @ t)
         slack = s * (f(prob["Bineq"]) - Ai @ x)
-        Rt = t * slack - mu * f(one_T(prob))
+    target = mu if sigma_mu is None else sigma_mu
+    if "Aineq" in prob:
+        # both complementarity residuals aim at the same target (0 for the
+        # affine predictor, sigma mu for the corrector)
+        Rt = t * slack - target * f(one_T(prob))
     LZ, LX = L_ops(X, Z, direction)
     Ivec = f(tt.rank1_vec([np.array([1.0, 0, 0, 1])] * prob["d"]))
-    target = mu if sigma_mu is None else sigma_mu
     coef = 2.0 if direction == "aho" else 1.0
     Rc = tt.full_mat(LZ) @ x - coef * target * Ivec
     return Rd, Rp, Rt, Rc
 
 
-def newton_dense(prob, X, Y, Z, T, mu, direction, Rc_override=None, sigma_mu=None):
+def newton_dense(prob, X, Y, Z, T, mu, direction, Rc_override=None, sigma_mu=None, Rt_override=None):
     """Solve the dense block Newton system; returns dense (dX, dY, dT, dZ)."""
     f = tt.full
     N2 = 4 ** prob["d"]
@@ -87,6 +90,8 @@ def newton_dense(prob, X, Y, Z, T, mu, direction, Rc_override=None, sigma_mu=Non
     Rd, Rp, Rt, Rc = residuals_dense(prob, X, Y, Z, T, mu, direction, sigma_mu)
     if Rc_override is not None:
         Rc = Rc_override
+    if Rt_override is not None:
+        Rt = Rt_override
     I = np.eye(N2)
     O = np.zeros((N2, N2))
     if "Aineq" not in prob:

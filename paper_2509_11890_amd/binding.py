@@ -381,7 +381,7 @@ class MLP:
 
     def __init__(self, block_n, hidden=256, seed=0):
         self.n = int(block_n)
-        self.in_dim = self.n * self.n + 4
+        self.in_dim = self.n * self.n + 5
         self.out_dim = self.n * self.n
         self.h = C.c_void_p()
         _check(lib.tt_mlp_create(self.in_dim, int(hidden), self.out_dim, int(seed), C.byref(self.h)))
@@ -410,12 +410,16 @@ class MLP:
 
     @staticmethod
     def _batch(F, R, Y, S, W):
+        def dev32(t):
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32 \
+                    or not t.is_contiguous():
+                raise TypeError("expected a contiguous float32 CUDA tensor")
+            return t.data_ptr()
         N, P, n = R.shape
-        b = tt_mlp_batch(N, P, n, _dev(F).value, _dev(R).value, _dev(Y).value, _dev(S).value, _dev(W).value)
-        return b
+        return tt_mlp_batch(N, P, n, dev32(F), dev32(R), dev32(Y), dev32(S), dev32(W))
 
     def loss_grad(self, F, R, Y, S, W):
-        """Device float32 tensors F [N][n*n+4], R/Y [N][P][n], S [N], W [N][P] -> (loss, grad numpy)."""
+        """Device float32 tensors F [N][n*n+5], R/Y [N][P][n], S [N], W [N][P] -> (loss, grad numpy)."""
         import numpy as np
         b = self._batch(F, R, Y, S, W)
         loss = C.c_double(0.0)

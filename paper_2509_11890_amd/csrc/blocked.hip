@@ -172,8 +172,173 @@ __global__ void permute_rhs_kernel(double* B, int n, int nrhs, const int* piv) {
 }
 
 // ---------------------------------------------------------------------------
-// host drivers
+// host drivers: recursive (divide and conquer) formulations.  Splitting the
+// range in two halves at a multiple of nb turns the updates into GEMMs whose
+// inner dimension is half the range, instead of nb-wide rank updates that
+// rewrite the trailing matrix n / nb times.  Leaves are the nb x nb diagonal
+// blocks (factorised and inverted by one workgroup) or the nb-wide LU panels.
 // ---------------------------------------------------------------------------
+namespace {
+
+int split_at(int len, int nb) {
+  int h = ((len / 2 + nb - 1) / nb) * nb;
+  return (h >= len) ? len - nb : h;
+}
+
+const double* dblock(const DevBuf& d, int j0, int nb) { return d.get() + (size_t)(j0 / nb) * nb * nb; }
+
+// op(L) X = B for rows [j0, j0+len) of B (ldb), L lower (ldl) with inverted
+// diagonal blocks dinv (block j0/nb, stride = its size).  trans: L^T X = B.
+void trsm_left_rec(const double* L, long ldl, const DevBuf& dinv, int nb, int j0, int len, double* B, long ldb,
+                   int nrhs, bool trans, DevBuf& tmp, Ctx& c) {
+  if (len <= nb) {
+    const double* D = dblock(dinv, j0, nb);
+    tmp.reserve((size_t)len * nrhs);
+    double* Bj = B + (long)j0 * ldb;
+    Gemm g;   // X = op(D) B_j
+    g.M = len; g.N = nrhs; g.K = len;
+    g.A = D; g.am = trans ? 1 : len; g.ak = trans ? len : 1;
+    g.B = Bj; g.bk = ldb; g.bn = 1;
+    g.C = tmp.get(); g.cm = nrhs; g.cn = 1;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+    copy2d(tmp.get(), nrhs, Bj, ldb, len, nrhs, c.s);
+    return;
+  }
+  const int h = split_at(len, nb);
+  if (!trans) {
+    trsm_left_rec(L, ldl, dinv, nb, j0, h, B, ldb, nrhs, trans, tmp, c);
+    // B2 -= L21 X1
+    gemm(gemm_nn(len - h, nrhs, h, L + (long)(j0 + h) * ldl + j0, ldl, B + (long)j0 * ldb, ldb,
+                 B + (long)(j0 + h) * ldb, ldb, -1.0, 1.0),
+         c.s, &c.ws, GemmPrec::F64);
+    trsm_left_rec(L, ldl, dinv, nb, j0 + h, len - h, B, ldb, nrhs, trans, tmp, c);
+  } else {
+    trsm_left_rec(L, ldl, dinv, nb, j0 + h, len - h, B, ldb, nrhs, trans, tmp, c);
+    Gemm u;   // B1 -= L21^T X2
+    u.M = h; u.N = nrhs; u.K = len - h;
+    u.A = L + (long)(j0 + h) * ldl + j0; u.am = 1; u.ak = ldl;
+    u.B = B + (long)(j0 + h) * ldb; u.bk = ldb; u.bn = 1;
+    u.C = B + (long)j0 * ldb; u.cm = ldb; u.cn = 1;
+    u.alpha = -1.0; u.beta = 1.0;
+    gemm(u, c.s, &c.ws, GemmPrec::F64);
+    trsm_left_rec(L, ldl, dinv, nb, j0, h, B, ldb, nrhs, trans, tmp, c);
+  }
+}
+
+// U X = B for rows [j0, j0+len) of B, U upper (ldu) with inverted diagonal blocks uinv.
+void trsm_upper_rec(const double* U, long ldu, const DevBuf& uinv, int nb, int j0, int len, double* B, long ldb,
+                    int nrhs, DevBuf& tmp, Ctx& c) {
+  if (len <= nb) {
+    const double* D = dblock(uinv, j0, nb);
+    tmp.reserve((size_t)len * nrhs);
+    double* Bj = B + (long)j0 * ldb;
+    gemm(gemm_nn(len, nrhs, len, D, len, Bj, ldb, tmp.get(), nrhs), c.s, &c.ws, GemmPrec::F64);
+    copy2d(tmp.get(), nrhs, Bj, ldb, len, nrhs, c.s);
+    return;
+  }
+  const int h = split_at(len, nb);
+  trsm_upper_rec(U, ldu, uinv, nb, j0 + h, len - h, B, ldb, nrhs, tmp, c);
+  // B1 -= U12 X2
+  gemm(gemm_nn(h, nrhs, len - h, U + (long)j0 * ldu + (j0 + h), ldu, B + (long)(j0 + h) * ldb, ldb,
+               B + (long)j0 * ldb, ldb, -1.0, 1.0),
+       c.s, &c.ws, GemmPrec::F64);
+  trsm_upper_rec(U, ldu, uinv, nb, j0, h, B, ldb, nrhs, tmp, c);
+}
+
+// X L^T = B (right side) for the diagonal range [j0, j0+len) of L; B is m x len (ldb),
+// its column q corresponds to L's row/column j0 + q.
+void trsm_right_lt_rec(const double* L, long ldl, const DevBuf& dinv, int nb, int j0, int len, double* B, long ldb,
+                       int m, DevBuf& tmp, Ctx& c) {
+  if (len <= nb) {
+    const double* D = dblock(dinv, j0, nb);
+    tmp.reserve((size_t)m * len);
+    Gemm g;   // X = B D^T
+    g.M = m; g.N = len; g.K = len;
+    g.A = B; g.am = ldb; g.ak = 1;
+    g.B = D; g.bk = 1; g.bn = len;
+    g.C = tmp.get(); g.cm = len; g.cn = 1;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+    copy2d(tmp.get(), len, B, ldb, m, len, c.s);
+    return;
+  }
+  const int h = split_at(len, nb);
+  trsm_right_lt_rec(L, ldl, dinv, nb, j0, h, B, ldb, m, tmp, c);
+  Gemm u;   // B2 -= X1 L21^T
+  u.M = m; u.N = len - h; u.K = h;
+  u.A = B; u.am = ldb; u.ak = 1;
+  u.B = L + (long)(j0 + h) * ldl + j0; u.bk = 1; u.bn = ldl;
+  u.C = B + h; u.cm = ldb; u.cn = 1;
+  u.alpha = -1.0; u.beta = 1.0;
+  gemm(u, c.s, &c.ws, GemmPrec::F64);
+  trsm_right_lt_rec(L, ldl, dinv, nb, j0 + h, len - h, B + h, ldb, m, tmp, c);
+}
+
+void chol_rec(double* A, int n, BlockedFactors& f, int j0, int len, int* st, DevBuf& tmp, Ctx& c) {
+  const int nb = f.nb;
+  if (len <= nb) {
+    double* Ajj = A + (long)j0 * n + j0;
+    hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(BT), 0, c.s, Ajj, len, (long)n, st, j0);
+    hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(std::max(64, ((len + 63) / 64) * 64)), 0, c.s, Ajj, len,
+                       (long)n, const_cast<double*>(dblock(f.dinv, j0, nb)), 0);
+    TT_HIP(hipGetLastError());
+    return;
+  }
+  const int h = split_at(len, nb);
+  chol_rec(A, n, f, j0, h, st, tmp, c);
+  // L21 = A21 L11^{-T}
+  double* A21 = A + (long)(j0 + h) * n + j0;
+  trsm_right_lt_rec(A, n, f.dinv, nb, j0, h, A21, n, len - h, tmp, c);
+  // A22 -= L21 L21^T
+  Gemm u;
+  u.M = len - h; u.N = len - h; u.K = h;
+  u.A = A21; u.am = n; u.ak = 1;
+  u.B = A21; u.bk = 1; u.bn = n;
+  u.C = A + (long)(j0 + h) * n + (j0 + h); u.cm = n; u.cn = 1;
+  u.alpha = -1.0; u.beta = 1.0;
+  gemm(u, c.s, &c.ws, GemmPrec::F64);
+  chol_rec(A, n, f, j0 + h, len - h, st, tmp, c);
+}
+
+// LU of the columns [j0, j0+w) over rows [j0, n), rows swapped inside these
+// columns only (the caller swaps the other columns).
+void lu_rec(double* A, int n, BlockedFactors& f, int* piv, int j0, int w, int* st, DevBuf& tmp, Ctx& c) {
+  const int nb = f.nb;
+  if (w <= nb) {
+    const double pm = n - j0;
+    const int tok = prof_begin(PK_PANEL_LU, c.s, pm * w * (double)w, 16.0 * pm * w);
+    hipLaunchKernelGGL(panel_lu_kernel, dim3(1), dim3(BT), 0, c.s, A + (long)j0 * n + j0, n - j0, w, (long)n, piv + j0,
+                       j0, st);
+    prof_end(tok, c.s);
+    double* Ajj = A + (long)j0 * n + j0;
+    const unsigned tb = std::max(64, ((w + 63) / 64) * 64);
+    hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(tb), 0, c.s, Ajj, w, (long)n,
+                       const_cast<double*>(dblock(f.dinv, j0, nb)), 1);
+    hipLaunchKernelGGL(trinv_upper_kernel, dim3(1), dim3(tb), 0, c.s, Ajj, w, (long)n,
+                       const_cast<double*>(dblock(f.uinv, j0, nb)));
+    TT_HIP(hipGetLastError());
+    return;
+  }
+  const int h = split_at(w, nb);
+  lu_rec(A, n, f, piv, j0, h, st, tmp, c);
+  // the left half's row swaps on the right half's columns
+  hipLaunchKernelGGL(apply_swaps_kernel, dim3(nblocks(w - h, 64)), dim3(64), 0, c.s, A, (long)n, piv + j0, j0, h,
+                     j0 + h, j0 + w);
+  TT_HIP(hipGetLastError());
+  // A12 = L11^{-1} A12 (unit lower), A22 -= A21 A12
+  double* A12 = A + (long)j0 * n + (j0 + h);
+  trsm_left_rec(A, n, f.dinv, nb, j0, h, A + (j0 + h), n, w - h, false, tmp, c);
+  gemm(gemm_nn(n - j0 - h, w - h, h, A + (long)(j0 + h) * n + j0, n, A12, n, A + (long)(j0 + h) * n + (j0 + h), n,
+               -1.0, 1.0),
+       c.s, &c.ws, GemmPrec::F64);
+  lu_rec(A, n, f, piv, j0 + h, w - h, st, tmp, c);
+  // the right half's row swaps on the left half's columns
+  hipLaunchKernelGGL(apply_swaps_kernel, dim3(nblocks(h, 64)), dim3(64), 0, c.s, A, (long)n, piv + j0 + h, j0 + h,
+                     w - h, j0, j0 + h);
+  TT_HIP(hipGetLastError());
+}
+
+}  // namespace
+
 int chol_blocked(double* A, int n, BlockedFactors& f, Ctx& c) {
   const int nb = f.nb;
   const int nblk = (n + nb - 1) / nb;
@@ -182,36 +347,8 @@ int chol_blocked(double* A, int n, BlockedFactors& f, Ctx& c) {
   c.ired.reserve(4);
   int* st = reinterpret_cast<int*>(c.ired.get());
   TT_HIP(hipMemsetAsync(st, 0, sizeof(int), c.s));
-  DevBuf T((size_t)n * nb);
-  for (int j = 0; j < n; j += nb) {
-    const int jb = std::min(nb, n - j);
-    double* Ajj = A + (long)j * n + j;
-    hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(BT), 0, c.s, Ajj, jb, (long)n, st, j);
-    double* Dj = f.dinv.get() + (size_t)(j / nb) * nb * nb;
-    hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(std::max(64, ((jb + 63) / 64) * 64)), 0, c.s, Ajj, jb,
-                       (long)n, Dj, 0);
-    TT_HIP(hipGetLastError());
-    const int rest = n - j - jb;
-    if (rest > 0) {
-      // panel <- panel L_jj^{-T}
-      double* Pn = A + (long)(j + jb) * n + j;
-      Gemm g;
-      g.M = rest; g.N = jb; g.K = jb;
-      g.A = Pn; g.am = n; g.ak = 1;
-      g.B = Dj; g.bk = 1; g.bn = jb;          // (L^{-1})^T [k][c] = L^{-1}[c][k]
-      g.C = T.get(); g.cm = jb; g.cn = 1;
-      gemm(g, c.s, &c.ws, GemmPrec::F64);
-      copy2d(T.get(), jb, Pn, n, rest, jb, c.s);
-      // trailing A22 -= P P^T
-      Gemm u;
-      u.M = rest; u.N = rest; u.K = jb;
-      u.A = Pn; u.am = n; u.ak = 1;
-      u.B = Pn; u.bk = 1; u.bn = n;
-      u.C = A + (long)(j + jb) * n + (j + jb); u.cm = n; u.cn = 1;
-      u.alpha = -1.0; u.beta = 1.0;
-      gemm(u, c.s, &c.ws, GemmPrec::F64);
-    }
-  }
+  DevBuf tmp;
+  chol_rec(A, n, f, 0, n, st, tmp, c);
   int hst = 0;
   TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
   c.sync();
@@ -219,95 +356,24 @@ int chol_blocked(double* A, int n, BlockedFactors& f, Ctx& c) {
 }
 
 void trsm_blocked(const double* L, int n, const BlockedFactors& f, double* B, int nrhs, bool trans, Ctx& c) {
-  const int nb = f.nb;
-  DevBuf X((size_t)nb * nrhs);
-  if (!trans) {
-    for (int j = 0; j < n; j += nb) {
-      const int jb = std::min(nb, n - j);
-      const double* Dj = f.dinv.get() + (size_t)(j / nb) * nb * nb;
-      double* Bj = B + (long)j * nrhs;
-      gemm(gemm_nn(jb, nrhs, jb, Dj, jb, Bj, nrhs, X.get(), nrhs), c.s, &c.ws, GemmPrec::F64);
-      TT_HIP(hipMemcpyAsync(Bj, X.get(), sizeof(double) * (size_t)jb * nrhs, hipMemcpyDeviceToDevice, c.s));
-      const int rest = n - j - jb;
-      if (rest > 0)
-        gemm(gemm_nn(rest, nrhs, jb, L + (long)(j + jb) * n + j, n, X.get(), nrhs, B + (long)(j + jb) * nrhs, nrhs,
-                     -1.0, 1.0),
-             c.s, &c.ws, GemmPrec::F64);
-    }
-  } else {
-    const int nblk = (n + nb - 1) / nb;
-    for (int bj = nblk - 1; bj >= 0; --bj) {
-      const int j = bj * nb;
-      const int jb = std::min(nb, n - j);
-      const double* Dj = f.dinv.get() + (size_t)bj * nb * nb;
-      double* Bj = B + (long)j * nrhs;
-      Gemm g;   // X = D_j^T B_j
-      g.M = jb; g.N = nrhs; g.K = jb;
-      g.A = Dj; g.am = 1; g.ak = jb;
-      g.B = Bj; g.bk = nrhs; g.bn = 1;
-      g.C = X.get(); g.cm = nrhs; g.cn = 1;
-      gemm(g, c.s, &c.ws, GemmPrec::F64);
-      TT_HIP(hipMemcpyAsync(Bj, X.get(), sizeof(double) * (size_t)jb * nrhs, hipMemcpyDeviceToDevice, c.s));
-      if (j > 0) {
-        Gemm u;   // B[0:j] -= L[j:j+jb, 0:j]^T X
-        u.M = j; u.N = nrhs; u.K = jb;
-        u.A = L + (long)j * n; u.am = 1; u.ak = n;
-        u.B = X.get(); u.bk = nrhs; u.bn = 1;
-        u.C = B; u.cm = nrhs; u.cn = 1;
-        u.alpha = -1.0; u.beta = 1.0;
-        gemm(u, c.s, &c.ws, GemmPrec::F64);
-      }
-    }
-  }
+  DevBuf tmp;
+  trsm_left_rec(L, n, f.dinv, f.nb, 0, n, B, nrhs, nrhs, trans, tmp, c);
+  c.sync();   // tmp is released at return
 }
 
 int lu_blocked(double* A, int n, BlockedFactors& f, Ctx& c) {
   const int nb = f.nb;
   const int nblk = (n + nb - 1) / nb;
   f.n = n;
-  f.piv.reserve((size_t)n / 2 + 1);     // ints packed in doubles
+  f.piv.reserve((size_t)n / 2 + 1);         // ints packed in doubles
   f.dinv.reserve((size_t)nblk * nb * nb);   // inverses of the unit-lower diagonal blocks
   f.uinv.reserve((size_t)nblk * nb * nb);   // inverses of the upper diagonal blocks
   int* piv = reinterpret_cast<int*>(f.piv.get());
   c.ired.reserve(4);
   int* st = reinterpret_cast<int*>(c.ired.get());
   TT_HIP(hipMemsetAsync(st, 0, sizeof(int), c.s));
-  DevBuf T((size_t)nb * n);
-  for (int j = 0; j < n; j += nb) {
-    const int jb = std::min(nb, n - j);
-    const double pm = n - j;
-    const int tok = prof_begin(PK_PANEL_LU, c.s, pm * jb * (double)jb, 16.0 * pm * jb);
-    hipLaunchKernelGGL(panel_lu_kernel, dim3(1), dim3(BT), 0, c.s, A + (long)j * n + j, n - j, jb, (long)n, piv + j, j,
-                       st);
-    prof_end(tok, c.s);
-    TT_HIP(hipGetLastError());
-    // panel pivots are relative to the panel's first row: convert to absolute rows
-    // (the kernel already adds row_base), then swap rows outside the panel columns
-    if (j > 0)
-      hipLaunchKernelGGL(apply_swaps_kernel, dim3(nblocks(j, 256)), dim3(256), 0, c.s, A, (long)n, piv + j, j, jb, 0, j);
-    if (j + jb < n)
-      hipLaunchKernelGGL(apply_swaps_kernel, dim3(nblocks(n - j - jb, 256)), dim3(256), 0, c.s, A, (long)n, piv + j, j,
-                         jb, j + jb, n);
-    TT_HIP(hipGetLastError());
-    double* Ajj = A + (long)j * n + j;
-    double* Dj = f.dinv.get() + (size_t)(j / nb) * nb * nb;
-    double* Uj = f.uinv.get() + (size_t)(j / nb) * nb * nb;
-    const unsigned tb = std::max(64, ((jb + 63) / 64) * 64);
-    hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(tb), 0, c.s, Ajj, jb, (long)n, Dj, 1);
-    hipLaunchKernelGGL(trinv_upper_kernel, dim3(1), dim3(tb), 0, c.s, Ajj, jb, (long)n, Uj);
-    TT_HIP(hipGetLastError());
-    const int rest = n - j - jb;
-    if (rest > 0) {
-      // U12 = L11^{-1} A12
-      double* A12 = A + (long)j * n + (j + jb);
-      gemm(gemm_nn(jb, rest, jb, Dj, jb, A12, n, T.get(), rest), c.s, &c.ws, GemmPrec::F64);
-      copy2d(T.get(), rest, A12, n, jb, rest, c.s);
-      // A22 -= L21 U12
-      gemm(gemm_nn(rest, rest, jb, A + (long)(j + jb) * n + j, n, A12, n, A + (long)(j + jb) * n + (j + jb), n, -1.0,
-                   1.0),
-           c.s, &c.ws, GemmPrec::F64);
-    }
-  }
+  DevBuf tmp;
+  lu_rec(A, n, f, piv, 0, n, st, tmp, c);
   int hst = 0;
   TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
   c.sync();
@@ -315,36 +381,14 @@ int lu_blocked(double* A, int n, BlockedFactors& f, Ctx& c) {
 }
 
 void lu_solve_blocked(const double* A, int n, const BlockedFactors& f, double* B, int nrhs, Ctx& c) {
-  const int nb = f.nb;
   const int* piv = reinterpret_cast<const int*>(f.piv.get());
   hipLaunchKernelGGL(permute_rhs_kernel, dim3(nblocks(nrhs, 64)), dim3(64), 0, c.s, B, n, nrhs, piv);
   TT_HIP(hipGetLastError());
-  DevBuf X((size_t)nb * nrhs);
-  // forward: unit lower
-  for (int j = 0; j < n; j += nb) {
-    const int jb = std::min(nb, n - j);
-    const double* Dj = f.dinv.get() + (size_t)(j / nb) * nb * nb;
-    double* Bj = B + (long)j * nrhs;
-    gemm(gemm_nn(jb, nrhs, jb, Dj, jb, Bj, nrhs, X.get(), nrhs), c.s, &c.ws, GemmPrec::F64);
-    TT_HIP(hipMemcpyAsync(Bj, X.get(), sizeof(double) * (size_t)jb * nrhs, hipMemcpyDeviceToDevice, c.s));
-    const int rest = n - j - jb;
-    if (rest > 0)
-      gemm(gemm_nn(rest, nrhs, jb, A + (long)(j + jb) * n + j, n, X.get(), nrhs, B + (long)(j + jb) * nrhs, nrhs, -1.0,
-                   1.0),
-           c.s, &c.ws, GemmPrec::F64);
-  }
-  // backward: upper
-  const int nblk = (n + nb - 1) / nb;
-  for (int bj = nblk - 1; bj >= 0; --bj) {
-    const int j = bj * nb;
-    const int jb = std::min(nb, n - j);
-    const double* Uj = f.uinv.get() + (size_t)bj * nb * nb;
-    double* Bj = B + (long)j * nrhs;
-    gemm(gemm_nn(jb, nrhs, jb, Uj, jb, Bj, nrhs, X.get(), nrhs), c.s, &c.ws, GemmPrec::F64);
-    TT_HIP(hipMemcpyAsync(Bj, X.get(), sizeof(double) * (size_t)jb * nrhs, hipMemcpyDeviceToDevice, c.s));
-    if (j > 0)
-      gemm(gemm_nn(j, nrhs, jb, A + j, n, X.get(), nrhs, B, nrhs, -1.0, 1.0), c.s, &c.ws, GemmPrec::F64);
-  }
+  DevBuf tmp;
+  // forward with the unit lower factor, then backward with the upper factor
+  trsm_left_rec(A, n, f.dinv, f.nb, 0, n, B, nrhs, nrhs, false, tmp, c);
+  trsm_upper_rec(A, n, f.uinv, f.nb, 0, n, B, nrhs, nrhs, tmp, c);
+  c.sync();
 }
 
 }  // namespace ttipm

@@ -159,7 +159,11 @@ void check_local_op(const tt_local_op* K) {
 void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c) {
   const long p = (long)K->r * K->m * K->rp;
   fill((long)K->L * p, 0.0, y, c.s);
-  DevBuf perm0, perm1, tmp(p);
+  // context-owned scratch: no allocation is released while kernels may still use it
+  DevBuf& perm0 = c.perm;
+  DevBuf& perm1 = c.perm2;
+  DevBuf& tmp = c.t3;
+  tmp.reserve(p);
   for (int b = 0; b < K->nblocks; ++b) {
     const tt_local_block& B = K->blocks[b];
     const double* xin = x + (long)B.col * p;
@@ -194,7 +198,6 @@ int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stre
     c.prec = K->precision == TTIPM_MIXED ? GemmPrec::BF16 : GemmPrec::F64;
     generic_matvec(K, x, y, c);
     c.prec = GemmPrec::F64;
-    c.sync();   // local scratch (permuted cores) is released on return
     return TT_OK;
   });
 }
@@ -561,8 +564,8 @@ static MlpBatch as_batch(const tt_mlp_batch* b, const tt_mlp* m) {
     mb = MlpBatch{(int)net.ds_N, net.ds_P, net.ds_n, net.dsF.get(), net.dsR.get(), net.dsY.get(), net.dsS.get(),
                   net.dsW.get()};
   }
-  if (mb.n * mb.n != m->net.out || mb.n * mb.n + 4 != m->net.in)
-    throw Error(TT_ERR_ARG, "batch block size does not match the network (in = n*n + 4, out = n*n)");
+  if (mb.n * mb.n != m->net.out || mb.n * mb.n + 5 != m->net.in)
+    throw Error(TT_ERR_ARG, "batch block size does not match the network (in = n*n + 5, out = n*n)");
   return mb;
 }
 
@@ -590,7 +593,7 @@ int tt_mlp_collect(tt_mlp* m, const tt_local_op* K, const float* context, int32_
     Ctx& c = ctx_for(stream);
     c.prec = GemmPrec::F64;
     const int n = K->L * K->m;
-    if (n * n != m->net.out || n * n + 4 != m->net.in) throw Error(TT_ERR_ARG, "block size does not match the network");
+    if (n * n != m->net.out || n * n + 5 != m->net.in) throw Error(TT_ERR_ARG, "block size does not match the network");
     BlockJacobi raw, inv;
     raw.init(K->r, K->rp, K->m, K->L, c);
     for (int b = 0; b < K->nblocks; ++b) {

@@ -21,6 +21,7 @@
 #include "gemm.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 
 namespace ttipm {
@@ -349,19 +350,33 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   g.alpha = q.alpha; g.beta = q.beta;
   // FP64 tile shape: 128 x 128 for large outputs, 128 x 64 / 64 x 128 for
   // skinny ones, 64 x 64 otherwise (BF16 always uses 64 x 64).
+  // The largest tile that still gives the chip enough workgroups (min_tiles,
+  // default two per CU so that two waves share each SIMD and hide each other's
+  // LDS and global latency) and does not overhang a dimension shorter than
+  // the tile; else 64 x 64.  TTIPM_GEMM_MIN_TILES overrides the threshold.
+  static const long min_tiles = [] {
+    const char* e = std::getenv("TTIPM_GEMM_MIN_TILES");
+    const long v = e ? std::atol(e) : 0;
+    return v > 0 ? v : 512L;
+  }();
   int TMs = BM, TNs = BN;
   if (prec == GemmPrec::F64) {
-    if (q.M >= 128 && q.N >= 128) { TMs = 128; TNs = 128; }
-    else if (q.M >= 128) { TMs = 128; TNs = 64; }
-    else if (q.N >= 128) { TMs = 64; TNs = 128; }
+    const int cand[3][2] = {{128, 128}, {128, 64}, {64, 128}};
+    for (const auto& t : cand) {
+      if (q.M < t[0] || q.N < t[1]) continue;
+      const long nt = (long)((q.M + t[0] - 1) / t[0]) * ((q.N + t[1] - 1) / t[1]) * q.batch;
+      if (nt >= min_tiles) { TMs = t[0]; TNs = t[1]; break; }
+    }
   }
   const int gm = (q.M + TMs - 1) / TMs, gn = (q.N + TNs - 1) / TNs;
   const long tiles = (long)gm * gn * q.batch;
-  // Split K when the output alone cannot fill the 256 CUs and K is long.
+  // Split K only when the output tiles cannot occupy half of the 256 CUs and K
+  // is long: every slice writes a full partial tile that the reduce kernel
+  // reads back, so the slice count is kept to what fills the chip.
   int ks = 1;
   const int kstep = (prec == GemmPrec::BF16) ? BK16 : BK;
-  if (tiles < 512 && q.K >= 8 * kstep) {
-    ks = (int)std::min<long>((512 + tiles - 1) / tiles, (long)q.K / (4 * kstep));
+  if (tiles < 128 && q.K >= 16 * kstep) {
+    ks = (int)std::min<long>((256 + tiles - 1) / tiles, (long)q.K / (8 * kstep));
     ks = std::max(1, std::min(ks, 64));
   }
   g.kslices = ks;

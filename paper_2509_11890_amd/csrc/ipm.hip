@@ -332,6 +332,65 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
 
 constexpr double kNoBound = 1e6;
 
+namespace {
+
+// Dense entries of a TT vector (row-major product of the cores; the first core
+// is the most significant index).  Used for the diagonal (elementwise) step
+// bounds of the inequality slack and multipliers, 4^d entries (d <= 13 keeps
+// this below 1 GiB per vector).
+void tt_full_device(const TT& v, DevBuf& out, DevBuf& tmp, Ctx& c) {
+  TT_REQUIRE(v.d <= 13, "dense evaluation limited to d <= 13");
+  const long m = (long)v.mo * v.mi;
+  long rows = m;
+  out.reserve((size_t)m * v.r[1]);
+  TT_HIP(hipMemcpyAsync(out.get(), v.core(0), sizeof(double) * m * v.r[1], hipMemcpyDeviceToDevice, c.s));
+  for (int k = 1; k < v.d; ++k) {
+    const int rk = v.r[k], rn = v.r[k + 1];
+    tmp.reserve((size_t)rows * m * rn);
+    gemm(gemm_nn((int)rows, (int)(m * rn), rk, out.get(), rk, v.core(k), m * rn, tmp.get(), m * rn), c.s, &c.ws,
+         GemmPrec::F64);
+    std::swap(out, tmp);
+    rows *= m;
+  }
+}
+
+__global__ void ratio_min_kernel(const double* v, const double* dv, const double* mask, long n, double* part) {
+  __shared__ double red[256];
+  double best = 1e300;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    if (mask[i] > 0.5 && dv[i] < 0.0) best = fmin(best, fmax(v[i], 0.0) / -dv[i]);
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// largest alpha with v + alpha dv >= 0 on the entries where mask = 1 (Sec. 3.4:
+// the smallest eigenvalue of the diagonal pencil is the smallest entry ratio)
+double ratio_step(const TT& v, const TT& dv, const TT& mask, Ctx& c) {
+  DevBuf a, b, m, tmp;
+  tt_full_device(v, a, tmp, c);
+  tt_full_device(dv, b, tmp, c);
+  tt_full_device(mask, m, tmp, c);
+  long n = 1;
+  for (int k = 0; k < v.d; ++k) n *= (long)v.mo * v.mi;
+  const int nb = 256;
+  DevBuf part(nb);
+  hipLaunchKernelGGL(ratio_min_kernel, dim3(nb), dim3(256), 0, c.s, a.get(), b.get(), m.get(), n, part.get());
+  TT_HIP(hipGetLastError());
+  std::vector<double> h(nb);
+  TT_HIP(hipMemcpyAsync(h.data(), part.get(), sizeof(double) * nb, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  double best = 1e300;
+  for (double x : h) best = std::min(best, x);
+  return std::min(best, kNoBound);
+}
+
+}  // namespace
+
 double step_length(const TT& M, const TT& dM, BlockTT& E, bool& have_E, const ttipm_params& prm,
                    unsigned long long seed, Ctx& c) {
   const double lam = min_gen_eig(M, dM, E, have_E, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps), seed, c);
@@ -344,8 +403,28 @@ double step_length(const TT& M, const TT& dM, BlockTT& E, bool& have_E, const tt
 // ---------------------------------------------------------------------------
 // the IPM iteration
 // ---------------------------------------------------------------------------
+// s(X) = s (B_ineq - A_ineq X): the inequality slack (>= 0 at feasible X)
+TT ineq_slack(const Problem& P, const TT& X, bool homogeneous, Ctx& c) {
+  TT AX = tt_matvec(P.Aineq, X, c);
+  if (homogeneous) {
+    tt_scale(AX, -P.sense, c);
+    return AX;
+  }
+  return tt_add({&P.Bineq, &AX}, {P.sense, -P.sense}, c);
+}
+
+// mu = (<X, Z> + <T, s(X)>) / (n + q)  (Sec. 3.2)
+double ipm_mu(const Problem& P, const State& S, Ctx& c) {
+  double xz = tt_dot(S.X, S.Z, c);
+  if (P.ineq) {
+    TT sx = ineq_slack(P, S.X, false, c);
+    xz += tt_dot(S.T, sx, c);
+  }
+  return xz / (P.n + P.q);
+}
+
 void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& c) {
-  const double mu = tt_dot(S.X, S.Z, c) / (P.n + P.q);
+  const double mu = ipm_mu(P, S, c);
   TT AY = tt_matvec(P.AeqT, S.Y, c);
   TT Rd = tt_add({&S.Z, &P.C, &AY}, {1.0, 1.0, -1.0}, c);
   TT AX = tt_matvec(P.Aeq, S.X, c);
@@ -364,7 +443,7 @@ void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& 
   }
   info.eps_d = std::sqrt(std::max(rdn2, 0.0)) / (1.0 + P.normC);
   info.rel_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
-  info.eps_c = tt_dot(S.X, S.Z, c) / ((P.n + P.q) * (1.0 + pobj));
+  info.eps_c = mu / (1.0 + std::fabs(pobj));
   info.rank_x = S.X.max_rank();
   info.rank_y = S.Y.max_rank();
   info.rank_z = S.Z.max_rank();
@@ -462,7 +541,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   ap.mlp = prm.mlp ? &const_cast<tt_mlp*>(static_cast<const tt_mlp*>(prm.mlp))->net : nullptr;
   ap.collect_probes = std::max(0, prm.collect_probes);
   ap.collect_cap = (long)prm.collect_cap;
-  ap.mu = std::max(tt_dot(S.X, S.Z, c) / (P.n + P.q), 1e-300);
+  ap.mu = std::max(mu, 1e-300);
   ap.seed = S.seed + 31ull * (unsigned long long)S.iter;
   // --- predictor: affine direction (target mu = 0) ---
   sys.terms = base;
@@ -477,14 +556,28 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   TT dX = S.W.component(0, c), dZ = S.W.component(L, c);
   double t1 = now();
   const unsigned long long sd = S.seed + 7919ull * (unsigned long long)S.iter;
-  // affine (predictor) steps: the full Thm. 1 step, clipped to 1
+  // affine (predictor) steps: the full Thm. 1 step, clipped to 1; with
+  // inequalities also s(X + a_p dX) >= 0 and T + a_d dT >= 0 on the active
+  // mask (Sec. 3.4: the diagonal pencils reduce to entry ratios)
   double a_p = std::min(1.0, step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, c));
   double a_d = std::min(1.0, step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, c));
+  TT dT, sx, dsx;
+  if (P.ineq) {
+    dT = S.W.component(2, c);
+    sx = ineq_slack(P, S.X, false, c);
+    dsx = ineq_slack(P, dX, true, c);
+    a_p = std::min(a_p, ratio_step(sx, dsx, P.oneT, c));
+    a_d = std::min(a_d, ratio_step(S.T, dT, P.oneT, c));
+  }
   info.t_step += now() - t1;
-  // mu_aff = <X + a_p dX, Z + a_d dZ> / (n + q)
+  // mu_aff = (<X + a_p dX, Z + a_d dZ> + <T + a_d dT, s(X + a_p dX)>) / (n + q)
   const double xz = tt_dot(S.X, S.Z, c), xdz = tt_dot(S.X, dZ, c), dxz = tt_dot(dX, S.Z, c),
                dxdz = tt_dot(dX, dZ, c);
-  const double mu_aff = (xz + a_d * xdz + a_p * dxz + a_p * a_d * dxdz) / (P.n + P.q);
+  double ts_aff = 0.0;
+  if (P.ineq)
+    ts_aff = tt_dot(S.T, sx, c) + a_p * tt_dot(S.T, dsx, c) + a_d * tt_dot(dT, sx, c) +
+             a_p * a_d * tt_dot(dT, dsx, c);
+  const double mu_aff = (xz + a_d * xdz + a_p * dxz + a_p * a_d * dxdz + ts_aff) / (P.n + P.q);
   const double sigma = std::pow(std::max(mu_aff, 0.0) / mu, 3.0);
   // --- corrector: centring and the second-order term L_{dZ_aff} vec dX_aff ---
   TT LdZ, LdX_unused;
@@ -503,7 +596,15 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   sys.terms.push_back({RES_C, 1.0, OP_LZ, &S.X});
   sys.terms.push_back({RES_C, 1.0, OP_EXTRA0, &dX});
   sys.terms.push_back({RES_C, -coef * sigma * mu, -1, &P.Ivec});
-  if (P.ineq) sys.terms.push_back({RES_T, -sigma * mu, -1, &P.oneT});
+  TT dTdiag;
+  if (P.ineq) {
+    sys.terms.push_back({RES_T, -sigma * mu, -1, &P.oneT});
+    // second-order term of R_t: dT_aff o ds_aff
+    dTdiag = tt_diag(dT, c);
+    tt_round_abs(dTdiag, told, 1 << 30, c);
+    sys.ops[OP_EXTRA1] = &dTdiag;
+    sys.terms.push_back({RES_T, 1.0, OP_EXTRA1, &dsx});
+  }
   AmenInfo ai_c;
   amen_solve(sys, S.W, ap, ai_c, c);
   S.frame_capped |= ai_c.capped;
@@ -511,6 +612,12 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   t1 = now();
   info.alpha_p_max = step_length(S.X, dX2, S.EX, S.has_EX, prm, sd + 3, c);
   info.alpha_d_max = step_length(S.Z, dZ2, S.EZ, S.has_EZ, prm, sd + 4, c);
+  if (P.ineq) {
+    TT dT2 = S.W.component(2, c);
+    TT ds2 = ineq_slack(P, dX2, true, c);
+    info.alpha_p_max = std::min(info.alpha_p_max, ratio_step(sx, ds2, P.oneT, c));
+    info.alpha_d_max = std::min(info.alpha_d_max, ratio_step(S.T, dT2, P.oneT, c));
+  }
   a_p = std::min(1.0, prm.tau * info.alpha_p_max);
   a_d = std::min(1.0, prm.tau * info.alpha_d_max);
   info.t_step += now() - t1;

@@ -158,7 +158,7 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, long n
   p[t] -= lr * (mt / c1) / (sqrtf(vt / c2) + eps);
 }
 
-// block features: F[b] = [D_b / s_b, ctx], S[b] = |D_b|_F
+// block features: F[b] = [D_b / s_b, log10 s_b, ctx], S[b] = |D_b|_F
 __global__ void block_features_kernel(const double* blk, int nb, int n, const float* ctx, float* F, float* S) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
@@ -167,9 +167,10 @@ __global__ void block_features_kernel(const double* blk, int nb, int n, const fl
   for (int q = 0; q < n * n; ++q) s += D[q] * D[q];
   s = sqrt(s);
   const double is = s > 0.0 ? 1.0 / s : 0.0;
-  float* f = F + (long)b * (n * n + 4);
+  float* f = F + (long)b * (n * n + 5);
   for (int q = 0; q < n * n; ++q) f[q] = (float)(D[q] * is);
-  for (int q = 0; q < 4; ++q) f[n * n + q] = ctx[q];
+  f[n * n] = (float)log10(s > 0.0 ? s : 1.0);
+  for (int q = 0; q < 4; ++q) f[n * n + 1 + q] = ctx[q];
   S[b] = (float)(s > 0.0 ? s : 1.0);
 }
 
@@ -391,7 +392,7 @@ void mlp_block_data(const BlockJacobi& raw, const BlockJacobi& inv, const std::f
   const int n = raw.L * raw.m;
   const long nb = (long)raw.r * raw.s;
   const long len = (long)raw.L * raw.r * raw.m * raw.s;
-  F.reserve((size_t)nb * (n * n + 4));
+  F.reserve((size_t)nb * (n * n + 5));
   S.reserve(nb);
   R.reserve((size_t)nb * nprobe * n);
   Y.reserve((size_t)nb * nprobe * n);
@@ -418,8 +419,8 @@ void mlp_block_data(const BlockJacobi& raw, const BlockJacobi& inv, const std::f
 void mlp_correct_blocks(Mlp& net, const BlockJacobi& raw, BlockJacobi& inv, const float ctx[4], Ctx& c) {
   const int n = raw.L * raw.m;
   const long nb = (long)raw.r * raw.s;
-  TT_REQUIRE(net.in == n * n + 4 && net.out == n * n, "network dimensions do not match the local blocks");
-  FBuf F((size_t)nb * (n * n + 4)), S(nb), o((size_t)nb * n * n), cdev(4);
+  TT_REQUIRE(net.in == n * n + 5 && net.out == n * n, "network dimensions do not match the local blocks");
+  FBuf F((size_t)nb * (n * n + 5)), S(nb), o((size_t)nb * n * n), cdev(4);
   TT_HIP(hipMemcpyAsync(cdev.get(), ctx, sizeof(float) * 4, hipMemcpyHostToDevice, c.s));
   hipLaunchKernelGGL(block_features_kernel, dim3(nblocks(nb, 64)), dim3(64), 0, c.s, raw.blk.get(), (int)nb, n,
                      cdev.get(), F.get(), S.get());

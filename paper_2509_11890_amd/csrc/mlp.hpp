@@ -69,8 +69,8 @@ struct Mlp {
 void mlp_train(Mlp& net, const MlpBatch& data, int epochs, int batch, float lr, unsigned long long seed,
                std::vector<double>& hist, Ctx& c);
 
-// Features and probe data of the (a, b) blocks of a local operator: F [nb][n*n+4]
-// (normalised block entries + 4 context scalars), S [nb] (block norms), and for
+// Features and probe data of the (a, b) blocks of a local operator: F [nb][n*n+5]
+// (normalised block entries, log10 of the block norm, 4 context scalars), S [nb] (block norms), and for
 // nprobe seeded probes x: R = x_b - B_b^{-1} y_b, Y = y_b (y = K x) [nb][P][n].
 // `apply_K` computes y = K x on [L][r][m][s] vectors.
 void mlp_block_data(const BlockJacobi& raw, const BlockJacobi& inv, const std::function<void(const double*, double*)>& apply_K,

@@ -36,7 +36,7 @@ struct TT {
 struct Ctx {
   hipStream_t s = nullptr;
   Workspace ws;               // split-K partials
-  DevBuf t1, t2, t3, perm;    // contraction intermediates
+  DevBuf t1, t2, t3, perm, perm2;   // contraction intermediates
   DevBuf dscr, dscr2, dscr3;  // dense factorisation scratch
   DevBuf ired;                // int scratch (status words)
   DevBuf dot_part, dot_out;

@@ -109,7 +109,10 @@ def test_solve_matches_closed_form(name, kind, make, value):
     P = _lib()
     g = make()
     pr = P.Problem(P.TTIPM_MAXCUT if kind == "maxcut" else P.TTIPM_THETA, g.cores)
-    prm = P.Params(rank_cap=8 if g.d >= 5 else 16, stop_gap=3e-7, delta=1e-10, max_iter=60)
+    # the grid instance is run at its configuration: TT ranks <= 8 for the iterates and the Newton frame
+    caps = dict(rank_cap=8, iter_rank_cap=8, max_iter=100) if name == "grid-4x8" else \
+        dict(rank_cap=8 if g.d >= 5 else 16, max_iter=60)
+    prm = P.Params(stop_gap=3e-7, delta=1e-10, **caps)
     st = P.State(pr, prm)
     res, log = P.ttipm_solve(pr, st, prm)
     print(name, res)
@@ -119,12 +122,114 @@ def test_solve_matches_closed_form(name, kind, make, value):
 
 
 def test_c1_grid_matches_dense_oracle():
-    """Config 1 (4x8 grid, d = 5, rank cap 8, FP64): objective vs the dense IPM."""
+    """Config 1 (4x8 grid, d = 5, TT ranks <= 8, FP64): objective vs the dense IPM."""
     P = _lib()
     g = I.grid_4x8()
     dense = S.solve(OP.maxcut_dense(g.dense))
     pr = P.Problem(P.TTIPM_MAXCUT, g.cores)
-    prm = P.Params(rank_cap=8, stop_gap=3e-7, delta=1e-10, max_iter=60)
+    prm = P.Params(rank_cap=8, iter_rank_cap=8, stop_gap=3e-7, delta=1e-10, max_iter=100)
     st = P.State(pr, prm)
-    res, _ = P.ttipm_solve(pr, st, prm)
+    res, log = P.ttipm_solve(pr, st, prm)
+    assert max(l["rank_x"] for l in log) <= 9          # rank 8 plus the rank-1 shift of Cor. 1
     assert abs(res["pobj"] - dense["pobj"]) / (1 + abs(dense["pobj"])) < 1e-6
+
+
+def _tt_vector_exact(v, d):
+    """Exact TT (mode 2) of a length-2^d vector by successive SVDs (input data)."""
+    cores, r, C = [], 1, np.asarray(v, dtype=np.float64).reshape(1, -1)
+    for k in range(d - 1):
+        C = C.reshape(r * 2, -1)
+        U, s, Vt = np.linalg.svd(C, full_matrices=False)
+        rk = max(1, int(np.sum(s > 1e-14 * max(s[0], 1e-300))))
+        cores.append(U[:, :rk].reshape(r, 2, rk))
+        C = s[:rk, None] * Vt[:rk]
+        r = rk
+    cores.append(C.reshape(r, 2, 1))
+    return cores
+
+
+@pytest.mark.parametrize("d,terms,seed", [(3, 2, 7), (4, 2, 3)])
+def test_cc_matches_dense_oracle(d, terms, seed):
+    """Correlation clustering (inequality constraints X_uv >= 0 on all pairs,
+    mirrored multipliers T, K_T; Sec. 4.3) against the dense IPM oracle."""
+    P = _lib()
+    g = I.signed_kron(d, terms, seed)
+    W = g.dense
+    dense = S.solve(OP.cc_dense(W))
+    negdeg = np.maximum(-W, 0.0).sum(axis=1)
+    pr = P.Problem(P.TTIPM_CC, g.cores, _tt_vector_exact(negdeg, d))
+    prm = P.Params(rank_cap=64, stop_gap=3e-7, delta=1e-10, max_iter=80)
+    st = P.State(pr, prm)
+    res, log = P.ttipm_solve(pr, st, prm)
+    print("cc", d, res, dense["pobj"])
+    assert res["time_to_gap"] > 0
+    assert abs(res["pobj"] - dense["pobj"]) / (1 + abs(dense["pobj"])) < 1e-6
+
+
+def _ratio(v, dv, mask):
+    """largest alpha with v + alpha dv >= 0 on the mask (inf if unbounded)."""
+    sel = (mask > 0.5) & (dv < 0)
+    return np.inf if not np.any(sel) else float(np.min(np.maximum(v[sel], 0.0) / -dv[sel]))
+
+
+def _dense_corrector_cc(prob, X0, Y0, Z0, T0, direction):
+    """Oracle Mehrotra step for the correlation-clustering system (slack and
+    multiplier ratio tests, mu with <T, s>, R_t second-order term)."""
+    d = prob["d"]
+    n = 2 ** d
+    idx = _perm(d)
+    f = ott.full
+    x, z, t = f(X0), f(Z0), f(T0)
+    Ai = ott.full_mat(prob["Aineq"])
+    sg = prob["sense"]
+    mask = f(kkt.one_T(prob))
+    q = int(round(mask.sum()))
+    slack = sg * (f(prob["Bineq"]) - Ai @ x)
+    mu = (x @ z + t @ slack) / (n + q)
+    dX, dY, dT, dZ = kkt.newton_dense(prob, X0, Y0, Z0, T0, mu, direction, sigma_mu=0.0)
+    sym = lambda A: 0.5 * (A + A.T)
+    X, Z = _mat(x, idx), _mat(z, idx)
+    ds = -sg * (Ai @ dX)
+    ap = min(1.0, S.max_step(sym(X), sym(_mat(dX, idx))), _ratio(slack, ds, mask))
+    ad = min(1.0, S.max_step(sym(Z), sym(_mat(dZ, idx))), _ratio(t, dT, mask))
+    mu_aff = ((x + ap * dX) @ (z + ad * dZ) + (t + ad * dT) @ (slack + ap * ds)) / (n + q)
+    sigma = (mu_aff / mu) ** 3
+    DX, DZ = _mat(dX, idx), _mat(dZ, idx)
+    coef = 2.0 if direction == "aho" else 1.0
+    second = DZ @ DX + DX @ DZ if direction == "aho" else DZ @ DX
+    _, _, Rt, Rc = kkt.residuals_dense(prob, X0, Y0, Z0, T0, mu, direction, sigma_mu=sigma * mu)
+    return kkt.newton_dense(prob, X0, Y0, Z0, T0, mu, direction, Rc_override=Rc + _vec(second, idx),
+                            Rt_override=Rt + dT * ds)
+
+
+@pytest.mark.parametrize("direction", ["xz", "aho"])
+def test_full_rank_cc_step_equals_dense_newton(direction):
+    """Correlation clustering at full TT rank: the corrector direction of one
+    ttipm_step (block AMEn with the inequality block row, slack and multiplier
+    ratio tests, mu with <T, s>, R_t second-order term) equals the dense
+    Mehrotra corrector of the oracle."""
+    P = _lib()
+    d = 3
+    g = I.signed_kron(d, 2, 7)
+    negdeg = np.maximum(-g.dense, 0.0).sum(axis=1)
+    nd = _tt_vector_exact(negdeg, d)
+    prob = OP.cc(g.cores, nd)
+    pr = P.Problem(P.TTIPM_CC, g.cores, nd)
+    prm = P.Params(eta0=1e-13, delta=1e-13, rank_cap=64, iter_rank_cap=256, amen_sweeps=8,
+                   n_xz=3 if direction == "xz" else 0, eig_rank=64, eig_sweeps=3)
+    st = P.State(pr, prm)
+    # initial point of Sec. 5.1 with inequalities (reading: alpha_p = lambda* = 2 for A_G = J - I,
+    # lambda*_ineq = 1e-3): X = 2 I + 0.2 (J - I), Z = 2 I, Y = 0, T = 1e-3 (J - I)
+    Iv = ott.rank1_vec([np.array([1.0, 0.0, 0.0, 1.0])] * d)
+    Jv = ott.rank1_vec([np.ones(4)] * d)
+    JmI = ott.add([Jv, Iv], [1.0, -1.0])
+    X0 = ott.add([Iv, JmI], [2.0, 0.2])
+    Z0 = ott.scale(Iv, 2.0)
+    Y0 = ott.scale(Iv, 0.0)
+    T0 = ott.scale(JmI, 1e-3)
+    ref = _dense_corrector_cc(prob, X0, Y0, Z0, T0, direction)
+    P.ttipm_step(pr, st, prm)
+    for comp, r in zip("xytz", ref):
+        got = ott.full(st.export(comp))
+        err = np.linalg.norm(got - r) / max(np.linalg.norm(r), 1e-300)
+        assert err < 1e-8, (comp, err)
