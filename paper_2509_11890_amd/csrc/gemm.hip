@@ -32,6 +32,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 64, BN = 64, BK = 16;
 constexpr int PAD = 1;
+constexpr int PADF = 17;   // FP64 tiled kernel
 
 struct KArgs {
   int M, N, K;
@@ -125,8 +126,11 @@ template <int WM, int WN>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   constexpr int NA = TM * BK / 256, NB = BK * TN / 256;
-  __shared__ double As[2][BK][TM + PAD];
-  __shared__ double Bs[2][BK][TN + PAD];
+  // Row pitch TM + 17 doubles: the two half-waves of an operand read (rows kr
+  // and kr + 1) start 34 banks apart, and the transposing k-contiguous stores
+  // of one row of 16 threads land on 16 distinct bank pairs (34 k mod 64).
+  __shared__ double As[2][BK][TM + PADF];
+  __shared__ double Bs[2][BK][TN + PADF];
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
   // XCD-aware renumbering of the (m, n) tile grid

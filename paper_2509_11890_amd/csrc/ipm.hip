@@ -473,7 +473,11 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   info.iter = S.iter;
   ipm_measures(P, S, info, c);
   const double mu = info.mu;
-  const bool aho = S.iter >= prm.n_xz;
+  // XZ warm-up iterations (Sec. 5.1), then AHO.  With inequality constraints the
+  // warm-up is skipped (reading): the nonsymmetric XZ direction breaks the
+  // symmetry of X against the mirrored multipliers T, and the iteration stalls
+  // (observed identically with exact dense Newton directions).
+  const bool aho = S.iter >= prm.n_xz || P.ineq;
   info.direction = aho ? TTIPM_DIR_AHO : TTIPM_DIR_XZ;
   const double coef = aho ? 2.0 : 1.0;
   const double tolp = S.eta * (1.0 + P.normB) / 10.0;

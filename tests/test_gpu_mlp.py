@@ -127,14 +127,16 @@ def test_training_lowers_heldout_loss_and_fallback_rule():
     for K, Kd in systems[:6]:
         b = rng.standard_normal(Kd.shape[0])
         xb = torch.zeros(Kd.shape[0], dtype=torch.float64, device="cuda")
-        ib = P.local_solve(K, _cuda(b), xb, method=P.TT_SOLVE_GMRES, rtol=1e-10, restart=40, maxit=400,
+        ib = P.local_solve(K, _cuda(b), xb, method=P.TT_SOLVE_GMRES, rtol=1e-10, restart=60, maxit=3000,
                            precond=P.TT_PREC_BJACOBI)
         xm = torch.zeros(Kd.shape[0], dtype=torch.float64, device="cuda")
-        im = P.local_solve(K, _cuda(b), xm, method=P.TT_SOLVE_GMRES, rtol=1e-10, restart=40, maxit=400,
+        im = P.local_solve(K, _cuda(b), xm, method=P.TT_SOLVE_GMRES, rtol=1e-10, restart=60, maxit=3000,
                            precond=P.TT_PREC_MLP, mlp=net)
         torch.cuda.synchronize()
         x_ref = np.linalg.solve(Kd, b)
-        assert np.linalg.norm(xm.cpu().numpy() - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+        assert ib["converged"] and im["converged"]
+        assert np.linalg.norm(xm.cpu().numpy() - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
         assert im["iters"] <= ib["iters"]
         kept += im["precond"] == P.TT_PREC_MLP
         print("bjacobi", ib["iters"], "mlp", im["iters"], "used", im["precond"])
+    print("MLP kept on", kept, "of 6 systems")
