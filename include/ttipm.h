@@ -279,7 +279,9 @@ TTIPM_API int tt_mlp_eval(tt_mlp* m, const tt_mlp_batch* data, double* loss, voi
 
 /* Kernel timing.  While profiling is on, every period-th launch of the
  * instrumented kernels (the FP64 and BF16 MFMA GEMMs, the Jacobi SVD, the LU
- * panel) is bracketed by HIP events recorded on its launch stream.
+ * panel, the Lanczos eigen-solver of the step length, and the single-workgroup
+ * Cholesky / LU / triangular solves as one group) is bracketed by HIP events
+ * recorded on its launch stream.
  * tt_profile_stop synchronises on those events, turns profiling off and writes
  * up to cap records (one per instrumented kernel) into out; *count receives
  * the number of instrumented kernels.  flops and bytes are the algorithmic

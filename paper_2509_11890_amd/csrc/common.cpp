@@ -68,7 +68,7 @@ size_t pool_bytes_in_use() { return pool().in_use; }
 
 namespace {
 const char* const kProfNames[PK_COUNT] = {"gemm_f64_kernel", "gemm_bf16_kernel", "jacobi_svd_kernel",
-                                          "panel_lu_kernel"};
+                                          "panel_lu_kernel", "lanczos_min_kernel", "dense_1wg_kernels"};
 struct ProfRec {
   hipEvent_t a, b;
   int kernel;

@@ -86,7 +86,7 @@ inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 // profiling is on, every period-th launch of an instrumented kernel is
 // bracketed by HIP events recorded on the launch stream; its algorithmic flops
 // and bytes are recorded with it.
-enum ProfKernel { PK_GEMM_F64 = 0, PK_GEMM_BF16, PK_JACOBI_SVD, PK_PANEL_LU, PK_COUNT };
+enum ProfKernel { PK_GEMM_F64 = 0, PK_GEMM_BF16, PK_JACOBI_SVD, PK_PANEL_LU, PK_LANCZOS, PK_DENSE_1WG, PK_COUNT };
 int prof_begin(int kernel, hipStream_t s, double flops, double bytes);   // -1 when not timed
 void prof_end(int token, hipStream_t s);
 void prof_start(int period);

@@ -243,6 +243,20 @@ __global__ __launch_bounds__(DT) void jacobi_svd_lds_kernel(const double* Ag, in
   jacobi_svd_body(As, m, n, Vs, U, sigma, V, order, max_sweeps, tol, sweeps_out, s_rot);
 }
 
+// Only A in LDS, the rotation accumulator in global memory (Vw, n*n doubles):
+// for matrices whose columns fit but whose V does not (e.g. 128 x 96, or the
+// n x n triangular factor of a QR for n up to 143).  Every dot product of a
+// rotation reads LDS; only the shorter V updates go through L2.
+__global__ __launch_bounds__(DT) void jacobi_svd_lds_a_kernel(const double* Ag, int m, int n, double* Vw, double* U,
+                                                              double* sigma, double* V, int* order, int max_sweeps,
+                                                              double tol, int* sweeps_out) {
+  extern __shared__ double lds[];
+  __shared__ int s_rot;
+  double* As = lds;
+  for (long t = threadIdx.x; t < (long)m * n; t += blockDim.x) As[t] = Ag[t];
+  jacobi_svd_body(As, m, n, Vw, U, sigma, V, order, max_sweeps, tol, sweeps_out, s_rot);
+}
+
 // ---------------------------------------------------------------------------
 // LU with partial pivoting of a row-major n x n matrix A and solve for nrhs
 // right-hand sides B (row-major n x nrhs), in place: on exit B holds X.
@@ -438,6 +452,71 @@ __device__ int lz_sturm(const double* a, const double* b, int k, double x) {
   return cnt;
 }
 
+// Smallest eigenvalue theta of the Lanczos tridiagonal T_k (diagonal al,
+// off-diagonal be[0..k-2]) by multisection of the Sturm count, and its unit
+// eigenvector y by inverse iteration.  Called by the whole workgroup; theta is
+// left in *s_theta, y in shared memory; h is scratch.
+__device__ void lz_ritz_min(const double* al, const double* be, int k, double* y, double* h, double* s_lo,
+                            double* s_hi, double* s_theta, int* s_first) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < k; ++i) {
+      const double r = ((i > 0) ? fabs(be[i - 1]) : 0.0) + ((i + 1 < k) ? fabs(be[i]) : 0.0);
+      lo = fmin(lo, al[i] - r);
+      hi = fmax(hi, al[i] + r);
+    }
+    *s_lo = lo - 1e-300;
+    *s_hi = hi + 1e-300;
+  }
+  __syncthreads();
+  for (int round = 0; round < 8; ++round) {
+    const double lo = *s_lo, hi = *s_hi;
+    if (!(hi - lo > 1e-15 * (fabs(lo) + fabs(hi)) + 1e-300)) break;
+    if (tid == 0) *s_first = DT;
+    __syncthreads();
+    const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(DT + 1);
+    if (lz_sturm(al, be, k, x) >= 1) atomicMin(s_first, tid);
+    __syncthreads();
+    if (tid == 0) {
+      const int f = *s_first;
+      const double xf = (f < DT) ? lo + (hi - lo) * (double)(f + 1) / (double)(DT + 1) : hi;
+      const double xp = (f > 0) ? lo + (hi - lo) * (double)f / (double)(DT + 1) : lo;
+      *s_lo = xp;
+      *s_hi = xf;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double theta = 0.5 * (*s_lo + *s_hi);
+    *s_theta = theta;
+    // inverse iteration on T - (theta - delta) I (positive definite)
+    double tn = 0.0;
+    for (int i = 0; i < k; ++i) tn = fmax(tn, fabs(al[i]) + ((i > 0) ? fabs(be[i - 1]) : 0.0) + ((i + 1 < k) ? fabs(be[i]) : 0.0));
+    const double sh = theta - (1e-12 * tn + 1e-300);
+    for (int i = 0; i < k; ++i) y[i] = 1.0;
+    for (int it = 0; it < 3; ++it) {
+      // LDL^T of the tridiagonal T - sh I, then solve in place (h holds D)
+      double dprev = al[0] - sh;
+      h[0] = dprev;
+      for (int i = 1; i < k; ++i) {
+        const double l = be[i - 1] / dprev;
+        dprev = al[i] - sh - l * be[i - 1];
+        if (dprev == 0.0) dprev = 1e-300;
+        h[i] = dprev;
+      }
+      for (int i = 1; i < k; ++i) y[i] -= (be[i - 1] / h[i - 1]) * y[i - 1];
+      for (int i = 0; i < k; ++i) y[i] /= h[i];
+      for (int i = k - 2; i >= 0; --i) y[i] -= (be[i] / h[i]) * y[i + 1];
+      double nn = 0.0;
+      for (int i = 0; i < k; ++i) nn += y[i] * y[i];
+      nn = sqrt(nn) + 1e-300;
+      for (int i = 0; i < k; ++i) y[i] /= nn;
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p, int kmax, int restarts, double tol,
                                                          double* Q, double* v, double* lam_out) {
   __shared__ double al[LZ_MAX], be[LZ_MAX], y[LZ_MAX], h[LZ_MAX];
@@ -530,63 +609,14 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
         if (tid == 0) be[j] = bj;
       }
       __syncthreads();
-    }
-    // smallest eigenvalue of T_k by multisection of the Sturm count
-    if (tid == 0) {
-      double lo = 1e300, hi = -1e300;
-      for (int i = 0; i < k; ++i) {
-        const double r = ((i > 0) ? fabs(be[i - 1]) : 0.0) + ((i + 1 < k) ? fabs(be[i]) : 0.0);
-        lo = fmin(lo, al[i] - r);
-        hi = fmax(hi, al[i] + r);
-      }
-      s_lo = lo - 1e-300;
-      s_hi = hi + 1e-300;
-    }
-    __syncthreads();
-    for (int round = 0; round < 8; ++round) {
-      const double lo = s_lo, hi = s_hi;
-      if (!(hi - lo > 1e-15 * (fabs(lo) + fabs(hi)) + 1e-300)) break;
-      if (tid == 0) s_first = DT;
-      __syncthreads();
-      const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(DT + 1);
-      if (lz_sturm(al, be, k, x) >= 1) atomicMin(&s_first, tid);
-      __syncthreads();
-      if (tid == 0) {
-        const int f = s_first;
-        const double xf = (f < DT) ? lo + (hi - lo) * (double)(f + 1) / (double)(DT + 1) : hi;
-        const double xp = (f > 0) ? lo + (hi - lo) * (double)f / (double)(DT + 1) : lo;
-        s_lo = xp;
-        s_hi = xf;
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      theta = 0.5 * (s_lo + s_hi);
-      s_theta = theta;
-      // inverse iteration on T - (theta - delta) I (positive definite)
-      double tn = 0.0;
-      for (int i = 0; i < k; ++i) tn = fmax(tn, fabs(al[i]) + ((i > 0) ? fabs(be[i - 1]) : 0.0) + fabs(be[i]));
-      const double sh = theta - (1e-12 * tn + 1e-300);
-      for (int i = 0; i < k; ++i) y[i] = 1.0;
-      for (int it = 0; it < 3; ++it) {
-        // LDL^T of the tridiagonal T - sh I, then solve in place (h holds D, reuse be for L)
-        double dprev = al[0] - sh;
-        h[0] = dprev;
-        for (int i = 1; i < k; ++i) {
-          const double l = be[i - 1] / dprev;
-          dprev = al[i] - sh - l * be[i - 1];
-          if (dprev == 0.0) dprev = 1e-300;
-          h[i] = dprev;
-        }
-        for (int i = 1; i < k; ++i) y[i] -= (be[i - 1] / h[i - 1]) * y[i - 1];
-        for (int i = 0; i < k; ++i) y[i] /= h[i];
-        for (int i = k - 2; i >= 0; --i) y[i] -= (be[i] / h[i]) * y[i + 1];
-        double nn = 0.0;
-        for (int i = 0; i < k; ++i) nn += y[i] * y[i];
-        nn = sqrt(nn) + 1e-300;
-        for (int i = 0; i < k; ++i) y[i] /= nn;
+      // every 8 steps: stop once the smallest Ritz pair of T_k has converged
+      // (its residual norm is |beta_k y_k|, exact under full reorthogonalisation)
+      if (k >= 16 && k % 8 == 0 && k < kmax) {
+        lz_ritz_min(al, be, k, y, h, &s_lo, &s_hi, &s_theta, &s_first);
+        if (be[k - 1] != 0.0 && fabs(be[k - 1] * y[k - 1]) <= 0.5 * tol * s_bnorm) break;
       }
     }
+    lz_ritz_min(al, be, k, y, h, &s_lo, &s_hi, &s_theta, &s_first);
     __syncthreads();
     theta = s_theta;
     // Ritz vector v = Q_k y and its residual |B v - theta v|
@@ -626,8 +656,10 @@ static size_t jacobi_lds_limit() {
     }
     size_t lim = (size_t)v - 256;
     if (lim > 65536 - 256 &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_lds_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
+        (hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_lds_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess ||
+         hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_lds_a_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess)) {
       (void)hipGetLastError();
       lim = 65536 - 256;
     }
@@ -640,8 +672,12 @@ void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, dou
                hipStream_t s, int max_sweeps, double tol) {
   const int tok = prof_begin(PK_JACOBI_SVD, s, 0.0, 8.0 * ((double)m * n * 2 + (double)n * n + n));
   const size_t lds_bytes = sizeof(double) * ((size_t)m * n + (size_t)n * n);
+  const size_t lds_a_bytes = sizeof(double) * (size_t)m * n;
   if (lds_bytes <= jacobi_lds_limit()) {
     hipLaunchKernelGGL(jacobi_svd_lds_kernel, dim3(1), dim3(DT), lds_bytes, s, A, m, n, U, sigma, V, iwork,
+                       max_sweeps, tol, iwork + n);
+  } else if (lds_a_bytes <= jacobi_lds_limit()) {
+    hipLaunchKernelGGL(jacobi_svd_lds_a_kernel, dim3(1), dim3(DT), lds_a_bytes, s, A, m, n, work, U, sigma, V, iwork,
                        max_sweeps, tol, iwork + n);
   } else {
     hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(DT), 0, s, A, m, n, work, U, sigma, V, iwork,
@@ -654,25 +690,40 @@ void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, dou
 void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* work, hipStream_t s, int kmax,
                        int restarts, double tol) {
   kmax = std::max(1, std::min({kmax, p, LZ_MAX - 1}));
+  // algorithmic traffic: B read once (the iteration count is decided on the device)
+  const int tok = prof_begin(PK_LANCZOS, s, 0.0, 8.0 * (double)p * p);
   hipLaunchKernelGGL(lanczos_min_kernel, dim3(1), dim3(DT), 0, s, B, p, kmax, restarts, tol, work, v, lam);
+  prof_end(tok, s);
   TT_HIP(hipGetLastError());
 }
 
+// The single-workgroup factorisations below are timed as one group; their
+// algorithmic flops are the textbook counts.
 void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s) {
+  const double nn = n;
+  const int tok = prof_begin(PK_DENSE_1WG, s, 2.0 / 3.0 * nn * nn * nn + 2.0 * nn * nn * nrhs,
+                             8.0 * (2.0 * nn * nn + 2.0 * nn * nrhs));
   hipLaunchKernelGGL(lu_solve_kernel, dim3(1), dim3(DT), 0, s, A, n, B, nrhs, status);
+  prof_end(tok, s);
   TT_HIP(hipGetLastError());
 }
 
 void dense_cholesky(double* A, int n, int* status, hipStream_t s) {
+  const double nn = n;
+  const int tok = prof_begin(PK_DENSE_1WG, s, nn * nn * nn / 3.0, 8.0 * 2.0 * nn * nn);
   hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(DT), 0, s, A, n, status);
+  prof_end(tok, s);
   TT_HIP(hipGetLastError());
 }
 
 void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s) {
+  const double nn = n;
+  const int tok = prof_begin(PK_DENSE_1WG, s, nn * nn * nrhs, 8.0 * (0.5 * nn * nn + 2.0 * nn * nrhs));
   if (transpose)
     hipLaunchKernelGGL(trsm_lower_t_kernel, dim3(1), dim3(DT), 0, s, L, n, B, nrhs);
   else
     hipLaunchKernelGGL(trsm_lower_kernel, dim3(1), dim3(DT), 0, s, L, n, B, nrhs);
+  prof_end(tok, s);
   TT_HIP(hipGetLastError());
 }
 

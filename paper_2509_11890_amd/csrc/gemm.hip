@@ -115,17 +115,29 @@ __device__ __forceinline__ void store_tile(const KArgs& g, int bidx, int slice, 
       }
 }
 
-// FP64 kernel, templated on the MFMA tiles per wave (WM x WN of 16 x 16): the
-// workgroup tile is (32 WM) x (32 WN).  The next k-tile is fetched into
+// FP64 kernel, templated on the MFMA tiles per wave (WM x WN of 16 x 16; the
+// workgroup tile is (32 WM) x (32 WN)) and on which operand index is unit
+// stride (AKC: A is k-contiguous, BKC: B is k-contiguous), so that the copy
+// pattern is fixed at compile time.  Every thread owns NA elements of each A
+// tile and NB of each B tile at fixed (row, k) positions; their 32-bit element
+// offsets are computed once, so a k-step costs one uniform pointer bump plus
+// one load per element.  Rows or columns past the matrix edge are clamped to
+// the last valid one (no divergent branches in the loop); only a ragged last
+// k-step checks k.  The next k-tile is fetched into
 // registers while the current one is consumed from LDS (two LDS buffers, one
-// barrier per k-step), so global latency overlaps the MFMA work.  Workgroups
-// are dispatched round-robin over the eight XCDs; tiles are renumbered so that
-// each XCD works on a contiguous run of output tiles (shared A row panels and
-// B column panels stay in that XCD's L2).
-template <int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
+// barrier per k-step).  The register budget is capped at two waves per SIMD
+// (256 VGPR + AGPR): a second wave hides the first one's LDS and barrier
+// stalls, which measured faster than one wave with more prefetch registers.
+// Workgroups are dispatched round-robin over the eight
+// XCDs; tiles are renumbered so that each XCD works on a contiguous run of
+// output tiles (shared A row panels and B column panels stay in its L2).
+template <int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_kernel(KArgs g) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   constexpr int NA = TM * BK / 256, NB = BK * TN / 256;
+  // element e of a thread sits at (fixed, base + STEP * e) along (m, k) or (k, m)
+  constexpr int ASTEP = AKC ? 256 / BK : 256 / TM;
+  constexpr int BSTEP = BKC ? 256 / BK : 256 / TN;
   // Row pitch TM + 17 doubles: the two half-waves of an operand read (rows kr
   // and kr + 1) start 34 banks apart, and the transposing k-contiguous stores
   // of one row of 16 threads land on 16 distinct bank pairs (34 k mod 64).
@@ -150,35 +162,65 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
   const int kbeg = slice * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
   const double* A = g.A + (long)bidx * g.sA;
   const double* B = g.B + (long)bidx * g.sB;
-  const bool a_kc = (g.ak == 1), b_kc = (g.bk == 1 && g.bn != 1);
+  // tile positions of this thread's elements
+  const int a_mt = AKC ? tid / BK : tid % TM;   // m of element 0
+  const int a_kt = AKC ? tid % BK : tid / TM;   // k of element 0
+  const int b_nt = BKC ? tid / BK : tid % TN;
+  const int b_kt = BKC ? tid % BK : tid / TN;
+  // Rows of A past M (columns of B past N) are clamped to the last valid one:
+  // they only feed output rows (columns) that the epilogue never stores, so
+  // they need no masking.  Only k past the end must contribute zero.
+  // Byte offsets (32-bit) from the uniform k-step base pointer: the loads
+  // then take the scalar-base + vector-offset form with no 64-bit VALU math.
+  unsigned offA[NA], offB[NB];
+#pragma unroll
+  for (int e = 0; e < NA; ++e) {
+    const int m = m0 + a_mt + (AKC ? ASTEP * e : 0), k = a_kt + (AKC ? 0 : ASTEP * e);
+    offA[e] = 8u * (unsigned)(min(m, g.M - 1) * (int)g.am + k * (int)g.ak);
+  }
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int n = n0 + b_nt + (BKC ? BSTEP * e : 0), k = b_kt + (BKC ? 0 : BSTEP * e);
+    offB[e] = 8u * (unsigned)(min(n, g.N - 1) * (int)g.bn + k * (int)g.bk);
+  }
   double ra[NA], rb[NB];
+  // Full k-steps load without any select, so the loads stay in flight across
+  // the MFMA block and are first waited on when stashed into LDS.
   auto fetch = [&](int k0) {
+    const char* Ak = reinterpret_cast<const char*>(A + (long)k0 * g.ak);
+    const char* Bk = reinterpret_cast<const char*>(B + (long)k0 * g.bk);
+    if (k0 + BK <= kend) {
 #pragma unroll
-    for (int e = 0; e < NA; ++e) {
-      const int q = tid + 256 * e;
-      const int m = a_kc ? q / BK : q % TM, k = a_kc ? q % BK : q / TM;
-      const int gm = m0 + m, gk = k0 + k;
-      ra[e] = (gm < g.M && gk < kend) ? A[(long)gm * g.am + (long)gk * g.ak] : 0.0;
-    }
+      for (int e = 0; e < NA; ++e) ra[e] = *reinterpret_cast<const double*>(Ak + offA[e]);
 #pragma unroll
-    for (int e = 0; e < NB; ++e) {
-      const int q = tid + 256 * e;
-      const int n = b_kc ? q / BK : q % TN, k = b_kc ? q % BK : q / TN;
-      const int gn = n0 + n, gk = k0 + k;
-      rb[e] = (gn < g.N && gk < kend) ? B[(long)gk * g.bk + (long)gn * g.bn] : 0.0;
+      for (int e = 0; e < NB; ++e) rb[e] = *reinterpret_cast<const double*>(Bk + offB[e]);
+    } else {
+      // ragged last k-step: clamp k to the last valid index and zero it
+#pragma unroll
+      for (int e = 0; e < NA; ++e) {
+        const int k = a_kt + (AKC ? 0 : ASTEP * e);
+        const int kc = min(k, kend - 1 - k0);
+        const double v = *reinterpret_cast<const double*>(Ak + offA[e] + 8L * (kc - k) * g.ak);
+        ra[e] = (k0 + k < kend) ? v : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const int k = b_kt + (BKC ? 0 : BSTEP * e);
+        const int kc = min(k, kend - 1 - k0);
+        const double v = *reinterpret_cast<const double*>(Bk + offB[e] + 8L * (kc - k) * g.bk);
+        rb[e] = (k0 + k < kend) ? v : 0.0;
+      }
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
-      const int q = tid + 256 * e;
-      const int m = a_kc ? q / BK : q % TM, k = a_kc ? q % BK : q / TM;
+      const int m = a_mt + (AKC ? ASTEP * e : 0), k = a_kt + (AKC ? 0 : ASTEP * e);
       As[buf][k][m] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      const int q = tid + 256 * e;
-      const int n = b_kc ? q / BK : q % TN, k = b_kc ? q % BK : q / TN;
+      const int n = b_nt + (BKC ? BSTEP * e : 0), k = b_kt + (BKC ? 0 : BSTEP * e);
       Bs[buf][k][n] = rb[e];
     }
   };
@@ -318,8 +360,18 @@ __global__ void splitk_reduce_kernel(KArgs g, int batch) {
   int b = (int)(idx / ((long)g.M * g.N));
   long rem = idx % ((long)g.M * g.N);
   int row = (int)(rem / g.N), col = (int)(rem % g.N);
-  double s = 0.0;
-  for (int sl = 0; sl < g.kslices; ++sl) s += g.P[(((long)b * g.kslices + sl) * g.M + row) * g.N + col];
+  // eight independent partial sums keep eight loads in flight per thread; the
+  // association is fixed, so results are reproducible run to run
+  const long stride = (long)g.M * g.N;
+  const double* p = g.P + (long)b * g.kslices * stride + rem;
+  double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int sl = 0;
+  for (; sl + 8 <= g.kslices; sl += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) part[u] += p[(long)(sl + u) * stride];
+  }
+  for (; sl < g.kslices; ++sl) part[0] += p[(long)sl * stride];
+  const double s = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
   double* c = g.C + (long)b * g.sC + (long)row * g.cm + (long)col * g.cn;
   *c = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*c);
 }
@@ -337,6 +389,19 @@ __global__ void scale_c_kernel(double* C, long cm, long cn, long sC, int M, int 
 
 static Workspace g_default_ws;
 
+template <int WM, int WN>
+void launch_f64(dim3 grid, hipStream_t stream, const KArgs& g) {
+  const bool akc = (g.ak == 1), bkc = (g.bk == 1 && g.bn != 1);
+  if (akc && bkc)
+    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, true, true>), grid, dim3(256), 0, stream, g);
+  else if (akc)
+    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, true, false>), grid, dim3(256), 0, stream, g);
+  else if (bkc)
+    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, false, true>), grid, dim3(256), 0, stream, g);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, false, false>), grid, dim3(256), 0, stream, g);
+}
+
 void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   if (q.M <= 0 || q.N <= 0 || q.batch <= 0) return;
   if (q.K <= 0) {  // C = beta C
@@ -346,6 +411,12 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
     TT_HIP(hipGetLastError());
     return;
   }
+  // the FP64 kernel addresses operands with 32-bit byte offsets from the
+  // (64-bit) batch and k-step base; strides are non-negative for every caller
+  if (q.am < 0 || q.ak < 0 || q.bk < 0 || q.bn < 0 ||
+      (double)(q.M - 1) * q.am + (double)(q.K - 1 + BK) * q.ak > 536870911.0 ||
+      (double)(q.N - 1) * q.bn + (double)(q.K - 1 + BK) * q.bk > 536870911.0)
+    throw Error(TT_ERR_ARG, "gemm operand too large for 32-bit byte offsets");
   KArgs g;
   g.M = q.M; g.N = q.N; g.K = q.K;
   g.A = q.A; g.am = q.am; g.ak = q.ak; g.sA = q.sA;
@@ -403,13 +474,13 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   if (prec == GemmPrec::BF16)
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
   else if (TMs == 128 && TNs == 128)
-    hipLaunchKernelGGL((gemm_f64_kernel<4, 4>), grid, dim3(256), 0, stream, g);
+    launch_f64<4, 4>(grid, stream, g);
   else if (TMs == 128)
-    hipLaunchKernelGGL((gemm_f64_kernel<4, 2>), grid, dim3(256), 0, stream, g);
+    launch_f64<4, 2>(grid, stream, g);
   else if (TNs == 128)
-    hipLaunchKernelGGL((gemm_f64_kernel<2, 4>), grid, dim3(256), 0, stream, g);
+    launch_f64<2, 4>(grid, stream, g);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<2, 2>), grid, dim3(256), 0, stream, g);
+    launch_f64<2, 2>(grid, stream, g);
   prof_end(tok, stream);
   TT_HIP(hipGetLastError());
   if (ks > 1) {

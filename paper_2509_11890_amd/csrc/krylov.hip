@@ -14,10 +14,62 @@ namespace ttipm {
 
 double dev_norm(const double* x, long n, Ctx& c);
 
+namespace {
+
+// One Arnoldi column on the device: h[0..j] are the projections of the new
+// vector and h[j+1] its squared norm after orthogonalisation.  Stores the
+// column into H (row-major, (m+1) x m), applies the previous Givens rotations,
+// forms rotation j, updates the rotated right-hand side g, and records the
+// residual estimate |g[j+1]|, the norm hn and the scale 1/hn of the new vector.
+__global__ void arnoldi_givens_kernel(int j, int m, const double* h, double* H, double* cs, double* sn, double* g,
+                                      double* res, double* hns, double* scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double hn = sqrt(fmax(h[j + 1], 0.0));
+  for (int i = 0; i <= j; ++i) H[(long)i * m + j] = h[i];
+  H[(long)(j + 1) * m + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[(long)i * m + j], b = H[(long)(i + 1) * m + j];
+    H[(long)i * m + j] = cs[i] * a + sn[i] * b;
+    H[(long)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[(long)j * m + j], b = H[(long)(j + 1) * m + j];
+  const double rr = hypot(a, b);
+  cs[j] = (rr == 0.0) ? 1.0 : a / rr;
+  sn[j] = (rr == 0.0) ? 0.0 : b / rr;
+  H[(long)j * m + j] = rr;
+  H[(long)(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  res[j] = fabs(g[j + 1]);
+  hns[j] = hn;
+  scal[0] = (hn > 0.0) ? 1.0 / hn : 0.0;
+}
+
+// x *= scal[0] (device scalar)
+__global__ void scale_dev_kernel(long n, double* x, const double* scal) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= scal[0];
+}
+
+__global__ void set_first_kernel(double* g, int len, double beta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) g[i] = (i == 0) ? beta : 0.0;
+}
+
+}  // namespace
+
+// Arnoldi steps run without host round trips: the Givens rotations are applied
+// on the device and the host reads the residual estimates every kCheck steps
+// (and at the end of a cycle).  A cycle that converged inside such a block
+// keeps only the columns up to the converged step (the rotated system of a
+// prefix is final once its step is done), so the extra steps cost time only;
+// info.iters counts the steps the solution uses.
 void gmres_solve(long n, const KrylovOps& ops, const double* f, double* u, const KrylovParams& prm, KrylovInfo& info,
                  Ctx& c) {
+  constexpr int kCheck = 4;
   const int m = std::max(1, prm.restart);
   DevBuf V((size_t)(m + 1) * n), r0(n), z(n), w(n), h(m + 2), h2(m + 2), yv(m + 1);
+  DevBuf Hd((size_t)(m + 1) * m), csd(m), snd(m), gd(m + 1), resd(m), hnd(m), scal(2);
   c.dot_part.reserve(mdot_part_size(m + 1));
   info = KrylovInfo{};
   const double bn = dev_norm(f, n, c);
@@ -26,8 +78,7 @@ void gmres_solve(long n, const KrylovOps& ops, const double* f, double* u, const
     c.sync();
     return;
   }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
-  double* hh = c.host(m + 2);
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1);
   double best = std::numeric_limits<double>::infinity();
   int stall = 0;
   while (true) {
@@ -46,9 +97,9 @@ void gmres_solve(long n, const KrylovOps& ops, const double* f, double* u, const
     }
     const double target = prm.mixed ? std::max(prm.rtol * bn, prm.inner_tol * beta) : prm.rtol * bn;
     axpby(n, 1.0 / beta, r0.get(), 0.0, V.get(), c.s);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int j = 0;
+    hipLaunchKernelGGL(set_first_kernel, dim3(nblocks(m + 1, 64)), dim3(64), 0, c.s, gd.get(), m + 1, beta);
+    TT_HIP(hipGetLastError());
+    int j = 0, jend = -1, jchk = 0;
     for (; j < m && info.iters < prm.maxit; ++j) {
       ++info.iters;
       const double* vj = V.get() + (size_t)j * n;
@@ -65,40 +116,49 @@ void gmres_solve(long n, const KrylovOps& ops, const double* f, double* u, const
       gemv_update(n, j + 1, V.get(), n, h2.get(), -1.0, v1, c.s);
       axpby(j + 1, 1.0, h2.get(), 1.0, h.get(), c.s);
       mdot(n, 1, v1, n, v1, h.get() + j + 1, c.dot_part.get(), c.s);
-      TT_HIP(hipMemcpyAsync(hh, h.get(), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, c.s));
-      c.sync();
-      const double hn = std::sqrt(std::max(hh[j + 1], 0.0));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
-      H[(size_t)(j + 1) * m + j] = hn;
-      if (hn > 0.0) axpby(n, 0.0, v1, 1.0 / hn, v1, c.s);
-      for (int i = 0; i < j; ++i) {
-        const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-      }
-      const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
-      const double rr = std::hypot(a, b);
-      cs[j] = (rr == 0.0) ? 1.0 : a / rr;
-      sn[j] = (rr == 0.0) ? 0.0 : b / rr;
-      H[(size_t)j * m + j] = rr;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      if (std::fabs(g[j + 1]) <= target || hn == 0.0) {
-        ++j;
-        break;
+      hipLaunchKernelGGL(arnoldi_givens_kernel, dim3(1), dim3(64), 0, c.s, j, m, h.get(), Hd.get(), csd.get(),
+                         snd.get(), gd.get(), resd.get(), hnd.get(), scal.get());
+      hipLaunchKernelGGL(scale_dev_kernel, dim3(nblocks(n, 256)), dim3(256), 0, c.s, n, v1, scal.get());
+      TT_HIP(hipGetLastError());
+      const bool last = (j + 1 == m) || (info.iters >= prm.maxit);
+      if ((j + 1 - jchk) >= kCheck || last) {
+        // residual estimates and norms of steps jchk .. j
+        const int cnt = j + 1 - jchk;
+        double* hh = c.host(2 * m + 2);   // pinned: residual estimates and norms of the block
+        TT_HIP(hipMemcpyAsync(hh, resd.get() + jchk, sizeof(double) * cnt, hipMemcpyDeviceToHost, c.s));
+        TT_HIP(hipMemcpyAsync(hh + m + 1, hnd.get() + jchk, sizeof(double) * cnt, hipMemcpyDeviceToHost, c.s));
+        c.sync();
+        for (int t = 0; t < cnt; ++t) {
+          if (hh[t] <= target || hh[m + 1 + t] == 0.0) {
+            jend = jchk + t + 1;
+            break;
+          }
+        }
+        jchk = j + 1;
+        if (jend >= 0) break;
       }
     }
-    std::vector<double> y(j, 0.0);
-    for (int i = j - 1; i >= 0; --i) {
+    if (jend < 0) {
+      jend = j;
+    } else {
+      info.iters -= (j + 1) - jend;   // steps computed past the converged one are not part of the solve
+    }
+    // back substitution on the host with the final rotated columns 0 .. jend-1
+    if (jend > 0) {
+      TT_HIP(hipMemcpyAsync(H.data(), Hd.get(), sizeof(double) * (size_t)jend * m, hipMemcpyDeviceToHost, c.s));
+      TT_HIP(hipMemcpyAsync(g.data(), gd.get(), sizeof(double) * (size_t)jend, hipMemcpyDeviceToHost, c.s));
+      c.sync();
+    }
+    std::vector<double> y(jend, 0.0);
+    for (int i = jend - 1; i >= 0; --i) {
       double acc = g[i];
-      for (int l = i + 1; l < j; ++l) acc -= H[(size_t)i * m + l] * y[l];
+      for (int l = i + 1; l < jend; ++l) acc -= H[(size_t)i * m + l] * y[l];
       y[i] = (H[(size_t)i * m + i] != 0.0) ? acc / H[(size_t)i * m + i] : 0.0;
     }
-    if (j > 0) {
-      TT_HIP(hipMemcpyAsync(yv.get(), y.data(), sizeof(double) * j, hipMemcpyHostToDevice, c.s));
+    if (jend > 0) {
+      TT_HIP(hipMemcpyAsync(yv.get(), y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, c.s));
       fill(n, 0.0, z.get(), c.s);
-      gemv_update(n, j, V.get(), n, yv.get(), 1.0, z.get(), c.s);      // z = V y
+      gemv_update(n, jend, V.get(), n, yv.get(), 1.0, z.get(), c.s);      // z = V y
       if (ops.precond) {
         ops.precond(z.get(), w.get());
         axpby(n, 1.0, w.get(), 1.0, u, c.s);
