@@ -166,6 +166,29 @@ def cpu_baseline(graph, budget_s=60.0):
             "pobj_1e9": res["pobj"], "dobj_1e9": res["dobj"]}
 
 
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    record (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a
+    copy of known size), or None when there is no record or the kernel's source
+    has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        with open(os.path.join(ROOT, kv["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != kv["source_sha256"]:
+                return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def calibration_copy(torch):
     """One elementwise pass that reads 256 MiB and writes 256 MiB: the
     reference dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -250,13 +273,15 @@ def main():
             prec = "bf16" if "bf16" in dom_name else "f64"
             achieved = dom["flops"] / (dom["time_ms"] / 1e3)
             roof = {"bound": "mfma", "kernel": dom_name, "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved / PEAK[prec], "traffic": None,
+                    "unit": "TFLOP/s", "frac": achieved / PEAK[prec], "traffic": stored_traffic(dom_name, args.workload),
+                    "algorithmic_bytes_per_launch": dom["bytes"] / dom["timed"],
                     "avg_launch_us": t_avg * 1e6, "launches": dom["launches"], "timed_launches": dom["timed"],
                     "flops_per_launch": dom["flops"] / dom["timed"]}
         else:
             achieved = dom["bytes"] / (dom["time_ms"] / 1e3)
             roof = {"bound": "hbm", "kernel": dom_name, "achieved": achieved / 1e9, "peak": HBM / 1e9,
-                    "unit": "GB/s", "frac": achieved / HBM, "traffic": None, "avg_launch_us": t_avg * 1e6,
+                    "unit": "GB/s", "frac": achieved / HBM, "traffic": stored_traffic(dom_name, args.workload),
+                    "avg_launch_us": t_avg * 1e6,
                     "launches": dom["launches"], "timed_launches": dom["timed"],
                     "bytes_per_launch": dom["bytes"] / dom["timed"]}
     kernel_share = {k: round(v["time_ms"] * (args.profile_period if v["timed"] else 0) / 1e3 / args.steps, 4)

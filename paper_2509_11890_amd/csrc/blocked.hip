@@ -305,10 +305,8 @@ void lu_rec(double* A, int n, BlockedFactors& f, int* piv, int j0, int w, int* s
   const int nb = f.nb;
   if (w <= nb) {
     const double pm = n - j0;
-    const int tok = prof_begin(PK_PANEL_LU, c.s, pm * w * (double)w, 16.0 * pm * w);
-    hipLaunchKernelGGL(panel_lu_kernel, dim3(1), dim3(BT), 0, c.s, A + (long)j0 * n + j0, n - j0, w, (long)n, piv + j0,
-                       j0, st);
-    prof_end(tok, c.s);
+    launch_prof(PK_PANEL_LU, pm * w * (double)w, 16.0 * pm * w, panel_lu_kernel, dim3(1), dim3(BT), 0, c.s,
+                A + (long)j0 * n + j0, n - j0, w, (long)n, piv + j0, j0, st);
     double* Ajj = A + (long)j0 * n + j0;
     const unsigned tb = std::max(64, ((w + 63) / 64) * 64);
     hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(tb), 0, c.s, Ajj, w, (long)n,

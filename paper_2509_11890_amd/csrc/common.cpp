@@ -98,23 +98,15 @@ hipEvent_t prof_event(Prof& P) {
 }
 }  // namespace
 
-int prof_begin(int kernel, hipStream_t s, double flops, double bytes) {
+ProfLaunch prof_launch(int kernel, double flops, double bytes) {
   Prof& P = prof();
   std::lock_guard<std::mutex> g(P.mu);
-  if (!P.on) return -1;
+  if (!P.on) return {};
   const long n = P.launches[kernel]++;
-  if (n % P.period) return -1;
+  if (n % P.period) return {};
   ProfRec r{prof_event(P), prof_event(P), kernel, flops, bytes};
-  TT_HIP(hipEventRecord(r.a, s));
   P.recs.push_back(r);
-  return (int)P.recs.size() - 1;
-}
-
-void prof_end(int token, hipStream_t s) {
-  if (token < 0) return;
-  Prof& P = prof();
-  std::lock_guard<std::mutex> g(P.mu);
-  TT_HIP(hipEventRecord(P.recs[token].b, s));
+  return {r.a, r.b};
 }
 
 void prof_start(int period) {

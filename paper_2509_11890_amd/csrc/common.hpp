@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -87,10 +88,27 @@ inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 // bracketed by HIP events recorded on the launch stream; its algorithmic flops
 // and bytes are recorded with it.
 enum ProfKernel { PK_GEMM_F64 = 0, PK_GEMM_BF16, PK_JACOBI_SVD, PK_PANEL_LU, PK_LANCZOS, PK_DENSE_1WG, PK_COUNT };
-int prof_begin(int kernel, hipStream_t s, double flops, double bytes);   // -1 when not timed
-void prof_end(int token, hipStream_t s);
+// A timed launch carries a start and a stop event that the dispatch itself
+// records (hipExtLaunchKernel), so the measured time is the kernel's execution
+// without the launch gap that separately recorded events would include.
+struct ProfLaunch {
+  hipEvent_t start = nullptr, stop = nullptr;   // null: this launch is not timed
+};
+ProfLaunch prof_launch(int kernel, double flops, double bytes);
 void prof_start(int period);
 int prof_stop(tt_kernel_stat* out, int cap);
+
+// hipLaunchKernelGGL with the launch counted (and every period-th one timed)
+// as an instance of the instrumented kernel `kernel`.
+template <typename F, typename... Args>
+void launch_prof(int kernel, double flops, double bytes, F func, dim3 grid, dim3 block, unsigned shmem, hipStream_t s,
+                 Args... args) {
+  const ProfLaunch pl = prof_launch(kernel, flops, bytes);
+  if (pl.start)
+    hipExtLaunchKernelGGL(func, grid, block, shmem, s, pl.start, pl.stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(func, grid, block, shmem, s, args...);
+}
 
 // Number of blocks for n items with b threads per block (at least 1).
 inline unsigned nblocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }

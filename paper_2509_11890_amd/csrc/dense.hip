@@ -668,22 +668,25 @@ static size_t jacobi_lds_limit() {
   return limit;
 }
 
+bool dense_svd_fits_lds(int m, int n) {
+  return sizeof(double) * ((size_t)m * n + (size_t)n * n) <= jacobi_lds_limit();
+}
+
 void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, double* work, int* iwork,
                hipStream_t s, int max_sweeps, double tol) {
-  const int tok = prof_begin(PK_JACOBI_SVD, s, 0.0, 8.0 * ((double)m * n * 2 + (double)n * n + n));
+  const double bytes = 8.0 * ((double)m * n * 2 + (double)n * n + n);
   const size_t lds_bytes = sizeof(double) * ((size_t)m * n + (size_t)n * n);
   const size_t lds_a_bytes = sizeof(double) * (size_t)m * n;
   if (lds_bytes <= jacobi_lds_limit()) {
-    hipLaunchKernelGGL(jacobi_svd_lds_kernel, dim3(1), dim3(DT), lds_bytes, s, A, m, n, U, sigma, V, iwork,
-                       max_sweeps, tol, iwork + n);
+    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_kernel, dim3(1), dim3(DT), (unsigned)lds_bytes, s,
+                (const double*)A, m, n, U, sigma, V, iwork, max_sweeps, tol, iwork + n);
   } else if (lds_a_bytes <= jacobi_lds_limit()) {
-    hipLaunchKernelGGL(jacobi_svd_lds_a_kernel, dim3(1), dim3(DT), lds_a_bytes, s, A, m, n, work, U, sigma, V, iwork,
-                       max_sweeps, tol, iwork + n);
+    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_a_kernel, dim3(1), dim3(DT), (unsigned)lds_a_bytes, s,
+                (const double*)A, m, n, work, U, sigma, V, iwork, max_sweeps, tol, iwork + n);
   } else {
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(DT), 0, s, A, m, n, work, U, sigma, V, iwork,
-                       max_sweeps, tol, iwork + n);
+    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_kernel, dim3(1), dim3(DT), 0u, s, A, m, n, work, U, sigma, V,
+                iwork, max_sweeps, tol, iwork + n);
   }
-  prof_end(tok, s);
   TT_HIP(hipGetLastError());
 }
 
@@ -691,9 +694,8 @@ void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* w
                        int restarts, double tol) {
   kmax = std::max(1, std::min({kmax, p, LZ_MAX - 1}));
   // algorithmic traffic: B read once (the iteration count is decided on the device)
-  const int tok = prof_begin(PK_LANCZOS, s, 0.0, 8.0 * (double)p * p);
-  hipLaunchKernelGGL(lanczos_min_kernel, dim3(1), dim3(DT), 0, s, B, p, kmax, restarts, tol, work, v, lam);
-  prof_end(tok, s);
+  launch_prof(PK_LANCZOS, 0.0, 8.0 * (double)p * p, lanczos_min_kernel, dim3(1), dim3(DT), 0u, s, B, p, kmax,
+              restarts, tol, work, v, lam);
   TT_HIP(hipGetLastError());
 }
 
@@ -701,29 +703,25 @@ void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* w
 // algorithmic flops are the textbook counts.
 void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s) {
   const double nn = n;
-  const int tok = prof_begin(PK_DENSE_1WG, s, 2.0 / 3.0 * nn * nn * nn + 2.0 * nn * nn * nrhs,
-                             8.0 * (2.0 * nn * nn + 2.0 * nn * nrhs));
-  hipLaunchKernelGGL(lu_solve_kernel, dim3(1), dim3(DT), 0, s, A, n, B, nrhs, status);
-  prof_end(tok, s);
+  launch_prof(PK_DENSE_1WG, 2.0 / 3.0 * nn * nn * nn + 2.0 * nn * nn * nrhs, 8.0 * (2.0 * nn * nn + 2.0 * nn * nrhs),
+              lu_solve_kernel, dim3(1), dim3(DT), 0u, s, A, n, B, nrhs, status);
   TT_HIP(hipGetLastError());
 }
 
 void dense_cholesky(double* A, int n, int* status, hipStream_t s) {
   const double nn = n;
-  const int tok = prof_begin(PK_DENSE_1WG, s, nn * nn * nn / 3.0, 8.0 * 2.0 * nn * nn);
-  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(DT), 0, s, A, n, status);
-  prof_end(tok, s);
+  launch_prof(PK_DENSE_1WG, nn * nn * nn / 3.0, 8.0 * 2.0 * nn * nn, cholesky_kernel, dim3(1), dim3(DT), 0u, s, A, n,
+              status);
   TT_HIP(hipGetLastError());
 }
 
 void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s) {
   const double nn = n;
-  const int tok = prof_begin(PK_DENSE_1WG, s, nn * nn * nrhs, 8.0 * (0.5 * nn * nn + 2.0 * nn * nrhs));
+  const double fl = nn * nn * nrhs, by = 8.0 * (0.5 * nn * nn + 2.0 * nn * nrhs);
   if (transpose)
-    hipLaunchKernelGGL(trsm_lower_t_kernel, dim3(1), dim3(DT), 0, s, L, n, B, nrhs);
+    launch_prof(PK_DENSE_1WG, fl, by, trsm_lower_t_kernel, dim3(1), dim3(DT), 0u, s, L, n, B, nrhs);
   else
-    hipLaunchKernelGGL(trsm_lower_kernel, dim3(1), dim3(DT), 0, s, L, n, B, nrhs);
-  prof_end(tok, s);
+    launch_prof(PK_DENSE_1WG, fl, by, trsm_lower_kernel, dim3(1), dim3(DT), 0u, s, L, n, B, nrhs);
   TT_HIP(hipGetLastError());
 }
 

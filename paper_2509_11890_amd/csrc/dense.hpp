@@ -15,6 +15,8 @@ void dense_qr_form_q(const double* A, int m, int n, int lda, const double* tau, 
 // work >= n*n doubles, iwork >= n + 1 ints (iwork[n] = sweeps used).
 void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, double* work, int* iwork,
                hipStream_t s, int max_sweeps = 40, double tol = 4e-16);
+// True when dense_svd of an m x n matrix keeps both A and V in LDS.
+bool dense_svd_fits_lds(int m, int n);
 // Smallest eigenpair of a symmetric row-major p x p matrix B (restarted Lanczos
 // with full reorthogonalisation): v (p, unit norm), lam (1 double, device).
 // work >= p * (min(kmax, p) + 1) doubles.

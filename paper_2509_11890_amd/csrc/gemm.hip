@@ -390,16 +390,16 @@ __global__ void scale_c_kernel(double* C, long cm, long cn, long sC, int M, int 
 static Workspace g_default_ws;
 
 template <int WM, int WN>
-void launch_f64(dim3 grid, hipStream_t stream, const KArgs& g) {
+void launch_f64(dim3 grid, hipStream_t stream, const KArgs& g, double flops, double bytes) {
   const bool akc = (g.ak == 1), bkc = (g.bk == 1 && g.bn != 1);
   if (akc && bkc)
-    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, true, true>), grid, dim3(256), 0, stream, g);
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_kernel<WM, WN, true, true>, grid, dim3(256), 0u, stream, g);
   else if (akc)
-    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, true, false>), grid, dim3(256), 0, stream, g);
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_kernel<WM, WN, true, false>, grid, dim3(256), 0u, stream, g);
   else if (bkc)
-    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, false, true>), grid, dim3(256), 0, stream, g);
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_kernel<WM, WN, false, true>, grid, dim3(256), 0u, stream, g);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, false, false>), grid, dim3(256), 0, stream, g);
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_kernel<WM, WN, false, false>, grid, dim3(256), 0u, stream, g);
 }
 
 void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
@@ -470,18 +470,16 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   dim3 grid(gm, gn, q.batch * ks);
   const double flops = 2.0 * q.M * q.N * (double)q.K * q.batch;
   const double bytes = 8.0 * q.batch * ((double)q.M * q.K + (double)q.K * q.N + (double)q.M * q.N * (q.beta != 0.0 ? 2 : 1));
-  const int tok = prof_begin(prec == GemmPrec::BF16 ? PK_GEMM_BF16 : PK_GEMM_F64, stream, flops, bytes);
   if (prec == GemmPrec::BF16)
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_kernel, grid, dim3(256), 0u, stream, g);
   else if (TMs == 128 && TNs == 128)
-    launch_f64<4, 4>(grid, stream, g);
+    launch_f64<4, 4>(grid, stream, g, flops, bytes);
   else if (TMs == 128)
-    launch_f64<4, 2>(grid, stream, g);
+    launch_f64<4, 2>(grid, stream, g, flops, bytes);
   else if (TNs == 128)
-    launch_f64<2, 4>(grid, stream, g);
+    launch_f64<2, 4>(grid, stream, g, flops, bytes);
   else
-    launch_f64<2, 2>(grid, stream, g);
-  prof_end(tok, stream);
+    launch_f64<2, 2>(grid, stream, g, flops, bytes);
   TT_HIP(hipGetLastError());
   if (ks > 1) {
     long total = (long)q.batch * q.M * q.N;

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <random>
 
+#include "blocked.hpp"
 #include "dense.hpp"
 #include "ttops.hpp"
 
@@ -196,26 +197,43 @@ void merge_pair(const TT& M, int k, DevBuf& out, Ctx& c) {
 
 // smallest eigenpair of the pencil (D, M) (p x p, row-major, symmetrised in place):
 // returns lambda and writes the M-normalised direction into e (p).
+// pencils from this size on use the blocked (GEMM-based) factorisations
+constexpr int kPencilBlocked = 96;
+
 double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c) {
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, Mm, p);
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, D, p);
   TT_HIP(hipGetLastError());
-  c.ired.reserve((size_t)p + 8);
-  int* st = reinterpret_cast<int*>(c.ired.get());
-  dense_cholesky(Mm, p, st, c.s);
+  // Pencils of a few hundred unknowns use the GEMM-based blocked Cholesky and
+  // triangular solves; the single-workgroup kernels win only for small ones.
+  const bool blocked = p >= kPencilBlocked;
+  BlockedFactors f;
   int hst = 0;
-  TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
-  c.sync();
+  if (blocked) {
+    hst = chol_blocked(Mm, p, f, c);
+  } else {
+    c.ired.reserve((size_t)p + 8);
+    int* st = reinterpret_cast<int*>(c.ired.get());
+    dense_cholesky(Mm, p, st, c.s);
+    TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
+    c.sync();
+  }
   if (hst != 0) throw Error(TT_ERR_NOT_PD, "projected iterate is not positive definite (step length)");
+  auto solve_L = [&](double* B, int nrhs, bool trans) {
+    if (blocked)
+      trsm_blocked(Mm, p, f, B, nrhs, trans, c);
+    else
+      dense_trsm_lower(Mm, p, B, nrhs, trans, c.s);
+  };
   DevBuf Bt((size_t)p * p), work((size_t)p * (std::min(p, 128) + 1)), lam(1);
-  dense_trsm_lower(Mm, p, D, p, false, c.s);                 // L^{-1} D
+  solve_L(D, p, false);                                      // L^{-1} D
   permute(D, Bt.get(), {p, p}, {1, 0}, c.s);                 // (L^{-1} D)^T = D L^{-T}
-  dense_trsm_lower(Mm, p, Bt.get(), p, false, c.s);          // L^{-1} D L^{-T}
+  solve_L(Bt.get(), p, false);                               // L^{-1} D L^{-T}
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, Bt.get(), p);
   TT_HIP(hipGetLastError());
   // smallest eigenpair of the reduced pencil (Lanczos), then e = L^{-T} v
   dense_sym_min_eig(Bt.get(), p, e, lam.get(), work.get(), c.s, 128);
-  dense_trsm_lower(Mm, p, e, 1, true, c.s);
+  solve_L(e, 1, true);
   double lmin = 0.0;
   TT_HIP(hipMemcpyAsync(&lmin, lam.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
   c.sync();

@@ -421,8 +421,10 @@ void svd_rowmajor(const double* M, int rows, int cols, SvdOut& out, Ctx& c) {
   DevBuf Ucm((size_t)m * n), Vcm((size_t)n * n), sig(n), work((size_t)n * n);
   c.ired.reserve((size_t)n + 8);
   int* iw = reinterpret_cast<int*>(c.ired.get());
-  if (m > 2 * n) {
-    // QR first: A = Q R with R (n x n); SVD of R keeps the Jacobi sweeps on n x n.
+  if (m > 2 * n || (!dense_svd_fits_lds(m, n) && dense_svd_fits_lds(n, n))) {
+    // QR first: A = Q R with R (n x n); SVD of R keeps the Jacobi sweeps on
+    // n x n -- for tall matrices, and wherever that lets the sweeps run with
+    // both R and the rotations resident in LDS.
     DevBuf Q((size_t)m * n), R((size_t)n * n), Rcm((size_t)n * n), Ur((size_t)n * n);
     qr_colmajor(A.get(), m, n, Q.get(), R.get(), c);
     permute(R.get(), Rcm.get(), {n, n}, {1, 0}, c.s);
