@@ -31,7 +31,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 64, BN = 64, BK = 16;
-constexpr int PAD = 1;
 constexpr int PADF = 17;   // FP64 tiled kernel
 
 struct KArgs {
@@ -44,76 +43,9 @@ struct KArgs {
   double* P;                // split-K partials [batch][kslices][M][N] (dense)
 };
 
-// Global -> LDS tile copies.  As is [BK][BM+PAD] (k-major), Bs is [BK][BN+PAD].
-template <typename T>
-__device__ __forceinline__ void load_tile_A(T (*As)[BM + PAD], const double* A, long am, long ak,
-                                            int m0, int k0, int kend, int M, int tid) {
-  if (ak == 1) {  // k contiguous: 16 threads along k, 16 rows per pass
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int m = tid / 16 + 16 * e, k = tid % 16;
-      int gm = m0 + m, gk = k0 + k;
-      double v = (gm < M && gk < kend) ? A[gm * am + gk] : 0.0;
-      As[k][m] = (T)v;
-    }
-  } else {        // m contiguous (or general): 64 threads along m
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int m = tid % 64, k = tid / 64 + 4 * e;
-      int gm = m0 + m, gk = k0 + k;
-      double v = (gm < M && gk < kend) ? A[gm * am + gk * ak] : 0.0;
-      As[k][m] = (T)v;
-    }
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void load_tile_B(T (*Bs)[BN + PAD], const double* B, long bk, long bn,
-                                            int n0, int k0, int kend, int N, int tid) {
-  if (bk == 1 && bn != 1) {  // k contiguous
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int n = tid / 16 + 16 * e, k = tid % 16;
-      int gn = n0 + n, gk = k0 + k;
-      double v = (gn < N && gk < kend) ? B[gk + gn * bn] : 0.0;
-      Bs[k][n] = (T)v;
-    }
-  } else {                   // n contiguous (or general)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int n = tid % 64, k = tid / 64 + 4 * e;
-      int gn = n0 + n, gk = k0 + k;
-      double v = (gn < N && gk < kend) ? B[gk * bk + gn * bn] : 0.0;
-      Bs[k][n] = (T)v;
-    }
-  }
-}
-
 // Result layouts of the 16 x 16 MFMA tiles (measured on gfx950): every lane
 // holds column lane%16; the four accumulator values are rows lane/16 + 4e for
 // v_mfma_f64_16x16x4f64 and rows 4*(lane/16) + e for v_mfma_f32_16x16x32_bf16.
-template <bool F64_LAYOUT>
-__device__ __forceinline__ void store_tile(const KArgs& g, int bidx, int slice, int m0, int n0,
-                                           int wm, int wn, int lane, const double (*acc)[2][4]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int row = m0 + wm * 32 + i * 16 + (F64_LAYOUT ? (lane / 16) + 4 * e : 4 * (lane / 16) + e);
-        int col = n0 + wn * 32 + j * 16 + (lane % 16);
-        if (row < g.M && col < g.N) {
-          double v = acc[i][j][e];
-          if (g.kslices > 1) {
-            g.P[(((long)bidx * g.kslices + slice) * g.M + row) * g.N + col] = v;
-          } else {
-            double* c = g.C + (long)bidx * g.sC + (long)row * g.cm + (long)col * g.cn;
-            *c = (g.beta == 0.0) ? g.alpha * v : g.alpha * v + g.beta * (*c);
-          }
-        }
-      }
-}
 
 // FP64 kernel, templated on the MFMA tiles per wave (WM x WN of 16 x 16; the
 // workgroup tile is (32 WM) x (32 WN)) and on which operand index is unit
@@ -276,81 +208,144 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
       }
 }
 
-// BF16 operands, FP32 accumulation: v_mfma_f32_16x16x32_bf16 consumes 8 k-values
-// per lane (k = 8*(lane/16) + 0..7 for both A and B), so a BK=32 step is one MFMA.
+// BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16): lane l supplies
+// row l%16 and the eight k-values 8(l/16)..8(l/16)+7 of each operand, so the
+// LDS tiles are stored with k contiguous ([m][k], row pitch 40 values = 80
+// bytes) and each operand is one 16-byte LDS read; the 16 rows of a read start
+// on distinct 4-bank groups.  FP64 operands are fetched with the same
+// precomputed-offset scheme as the FP64 kernel (loads in flight across the
+// MFMA block) and rounded to BF16 when stashed into LDS; BK = 32 is one MFMA
+// k-depth.  Accumulators are FP32; the epilogue writes FP64.
 constexpr int BK16 = 32;
+constexpr int P16 = 40;   // LDS row pitch in bf16 values
 
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(KArgs g) {
-  __shared__ __bf16 As[BK16][BM + 8];
-  __shared__ __bf16 Bs[BK16][BN + 8];
+template <int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_kernel(KArgs g) {
+  constexpr int TM = 32 * WM, TN = 32 * WN;
+  constexpr int NA = TM * BK16 / 256, NB = BK16 * TN / 256;
+  constexpr int ASTEP = AKC ? 256 / BK16 : 256 / TM;
+  constexpr int BSTEP = BKC ? 256 / BK16 : 256 / TN;
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][TM][P16];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][TN][P16];
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int gmt = gridDim.x, gnt = gridDim.y;
+  const int tiles = gmt * gnt;
+  const int lin = blockIdx.y * gmt + blockIdx.x;
+  int t = lin;
+  if (tiles >= 16) {
+    const int per = (tiles + 7) / 8;
+    const int cand = (lin % 8) * per + lin / 8;
+    t = (tiles % 8 == 0) ? cand : lin;
+  }
+  const int tm = t / gnt, tn = t % gnt;
+  const int m0 = tm * TM, n0 = tn * TN;
   const int bidx = blockIdx.z / g.kslices, slice = blockIdx.z % g.kslices;
   const int kbeg = slice * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
   const double* A = g.A + (long)bidx * g.sA;
   const double* B = g.B + (long)bidx * g.sB;
-  f32x4 acc[2][2];
+  const int a_mt = AKC ? tid / BK16 : tid % TM;
+  const int a_kt = AKC ? tid % BK16 : tid / TM;
+  const int b_nt = BKC ? tid / BK16 : tid % TN;
+  const int b_kt = BKC ? tid % BK16 : tid / TN;
+  unsigned offA[NA], offB[NB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += BK16) {
-    // 32 x 64 tiles = 2048 values, 8 per thread
-    if (g.ak == 1) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        int m = tid / 32 + 8 * e, k = tid % 32;
-        int gm = m0 + m, gk = k0 + k;
-        As[k][m] = (__bf16)((gm < g.M && gk < kend) ? A[gm * g.am + gk] : 0.0);
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        int m = tid % 64, k = tid / 64 + 4 * e;
-        int gm = m0 + m, gk = k0 + k;
-        As[k][m] = (__bf16)((gm < g.M && gk < kend) ? A[gm * g.am + gk * g.ak] : 0.0);
-      }
-    }
-    if (g.bk == 1 && g.bn != 1) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        int n = tid / 32 + 8 * e, k = tid % 32;
-        int gn = n0 + n, gk = k0 + k;
-        Bs[k][n] = (__bf16)((gn < g.N && gk < kend) ? B[gk + gn * g.bn] : 0.0);
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        int n = tid % 64, k = tid / 64 + 4 * e;
-        int gn = n0 + n, gk = k0 + k;
-        Bs[k][n] = (__bf16)((gn < g.N && gk < kend) ? B[gk * g.bk + gn * g.bn] : 0.0);
-      }
-    }
-    __syncthreads();
-    bf16x8 a[2], b[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        a[i][t] = As[8 * (lane / 16) + t][wm * 32 + i * 16 + (lane % 16)];
-        b[i][t] = Bs[8 * (lane / 16) + t][wn * 32 + i * 16 + (lane % 16)];
-      }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
+  for (int e = 0; e < NA; ++e) {
+    const int m = m0 + a_mt + (AKC ? ASTEP * e : 0), k = a_kt + (AKC ? 0 : ASTEP * e);
+    offA[e] = 8u * (unsigned)(min(m, g.M - 1) * (int)g.am + k * (int)g.ak);
   }
-  double out[2][2][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int e = 0; e < NB; ++e) {
+    const int n = n0 + b_nt + (BKC ? BSTEP * e : 0), k = b_kt + (BKC ? 0 : BSTEP * e);
+    offB[e] = 8u * (unsigned)(min(n, g.N - 1) * (int)g.bn + k * (int)g.bk);
+  }
+  double ra[NA], rb[NB];
+  auto fetch = [&](int k0) {
+    const char* Ak = reinterpret_cast<const char*>(A + (long)k0 * g.ak);
+    const char* Bk = reinterpret_cast<const char*>(B + (long)k0 * g.bk);
+    if (k0 + BK16 <= kend) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int e = 0; e < NA; ++e) ra[e] = *reinterpret_cast<const double*>(Ak + offA[e]);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) out[i][j][e] = (double)acc[i][j][e];
-  store_tile<false>(g, bidx, slice, m0, n0, wm, wn, lane, out);
+      for (int e = 0; e < NB; ++e) rb[e] = *reinterpret_cast<const double*>(Bk + offB[e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < NA; ++e) {
+        const int k = a_kt + (AKC ? 0 : ASTEP * e);
+        const int kc = min(k, kend - 1 - k0);
+        const double v = *reinterpret_cast<const double*>(Ak + offA[e] + 8L * (kc - k) * g.ak);
+        ra[e] = (k0 + k < kend) ? v : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const int k = b_kt + (BKC ? 0 : BSTEP * e);
+        const int kc = min(k, kend - 1 - k0);
+        const double v = *reinterpret_cast<const double*>(Bk + offB[e] + 8L * (kc - k) * g.bk);
+        rb[e] = (k0 + k < kend) ? v : 0.0;
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int m = a_mt + (AKC ? ASTEP * e : 0), k = a_kt + (AKC ? 0 : ASTEP * e);
+      As[buf][m][k] = (__bf16)ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int n = b_nt + (BKC ? BSTEP * e : 0), k = b_kt + (BKC ? 0 : BSTEP * e);
+      Bs[buf][n][k] = (__bf16)rb[e];
+    }
+  };
+  f32x4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int buf = 0;
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  const int kq = 8 * (lane / 16);
+  for (int k0 = kbeg; k0 < kend; k0 += BK16) {
+    const bool more = k0 + BK16 < kend;
+    if (more) fetch(k0 + BK16);
+    bf16x8 a[WM], b[WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * (16 * WM) + i * 16 + (lane % 16)][kq]);
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * (16 * WN) + j * 16 + (lane % 16)][kq]);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // epilogue: rows 4(lane/16) + e, column lane%16 of each 16 x 16 block
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = m0 + wm * (16 * WM) + i * 16 + 4 * (lane / 16) + e;
+        const int col = n0 + wn * (16 * WN) + j * 16 + (lane % 16);
+        if (row < g.M && col < g.N) {
+          const double v = (double)acc[i][j][e];
+          if (g.kslices > 1) {
+            g.P[(((long)bidx * g.kslices + slice) * g.M + row) * g.N + col] = v;
+          } else {
+            double* c = g.C + (long)bidx * g.sC + (long)row * g.cm + (long)col * g.cn;
+            *c = (g.beta == 0.0) ? g.alpha * v : g.alpha * v + g.beta * (*c);
+          }
+        }
+      }
 }
 
 __global__ void splitk_reduce_kernel(KArgs g, int batch) {
@@ -390,6 +385,19 @@ __global__ void scale_c_kernel(double* C, long cm, long cn, long sC, int M, int 
 static Workspace g_default_ws;
 
 template <int WM, int WN>
+void launch_bf16(dim3 grid, hipStream_t stream, const KArgs& g, double flops, double bytes) {
+  const bool akc = (g.ak == 1), bkc = (g.bk == 1 && g.bn != 1);
+  if (akc && bkc)
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_kernel<WM, WN, true, true>, grid, dim3(256), 0u, stream, g);
+  else if (akc)
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_kernel<WM, WN, true, false>, grid, dim3(256), 0u, stream, g);
+  else if (bkc)
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_kernel<WM, WN, false, true>, grid, dim3(256), 0u, stream, g);
+  else
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_kernel<WM, WN, false, false>, grid, dim3(256), 0u, stream, g);
+}
+
+template <int WM, int WN>
 void launch_f64(dim3 grid, hipStream_t stream, const KArgs& g, double flops, double bytes) {
   const bool akc = (g.ak == 1), bkc = (g.bk == 1 && g.bn != 1);
   if (akc && bkc)
@@ -414,8 +422,8 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   // the FP64 kernel addresses operands with 32-bit byte offsets from the
   // (64-bit) batch and k-step base; strides are non-negative for every caller
   if (q.am < 0 || q.ak < 0 || q.bk < 0 || q.bn < 0 ||
-      (double)(q.M - 1) * q.am + (double)(q.K - 1 + BK) * q.ak > 536870911.0 ||
-      (double)(q.N - 1) * q.bn + (double)(q.K - 1 + BK) * q.bk > 536870911.0)
+      (double)(q.M - 1) * q.am + (double)(q.K - 1 + BK16) * q.ak > 536870911.0 ||
+      (double)(q.N - 1) * q.bn + (double)(q.K - 1 + BK16) * q.bk > 536870911.0)
     throw Error(TT_ERR_ARG, "gemm operand too large for 32-bit byte offsets");
   KArgs g;
   g.M = q.M; g.N = q.N; g.K = q.K;
@@ -423,8 +431,8 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   g.B = q.B; g.bk = q.bk; g.bn = q.bn; g.sB = q.sB;
   g.C = q.C; g.cm = q.cm; g.cn = q.cn; g.sC = q.sC;
   g.alpha = q.alpha; g.beta = q.beta;
-  // FP64 tile shape: 128 x 128 for large outputs, 128 x 64 / 64 x 128 for
-  // skinny ones, 64 x 64 otherwise (BF16 always uses 64 x 64).
+  // Tile shape (both precisions): 128 x 128 for large outputs, 128 x 64 /
+  // 64 x 128 for skinny ones, 64 x 64 otherwise.
   // The largest tile that still gives the chip enough workgroups (min_tiles,
   // default two per CU so that two waves share each SIMD and hide each other's
   // LDS and global latency) and does not overhang a dimension shorter than
@@ -435,7 +443,7 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
     return v > 0 ? v : 512L;
   }();
   int TMs = BM, TNs = BN;
-  if (prec == GemmPrec::F64) {
+  {
     const int cand[3][2] = {{128, 128}, {128, 64}, {64, 128}};
     for (const auto& t : cand) {
       if (q.M < t[0] || q.N < t[1]) continue;
@@ -470,9 +478,16 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   dim3 grid(gm, gn, q.batch * ks);
   const double flops = 2.0 * q.M * q.N * (double)q.K * q.batch;
   const double bytes = 8.0 * q.batch * ((double)q.M * q.K + (double)q.K * q.N + (double)q.M * q.N * (q.beta != 0.0 ? 2 : 1));
-  if (prec == GemmPrec::BF16)
-    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_kernel, grid, dim3(256), 0u, stream, g);
-  else if (TMs == 128 && TNs == 128)
+  if (prec == GemmPrec::BF16) {
+    if (TMs == 128 && TNs == 128)
+      launch_bf16<4, 4>(grid, stream, g, flops, bytes);
+    else if (TMs == 128)
+      launch_bf16<4, 2>(grid, stream, g, flops, bytes);
+    else if (TNs == 128)
+      launch_bf16<2, 4>(grid, stream, g, flops, bytes);
+    else
+      launch_bf16<2, 2>(grid, stream, g, flops, bytes);
+  } else if (TMs == 128 && TNs == 128)
     launch_f64<4, 4>(grid, stream, g, flops, bytes);
   else if (TMs == 128)
     launch_f64<4, 2>(grid, stream, g, flops, bytes);
