@@ -449,9 +449,11 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
       }
       if (it >= prm->max_iter) break;
       // Stall: the TT direction no longer admits a step (both step lengths
-      // collapsed twice in a row), or an iterate lost positive definiteness in
+      // below 1e-3 in five consecutive iterations: from the scaled identity
+      // start, the first steps on large instances can be of order 1/n before
+      // the iteration recovers), or an iterate lost positive definiteness in
       // the step-length test; the last accepted iterate is the result.
-      if (short_steps >= 2) {
+      if (short_steps >= 5) {
         r.status = TT_ERR_NOT_CONVERGED;
         break;
       }
