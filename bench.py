@@ -20,6 +20,9 @@ Beside it, the line carries
     algorithmic flops per second against the MI355X peak of its precision;
   * local_contraction: TFLOP/s of the projected local matvec (three MFMA GEMM
     stages) at the workload's shape and at r = 64, R = 128;
+  * precision_variants_grid_d5: the 4x8 grid solved with FP64 direct, FP64 GMRES,
+    mixed BF16 GMRES with FP64 refinement, and mixed + learned preconditioner;
+  * time_to_gap_n1024_closed_forms: K_1024 and Q_10 MaxCut to the 1e-4 mark;
   * cpu_baseline: the dense FP64 HKM interior-point oracle on the same
     instance, timed on the host cores to the same gap rule.
 """
@@ -55,7 +58,8 @@ def parse():
     ap.add_argument("--profile-period", type=int, default=4,
                     help="event-time every n-th launch of the instrumented kernels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-variants", action="store_true", help="skip the mixed / learned comparison")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the mixed / learned comparison and the n = 1024 closed-form solves")
     ap.add_argument("--contraction-only", action="store_true",
                     help="only the local-contraction microbenchmarks (and a 256 MiB device copy used to calibrate "
                          "the HBM byte counters)")
@@ -144,6 +148,21 @@ def precision_variants(P, I):
     run("mixed_gmres_mlp", direct_max=64, precond=P.TT_PREC_MLP, precision=P.TTIPM_MIXED, gmres_restart=40,
         gmres_maxit=800, mlp=net.h.value)
     out["mlp_training"] = {"blocks": net.dataset_size, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    return out
+
+
+def closed_forms_d10(P, I):
+    """Time to the 1e-4 gap mark on the n = 1024 MaxCut instances with closed-form
+    values (K_1024: n^2/4; Q_10: |E| = 5120) at TT ranks <= 8, FP64."""
+    out = {}
+    for name, g, value in (("K1024", I.complete(10), 1024.0 ** 2 / 4), ("Q10_maxcut", I.hypercube(10), 5120.0)):
+        prob = P.Problem(P.TTIPM_MAXCUT, g.cores)
+        prm = P.Params(rank_cap=8, iter_rank_cap=8, stop_gap=1e-4, max_iter=60)
+        res, log = P.ttipm_solve(prob, P.State(prob, prm), prm)
+        out[name] = {"time_to_gap_s": res["time_to_gap"], "iterations": res["iterations"],
+                     "rel_gap": res["rel_gap"], "eps_p": res["eps_p"], "eps_d": res["eps_d"],
+                     "pobj_err_vs_closed_form": abs(res["pobj"] - value) / (1 + value),
+                     "dobj_err_vs_closed_form": abs(res["dobj"] - value) / (1 + value)}
     return out
 
 
@@ -290,6 +309,7 @@ def main():
     contraction = [contraction_rate(P, torch, r, R) for r, R in ((cap, 2 * cap), (64, 128))]
     contraction += [contraction_rate_bf16(P, torch, r, R) for r, R in ((cap, 2 * cap), (64, 128))]
     variants = None if args.no_variants else precision_variants(P, I)
+    closed = None if args.no_variants else closed_forms_d10(P, I)
 
     cpu = None
     if not args.no_cpu and graph.dense is not None:
@@ -330,6 +350,7 @@ def main():
         "roofline": roof,
         "local_contraction": contraction,
         "precision_variants_grid_d5": variants,
+        "time_to_gap_n1024_closed_forms": closed,
         "cpu_baseline": cpu,
     }
     calibration_copy(torch)

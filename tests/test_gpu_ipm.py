@@ -101,7 +101,30 @@ CLOSED = [
     ("theta-Q5", "theta", lambda: I.hypercube(5), 16.0),
     ("theta-C5+3K1", "theta", lambda: I.c5_plus_3k1(), 3 + math.sqrt(5)),
     ("grid-4x8", "maxcut", lambda: I.grid_4x8(), 52.0),
+    ("K32", "maxcut", lambda: I.complete(5), 256.0),
 ]
+
+# n = 1024 members of the closed-form suite: the 1e-4 time-to-gap mark (rel_gap <= 1e-4,
+# eps_p, eps_d <= 2e-4) at TT ranks <= 8.  rel_gap is normalised by 1 + |p| + |d| (about twice
+# the value), so at the mark each objective lies within about 2e-4 of the value (relative).
+CLOSED_D10 = [
+    ("K1024", lambda: I.complete(10), 1024.0 ** 2 / 4),
+    ("Q10-maxcut", lambda: I.hypercube(10), 10 * 512.0),
+]
+
+
+@pytest.mark.parametrize("name,make,value", CLOSED_D10, ids=[c[0] for c in CLOSED_D10])
+def test_d10_maxcut_reaches_gap_mark(name, make, value):
+    P = _lib()
+    g = make()
+    pr = P.Problem(P.TTIPM_MAXCUT, g.cores)
+    prm = P.Params(rank_cap=8, iter_rank_cap=8, stop_gap=1e-4, max_iter=60)
+    st = P.State(pr, prm)
+    res, log = P.ttipm_solve(pr, st, prm)
+    print(name, res)
+    assert res["status"] == P.TT_OK and res["time_to_gap"] > 0
+    assert abs(res["pobj"] - value) / (1 + value) < 2.5e-4
+    assert abs(res["dobj"] - value) / (1 + value) < 2.5e-4
 
 
 @pytest.mark.parametrize("name,kind,make,value", CLOSED, ids=[c[0] for c in CLOSED])
