@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--iter-rank-cap", type=int, default=None, help="override the iterate rank cap")
     ap.add_argument("--max-iter", type=int, default=12,
                     help="IPM iteration limit of a step (the step ends earlier at the gap mark)")
-    ap.add_argument("--profile-period", type=int, default=4,
+    ap.add_argument("--profile-period", type=int, default=32,
                     help="event-time every n-th launch of the instrumented kernels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true",
