@@ -329,6 +329,9 @@ typedef struct {
   int32_t collect_probes; /* > 0 and mlp set: every local system of the AMEn solves adds its
                            blocks with this many probes to the mlp handle's dataset        */
   int64_t collect_cap;  /* dataset size limit (blocks) for collect_probes                 */
+  int32_t xz_fallback;  /* 1: redo an AHO iteration with the XZ direction when its predictor
+                           solve misses the residual target within the rank and sweep budget
+                           or admits a step below 1e-3 (Sec. 3.5); not with inequalities (1) */
 } ttipm_params;
 
 TTIPM_API void ttipm_params_default(ttipm_params* p);
@@ -348,6 +351,7 @@ typedef struct {
   int32_t backtracks;               /* step halvings forced by the positive-definiteness check */
   int32_t mlp_used, mlp_fallbacks;  /* local solves with the MLP preconditioner kept / replaced by
                                        block Jacobi under the fallback rule */
+  int32_t xz_fallback;              /* 1 when this iteration fell back from AHO to XZ */
   double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration */
 } ttipm_step_info;
 

@@ -495,20 +495,22 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   // warm-up is skipped (reading): the nonsymmetric XZ direction breaks the
   // symmetry of X against the mirrored multipliers T, and the iteration stalls
   // (observed identically with exact dense Newton directions).
-  const bool aho = S.iter >= prm.n_xz || P.ineq;
+  bool aho = S.iter >= prm.n_xz || P.ineq;
   info.direction = aho ? TTIPM_DIR_AHO : TTIPM_DIR_XZ;
-  const double coef = aho ? 2.0 : 1.0;
   const double tolp = S.eta * (1.0 + P.normB) / 10.0;
   const double told = S.eta * (1.0 + P.normC) / 10.0;
   // operators L_Z, L_X (Sec. 3.3) rounded at the primal/dual tolerances (Sec. 3.5)
-  double t0 = now();
   TT LZ, LX;
-  L_ops(P, S.X, S.Z, aho, LZ, LX, c);
-  // reading: L_Z and L_X are rounded with the Cor. 1 shift (S = I kron I) so
-  // that they stay positive definite when Z and X approach singularity
-  LZ = round_shift(std::move(LZ), told, &P.I16, 1 << 30, c, nullptr);
-  LX = round_shift(std::move(LX), tolp, &P.I16, 1 << 30, c, nullptr);
-  info.t_round += now() - t0;
+  auto build_L = [&](bool use_aho) {
+    const double t0 = now();
+    L_ops(P, S.X, S.Z, use_aho, LZ, LX, c);
+    // reading: L_Z and L_X are rounded with the Cor. 1 shift (S = I kron I) so
+    // that they stay positive definite when Z and X approach singularity
+    LZ = round_shift(std::move(LZ), told, &P.I16, 1 << 30, c, nullptr);
+    LX = round_shift(std::move(LX), tolp, &P.I16, 1 << 30, c, nullptr);
+    info.t_round += now() - t0;
+  };
+  build_L(aho);
   NewtonSys sys;
   sys.ineq = P.ineq;
   sys.sense = P.sense;
@@ -535,12 +537,24 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   }
   // residual terms: R_d = Z + C - Aeq^T Y (- s Aineq^T T), R_p = B - Aeq X,
   // R_t = T o s(X) - mu 1_T = -s diag(T) A_ineq X (+ s diag(T) B_ineq) - mu 1_T
-  std::vector<Term> base = {{RES_D, 1.0, -1, &S.Z}, {RES_D, 1.0, -1, &P.C}, {RES_D, -1.0, OP_AEQT, &S.Y},
-                            {RES_P, 1.0, -1, &P.Beq}, {RES_P, -1.0, OP_AEQ, &S.X}};
-  if (P.ineq) {
-    base.push_back({RES_D, -P.sense, OP_AIT, &S.T});
-    base.push_back({RES_T, -P.sense, OP_TA, &S.X});
+  //
+  // Zero blocks (Sec. 3.5): a feasibility residual that already meets its
+  // stopping threshold (relative 2 stop_gap) is set to zero in the Newton
+  // system, so its terms are neither projected nor contracted.
+  const bool zero_p = info.eps_p <= 2.0 * prm.stop_gap;
+  const bool zero_d = info.eps_d <= 2.0 * prm.stop_gap;
+  std::vector<Term> base;
+  if (!zero_d) {
+    base.push_back({RES_D, 1.0, -1, &S.Z});
+    base.push_back({RES_D, 1.0, -1, &P.C});
+    base.push_back({RES_D, -1.0, OP_AEQT, &S.Y});
+    if (P.ineq) base.push_back({RES_D, -P.sense, OP_AIT, &S.T});
   }
+  if (!zero_p) {
+    base.push_back({RES_P, 1.0, -1, &P.Beq});
+    base.push_back({RES_P, -1.0, OP_AEQ, &S.X});
+  }
+  if (P.ineq) base.push_back({RES_T, -P.sense, OP_TA, &S.X});
   if (!S.has_W) {
     S.W = block_from_frame(P.Ivec, sys.Lp(), c);
     S.has_W = true;
@@ -566,32 +580,49 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   ap.mu = std::max(mu, 1e-300);
   ap.seed = S.seed + 31ull * (unsigned long long)S.iter;
   // --- predictor: affine direction (target mu = 0) ---
-  sys.terms = base;
-  sys.terms.push_back({RES_C, 1.0, OP_LZ, &S.X});
-  if (P.ineq) {
-    // (R_t keeps its mu term only in the corrector)
-  }
-  AmenInfo ai_p;
-  amen_solve(sys, S.W, ap, ai_p, c);
-  S.frame_capped |= ai_p.capped;
   const int L = sys.L();
-  TT dX = S.W.component(0, c), dZ = S.W.component(L, c);
-  double t1 = now();
   const unsigned long long sd = S.seed + 7919ull * (unsigned long long)S.iter;
-  // affine (predictor) steps: the full Thm. 1 step, clipped to 1; with
-  // inequalities also s(X + a_p dX) >= 0 and T + a_d dT >= 0 on the active
-  // mask (Sec. 3.4: the diagonal pencils reduce to entry ratios)
-  double a_p = std::min(1.0, step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, c));
-  double a_d = std::min(1.0, step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, c));
-  TT dT, sx, dsx;
-  if (P.ineq) {
-    dT = S.W.component(2, c);
-    sx = ineq_slack(P, S.X, false, c);
-    dsx = ineq_slack(P, dX, true, c);
-    a_p = std::min(a_p, ratio_step(sx, dsx, P.oneT, c));
-    a_d = std::min(a_d, ratio_step(S.T, dT, P.oneT, c));
+  AmenInfo ai_p;
+  TT dX, dZ, dT, sx, dsx;
+  double a_p = 0.0, a_d = 0.0;
+  auto predictor = [&]() {
+    sys.terms = base;
+    sys.terms.push_back({RES_C, 1.0, OP_LZ, &S.X});   // (R_t keeps its mu term only in the corrector)
+    ai_p = AmenInfo{};
+    amen_solve(sys, S.W, ap, ai_p, c);
+    S.frame_capped |= ai_p.capped;
+    dX = S.W.component(0, c);
+    dZ = S.W.component(L, c);
+    const double t1 = now();
+    // affine (predictor) steps: the full Thm. 1 step, clipped to 1; with
+    // inequalities also s(X + a_p dX) >= 0 and T + a_d dT >= 0 on the active
+    // mask (Sec. 3.4: the diagonal pencils reduce to entry ratios)
+    a_p = std::min(1.0, step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, c));
+    a_d = std::min(1.0, step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, c));
+    if (P.ineq) {
+      dT = S.W.component(2, c);
+      sx = ineq_slack(P, S.X, false, c);
+      dsx = ineq_slack(P, dX, true, c);
+      a_p = std::min(a_p, ratio_step(sx, dsx, P.oneT, c));
+      a_d = std::min(a_d, ratio_step(S.T, dT, P.oneT, c));
+    }
+    info.t_step += now() - t1;
+  };
+  predictor();
+  // AHO -> XZ fallback (Sec. 3.5): when the AHO solve misses its residual
+  // target within the rank and sweep budget, or admits almost no step, the
+  // iteration is redone with the XZ direction, which often needs lower TT
+  // ranks.  Not with inequalities (reading: XZ breaks the symmetry of X
+  // against the mirrored multipliers there).
+  if (aho && !P.ineq && prm.xz_fallback && (ai_p.last_max_res > ap.tol || std::max(a_p, a_d) < 1e-3)) {
+    aho = false;
+    info.direction = TTIPM_DIR_XZ;
+    info.xz_fallback = 1;
+    build_L(false);
+    predictor();
   }
-  info.t_step += now() - t1;
+  const double coef = aho ? 2.0 : 1.0;
+  double t1 = 0.0;
   // mu_aff = (<X + a_p dX, Z + a_d dZ> + <T + a_d dT, s(X + a_p dX)>) / (n + q)
   const double xz = tt_dot(S.X, S.Z, c), xdz = tt_dot(S.X, dZ, c), dxz = tt_dot(dX, S.Z, c),
                dxdz = tt_dot(dX, dZ, c);
