@@ -330,8 +330,8 @@ typedef struct {
                            blocks with this many probes to the mlp handle's dataset        */
   int64_t collect_cap;  /* dataset size limit (blocks) for collect_probes                 */
   int32_t xz_fallback;  /* 1: redo an AHO iteration with the XZ direction when its predictor
-                           solve misses the residual target within the rank and sweep budget
-                           or admits a step below 1e-3 (Sec. 3.5); not with inequalities (1) */
+                           solve ends at the rank cap above its residual target, or admits a
+                           step below 1e-3 (Sec. 3.5); not with inequalities (0)            */
 } ttipm_params;
 
 TTIPM_API void ttipm_params_default(ttipm_params* p);

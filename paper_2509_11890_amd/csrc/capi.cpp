@@ -366,7 +366,7 @@ void ttipm_params_default(ttipm_params* p) {
   p->kick_sweeps = 1 << 30;
   p->collect_probes = 0;
   p->collect_cap = 1 << 20;
-  p->xz_fallback = 1;
+  p->xz_fallback = 0;
 }
 
 int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {

@@ -610,11 +610,12 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   };
   predictor();
   // AHO -> XZ fallback (Sec. 3.5): when the AHO solve misses its residual
-  // target within the rank and sweep budget, or admits almost no step, the
+  // target with the rank cap binding, or admits almost no step, the
   // iteration is redone with the XZ direction, which often needs lower TT
   // ranks.  Not with inequalities (reading: XZ breaks the symmetry of X
   // against the mirrored multipliers there).
-  if (aho && !P.ineq && prm.xz_fallback && (ai_p.last_max_res > ap.tol || std::max(a_p, a_d) < 1e-3)) {
+  if (aho && !P.ineq && prm.xz_fallback &&
+      ((ai_p.capped && ai_p.last_max_res > ap.tol) || std::max(a_p, a_d) < 1e-3)) {
     aho = false;
     info.direction = TTIPM_DIR_XZ;
     info.xz_fallback = 1;

@@ -144,6 +144,23 @@ def test_solve_matches_closed_form(name, kind, make, value):
     assert abs(res["dobj"] - value) / (1 + value) < 1e-6
 
 
+@pytest.mark.parametrize("enabled", [0, 1])
+def test_aho_to_xz_fallback_is_taken_and_logged(enabled):
+    """A frame capped at rank 1 with a single sweep cannot meet the AHO residual
+    target, so with the fallback on AHO iterations are redone with XZ (and
+    logged); with it off none is."""
+    P = _lib()
+    g = I.complete(4)
+    pr = P.Problem(P.TTIPM_MAXCUT, g.cores)
+    prm = P.Params(rank_cap=1, amen_sweeps=1, n_xz=1, max_iter=6, xz_fallback=enabled)
+    st = P.State(pr, prm)
+    res, log = P.ttipm_solve(pr, st, prm)
+    aho_iters = [l for l in log if l["iter"] >= 1]
+    assert aho_iters and all(np.isfinite(l["pobj"]) for l in log)
+    flags = [l["xz_fallback"] for l in aho_iters]
+    assert (any(flags) if enabled else not any(flags)), flags
+
+
 def test_c1_grid_matches_dense_oracle():
     """Config 1 (4x8 grid, d = 5, TT ranks <= 8, FP64): objective vs the dense IPM."""
     P = _lib()
