@@ -91,6 +91,32 @@ def contraction_rate(P, torch, r, R, reps=50, warm=5):
             "tflops": flops / t / 1e12, "frac_of_peak": flops / t / PEAK["f64"]}
 
 
+def interface_rate(P, torch, r, R, reps=50, warm=5):
+    """FP64 TFLOP/s of one left environment step (tt_contract_interfaces) at
+    core k = 1 of a 3-core frame: test/trial cores [r, 4, r], operator core
+    [R, 4, 4, R], environment [r][R][r]."""
+    g = torch.Generator(device="cpu").manual_seed(r * 1000 + R + 7)
+    rnd = lambda *s: torch.randn(*s, generator=g, dtype=torch.float64).cuda()
+    m = 4
+    V = [rnd(1, m, r), rnd(r, m, r), rnd(r, m, 1)]
+    U = [rnd(1, m, r), rnd(r, m, r), rnd(r, m, 1)]
+    O = [rnd(1, m, m, R), rnd(R, m, m, R), rnd(R, m, m, 1)]
+    phi_in, phi_out = rnd(r * R * r), torch.empty(r * R * r, dtype=torch.float64, device="cuda")
+    for _ in range(warm):
+        P.contract_interfaces(V, O, U, 1, P.TT_LEFT, phi_in, phi_out)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        P.contract_interfaces(V, O, U, 1, P.TT_LEFT, phi_in, phi_out)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    flops = 16.0 * r ** 3 * R + 32.0 * r ** 2 * R ** 2
+    return {"op": "interface", "r": r, "R": R, "dtype": "f64", "us": t * 1e6, "tflops": flops / t / 1e12,
+            "frac_of_peak": flops / t / PEAK["f64"]}
+
+
 def contraction_rate_bf16(P, torch, r, R, reps=50, warm=5):
     """Same projected matvec with BF16 operands / FP32 accumulation (tt_local_op.precision)."""
     g = torch.Generator(device="cpu").manual_seed(r * 1000 + R)
@@ -231,12 +257,17 @@ def main():
     import paper_2509_11890_amd as P
 
     if args.contraction_only:
+        # local matvec (FP64 and BF16) and environment step (FP64) at r in {8, 32, 64, 128},
+        # R in {1, 2, r, 2r}
         torch.cuda.set_device(0)
-        rows = []
-        for r, R in ((32, 64), (64, 128), (128, 256)):
-            rows.append(contraction_rate(P, torch, r, R))
-            rows.append(contraction_rate_bf16(P, torch, r, R))
-        print(json.dumps({"local_contraction": rows, "copy_bytes": calibration_copy(torch)}), flush=True)
+        rows, envs = [], []
+        for r in (8, 32, 64, 128):
+            for R in sorted({1, 2, r, 2 * r}):
+                rows.append(contraction_rate(P, torch, r, R))
+                rows.append(contraction_rate_bf16(P, torch, r, R))
+                envs.append(interface_rate(P, torch, r, R))
+        print(json.dumps({"local_contraction": rows, "interfaces": envs, "copy_bytes": calibration_copy(torch)}),
+              flush=True)
         return
 
     cfg_name, cap, icap = WORKLOADS[args.workload]

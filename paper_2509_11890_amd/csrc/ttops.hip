@@ -228,8 +228,9 @@ void gemv_update(long n, int k, const double* V, long ld, const double* coef, do
   TT_HIP(hipGetLastError());
 }
 
-// Deterministic multi-dot: out[j] = <V_j, w> for k vectors.  Stage 1 writes
-// per-block partials part[j][blk]; stage 2 reduces them in index order.
+// Deterministic multi-dot: out[j] = <V_j, w> for k vectors.  Short vectors
+// take one workgroup per product; longer ones a two-stage reduction (stage 1
+// writes per-block partials part[j][blk], stage 2 sums them in index order).
 constexpr int DOT_BLOCKS = 256;
 
 __global__ void mdot_stage1(long n, int k, const double* V, long ld, const double* w, double* part) {
@@ -264,8 +265,33 @@ __global__ void mdot_stage2(int nb, int k, const double* part, double* out) {
   if (threadIdx.x == 0) out[j] = red[0];
 }
 
+// Vectors up to this length: one workgroup per dot product, one launch.
+constexpr long DOT_SINGLE_MAX = 32768;
+
+__global__ void mdot_single(long n, const double* V, long ld, const double* w, double* out) {
+  __shared__ double red[TB / 64];
+  const int j = blockIdx.x;
+  const double* v = V + (long)j * ld;
+  double acc = 0.0;
+  for (long t = threadIdx.x; t < n; t += blockDim.x) acc += v[t] * w[t];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int i = 0; i < TB / 64; ++i) sum += red[i];
+    out[j] = sum;
+  }
+}
+
 void mdot(long n, int k, const double* V, long ld, const double* w, double* out, double* part, hipStream_t s) {
   if (k <= 0) return;
+  if (n <= DOT_SINGLE_MAX) {
+    hipLaunchKernelGGL(mdot_single, dim3(k), dim3(TB), 0, s, n, V, ld, w, out);
+    TT_HIP(hipGetLastError());
+    return;
+  }
   int nb = (int)std::min<long>(DOT_BLOCKS, std::max<long>(1, (n + TB - 1) / TB));
   hipLaunchKernelGGL(mdot_stage1, dim3(nb, k), dim3(TB), 0, s, n, k, V, ld, w, part);
   TT_HIP(hipGetLastError());

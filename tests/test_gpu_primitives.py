@@ -117,6 +117,34 @@ def test_local_matvec_blocks_and_chains(r, R, rp):
     assert _rel(y.cpu().numpy(), y_ref) < RTOL
 
 
+# Full sizes: the shapes and launch configuration of the contraction microbenchmark
+# (bench.py: r, R = (32, 64), (64, 128), (128, 256), m = 4); the oracle contracts
+# the whole product, so every output entry is compared.
+@pytest.mark.parametrize("r,R", [(32, 64), (64, 128), (128, 256)])
+def test_local_matvec_and_interfaces_full_size(r, R):
+    P = _lib()
+    rng = np.random.default_rng(r * 7 + R)
+    m = 4
+    phiL, core, phiR = (rng.standard_normal((r, R, r)), rng.standard_normal((R, m, m, R)),
+                        rng.standard_normal((r, R, r)))
+    x = rng.standard_normal((r, m, r))
+    ref = ott.local_apply(phiL, core, x, phiR)
+    K = P.LocalOp(r, r, 1, [P.LocalBlock(0, 0, 1.0, [P.ProjOp(_cuda(phiL), _cuda(core), _cuda(phiR))])])
+    y = torch.zeros(r * m * r, dtype=torch.float64, device="cuda")
+    P.local_matvec(K, _cuda(x), y)
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy().reshape(r, m, r), ref) < RTOL
+    V = [rng.standard_normal((1, m, r)), rng.standard_normal((r, m, r)), rng.standard_normal((r, m, 1))]
+    U = [rng.standard_normal((1, m, r)), rng.standard_normal((r, m, r)), rng.standard_normal((r, m, 1))]
+    O = [rng.standard_normal((1, m, m, R)), core, rng.standard_normal((R, m, m, 1))]
+    ref = ott.env_left_step(phiL, V[1], O[1], U[1])
+    out = torch.zeros(ref.shape, dtype=torch.float64, device="cuda")
+    P.contract_interfaces([_cuda(G) for G in V], [_cuda(G) for G in O], [_cuda(G) for G in U], 1, P.TT_LEFT,
+                          _cuda(phiL), out)
+    torch.cuda.synchronize()
+    assert _rel(out.cpu().numpy(), ref) < RTOL
+
+
 @pytest.mark.parametrize("ranks", [[1, 4, 9, 9, 4, 1], [1, 3, 12, 30, 12, 3, 1]])
 def test_round_recovers_redundant_tt(ranks):
     """T + T has doubled ranks; rounding at 1e-12 returns rank(T) and 2T exactly
