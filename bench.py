@@ -22,6 +22,8 @@ Beside it, the line carries
     stages) at the workload's shape and at r = 64, R = 128;
   * precision_variants_grid_d5: the 4x8 grid solved with FP64 direct, FP64 GMRES,
     mixed BF16 GMRES with FP64 refinement, and mixed + learned preconditioner;
+  * mixed_precision_same_step: the same step with BF16 Arnoldi products and
+    FP64 refinement of the local solves (untimed by the step clock);
   * time_to_gap_n1024_closed_forms: K_1024 and Q_10 MaxCut to the 1e-4 mark;
   * cpu_baseline: the dense FP64 HKM interior-point oracle on the same
     instance, timed on the host cores to the same gap rule.
@@ -337,6 +339,17 @@ def main():
     kernel_share = {k: round(v["time_ms"] * (args.profile_period if v["timed"] else 0) / 1e3 / args.steps, 4)
                     for k, v in kstats.items()}
 
+    # the same C2 step with BF16 Arnoldi products and FP64 refinement (mixed precision)
+    c2_mixed = None
+    if not args.no_variants:
+        pm = P.Params(rank_cap=cap, iter_rank_cap=icap, stop_gap=1e-4, eps_gap=1e-4, max_iter=args.max_iter,
+                      precision=P.TTIPM_MIXED, **solver)
+        t0m = time.perf_counter()
+        resm, logm = P.ttipm_solve(prob, P.State(prob, pm), pm)
+        c2_mixed = {"wall_s": time.perf_counter() - t0m, "iterations": resm["iterations"],
+                    "time_to_gap_s": resm["time_to_gap"], "rel_gap": resm["rel_gap"], "eps_p": resm["eps_p"],
+                    "eps_d": resm["eps_d"], "krylov_iters": int(sum(l["krylov_iters"] for l in logm)),
+                    "krylov_iters_f64": int(sum(l["krylov_iters"] for l in last_log))}
     contraction = [contraction_rate(P, torch, r, R) for r, R in ((cap, 2 * cap), (64, 128))]
     contraction += [contraction_rate_bf16(P, torch, r, R) for r, R in ((cap, 2 * cap), (64, 128))]
     variants = None if args.no_variants else precision_variants(P, I)
@@ -381,6 +394,7 @@ def main():
         "roofline": roof,
         "local_contraction": contraction,
         "precision_variants_grid_d5": variants,
+        "mixed_precision_same_step": c2_mixed,
         "time_to_gap_n1024_closed_forms": closed,
         "cpu_baseline": cpu,
     }
