@@ -673,7 +673,12 @@ bool dense_svd_fits_lds(int m, int n) {
 }
 
 void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, double* work, int* iwork,
-               hipStream_t s, int max_sweeps, double tol) {
+               hipStream_t s, int max_sweeps, double tol_in) {
+  // A pair counts as orthogonal below max(tol, 4 eps sqrt(m)) relative: the
+  // computed inner product of two exactly orthogonal columns of length m is
+  // rounding noise of about eps sqrt(m), so a tighter threshold cannot be
+  // certified by the computed products.
+  const double tol = std::max(tol_in, 4.0 * 2.220446049250313e-16 * std::sqrt((double)m));
   const double bytes = 8.0 * ((double)m * n * 2 + (double)n * n + n);
   const size_t lds_bytes = sizeof(double) * ((size_t)m * n + (size_t)n * n);
   const size_t lds_a_bytes = sizeof(double) * (size_t)m * n;

@@ -11,7 +11,8 @@ void dense_qr(double* A, int m, int n, int lda, double* tau, hipStream_t s);
 void dense_qr_form_q(const double* A, int m, int n, int lda, const double* tau, double* Q, int k, int ldq,
                      hipStream_t s);
 // One-sided Jacobi SVD of column-major A (m x n, lda = m, destroyed):
-// U (m x n col-major), sigma[n] descending, V (n x n col-major).
+// U (m x n col-major), sigma[n] descending, V (n x n col-major).  Column
+// pairs count as orthogonal below max(tol, 4 eps sqrt(m)) relative.
 // work >= n*n doubles, iwork >= n + 1 ints (iwork[n] = sweeps used).
 void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, double* work, int* iwork,
                hipStream_t s, int max_sweeps = 40, double tol = 4e-16);
