@@ -395,6 +395,16 @@ TTIPM_API int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* 
 TTIPM_API int ttipm_state_export(const ttipm_state* s, int32_t which, int32_t* ranks_out, double* host_out,
                        size_t cap, size_t* needed);
 
+/*
+ * Replace one iterate ('X', 'Y', 'Z' or 'T') with a TT given on the host, in
+ * the packing of ttipm_state_export (d+1 ranks, boundary ranks 1; cores one
+ * after another, count doubles in all): checkpoint / resume of a solve.  The
+ * warm starts of the Newton frame and of the step-length eigenvectors are
+ * kept.  Returns TT_ERR_ARG on a rank or size mismatch.  Synchronises.
+ */
+TTIPM_API int ttipm_state_import(ttipm_state* s, int32_t which, const int32_t* ranks, const double* host_in,
+                                 size_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -136,6 +136,7 @@ lib.ttipm_solve.argtypes = [_P, _P, C.POINTER(ttipm_params), C.POINTER(ttipm_res
                             C.POINTER(ttipm_step_info), C.c_int32, _P]
 lib.ttipm_state_export.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                    C.c_size_t, C.POINTER(C.c_size_t)]
+lib.ttipm_state_import.argtypes = [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_size_t]
 
 
 class tt_kernel_stat(C.Structure):
@@ -334,6 +335,17 @@ class State:
             out.append(arr[off:off + n].reshape(ranks[k], 4, ranks[k + 1]))
             off += n
         return out
+
+    def import_(self, which, cores):
+        """Replace an iterate ('X', 'Y', 'Z', 'T') by host cores [r, 4, r'] (the export packing)."""
+        import numpy as np
+        d = self.problem.d
+        if len(cores) != d:
+            raise ValueError("need one core per mode")
+        ranks = (C.c_int32 * (d + 1))(*([int(cores[0].shape[0])] + [int(G.shape[-1]) for G in cores]))
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(G, dtype=np.float64).ravel() for G in cores]))
+        _check(lib.ttipm_state_import(self.h, ord(which), ranks, flat.ctypes.data_as(C.POINTER(C.c_double)),
+                                      flat.size))
 
     def __del__(self):
         if getattr(self, "h", None) and self.h.value:

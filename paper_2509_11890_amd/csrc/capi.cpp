@@ -519,6 +519,40 @@ int ttipm_state_export(const ttipm_state* s, int32_t which, int32_t* ranks_out, 
   });
 }
 
+int ttipm_state_import(ttipm_state* s, int32_t which, const int32_t* ranks, const double* host_in, size_t count) {
+  return guarded([&]() -> int {
+    if (!s || !ranks || !host_in) throw Error(TT_ERR_ARG, "NULL argument");
+    TT* t = nullptr;
+    switch (which) {
+      case 'X': t = &s->S.X; break;
+      case 'Y': t = &s->S.Y; break;
+      case 'Z': t = &s->S.Z; break;
+      case 'T': t = &s->S.T; break;
+      default: throw Error(TT_ERR_ARG, "which must be one of X Y Z T");
+    }
+    if (t->d == 0) throw Error(TT_ERR_ARG, "iterate not present in this state");
+    const int d = t->d;
+    if (ranks[0] != 1 || ranks[d] != 1) throw Error(TT_ERR_ARG, "boundary ranks must be 1");
+    size_t total = 0;
+    for (int k = 0; k < d; ++k) {
+      if (ranks[k + 1] < 1) throw Error(TT_ERR_ARG, "ranks must be positive");
+      total += (size_t)ranks[k] * t->mo * t->mi * ranks[k + 1];
+    }
+    if (count != total) throw Error(TT_ERR_ARG, "core data size does not match the ranks");
+    std::vector<std::vector<double>> cores(d);
+    size_t off = 0;
+    for (int k = 0; k < d; ++k) {
+      const size_t n = (size_t)ranks[k] * t->mo * t->mi * ranks[k + 1];
+      cores[k].assign(host_in + off, host_in + off + n);
+      off += n;
+    }
+    Ctx& c = ctx_for(nullptr);
+    *t = tt_from_host(cores, std::vector<int>(ranks, ranks + d + 1), t->mo, t->mi, c);
+    c.sync();
+    return TT_OK;
+  });
+}
+
 int tt_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, int32_t seed, tt_mlp** out) {
   return guarded([&]() -> int {
     if (!out) throw Error(TT_ERR_ARG, "out is NULL");

@@ -273,3 +273,36 @@ def test_full_rank_cc_step_equals_dense_newton(direction):
         got = ott.full(st.export(comp))
         err = np.linalg.norm(got - r) / max(np.linalg.norm(r), 1e-300)
         assert err < 1e-8, (comp, err)
+
+
+def test_checkpoint_resume_through_state_import():
+    """Checkpoint / resume: iterates exported after a few steps and imported
+    into a fresh state are the same TTs (bit for bit), give the same measures at
+    entry of the next step, and the resumed solve reaches the closed-form value
+    (MaxCut on K_32: n^2/4 = 256).  Malformed imports are rejected."""
+    P = _lib()
+    g = I.complete(5)
+    pr = P.Problem(P.TTIPM_MAXCUT, g.cores)
+    prm = P.Params(rank_cap=8, stop_gap=3e-7, delta=1e-10, max_iter=60)
+    a = P.State(pr, prm)
+    for _ in range(4):
+        P.ttipm_step(pr, a, prm)
+    saved = {w: a.export(w) for w in "XYZ"}
+    b = P.State(pr, prm)
+    for w, cores in saved.items():
+        b.import_(w, cores)
+        back = b.export(w)
+        assert [G.shape for G in back] == [G.shape for G in cores]
+        assert all(np.array_equal(G, H) for G, H in zip(back, cores))
+    ia, ib = P.ttipm_step(pr, a, prm), P.ttipm_step(pr, b, prm)
+    for k in ("mu", "pobj", "dobj", "eps_p", "eps_d"):
+        assert abs(ia[k] - ib[k]) <= 1e-12 * (1 + abs(ia[k])), (k, ia[k], ib[k])
+
+    res, _ = P.ttipm_solve(pr, b, prm)
+    assert abs(res["pobj"] - 256.0) / 257.0 < 1e-6 and abs(res["dobj"] - 256.0) / 257.0 < 1e-6
+
+    bad = [G.copy() for G in saved["X"]]
+    with pytest.raises(P.TTError):
+        b.import_("Q", bad)
+    with pytest.raises(P.TTError):                     # inner rank mismatch between neighbours
+        b.import_("X", bad[:-1] + [np.zeros((bad[-1].shape[0] + 1, 4, 1))])
