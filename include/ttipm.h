@@ -332,6 +332,7 @@ typedef struct {
   int32_t xz_fallback;  /* 1: redo an AHO iteration with the XZ direction when its predictor
                            solve ends at the rank cap above its residual target, or admits a
                            step below 1e-3 (Sec. 3.5); not with inequalities (0)            */
+  int32_t eig_kick;     /* random kick ranks per core split of the step-length DMRG (2)   */
 } ttipm_params;
 
 TTIPM_API void ttipm_params_default(ttipm_params* p);

@@ -88,7 +88,7 @@ class ttipm_params(C.Structure):
                 ("precond", C.c_int32), ("mlp", C.c_void_p), ("eig_rank", C.c_int32),
                 ("eig_sweeps", C.c_int32), ("verbose", C.c_int32), ("kick", C.c_int32), ("seed", C.c_int32),
                 ("kick_sweeps", C.c_int32), ("collect_probes", C.c_int32), ("collect_cap", C.c_int64),
-                ("xz_fallback", C.c_int32)]
+                ("xz_fallback", C.c_int32), ("eig_kick", C.c_int32)]
 
 
 class ttipm_step_info(C.Structure):

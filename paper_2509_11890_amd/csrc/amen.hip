@@ -215,7 +215,6 @@ double dev_norm(const double* x, long n, Ctx& c) {
   return std::sqrt(std::max(h[0], 0.0));
 }
 
-// Move the block index from W.pos to W.pos + 1 (dir > 0) or W.pos - 1 (dir < 0).
 // n x q block of seeded standard normal numbers (row-major), uploaded to dev.
 static void random_block(double* dev, long count, unsigned long long seed, Ctx& c) {
   std::mt19937_64 rng(seed);
@@ -225,6 +224,33 @@ static void random_block(double* dev, long count, unsigned long long seed, Ctx& 
   TT_HIP(hipMemcpyAsync(dev, h.data(), sizeof(double) * count, hipMemcpyHostToDevice, c.s));
   c.sync();
 }
+
+void random_orth_rows(const double* B, int q0, long bj, long bi, int len, double* G, int q, unsigned long long seed,
+                      Ctx& c) {
+  if (q <= 0) return;
+  random_block(G, (long)q * len, seed, c);
+  if (q0 > 0) {
+    DevBuf T((size_t)q * q0);
+    for (int pass = 0; pass < 2; ++pass) {
+      Gemm g1;   // T = G B^T  (q x q0)
+      g1.M = q; g1.N = q0; g1.K = len;
+      g1.A = G; g1.am = len; g1.ak = 1;
+      g1.B = B; g1.bk = bi; g1.bn = bj;
+      g1.C = T.get(); g1.cm = q0; g1.cn = 1;
+      gemm(g1, c.s, &c.ws, GemmPrec::F64);
+      Gemm g2;   // G -= T B
+      g2.M = q; g2.N = len; g2.K = q0;
+      g2.A = T.get(); g2.am = q0; g2.ak = 1;
+      g2.B = B; g2.bk = bj; g2.bn = bi;
+      g2.C = G; g2.cm = len; g2.cn = 1;
+      g2.alpha = -1.0; g2.beta = 1.0;
+      gemm(g2, c.s, &c.ws, GemmPrec::F64);
+    }
+  }
+  orth_rows(G, q, len, c);
+}
+
+// Move the block index from W.pos to W.pos + 1 (dir > 0) or W.pos - 1 (dir < 0).
 
 bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick, unsigned long long seed) {
   bool capped = false;
@@ -253,7 +279,7 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
                        Lp, r, md, s, ones.get());
     TT_HIP(hipGetLastError());
     SvdOut sv;
-    svd_rowmajor(Ms.get(), rows, cols, sv, c);
+    svd_rowmajor_side(Ms.get(), rows, cols, true, sv, c);
     // Enrichment fills only the capacity the rank cap leaves: once the cap
     // binds, the truncated SVD directions are kept in full.
     const int rk_tol = rank_for(sv.sigma, tol_rel, sv.k);
@@ -265,25 +291,9 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     W.cores[k].reserve((size_t)rows * rk);
     copy2d(sv.U.get(), sv.k, W.cores[k].get(), rk, rows, rk0, c.s);
     if (q > 0) {
-      // random columns orthogonalised against U (twice) and orthonormalised
-      DevBuf G((size_t)q * rows), T((size_t)q * rk0);
-      random_block(G.get(), (long)q * rows, seed, c);          // G^T: q x rows
-      for (int pass = 0; pass < 2; ++pass) {
-        Gemm g1;   // T = G^T U  (q x rk0)
-        g1.M = q; g1.N = rk0; g1.K = rows;
-        g1.A = G.get(); g1.am = rows; g1.ak = 1;
-        g1.B = W.cores[k].get(); g1.bk = rk; g1.bn = 1;
-        g1.C = T.get(); g1.cm = rk0; g1.cn = 1;
-        gemm(g1, c.s, &c.ws, GemmPrec::F64);
-        Gemm g2;   // G^T -= T U^T
-        g2.M = q; g2.N = rows; g2.K = rk0;
-        g2.A = T.get(); g2.am = rk0; g2.ak = 1;
-        g2.B = W.cores[k].get(); g2.bk = 1; g2.bn = rk;
-        g2.C = G.get(); g2.cm = rows; g2.cn = 1;
-        g2.alpha = -1.0; g2.beta = 1.0;
-        gemm(g2, c.s, &c.ws, GemmPrec::F64);
-      }
-      orth_rows(G.get(), q, rows, c);
+      // random columns orthonormalised against U (the columns of W_k)
+      DevBuf G((size_t)q * rows);                                // G^T: q x rows
+      random_orth_rows(W.cores[k].get(), rk0, 1, rk, rows, G.get(), q, seed, c);
       // columns rk0.. of W_k = G (transposed)
       DevBuf Gt((size_t)rows * q);
       permute(G.get(), Gt.get(), {q, rows}, {1, 0}, c.s);
@@ -315,7 +325,7 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
                        M.get(), Lp, r, md, s, ones.get());
     TT_HIP(hipGetLastError());
     SvdOut sv;
-    svd_rowmajor(Ms.get(), rows, cols, sv, c);
+    svd_rowmajor_side(Ms.get(), rows, cols, false, sv, c);
     const int rk_tol = rank_for(sv.sigma, tol_rel, sv.k);
     const int rk0 = std::max(1, std::min(rk_tol, cap));
     capped = rk_tol > cap;
@@ -325,27 +335,8 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     W.cores[k].reserve((size_t)rk * cols);
     TT_HIP(hipMemcpyAsync(W.cores[k].get(), sv.Vt.get(), sizeof(double) * (size_t)rk0 * cols, hipMemcpyDeviceToDevice,
                           c.s));
-    if (q > 0) {
-      double* G = W.cores[k].get() + (size_t)rk0 * cols;        // q x cols
-      random_block(G, (long)q * cols, seed, c);
-      DevBuf T((size_t)q * rk0);
-      for (int pass = 0; pass < 2; ++pass) {
-        Gemm g1;   // T = G Vt^T (q x rk0)
-        g1.M = q; g1.N = rk0; g1.K = cols;
-        g1.A = G; g1.am = cols; g1.ak = 1;
-        g1.B = W.cores[k].get(); g1.bk = 1; g1.bn = cols;
-        g1.C = T.get(); g1.cm = rk0; g1.cn = 1;
-        gemm(g1, c.s, &c.ws, GemmPrec::F64);
-        Gemm g2;   // G -= T Vt
-        g2.M = q; g2.N = cols; g2.K = rk0;
-        g2.A = T.get(); g2.am = rk0; g2.ak = 1;
-        g2.B = W.cores[k].get(); g2.bk = cols; g2.bn = 1;
-        g2.C = G; g2.cm = cols; g2.cn = 1;
-        g2.alpha = -1.0; g2.beta = 1.0;
-        gemm(g2, c.s, &c.ws, GemmPrec::F64);
-      }
-      orth_rows(G, q, cols, c);
-    }
+    if (q > 0)   // random rows orthonormalised against those of Vt
+      random_orth_rows(W.cores[k].get(), rk0, cols, 1, cols, W.cores[k].get() + (size_t)rk0 * cols, q, seed, c);
     // coef = M Vt[:rk]^T  ((a,l) x rk)
     DevBuf coef((size_t)rows * rk);
     Gemm g;
@@ -692,7 +683,12 @@ BlockTT block_from_frame(const TT& frame, int Lp, Ctx& c) {
 }
 
 void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInfo& info, Ctx& c) {
-  TT_REQUIRE(W.pos == 0, "amen_solve expects the block at core 0");
+  // The block sits at an end core: core 0 (the first sweep runs left to
+  // right) or core d-1, where the previous solve's last sweep left it (the
+  // first sweep runs right to left).  Either way every other core is
+  // orthogonal towards the block, which is what the environments assume.
+  const bool from_right = W.pos == W.d - 1 && W.d > 1;
+  TT_REQUIRE(W.pos == 0 || from_right, "amen_solve expects the block at an end core");
   TT_REQUIRE(W.Lp == sys.Lp(), "block size");
   const int d = W.d;
   const int L = sys.L();
@@ -714,11 +710,14 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   Envs envs;
   envs.init(keys, d, c);
   double t0 = now();
-  for (int k = d - 1; k > 0; --k) envs.update_right(W, k, c);
+  if (from_right)
+    for (int k = 0; k < d - 1; ++k) envs.update_left(W, k, c);
+  else
+    for (int k = d - 1; k > 0; --k) envs.update_right(W, k, c);
   c.sync();
   info.t_env += now() - t0;
   const double tol_svd = prm.tol / std::sqrt((double)d);
-  int dir = +1;
+  int dir = from_right ? -1 : +1;
   info.sweeps = 0;
   info.krylov_iters = 0;
   std::vector<DevBuf> Rhat(4);
@@ -846,8 +845,9 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
     dir = -dir;
     if (max_res < prm.tol && sweep >= 1) break;
   }
-  // return the block to core 0 without truncation
-  while (W.pos > 0) split_block(W, -1, 0.0, 1 << 30, c);
+  // The block stays where the last sweep left it (an end core): moving it back
+  // without truncation would only merge the components into the shared frame
+  // and inflate every component's TT ranks (up to L+1 times the frame rank).
   info.max_rank = 0;
   for (int x : W.r) info.max_rank = std::max(info.max_rank, x);
 }

@@ -52,6 +52,11 @@ struct BlockTT {
 // SVD of the component-normalised block core (relative tolerance, rank cap).
 // kick > 0 appends that many seeded random orthonormal directions to the kept
 // factor (enrichment), within the rank cap.
+// G (q x len, row-major) = q seeded Gaussian rows orthonormalised against q0
+// orthonormal vectors b_j (element i of b_j at B[j*bj + i*bi]; two Gram-Schmidt
+// passes) and against each other (QR): the random enrichment of a TT core.
+void random_orth_rows(const double* B, int q0, long bj, long bi, int len, double* G, int q, unsigned long long seed,
+                      Ctx& c);
 bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick = 0,
                  unsigned long long seed = 0);
 // Norm of a device vector (deterministic; synchronises).

@@ -367,6 +367,7 @@ void ttipm_params_default(ttipm_params* p) {
   p->collect_probes = 0;
   p->collect_cap = 1 << 20;
   p->xz_fallback = 0;
+  p->eig_kick = 2;
 }
 
 int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {

@@ -118,15 +118,19 @@ __global__ __launch_bounds__(DT) void qr_form_q_kernel(const double* A, int m, i
 // pairs per step, one wavefront per pair.  On exit U (m x n, column-major),
 // sigma (descending) and V (n x n, column-major) with A = U diag(sigma) V^T.
 // Columns of U with sigma = 0 are zero.  work: m*n + n*n doubles + n ints.
+// With Vw == nullptr the rotations are not accumulated and V is not written:
+// the left singular vectors and the singular values alone (n <= 4096).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double* Vw, double* U, double* sigma,
                                                 double* V, int* order, int max_sweeps, double tol, int* sweeps_out,
                                                 int& s_rot) {
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
-    int c = (int)(t / n), i = (int)(t % n);
-    Vw[t] = (i == c) ? 1.0 : 0.0;
-  }
+  const bool wantv = Vw != nullptr;
+  if (wantv)
+    for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
+      int c = (int)(t / n), i = (int)(t % n);
+      Vw[t] = (i == c) ? 1.0 : 0.0;
+    }
   __syncthreads();
   const int N = (n % 2) ? n + 1 : n;   // players incl. a dummy when n is odd
   // 16-lane groups rotate one column pair each (64 pairs in flight per step);
@@ -167,12 +171,14 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
           ap[i] = c * x - s * y;
           aq[i] = s * x + c * y;
         }
-        double* vp = Vw + (long)p * n;
-        double* vq = Vw + (long)q * n;
-        for (int i = gl; i < n; i += 16) {
-          double x = vp[i], y = vq[i];
-          vp[i] = c * x - s * y;
-          vq[i] = s * x + c * y;
+        if (wantv) {
+          double* vp = Vw + (long)p * n;
+          double* vq = Vw + (long)q * n;
+          for (int i = gl; i < n; i += 16) {
+            double x = vp[i], y = vq[i];
+            vp[i] = c * x - s * y;
+            vq[i] = s * x + c * y;
+          }
         }
         if (gl == 0) s_rot = 1;
       }
@@ -208,17 +214,25 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
     double sc = sigma[c];
     U[t] = (sc > 0.0) ? A[(long)c * m + i] / sc : 0.0;
   }
-  for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
-    int rnk = (int)(t / n), i = (int)(t % n);
-    V[t] = Vw[(long)order[rnk] * n + i];
+  if (wantv)
+    for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
+      int rnk = (int)(t / n), i = (int)(t % n);
+      V[t] = Vw[(long)order[rnk] * n + i];
+    }
+  // sigma in sorted order: gathered into registers, written back after a barrier
+  double sv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int rnk = threadIdx.x + j * blockDim.x;
+    sv[j] = (rnk < n) ? sigma[order[rnk]] : 0.0;
   }
   __syncthreads();
-  // sigma in sorted order (in place via U-independent pass)
-  if (threadIdx.x == 0) {
-    for (int rnk = 0; rnk < n; ++rnk) Vw[rnk] = sigma[order[rnk]];
-    for (int rnk = 0; rnk < n; ++rnk) sigma[rnk] = Vw[rnk];
-    if (sweeps_out) *sweeps_out = sweep;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int rnk = threadIdx.x + j * blockDim.x;
+    if (rnk < n) sigma[rnk] = sv[j];
   }
+  if (threadIdx.x == 0 && sweeps_out) *sweeps_out = sweep;
 }
 
 __global__ __launch_bounds__(DT) void jacobi_svd_kernel(double* A, int m, int n, double* Vw, double* U,
@@ -232,13 +246,14 @@ __global__ __launch_bounds__(DT) void jacobi_svd_kernel(double* A, int m, int n,
 // shared memory of (m*n + n*n) doubles): every column access of a rotation is
 // then an LDS access instead of an L2 round trip, which is what bounds the
 // latency-bound sweeps for the small matrices of the TT splits and roundings.
+// With wantv == 0 only A is resident (m*n doubles) and V is not formed.
 __global__ __launch_bounds__(DT) void jacobi_svd_lds_kernel(const double* Ag, int m, int n, double* U,
                                                             double* sigma, double* V, int* order, int max_sweeps,
-                                                            double tol, int* sweeps_out) {
+                                                            double tol, int* sweeps_out, int wantv) {
   extern __shared__ double lds[];
   __shared__ int s_rot;
   double* As = lds;
-  double* Vs = lds + (long)m * n;
+  double* Vs = wantv ? lds + (long)m * n : nullptr;
   for (long t = threadIdx.x; t < (long)m * n; t += blockDim.x) As[t] = Ag[t];
   jacobi_svd_body(As, m, n, Vs, U, sigma, V, order, max_sweeps, tol, sweeps_out, s_rot);
 }
@@ -678,13 +693,14 @@ void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, dou
   // computed inner product of two exactly orthogonal columns of length m is
   // rounding noise of about eps sqrt(m), so a tighter threshold cannot be
   // certified by the computed products.
+  if (n > 4 * DT) throw Error(TT_ERR_ARG, "dense_svd: more than 4096 columns");
   const double tol = std::max(tol_in, 4.0 * 2.220446049250313e-16 * std::sqrt((double)m));
   const double bytes = 8.0 * ((double)m * n * 2 + (double)n * n + n);
   const size_t lds_bytes = sizeof(double) * ((size_t)m * n + (size_t)n * n);
   const size_t lds_a_bytes = sizeof(double) * (size_t)m * n;
   if (lds_bytes <= jacobi_lds_limit()) {
     launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_kernel, dim3(1), dim3(DT), (unsigned)lds_bytes, s,
-                (const double*)A, m, n, U, sigma, V, iwork, max_sweeps, tol, iwork + n);
+                (const double*)A, m, n, U, sigma, V, iwork, max_sweeps, tol, iwork + n, 1);
   } else if (lds_a_bytes <= jacobi_lds_limit()) {
     launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_a_kernel, dim3(1), dim3(DT), (unsigned)lds_a_bytes, s,
                 (const double*)A, m, n, work, U, sigma, V, iwork, max_sweeps, tol, iwork + n);
@@ -692,6 +708,25 @@ void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, dou
     launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_kernel, dim3(1), dim3(DT), 0u, s, A, m, n, work, U, sigma, V,
                 iwork, max_sweeps, tol, iwork + n);
   }
+  TT_HIP(hipGetLastError());
+}
+
+bool dense_svd_left_fits_lds(int m, int n) {
+  return sizeof(double) * (size_t)m * n <= jacobi_lds_limit();
+}
+
+void dense_svd_left(double* A, int m, int n, double* U, double* sigma, int* iwork, hipStream_t s, int max_sweeps,
+                    double tol_in) {
+  if (n > 4 * DT) throw Error(TT_ERR_ARG, "dense_svd_left: more than 4096 columns");
+  const double tol = std::max(tol_in, 4.0 * 2.220446049250313e-16 * std::sqrt((double)m));
+  const double bytes = 8.0 * ((double)m * n * 2 + n);
+  const size_t lds_bytes = sizeof(double) * (size_t)m * n;
+  if (lds_bytes <= jacobi_lds_limit())
+    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_kernel, dim3(1), dim3(DT), (unsigned)lds_bytes, s,
+                (const double*)A, m, n, U, sigma, (double*)nullptr, iwork, max_sweeps, tol, iwork + n, 0);
+  else
+    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_kernel, dim3(1), dim3(DT), 0u, s, A, m, n, (double*)nullptr, U,
+                sigma, (double*)nullptr, iwork, max_sweeps, tol, iwork + n);
   TT_HIP(hipGetLastError());
 }
 

@@ -18,6 +18,13 @@ void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, dou
                hipStream_t s, int max_sweeps = 40, double tol = 4e-16);
 // True when dense_svd of an m x n matrix keeps both A and V in LDS.
 bool dense_svd_fits_lds(int m, int n);
+// The same sweeps without accumulating the rotations: U (m x n col-major) and
+// sigma[n] descending only; A is destroyed unless it fits in LDS.  n <= 4096.
+// iwork >= n + 1 ints (iwork[n] = sweeps used).
+void dense_svd_left(double* A, int m, int n, double* U, double* sigma, int* iwork, hipStream_t s,
+                    int max_sweeps = 40, double tol = 4e-16);
+// True when dense_svd_left of an m x n matrix keeps A in LDS.
+bool dense_svd_left_fits_lds(int m, int n);
 // Smallest eigenpair of a symmetric row-major p x p matrix B (restarted Lanczos
 // with full reorthogonalisation): v (p, unit norm), lam (1 double, device).
 // work >= p * (min(kmax, p) + 1) doubles.

@@ -242,7 +242,7 @@ double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c) {
 
 }  // namespace
 
-double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int rank, int sweeps,
+double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int rank, int sweeps, int kick,
                    unsigned long long seed, Ctx& c) {
   const int d = Mv.d;
   TT M = tt_as_matrix(Mv, 2, c);
@@ -319,21 +319,41 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
         for (int j = 1; j < sv.k; ++j)
           if (sv.sigma[j] > 1e-10 * std::sqrt(tot)) q = j + 1;
         q = std::max(1, std::min(q, rank));
-        E.cores[k].reserve((size_t)2 * r * q);
-        E.cores[k + 1].reserve((size_t)q * 2 * s);
-        DevBuf sd(q);
-        TT_HIP(hipMemcpyAsync(sd.get(), sv.sigma.data(), sizeof(double) * q, hipMemcpyHostToDevice, c.s));
+        // Random kick ranks (Sec. 3.4): qk seeded random directions,
+        // orthonormal to the kept ones, join the orthogonal core with zero
+        // weight in its neighbour.  E is unchanged, but the next two-site
+        // problem sees a larger frame, so a vector that has collapsed to a
+        // low rank can still grow towards the true minimiser.
+        const int qk = std::max(0, std::min(kick, (lr ? 2 * r : 2 * s) - q));
+        const int rq = q + qk;
+        const unsigned long long ks = seed * 1000003ull + (unsigned long long)((sw * 2 + pass) * 131 + k);
+        E.cores[k].reserve((size_t)2 * r * rq);
+        E.cores[k + 1].reserve((size_t)rq * 2 * s);
         if (lr) {
-          copy2d(sv.U.get(), sv.k, E.cores[k].get(), q, 2 * r, q, c.s);                   // left-orthonormal
+          copy2d(sv.U.get(), sv.k, E.cores[k].get(), rq, 2 * r, q, c.s);                  // left-orthonormal
           TT_HIP(hipMemcpyAsync(E.cores[k + 1].get(), sv.Vt.get(), sizeof(double) * (size_t)q * 2 * s,
                                 hipMemcpyDeviceToDevice, c.s));
-          E.r[k + 1] = q;
+          if (qk > 0) {
+            DevBuf G((size_t)qk * 2 * r), Gt((size_t)2 * r * qk);
+            random_orth_rows(E.cores[k].get(), q, 1, rq, 2 * r, G.get(), qk, ks, c);
+            permute(G.get(), Gt.get(), {qk, 2 * r}, {1, 0}, c.s);
+            copy2d(Gt.get(), qk, E.cores[k].get() + q, rq, 2 * r, qk, c.s);
+            fill((long)qk * 2 * s, 0.0, E.cores[k + 1].get() + (size_t)q * 2 * s, c.s);
+          }
+          E.r[k + 1] = rq;
           upd_left(k);
         } else {
           TT_HIP(hipMemcpyAsync(E.cores[k + 1].get(), sv.Vt.get(), sizeof(double) * (size_t)q * 2 * s,
                                 hipMemcpyDeviceToDevice, c.s));                           // right-orthonormal
-          copy2d(sv.U.get(), sv.k, E.cores[k].get(), q, 2 * r, q, c.s);
-          E.r[k + 1] = q;
+          copy2d(sv.U.get(), sv.k, E.cores[k].get(), rq, 2 * r, q, c.s);
+          if (qk > 0) {
+            random_orth_rows(E.cores[k + 1].get(), q, 2 * s, 1, 2 * s, E.cores[k + 1].get() + (size_t)q * 2 * s, qk,
+                             ks, c);
+            DevBuf Z((size_t)2 * r * qk);
+            fill((long)2 * r * qk, 0.0, Z.get(), c.s);
+            copy2d(Z.get(), qk, E.cores[k].get() + q, rq, 2 * r, qk, c.s);
+          }
+          E.r[k + 1] = rq;
           upd_right(k + 1);
         }
         c.sync();
@@ -411,7 +431,8 @@ double ratio_step(const TT& v, const TT& dv, const TT& mask, Ctx& c) {
 
 double step_length(const TT& M, const TT& dM, BlockTT& E, bool& have_E, const ttipm_params& prm,
                    unsigned long long seed, Ctx& c) {
-  const double lam = min_gen_eig(M, dM, E, have_E, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps), seed, c);
+  const double lam = min_gen_eig(M, dM, E, have_E, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps),
+                                 std::max(0, prm.eig_kick), seed, c);
   // Thm. 1: the largest alpha with M + alpha dM positive definite is -1/lambda_min
   // when lambda_min < 0 and unbounded otherwise (reported as kNoBound).
   if (!(lam < 0.0)) return kNoBound;
@@ -684,7 +705,8 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   const int cap = prm.iter_rank_cap > 0 ? prm.iter_rank_cap : 4 * prm.rank_cap;
   {
     auto pd_min = [&](const TT& M, BlockTT& E, bool& have) {
-      return min_gen_eig(P.Ivec, M, E, have, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps), sd + 11, c);
+      return min_gen_eig(P.Ivec, M, E, have, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps),
+                         std::max(0, prm.eig_kick), sd + 11, c);
     };
     TT Xn, Zn;
     for (int tries = 0;; ++tries) {

@@ -46,9 +46,10 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
 void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& c);
 
 // Smallest generalised eigenvalue of (dM, M) over TT vectors of the given rank
-// (one-site ALS with Cholesky reduction of the projected pencil; Sec. 3.4).
+// (two-site DMRG with Cholesky reduction of the projected pencil and `kick`
+// random kick ranks per split; Sec. 3.4).
 // Throws TT_ERR_NOT_PD if a projected M is not positive definite.
-double min_gen_eig(const TT& M, const TT& dM, BlockTT& E, bool& have_E, int rank, int sweeps,
+double min_gen_eig(const TT& M, const TT& dM, BlockTT& E, bool& have_E, int rank, int sweeps, int kick,
                    unsigned long long seed, Ctx& c);
 // Largest alpha in (0, 1] with M + alpha dM psd, scaled by tau (Sec. 3.4).
 double step_length(const TT& M, const TT& dM, BlockTT& E, bool& have_E, const ttipm_params& prm,

@@ -386,12 +386,6 @@ __global__ void upper_to_rowmajor_kernel(const double* Acm, int lda, int k, int 
   R[t] = (i <= j) ? Acm[(long)j * lda + i] : 0.0;
 }
 
-__global__ void scale_rows_kernel(double* A, int rows, int cols, const double* s) {
-  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)rows * cols) return;
-  A[t] *= s[t / cols];
-}
-
 // Householder QR of a row-major matrix given as its column-major transpose:
 // the input `Mt_cm` is column-major (m x n) = row-major (n x m).  Returns Q
 // column-major (m x k) and R row-major (k x n), k = min(m, n).
@@ -455,6 +449,66 @@ void svd_rowmajor(const double* M, int rows, int cols, SvdOut& out, Ctx& c) {
   c.sync();
 }
 
+void svd_rowmajor_side(const double* M, int rows, int cols, bool left, SvdOut& out, Ctx& c) {
+  // T is the matrix whose left singular vectors are wanted: M itself (left) or
+  // M^T (right, whose left vectors are the right vectors of M).  The Jacobi
+  // sweeps then need no rotation accumulator: the vectors are the normalised
+  // final columns.
+  const int mt = left ? rows : cols, nt = left ? cols : rows;
+  const int k = std::min(mt, nt);
+  out.k = k;
+  DevBuf Ut((size_t)mt * k), sig(k);
+  c.ired.reserve((size_t)k + 8);
+  int* iw = reinterpret_cast<int*>(c.ired.get());
+  if (mt >= nt) {
+    // column-major T: M^T's is the row-major M itself, M's is its transpose
+    DevBuf A((size_t)mt * nt);
+    if (left)
+      permute(M, A.get(), {rows, cols}, {1, 0}, c.s);
+    else
+      TT_HIP(hipMemcpyAsync(A.get(), M, sizeof(double) * (size_t)mt * nt, hipMemcpyDeviceToDevice, c.s));
+    if (mt > 2 * nt || (!dense_svd_left_fits_lds(mt, nt) && dense_svd_left_fits_lds(nt, nt))) {
+      // T = Q R: the left vectors of T are Q times those of R (n x n)
+      DevBuf Q((size_t)mt * nt), R((size_t)nt * nt), Rcm((size_t)nt * nt), Ur((size_t)nt * nt);
+      qr_colmajor(A.get(), mt, nt, Q.get(), R.get(), c);
+      permute(R.get(), Rcm.get(), {nt, nt}, {1, 0}, c.s);
+      dense_svd_left(Rcm.get(), nt, nt, Ur.get(), sig.get(), iw, c.s);
+      Gemm g;   // Ut (mt x nt col-major) = Q Ur; row-major view Ut^T = Ur^T Q^T
+      g.M = nt; g.N = mt; g.K = nt;
+      g.A = Ur.get(); g.am = nt; g.ak = 1;
+      g.B = Q.get(); g.bk = mt; g.bn = 1;
+      g.C = Ut.get(); g.cm = mt; g.cn = 1;
+      gemm(g, c.s, &c.ws, GemmPrec::F64);
+    } else {
+      dense_svd_left(A.get(), mt, nt, Ut.get(), sig.get(), iw, c.s);
+    }
+  } else {
+    // wide T: T^T = Q R gives T = R^T Q^T, whose left vectors are those of the
+    // square R^T; the column-major R^T is the row-major R of the factorisation
+    DevBuf A((size_t)nt * mt), R((size_t)mt * mt);
+    if (left)
+      TT_HIP(hipMemcpyAsync(A.get(), M, sizeof(double) * (size_t)nt * mt, hipMemcpyDeviceToDevice, c.s));
+    else
+      permute(M, A.get(), {rows, cols}, {1, 0}, c.s);
+    c.dscr3.reserve((size_t)mt + 1);
+    dense_qr(A.get(), nt, mt, nt, c.dscr3.get(), c.s);
+    hipLaunchKernelGGL(upper_to_rowmajor_kernel, dim3(nblocks((long)mt * mt, 256)), dim3(256), 0, c.s, A.get(), nt,
+                       mt, mt, R.get());
+    TT_HIP(hipGetLastError());
+    dense_svd_left(R.get(), mt, mt, Ut.get(), sig.get(), iw, c.s);
+  }
+  out.sigma.resize(k);
+  TT_HIP(hipMemcpyAsync(out.sigma.data(), sig.get(), sizeof(double) * k, hipMemcpyDeviceToHost, c.s));
+  if (left) {
+    out.U.reserve((size_t)rows * k);       // row-major rows x k = transpose of Ut
+    permute(Ut.get(), out.U.get(), {k, rows}, {1, 0}, c.s);
+  } else {
+    out.Vt.reserve((size_t)k * cols);      // row-major k x cols = the column-major Ut buffer
+    TT_HIP(hipMemcpyAsync(out.Vt.get(), Ut.get(), sizeof(double) * (size_t)k * cols, hipMemcpyDeviceToDevice, c.s));
+  }
+  c.sync();
+}
+
 void orth_rows(double* G, int q, int len, Ctx& c) {
   // rows of G (q x len, row-major) = columns of a column-major len x q matrix
   if (q <= 0) return;
@@ -504,7 +558,7 @@ double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped) {
   for (int k = 0; k < t.d - 1; ++k) {
     const int rows = (int)(t.r[k] * mid), cols = t.r[k + 1];
     SvdOut sv;
-    svd_rowmajor(t.core(k), rows, cols, sv, c);
+    svd_rowmajor_side(t.core(k), rows, cols, true, sv, c);
     const int kk = sv.k;
     // smallest rank whose discarded tail is within eps_k
     std::vector<double> tail(kk + 1, 0.0);
@@ -521,13 +575,17 @@ double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped) {
     // new core k = U[:, :rk] (leading columns of the row-major U)
     DevBuf nc((size_t)rows * rk);
     copy2d(sv.U.get(), kk, nc.get(), rk, rows, rk, c.s);
-    // S Vt[:rk] into the next core: next = diag(s) Vt[:rk, :] core_{k+1}
-    DevBuf svt((size_t)rk * cols), s_dev(rk);
-    TT_HIP(hipMemcpyAsync(svt.get(), sv.Vt.get(), sizeof(double) * (size_t)rk * cols, hipMemcpyDeviceToDevice, c.s));
-    TT_HIP(hipMemcpyAsync(s_dev.get(), sv.sigma.data(), sizeof(double) * rk, hipMemcpyHostToDevice, c.s));
-    hipLaunchKernelGGL(scale_rows_kernel, dim3(nblocks((long)rk * cols, 256)), dim3(256), 0, c.s, svt.get(), rk, cols,
-                       s_dev.get());
-    TT_HIP(hipGetLastError());
+    // S Vt[:rk] = U[:, :rk]^T core_k (the projection onto the kept left
+    // vectors) goes into the next core: next = U[:, :rk]^T core_k core_{k+1}
+    DevBuf svt((size_t)rk * cols);
+    {
+      Gemm g;
+      g.M = rk; g.N = cols; g.K = rows;
+      g.A = nc.get(); g.am = 1; g.ak = rk;
+      g.B = t.core(k); g.bk = cols; g.bn = 1;
+      g.C = svt.get(); g.cm = cols; g.cn = 1;
+      gemm(g, c.s, &c.ws, GemmPrec::F64);
+    }
     const int ncols = (int)(mid * t.r[k + 2]);
     DevBuf nn((size_t)rk * ncols);
     gemm(gemm_nn(rk, ncols, cols, svt.get(), cols, t.core(k + 1), ncols, nn.get(), ncols), c.s, &c.ws, GemmPrec::F64);

@@ -101,5 +101,7 @@ struct SvdOut {
   int k = 0;
 };
 void svd_rowmajor(const double* M, int rows, int cols, SvdOut& out, Ctx& c);
+// One side only: sigma and U (left) or Vt (right), with k = min(rows, cols).
+void svd_rowmajor_side(const double* M, int rows, int cols, bool left, SvdOut& out, Ctx& c);
 
 }  // namespace ttipm
