@@ -123,9 +123,10 @@ __global__ __launch_bounds__(DT) void qr_form_q_kernel(const double* A, int m, i
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double* Vw, double* U, double* sigma,
                                                 double* V, int* order, int max_sweeps, double tol, int* sweeps_out,
-                                                int& s_rot) {
+                                                int* s_rot) {
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const bool wantv = Vw != nullptr;
+  const double big = sqrt(tol);
   if (wantv)
     for (long t = threadIdx.x; t < (long)n * n; t += blockDim.x) {
       int c = (int)(t / n), i = (int)(t % n);
@@ -139,7 +140,7 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
   constexpr int NG = DT / 16;
   int sweep = 0;
   for (; sweep < max_sweeps && N > 1; ++sweep) {
-    if (threadIdx.x == 0) s_rot = 0;
+    if (threadIdx.x == 0) { s_rot[0] = 0; s_rot[1] = 0; }
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
       for (int pi = gid; pi < N / 2; pi += NG) {
@@ -180,12 +181,19 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
             vq[i] = s * x + c * y;
           }
         }
-        if (gl == 0) s_rot = 1;
+        if (gl == 0) {
+          s_rot[0] = 1;
+          if (fabs(ga) > big * sqrt(al * be)) s_rot[1] = 1;
+        }
       }
       __syncthreads();
     }
     __syncthreads();
-    if (!s_rot) { ++sweep; break; }
+    // Stop after a sweep without rotations, or one whose rotations were all
+    // below sqrt(tol): convergence is quadratic, so the next sweep would find
+    // every pair orthogonal to about tol and rotate none.
+    if (!s_rot[0]) { ++sweep; break; }
+    if (!s_rot[1]) { ++sweep; break; }
     __syncthreads();
   }
   // column norms
@@ -238,7 +246,7 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
 __global__ __launch_bounds__(DT) void jacobi_svd_kernel(double* A, int m, int n, double* Vw, double* U,
                                                         double* sigma, double* V, int* order, int max_sweeps,
                                                         double tol, int* sweeps_out) {
-  __shared__ int s_rot;
+  __shared__ int s_rot[2];
   jacobi_svd_body(A, m, n, Vw, U, sigma, V, order, max_sweeps, tol, sweeps_out, s_rot);
 }
 
@@ -251,7 +259,7 @@ __global__ __launch_bounds__(DT) void jacobi_svd_lds_kernel(const double* Ag, in
                                                             double* sigma, double* V, int* order, int max_sweeps,
                                                             double tol, int* sweeps_out, int wantv) {
   extern __shared__ double lds[];
-  __shared__ int s_rot;
+  __shared__ int s_rot[2];
   double* As = lds;
   double* Vs = wantv ? lds + (long)m * n : nullptr;
   for (long t = threadIdx.x; t < (long)m * n; t += blockDim.x) As[t] = Ag[t];
@@ -266,7 +274,7 @@ __global__ __launch_bounds__(DT) void jacobi_svd_lds_a_kernel(const double* Ag, 
                                                               double* sigma, double* V, int* order, int max_sweeps,
                                                               double tol, int* sweeps_out) {
   extern __shared__ double lds[];
-  __shared__ int s_rot;
+  __shared__ int s_rot[2];
   double* As = lds;
   for (long t = threadIdx.x; t < (long)m * n; t += blockDim.x) As[t] = Ag[t];
   jacobi_svd_body(As, m, n, Vw, U, sigma, V, order, max_sweeps, tol, sweeps_out, s_rot);
@@ -533,14 +541,21 @@ __device__ void lz_ritz_min(const double* al, const double* be, int k, double* y
 }
 
 __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p, int kmax, int restarts, double tol,
-                                                         double* Q, double* v, double* lam_out) {
+                                                         double* Q, double* v, double* lam_out, int v_init) {
   __shared__ double al[LZ_MAX], be[LZ_MAX], y[LZ_MAX], h[LZ_MAX];
   __shared__ double red[NW];
   __shared__ double s_theta, s_lo, s_hi, s_bnorm;
   __shared__ int s_first;
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
-  // start vector
-  for (int i = tid; i < p; i += DT) v[i] = 1.0 + 0.25 * lz_pseudo(i, 0);
+  // start vector: the caller's (a warm start) unless it is absent or zero
+  if (v_init) {
+    double part = 0.0;
+    for (int i = tid; i < p; i += DT) part += v[i] * v[i];
+    const double nv = block_sum(part, red);
+    v_init = (nv > 0.0 && nv < 1e300) ? 1 : 0;
+  }
+  if (!v_init)
+    for (int i = tid; i < p; i += DT) v[i] = 1.0 + 0.25 * lz_pseudo(i, 0);
   __syncthreads();
   // Frobenius norm of B (scale for tolerances)
   {
@@ -624,9 +639,10 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
         if (tid == 0) be[j] = bj;
       }
       __syncthreads();
-      // every 8 steps: stop once the smallest Ritz pair of T_k has converged
-      // (its residual norm is |beta_k y_k|, exact under full reorthogonalisation)
-      if (k >= 16 && k % 8 == 0 && k < kmax) {
+      // after 4 and 8 steps, then every 8: stop once the smallest Ritz pair of
+      // T_k has converged (its residual norm is |beta_k y_k|, exact under full
+      // reorthogonalisation); a warm start often converges within the first checks
+      if ((k == 4 || (k >= 8 && k % 8 == 0)) && k < kmax) {
         lz_ritz_min(al, be, k, y, h, &s_lo, &s_hi, &s_theta, &s_first);
         if (be[k - 1] != 0.0 && fabs(be[k - 1] * y[k - 1]) <= 0.5 * tol * s_bnorm) break;
       }
@@ -731,11 +747,11 @@ void dense_svd_left(double* A, int m, int n, double* U, double* sigma, int* iwor
 }
 
 void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* work, hipStream_t s, int kmax,
-                       int restarts, double tol) {
+                       int restarts, double tol, bool v_init) {
   kmax = std::max(1, std::min({kmax, p, LZ_MAX - 1}));
   // algorithmic traffic: B read once (the iteration count is decided on the device)
   launch_prof(PK_LANCZOS, 0.0, 8.0 * (double)p * p, lanczos_min_kernel, dim3(1), dim3(DT), 0u, s, B, p, kmax,
-              restarts, tol, work, v, lam);
+              restarts, tol, work, v, lam, v_init ? 1 : 0);
   TT_HIP(hipGetLastError());
 }
 

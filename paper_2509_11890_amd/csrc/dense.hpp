@@ -27,9 +27,11 @@ void dense_svd_left(double* A, int m, int n, double* U, double* sigma, int* iwor
 bool dense_svd_left_fits_lds(int m, int n);
 // Smallest eigenpair of a symmetric row-major p x p matrix B (restarted Lanczos
 // with full reorthogonalisation): v (p, unit norm), lam (1 double, device).
+// With v_init, v holds the start vector on entry (a warm start; a zero vector
+// falls back to the fixed pseudo-random start).
 // work >= p * (min(kmax, p) + 1) doubles.
 void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* work, hipStream_t s,
-                       int kmax = 128, int restarts = 8, double tol = 1e-12);
+                       int kmax = 128, int restarts = 8, double tol = 1e-12, bool v_init = false);
 // LU with partial pivoting; solves A X = B in place (row-major).  status[0] != 0 on a zero pivot.
 void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s);
 // Cholesky (lower, row-major, in place).  status[0] = j+1 if not positive definite.

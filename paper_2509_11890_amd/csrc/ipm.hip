@@ -179,8 +179,9 @@ void init_state(const Problem& P, const ttipm_params& prm, State& S, Ctx& c) {
 // step length (Sec. 3.4): extreme generalised Rayleigh quotient in TT form,
 // solved by a two-site DMRG sweep.  At each pair of cores the projected pencil
 // (dM^, M^) is reduced with the Cholesky factor of M^ and its smallest
-// eigenpair is taken from a Jacobi eigen-decomposition; the pair is then split
-// by a truncated SVD, which adapts the rank of E up to `rank`.
+// eigenpair is taken by Lanczos, warm-started from the current E projected on
+// the pair's frame; the pair is then split by a truncated SVD, which adapts the
+// rank of E up to `rank`.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -195,12 +196,36 @@ void merge_pair(const TT& M, int k, DevBuf& out, Ctx& c) {
   permute(tmp.get(), out.get(), {R0, 2, 2, 2, 2, R2}, {0, 1, 3, 2, 4, 5}, c.s);
 }
 
+// y = L^T x for a lower triangular row-major L (only the lower triangle is read)
+__global__ void trmv_lt_kernel(const double* L, int p, const double* x, double* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p) return;
+  double acc = 0.0;
+  for (int j = i; j < p; ++j) acc += L[(long)j * p + i] * x[j];
+  y[i] = acc;
+}
+
+__global__ void scale_rows_kernel(double* A, int rows, int cols, long ld, const double* s) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)rows * cols) return;
+  const int i = (int)(t / cols), j = (int)(t % cols);
+  A[i * ld + j] *= s[i];
+}
+
+__global__ void scale_cols_kernel(double* A, int rows, int cols, long ld, const double* s) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)rows * cols) return;
+  const int i = (int)(t / cols), j = (int)(t % cols);
+  A[i * ld + j] *= s[j];
+}
+
 // smallest eigenpair of the pencil (D, M) (p x p, row-major, symmetrised in place):
-// returns lambda and writes the M-normalised direction into e (p).
+// returns lambda and writes the M-normalised direction into e (p).  e0 (or
+// nullptr): an approximate eigenvector that starts the Lanczos iteration.
 // pencils from this size on use the blocked (GEMM-based) factorisations
 constexpr int kPencilBlocked = 96;
 
-double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c) {
+double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c, const double* e0 = nullptr) {
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, Mm, p);
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, D, p);
   TT_HIP(hipGetLastError());
@@ -231,8 +256,13 @@ double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c) {
   solve_L(Bt.get(), p, false);                               // L^{-1} D L^{-T}
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks((long)p * p, 256)), dim3(256), 0, c.s, Bt.get(), p);
   TT_HIP(hipGetLastError());
-  // smallest eigenpair of the reduced pencil (Lanczos), then e = L^{-T} v
-  dense_sym_min_eig(Bt.get(), p, e, lam.get(), work.get(), c.s, 128);
+  // smallest eigenpair of the reduced pencil (Lanczos, started from v = L^T e0
+  // when given), then e = L^{-T} v
+  if (e0) {
+    hipLaunchKernelGGL(trmv_lt_kernel, dim3(nblocks(p, 256)), dim3(256), 0, c.s, Mm, p, e0, e);
+    TT_HIP(hipGetLastError());
+  }
+  dense_sym_min_eig(Bt.get(), p, e, lam.get(), work.get(), c.s, 128, 8, 1e-12, e0 != nullptr);
   solve_L(e, 1, true);
   double lmin = 0.0;
   TT_HIP(hipMemcpyAsync(&lmin, lam.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
@@ -269,6 +299,12 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
     TT_HIP(hipMemcpyAsync(Dl.get(), dM.core(0), 4 * sizeof(double), hipMemcpyDeviceToDevice, c.s));
     return pencil_min(Ml.get(), Dl.get(), 2, e.get(), c);
   }
+  if (!E.cores[0].get()) {
+    // a fresh start has no weights in core 0 yet: the first pair starts Lanczos
+    // from its fixed pseudo-random vector
+    E.cores[0].reserve((size_t)2 * E.r[1]);
+    fill((long)2 * E.r[1], 0.0, E.cores[0].get(), c.s);
+  }
   std::vector<DevBuf> ML(d), MR(d), DL(d), DR(d);
   for (auto* v : {&ML, &DL}) { (*v)[0].reserve(1); fill(1, 1.0, (*v)[0].get(), c.s); }
   for (auto* v : {&MR, &DR}) { (*v)[d - 1].reserve(1); fill(1, 1.0, (*v)[d - 1].get(), c.s); }
@@ -292,7 +328,7 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
   };
   for (int k = d - 1; k > 0; --k) upd_right(k);
   double lam_best = 1e300;
-  DevBuf M2, D2, Ml, Dl, e;
+  DevBuf M2, D2, Ml, Dl, e, e0, sg;
   // one sweep = left-to-right then right-to-left over the pairs (k, k+1)
   for (int sw = 0; sw < sweeps; ++sw) {
     for (int pass = 0; pass < 2; ++pass) {
@@ -308,7 +344,13 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
         local_dense_op(ML[k].get(), r, M.r[k], M2.get(), 4, MR[k + 1].get(), s, M.r[k + 2], Ml.get(), c);
         local_dense_op(DL[k].get(), r, dM.r[k], D2.get(), 4, DR[k + 1].get(), s, dM.r[k + 2], Dl.get(), c);
         e.reserve(p);
-        const double lam = pencil_min(Ml.get(), Dl.get(), p, e.get(), c);
+        // warm start: the current E on this pair's frame (the non-orthogonal
+        // core carries the singular values of the last split)
+        const int q0 = E.r[k + 1];
+        e0.reserve(p);
+        gemm(gemm_nn(2 * r, 2 * s, q0, E.cores[k].get(), q0, E.cores[k + 1].get(), 2 * s, e0.get(), 2 * s), c.s,
+             &c.ws, GemmPrec::F64);
+        const double lam = pencil_min(Ml.get(), Dl.get(), p, e.get(), c, e0.get());
         lam_best = std::min(lam_best, lam);
         // split the supercore [(r,i)][(i',s)] by a truncated SVD
         SvdOut sv;
@@ -329,10 +371,15 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
         const unsigned long long ks = seed * 1000003ull + (unsigned long long)((sw * 2 + pass) * 131 + k);
         E.cores[k].reserve((size_t)2 * r * rq);
         E.cores[k + 1].reserve((size_t)rq * 2 * s);
+        sg.reserve(q);
+        TT_HIP(hipMemcpyAsync(sg.get(), sv.sigma.data(), sizeof(double) * q, hipMemcpyHostToDevice, c.s));
         if (lr) {
           copy2d(sv.U.get(), sv.k, E.cores[k].get(), rq, 2 * r, q, c.s);                  // left-orthonormal
           TT_HIP(hipMemcpyAsync(E.cores[k + 1].get(), sv.Vt.get(), sizeof(double) * (size_t)q * 2 * s,
                                 hipMemcpyDeviceToDevice, c.s));
+          hipLaunchKernelGGL(scale_rows_kernel, dim3(nblocks((long)q * 2 * s, 256)), dim3(256), 0, c.s,
+                             E.cores[k + 1].get(), q, 2 * s, (long)2 * s, sg.get());      // S Vt
+          TT_HIP(hipGetLastError());
           if (qk > 0) {
             DevBuf G((size_t)qk * 2 * r), Gt((size_t)2 * r * qk);
             random_orth_rows(E.cores[k].get(), q, 1, rq, 2 * r, G.get(), qk, ks, c);
@@ -346,6 +393,9 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
           TT_HIP(hipMemcpyAsync(E.cores[k + 1].get(), sv.Vt.get(), sizeof(double) * (size_t)q * 2 * s,
                                 hipMemcpyDeviceToDevice, c.s));                           // right-orthonormal
           copy2d(sv.U.get(), sv.k, E.cores[k].get(), rq, 2 * r, q, c.s);
+          hipLaunchKernelGGL(scale_cols_kernel, dim3(nblocks((long)2 * r * q, 256)), dim3(256), 0, c.s,
+                             E.cores[k].get(), 2 * r, q, (long)rq, sg.get());            // U S
+          TT_HIP(hipGetLastError());
           if (qk > 0) {
             random_orth_rows(E.cores[k + 1].get(), q, 2 * s, 1, 2 * s, E.cores[k + 1].get() + (size_t)q * 2 * s, qk,
                              ks, c);
