@@ -723,6 +723,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   std::vector<DevBuf> Rhat(4);
   DevBuf f, u, Ku, dz;
   std::vector<int> bj_ref(d, 0);   // block-Jacobi Krylov counts per core (MLP fallback budget)
+  std::vector<double> res_hist;   // max_res of each sweep
   for (int sweep = 0; sweep < prm.max_sweeps; ++sweep) {
     double max_res = 0.0;
     for (int step = 0; step < d; ++step) {
@@ -844,6 +845,12 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
     }
     dir = -dir;
     if (max_res < prm.tol && sweep >= 1) break;
+    // With the rank cap binding the sweeps settle into a cycle of period two
+    // (the same truncated frames in each direction) above the target: stop
+    // once a sweep improves on the one two back (same direction) by less
+    // than 10 %.
+    res_hist.push_back(max_res);
+    if (info.capped && sweep >= 2 && max_res > 0.9 * res_hist[sweep - 2]) break;
   }
   // The block stays where the last sweep left it (an end core): moving it back
   // without truncation would only merge the components into the shared frame
