@@ -12,15 +12,21 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 const char* last_error() { return g_last_error.c_str(); }
 
 namespace {
+// Freed blocks are reused without waiting for the stream: correct as long as
+// one stream does all the work that touches the blocks of one free list.  A
+// thread running work on a stream of its own therefore caches its frees in a
+// pool of its own (pool_local_begin / pool_local_end).
 struct Pool {
   std::mutex mu;
   std::map<size_t, std::vector<void*>> free_lists;   // size class -> blocks
-  size_t in_use = 0;
+  long long in_use = 0;
 };
-Pool& pool() {
+Pool& global_pool() {
   static Pool* p = new Pool();   // never destroyed: blocks live until process exit
   return *p;
 }
+thread_local Pool* t_pool = nullptr;
+Pool& pool() { return t_pool ? *t_pool : global_pool(); }
 size_t size_class(size_t bytes) {
   size_t c = 256;
   while (c < bytes) c <<= 1;
@@ -64,7 +70,29 @@ void pool_free(void* p, size_t bytes) {
   P.in_use -= cls;
 }
 
-size_t pool_bytes_in_use() { return pool().in_use; }
+size_t pool_bytes_in_use() {
+  const long long n = pool().in_use;
+  return n > 0 ? (size_t)n : 0;
+}
+
+void pool_local_begin() {
+  if (!t_pool) t_pool = new Pool();
+}
+
+void pool_local_end() {
+  if (!t_pool) return;
+  Pool& G = global_pool();
+  {
+    std::lock_guard<std::mutex> g(G.mu);
+    for (auto& kv : t_pool->free_lists) {
+      auto& dst = G.free_lists[kv.first];
+      dst.insert(dst.end(), kv.second.begin(), kv.second.end());
+    }
+    G.in_use += t_pool->in_use;
+  }
+  delete t_pool;
+  t_pool = nullptr;
+}
 
 namespace {
 const char* const kProfNames[PK_COUNT] = {"gemm_f64_kernel", "gemm_bf16_kernel", "jacobi_svd_kernel",

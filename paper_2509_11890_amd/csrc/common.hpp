@@ -48,6 +48,11 @@ void* pool_alloc(size_t bytes);
 void pool_free(void* p, size_t bytes);
 size_t pool_bytes_in_use();
 void pool_trim();
+// The calling thread caches its frees apart from the shared pool until
+// pool_local_end, which hands them over; the thread's stream must be
+// synchronised by then.
+void pool_local_begin();
+void pool_local_end();
 
 // Owning device buffer of doubles.  Grows, never shrinks.
 class DevBuf {

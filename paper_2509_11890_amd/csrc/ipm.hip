@@ -668,8 +668,9 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     // affine (predictor) steps: the full Thm. 1 step, clipped to 1; with
     // inequalities also s(X + a_p dX) >= 0 and T + a_d dT >= 0 on the active
     // mask (Sec. 3.4: the diagonal pencils reduce to entry ratios)
-    a_p = std::min(1.0, step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, c));
-    a_d = std::min(1.0, step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, c));
+    // the primal and dual eigen-solves are independent: one stream each
+    run_concurrent(c, {[&](Ctx& cx) { a_p = std::min(1.0, step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, cx)); },
+                       [&](Ctx& cx) { a_d = std::min(1.0, step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, cx)); }});
     if (P.ineq) {
       dT = S.W.component(2, c);
       sx = ineq_slack(P, S.X, false, c);
@@ -735,8 +736,8 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   S.frame_capped |= ai_c.capped;
   TT dX2 = S.W.component(0, c), dY2 = S.W.component(1, c), dZ2 = S.W.component(L, c);
   t1 = now();
-  info.alpha_p_max = step_length(S.X, dX2, S.EX, S.has_EX, prm, sd + 3, c);
-  info.alpha_d_max = step_length(S.Z, dZ2, S.EZ, S.has_EZ, prm, sd + 4, c);
+  run_concurrent(c, {[&](Ctx& cx) { info.alpha_p_max = step_length(S.X, dX2, S.EX, S.has_EX, prm, sd + 3, cx); },
+                     [&](Ctx& cx) { info.alpha_d_max = step_length(S.Z, dZ2, S.EZ, S.has_EZ, prm, sd + 4, cx); }});
   if (P.ineq) {
     TT dT2 = S.W.component(2, c);
     TT ds2 = ineq_slack(P, dX2, true, c);
@@ -754,43 +755,52 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   t1 = now();
   const int cap = prm.iter_rank_cap > 0 ? prm.iter_rank_cap : 4 * prm.rank_cap;
   {
-    auto pd_min = [&](const TT& M, BlockTT& E, bool& have) {
+    auto pd_min = [&](const TT& M, BlockTT& E, bool& have, Ctx& cx) {
       return min_gen_eig(P.Ivec, M, E, have, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps),
-                         std::max(0, prm.eig_kick), sd + 11, c);
+                         std::max(0, prm.eig_kick), sd + 11, cx);
     };
+    // X + a_p dX and Z + a_d dZ: rounding, shift and safeguard, one stream each
+    // (the dual step a_d is final once the Z branch ends, so Y follows it)
     TT Xn, Zn;
-    for (int tries = 0;; ++tries) {
-      if (tries > 6) {           // no acceptable step: keep the iterate
-        a_p = 0.0;
-        Xn = tt_clone(S.X, c);
-        break;
+    int bt_p = 0, bt_d = 0;
+    auto primal = [&](Ctx& cx) {
+      for (int tries = 0;; ++tries) {
+        if (tries > 6) {           // no acceptable step: keep the iterate
+          a_p = 0.0;
+          Xn = tt_clone(S.X, cx);
+          break;
+        }
+        TT Xs = tt_add({&S.X, &dX2}, {1.0, a_p}, cx);
+        Xn = round_shift(std::move(Xs), tolp, &P.Ivec, cap, cx, nullptr);
+        if (pd_min(Xn, S.EXc, S.has_EXc, cx) > 0.0) break;
+        a_p *= 0.5;
+        bt_p++;
       }
-      TT Xs = tt_add({&S.X, &dX2}, {1.0, a_p}, c);
-      Xn = round_shift(std::move(Xs), tolp, &P.Ivec, cap, c, nullptr);
-      if (pd_min(Xn, S.EXc, S.has_EXc) > 0.0) break;
-      a_p *= 0.5;
-      info.backtracks++;
-    }
-    for (int tries = 0;; ++tries) {
-      if (tries > 6) {
-        a_d = 0.0;
-        Zn = tt_clone(S.Z, c);
-        break;
+    };
+    auto dual = [&](Ctx& cx) {
+      for (int tries = 0;; ++tries) {
+        if (tries > 6) {
+          a_d = 0.0;
+          Zn = tt_clone(S.Z, cx);
+          break;
+        }
+        TT Zs = tt_add({&S.Z, &dZ2}, {1.0, a_d}, cx);
+        Zn = round_shift(std::move(Zs), told, &P.Ivec, cap, cx, nullptr);
+        if (pd_min(Zn, S.EZc, S.has_EZc, cx) > 0.0) break;
+        a_d *= 0.5;
+        bt_d++;
       }
-      TT Zs = tt_add({&S.Z, &dZ2}, {1.0, a_d}, c);
-      Zn = round_shift(std::move(Zs), told, &P.Ivec, cap, c, nullptr);
-      if (pd_min(Zn, S.EZc, S.has_EZc) > 0.0) break;
-      a_d *= 0.5;
-      info.backtracks++;
-    }
+      TT Yn = tt_add({&S.Y, &dY2}, {1.0, a_d}, cx);
+      S.Y = round_shift(std::move(Yn), told, nullptr, cap, cx, nullptr);
+    };
+    run_concurrent(c, {primal, dual});
+    info.backtracks += bt_p + bt_d;
     S.X = std::move(Xn);
     S.Z = std::move(Zn);
     S.dX = tt_clone(dX2, c);
     S.dY = tt_clone(dY2, c);
     S.dZ = tt_clone(dZ2, c);
     if (P.ineq) S.dT = S.W.component(2, c);
-    TT Yn = tt_add({&S.Y, &dY2}, {1.0, a_d}, c);
-    S.Y = round_shift(std::move(Yn), told, nullptr, cap, c, nullptr);
     if (P.ineq) {
       TT dT2 = S.W.component(2, c);
       TT Tn = tt_add({&S.T, &dT2}, {1.0, a_d}, c);

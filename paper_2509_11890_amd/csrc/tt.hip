@@ -7,6 +7,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <memory>
+#include <mutex>
+#include <thread>
 
 #include "dense.hpp"
 #include "ttops.hpp"
@@ -15,6 +19,75 @@ namespace ttipm {
 
 Ctx::~Ctx() {
   if (hbuf) (void)hipHostFree(hbuf);
+}
+
+namespace {
+// Idle worker contexts, each with a non-blocking stream of its own (default
+// priority), kept for the life of the process.
+std::mutex g_workers_mu;
+std::vector<std::unique_ptr<Ctx>> g_workers;
+
+std::unique_ptr<Ctx> acquire_worker() {
+  {
+    std::lock_guard<std::mutex> g(g_workers_mu);
+    if (!g_workers.empty()) {
+      std::unique_ptr<Ctx> w = std::move(g_workers.back());
+      g_workers.pop_back();
+      return w;
+    }
+  }
+  auto w = std::make_unique<Ctx>();
+  TT_HIP(hipStreamCreateWithFlags(&w->s, hipStreamNonBlocking));
+  return w;
+}
+
+void release_worker(std::unique_ptr<Ctx> w) {
+  std::lock_guard<std::mutex> g(g_workers_mu);
+  g_workers.push_back(std::move(w));
+}
+}  // namespace
+
+void run_concurrent(Ctx& c, const std::vector<std::function<void(Ctx&)>>& tasks) {
+  if (tasks.empty()) return;
+  if (tasks.size() == 1) {
+    tasks[0](c);
+    return;
+  }
+  c.sync();   // everything the tasks read is complete before other streams see it
+  int dev = 0;
+  TT_HIP(hipGetDevice(&dev));
+  const size_t nw = tasks.size() - 1;
+  std::vector<std::unique_ptr<Ctx>> w(nw);
+  for (auto& x : w) {
+    x = acquire_worker();
+    x->prec = c.prec;
+  }
+  std::vector<std::exception_ptr> err(tasks.size());
+  std::vector<std::thread> th;
+  th.reserve(nw);
+  for (size_t i = 0; i < nw; ++i)
+    th.emplace_back([&, i] {
+      pool_local_begin();
+      try {
+        TT_HIP(hipSetDevice(dev));
+        tasks[i + 1](*w[i]);
+        w[i]->sync();
+      } catch (...) {
+        err[i + 1] = std::current_exception();
+        (void)hipStreamSynchronize(w[i]->s);
+      }
+      pool_local_end();
+    });
+  try {
+    tasks[0](c);
+    c.sync();
+  } catch (...) {
+    err[0] = std::current_exception();
+  }
+  for (auto& t : th) t.join();
+  for (auto& x : w) release_worker(std::move(x));
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
 }
 
 double* Ctx::host(size_t n) {

@@ -4,6 +4,7 @@
 // environments (interfaces), projected local products and rounding.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "common.hpp"
@@ -47,6 +48,13 @@ struct Ctx {
   double* host(size_t n);     // pinned host buffer of >= n doubles
   void sync() { TT_HIP(hipStreamSynchronize(s)); }
 };
+
+// Runs the tasks concurrently: the first on the calling thread with c, the
+// others on threads of their own, each with a worker context (own stream and
+// scratch, c's GEMM precision).  c is synchronised first and every context at
+// the end; the first exception of any task is rethrown.  Tasks must not write
+// shared state.
+void run_concurrent(Ctx& c, const std::vector<std::function<void(Ctx&)>>& tasks);
 
 // ---- construction and copies ---------------------------------------------
 TT tt_from_host(const std::vector<std::vector<double>>& cores, const std::vector<int>& ranks, int mo, int mi,
