@@ -540,18 +540,15 @@ void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& 
 
 namespace {
 
-void L_ops(const Problem& P, const TT& Xv, const TT& Zv, bool aho, TT& LZ, TT& LX, Ctx& c) {
-  TT Xm = tt_as_matrix(Xv, 2, c);
-  TT Zm = tt_as_matrix(Zv, 2, c);
+// L_Z = I kron Z + Z kron I (AHO) or Z kron I (XZ); L_X = I kron X + X kron I
+// (AHO) or I kron X (XZ)
+TT L_op(const Problem& P, const TT& Mv, bool aho, bool left_identity, Ctx& c) {
+  TT Mm = tt_as_matrix(Mv, 2, c);
   if (aho) {
-    TT a = tt_kron(P.I2, Zm, c), b = tt_kron(Zm, P.I2, c);
-    LZ = tt_add({&a, &b}, {1.0, 1.0}, c);
-    TT e = tt_kron(P.I2, Xm, c), f = tt_kron(Xm, P.I2, c);
-    LX = tt_add({&e, &f}, {1.0, 1.0}, c);
-  } else {
-    LZ = tt_kron(Zm, P.I2, c);
-    LX = tt_kron(P.I2, Xm, c);
+    TT a = tt_kron(P.I2, Mm, c), b = tt_kron(Mm, P.I2, c);
+    return tt_add({&a, &b}, {1.0, 1.0}, c);
   }
+  return left_identity ? tt_kron(P.I2, Mm, c) : tt_kron(Mm, P.I2, c);
 }
 
 }  // namespace
@@ -574,11 +571,15 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   TT LZ, LX;
   auto build_L = [&](bool use_aho) {
     const double t0 = now();
-    L_ops(P, S.X, S.Z, use_aho, LZ, LX, c);
     // reading: L_Z and L_X are rounded with the Cor. 1 shift (S = I kron I) so
-    // that they stay positive definite when Z and X approach singularity
-    LZ = round_shift(std::move(LZ), told, &P.I16, 1 << 30, c, nullptr);
-    LX = round_shift(std::move(LX), tolp, &P.I16, 1 << 30, c, nullptr);
+    // that they stay positive definite when Z and X approach singularity;
+    // the two are independent, one stream each
+    run_concurrent(c, {[&](Ctx& cx) {
+                         LZ = round_shift(L_op(P, S.Z, use_aho, false, cx), told, &P.I16, 1 << 30, cx, nullptr);
+                       },
+                       [&](Ctx& cx) {
+                         LX = round_shift(L_op(P, S.X, use_aho, true, cx), tolp, &P.I16, 1 << 30, cx, nullptr);
+                       }});
     info.t_round += now() - t0;
   };
   build_L(aho);
