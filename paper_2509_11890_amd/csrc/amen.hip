@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <initializer_list>
 #include <random>
 
 #include "dense.hpp"
@@ -126,11 +127,74 @@ struct LocalKKT {
                 x, y, alpha, beta, c);
   }
 
+  // Stage products of y = alpha P_o x + beta y for several operators, one
+  // grouped launch per stage (the same three contractions as local_apply,
+  // with stage buffers of each operator's own).
+  struct Ap {
+    int o;
+    const double* x;
+    double* y;
+    double alpha, beta;
+  };
+  DevBuf gt1[OP_COUNT], gt2[OP_COUNT];
+
+  void stages12(std::initializer_list<Ap> aps, Ctx& c) {
+    Gemm s1[OP_COUNT], s2[OP_COUNT];
+    int n = 0;
+    for (const Ap& a : aps) {
+      const TT* op = sys->ops[a.o];
+      const int key = key_of_op[a.o], R = op->r[k], Rp = op->r[k + 1];
+      gt1[a.o].reserve((size_t)r * R * 4 * s);
+      gt2[a.o].reserve((size_t)r * 4 * Rp * s);
+      // t1[(a,alpha)][(j,e)] = phiL[(a,alpha)][c] x[c][(j,e)]
+      s1[n] = gemm_nn(r * R, 4 * s, r, envs->L[key][k].get(), r, a.x, 4 * s, gt1[a.o].get(), 4 * s);
+      // t2[a][(i,beta)][e] = O'[(i,beta)][(alpha,j)] t1[a][(alpha,j)][e], batched over a
+      Gemm& g = s2[n];
+      g.M = 4 * Rp; g.N = s; g.K = R * 4; g.batch = r;
+      g.A = operm[a.o].get(); g.am = (long)R * 4; g.ak = 1; g.sA = 0;
+      g.B = gt1[a.o].get(); g.bk = s; g.bn = 1; g.sB = (long)R * 4 * s;
+      g.C = gt2[a.o].get(); g.cm = s; g.cn = 1; g.sC = (long)4 * Rp * s;
+      ++n;
+    }
+    gemm_grouped(s1, n, c.s, &c.ws);
+    gemm_grouped(s2, n, c.s, &c.ws);
+  }
+
+  void stage3(std::initializer_list<Ap> aps, Ctx& c) {
+    Gemm s3[OP_COUNT];
+    int n = 0;
+    for (const Ap& a : aps) {
+      const TT* op = sys->ops[a.o];
+      const int key = key_of_op[a.o], Rp = op->r[k + 1];
+      // y[(a,i)][b] = alpha sum_(beta,e) t2[(a,i)][(beta,e)] phiR[b][(beta,e)] + beta y
+      Gemm& g = s3[n];
+      g.M = r * 4; g.N = s; g.K = Rp * s;
+      g.A = gt2[a.o].get(); g.am = (long)Rp * s; g.ak = 1;
+      g.B = envs->R[key][k].get(); g.bk = 1; g.bn = (long)Rp * s;
+      g.C = a.y; g.cm = s; g.cn = 1;
+      g.alpha = a.alpha; g.beta = a.beta;
+      ++n;
+    }
+    gemm_grouped(s3, n, c.s, &c.ws);
+  }
+
   // out = K u (u, out: [L][p])
   void matvec(const double* u, double* out, Ctx& c) {
     const double* x = u;
     const double* y = u + p;
     const double sg = sys->sense;
+    if (!sys->ineq && c.prec == GemmPrec::F64) {
+      // Two levels of grouped stages: every operator applied to u, then L_X
+      // applied to the eliminated dZ part.  K_Y's last stage waits for the
+      // second level so that no launch has two products writing one row.
+      double* oc = out + (size_t)(L - 1) * p;
+      stages12({{OP_AEQ, x, out, -1.0, 0.0}, {OP_KY, y, out, 1.0, 1.0}, {OP_AEQT, y, tmp.get(), 1.0, 0.0},
+                {OP_LZ, x, oc, 1.0, 0.0}}, c);
+      stage3({{OP_AEQ, x, out, -1.0, 0.0}, {OP_AEQT, y, tmp.get(), 1.0, 0.0}, {OP_LZ, x, oc, 1.0, 0.0}}, c);
+      stages12({{OP_LX, tmp.get(), oc, 1.0, 1.0}}, c);
+      stage3({{OP_LX, tmp.get(), oc, 1.0, 1.0}, {OP_KY, y, out, 1.0, 1.0}}, c);
+      return;
+    }
     // row p
     apply(OP_AEQ, x, out, -1.0, 0.0, c);
     apply(OP_KY, y, out, 1.0, 1.0, c);

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstdio>
+#include <vector>
 
 namespace ttipm {
 
@@ -63,8 +64,9 @@ struct KArgs {
 // Workgroups are dispatched round-robin over the eight
 // XCDs; tiles are renumbered so that each XCD works on a contiguous run of
 // output tiles (shared A row panels and B column panels stay in its L2).
+// One output tile (tm, tn) of batch entry bidx, K slice `slice`.
 template <int WM, int WN, bool AKC, bool BKC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_kernel(KArgs g) {
+__device__ __forceinline__ void gemm_f64_tile(const KArgs& g, int tm, int tn, int bidx, int slice) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   constexpr int NA = TM * BK / 256, NB = BK * TN / 256;
   // element e of a thread sits at (fixed, base + STEP * e) along (m, k) or (k, m)
@@ -77,20 +79,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   __shared__ double Bs[2][BK][TN + PADF];
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
-  // XCD-aware renumbering of the (m, n) tile grid
-  const int gmt = gridDim.x, gnt = gridDim.y;
-  const int tiles = gmt * gnt;
-  const int lin = blockIdx.y * gmt + blockIdx.x;
-  int t = lin;
-  if (tiles >= 16) {
-    const int per = (tiles + 7) / 8;
-    const int cand = (lin % 8) * per + lin / 8;
-    // keep the map a bijection when tiles is not a multiple of 8
-    t = (tiles % 8 == 0) ? cand : lin;
-  }
-  const int tm = t / gnt, tn = t % gnt;
   const int m0 = tm * TM, n0 = tn * TN;
-  const int bidx = blockIdx.z / g.kslices, slice = blockIdx.z % g.kslices;
   const int kbeg = slice * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
   const double* A = g.A + (long)bidx * g.sA;
   const double* B = g.B + (long)bidx * g.sB;
@@ -206,6 +195,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
           }
         }
       }
+}
+
+template <int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_kernel(KArgs g) {
+  // XCD-aware renumbering of the (m, n) tile grid
+  const int gmt = gridDim.x, gnt = gridDim.y;
+  const int tiles = gmt * gnt;
+  const int lin = blockIdx.y * gmt + blockIdx.x;
+  int t = lin;
+  if (tiles >= 16) {
+    const int per = (tiles + 7) / 8;
+    const int cand = (lin % 8) * per + lin / 8;
+    // keep the map a bijection when tiles is not a multiple of 8
+    t = (tiles % 8 == 0) ? cand : lin;
+  }
+  gemm_f64_tile<WM, WN, AKC, BKC>(g, t / gnt, t % gnt, blockIdx.z / g.kslices, blockIdx.z % g.kslices);
+}
+
+// Several independent products in one launch: problem i owns the workgroups
+// [end[i-1], end[i]) of a 1-D grid, tiles * batch * kslices of them.  A
+// projected local product applies several operators to the same block
+// vector; each stage of all of them then costs one launch whose workgroups
+// run side by side instead of one small launch per operator.
+constexpr int kMaxGroup = 8;
+struct GroupArgs {
+  KArgs g[kMaxGroup];
+  int end[kMaxGroup];       // prefix sums of the workgroup counts
+  int gn[kMaxGroup];        // tile columns of each problem
+  int tiles[kMaxGroup];     // output tiles of each problem
+  int n;
+};
+
+template <int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_grouped_kernel(GroupArgs ga) {
+  const int lin = blockIdx.x;
+  int i = 0;
+  while (i + 1 < ga.n && lin >= ga.end[i]) ++i;
+  const int local = lin - (i ? ga.end[i - 1] : 0);
+  const KArgs& g = ga.g[i];
+  const int t = local % ga.tiles[i], z = local / ga.tiles[i];
+  gemm_f64_tile<WM, WN, AKC, BKC>(g, t / ga.gn[i], t % ga.gn[i], z / g.kslices, z % g.kslices);
 }
 
 // BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16): lane l supplies
@@ -348,10 +378,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
       }
 }
 
-__global__ void splitk_reduce_kernel(KArgs g, int batch) {
-  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  long total = (long)batch * g.M * g.N;
-  if (idx >= total) return;
+__device__ __forceinline__ void splitk_reduce_one(const KArgs& g, long idx) {
   int b = (int)(idx / ((long)g.M * g.N));
   long rem = idx % ((long)g.M * g.N);
   int row = (int)(rem / g.N), col = (int)(rem % g.N);
@@ -369,6 +396,24 @@ __global__ void splitk_reduce_kernel(KArgs g, int batch) {
   const double s = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
   double* c = g.C + (long)b * g.sC + (long)row * g.cm + (long)col * g.cn;
   *c = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*c);
+}
+
+__global__ void splitk_reduce_kernel(KArgs g, int batch) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)batch * g.M * g.N;
+  if (idx >= total) return;
+  splitk_reduce_one(g, idx);
+}
+
+// Reduce of the split problems of a grouped launch: problem i owns outputs
+// [end[i-1], end[i]) of a 1-D index space (`end` holds output, not workgroup,
+// counts here; unsplit problems own none).
+__global__ void splitk_reduce_grouped_kernel(GroupArgs ga) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ga.end[ga.n - 1]) return;
+  int i = 0;
+  while (i + 1 < ga.n && idx >= ga.end[i]) ++i;
+  splitk_reduce_one(ga.g[i], idx - (i ? ga.end[i - 1] : 0));
 }
 
 __global__ void scale_c_kernel(double* C, long cm, long cn, long sC, int M, int N, int batch, double beta) {
@@ -499,6 +544,112 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   if (ks > 1) {
     long total = (long)q.batch * q.M * q.N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nblocks(total, 256)), dim3(256), 0, stream, g, q.batch);
+    TT_HIP(hipGetLastError());
+  }
+}
+
+template <int WM, int WN>
+void launch_f64_grouped(int blocks, hipStream_t stream, const GroupArgs& ga, bool akc, bool bkc, double flops,
+                        double bytes) {
+  const dim3 grid(blocks), blk(256);
+  if (akc && bkc)
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_grouped_kernel<WM, WN, true, true>, grid, blk, 0u, stream, ga);
+  else if (akc)
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_grouped_kernel<WM, WN, true, false>, grid, blk, 0u, stream, ga);
+  else if (bkc)
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_grouped_kernel<WM, WN, false, true>, grid, blk, 0u, stream, ga);
+  else
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_grouped_kernel<WM, WN, false, false>, grid, blk, 0u, stream, ga);
+}
+
+void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws) {
+  // problems that the grouped launch does not take go through gemm() one by one
+  std::vector<const Gemm*> take;
+  bool akc0 = false, bkc0 = false;
+  for (int i = 0; i < count; ++i) {
+    const Gemm& q = qs[i];
+    if (q.M <= 0 || q.N <= 0 || q.batch <= 0) continue;
+    const bool akc = (q.ak == 1), bkc = (q.bk == 1 && q.bn != 1);
+    const bool fits = q.K > 0 && (int)take.size() < kMaxGroup && q.am >= 0 && q.ak >= 0 && q.bk >= 0 && q.bn >= 0 &&
+                      (double)(q.M - 1) * q.am + (double)(q.K - 1 + BK16) * q.ak <= 536870911.0 &&
+                      (double)(q.N - 1) * q.bn + (double)(q.K - 1 + BK16) * q.bk <= 536870911.0 &&
+                      (take.empty() || (akc == akc0 && bkc == bkc0));
+    if (!fits) {
+      gemm(q, stream, ws, GemmPrec::F64);
+      continue;
+    }
+    if (take.empty()) { akc0 = akc; bkc0 = bkc; }
+    take.push_back(&q);
+  }
+  if (take.empty()) return;
+  if (take.size() == 1) {
+    gemm(*take[0], stream, ws, GemmPrec::F64);
+    return;
+  }
+  // 64 x 64 tiles throughout (the products grouped here are small); K is
+  // split where a problem's own tiles are few and its K is long, by the rule
+  // of the single launch
+  GroupArgs ga{};
+  ga.n = (int)take.size();
+  long blocks = 0, part = 0;
+  double flops = 0.0, bytes = 0.0;
+  int split = 0;
+  for (int i = 0; i < ga.n; ++i) {
+    const Gemm& q = *take[i];
+    KArgs& g = ga.g[i];
+    g.M = q.M; g.N = q.N; g.K = q.K;
+    g.A = q.A; g.am = q.am; g.ak = q.ak; g.sA = q.sA;
+    g.B = q.B; g.bk = q.bk; g.bn = q.bn; g.sB = q.sB;
+    g.C = q.C; g.cm = q.cm; g.cn = q.cn; g.sC = q.sC;
+    g.alpha = q.alpha; g.beta = q.beta;
+    const int gm = (q.M + BM - 1) / BM, gn = (q.N + BN - 1) / BN;
+    const long tiles = (long)gm * gn * q.batch;
+    int ks = 1;
+    if (tiles < 128 && q.K >= 16 * BK) {
+      ks = (int)std::min<long>((256 + tiles - 1) / tiles, (long)q.K / (8 * BK));
+      ks = std::max(1, std::min(ks, 64));
+    }
+    int chunk = (q.K + ks - 1) / ks;
+    chunk = ((chunk + BK - 1) / BK) * BK;
+    ks = (q.K + chunk - 1) / chunk;
+    g.kslices = ks;
+    g.kchunk = chunk;
+    g.P = nullptr;
+    if (ks > 1) {
+      ++split;
+      part += (long)q.batch * ks * q.M * q.N;
+    }
+    ga.gn[i] = gn;
+    ga.tiles[i] = gm * gn;
+    blocks += tiles * ks;
+    ga.end[i] = (int)blocks;
+    flops += 2.0 * q.M * q.N * (double)q.K * q.batch;
+    bytes += 8.0 * q.batch * ((double)q.M * q.K + (double)q.K * q.N + (double)q.M * q.N * (q.beta != 0.0 ? 2 : 1));
+  }
+  if (blocks > (1L << 30)) throw Error(TT_ERR_ARG, "gemm_grouped: grid too large");
+  GroupArgs red{};
+  if (split) {
+    Workspace* w = ws ? ws : &g_default_ws;
+    w->buf.reserve((size_t)part);
+    long off = 0, outs = 0;
+    for (int i = 0; i < ga.n; ++i) {
+      KArgs& g = ga.g[i];
+      if (g.kslices <= 1) continue;
+      const Gemm& q = *take[i];
+      g.P = w->buf.get() + off;
+      off += (long)q.batch * g.kslices * q.M * q.N;
+      red.g[red.n] = g;
+      outs += (long)q.batch * q.M * q.N;
+      if (outs > (1L << 30)) throw Error(TT_ERR_ARG, "gemm_grouped: reduce too large");
+      red.end[red.n] = (int)outs;
+      ++red.n;
+    }
+  }
+  launch_f64_grouped<2, 2>((int)blocks, stream, ga, akc0, bkc0, flops, bytes);
+  TT_HIP(hipGetLastError());
+  if (split) {
+    hipLaunchKernelGGL(splitk_reduce_grouped_kernel, dim3(nblocks((long)red.end[red.n - 1], 256)), dim3(256), 0,
+                       stream, red);
     TT_HIP(hipGetLastError());
   }
 }
