@@ -25,65 +25,86 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// Cholesky of an n x n diagonal block (row-major, leading dimension lda), in place (lower).
+constexpr int kTriMax = 32;
+
+// Cholesky of an n x n (n <= 32) diagonal block (row-major, leading dimension
+// lda), in place (lower), staged through LDS so that the n dependent steps do
+// not wait on global memory.
 __global__ __launch_bounds__(BT) void chol_block_kernel(double* A, int n, long lda, int* status, int offset) {
-  __shared__ double s_d;
+  __shared__ double As[kTriMax][kTriMax + 1];
   __shared__ int s_bad;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) As[t / n][t % n] = A[(long)(t / n) * lda + t % n];
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double d = A[(long)j * lda + j];
-      if (!(d > 0.0)) {
-        s_bad = 1;
-        if (status[0] == 0) status[0] = offset + j + 1;
-      }
-      s_d = (d > 0.0) ? sqrt(d) : 1.0;
-      A[(long)j * lda + j] = s_d;
+    const double d = As[j][j];
+    if (!(d > 0.0)) {
+      if (threadIdx.x == 0 && status[0] == 0) status[0] = offset + j + 1;
+      s_bad = 1;
+      break;
     }
-    __syncthreads();
-    if (s_bad) return;
-    const double dj = s_d;
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(long)i * lda + j] /= dj;
+    const double dj = sqrt(d);
+    __syncthreads();   // every thread has read As[j][j]
+    if (threadIdx.x == 0) As[j][j] = dj;
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) As[i][j] /= dj;
     __syncthreads();
     const int rows = n - j - 1;
-    for (long t = threadIdx.x; t < (long)rows * rows; t += blockDim.x) {
-      int i = j + 1 + (int)(t / rows), c = j + 1 + (int)(t % rows);
-      if (c <= i) A[(long)i * lda + c] -= A[(long)i * lda + j] * A[(long)c * lda + j];
+    for (int t = threadIdx.x; t < rows * rows; t += blockDim.x) {
+      const int i = j + 1 + t / rows, c = j + 1 + t % rows;
+      if (c <= i) As[i][c] -= As[i][j] * As[c][j];
     }
     __syncthreads();
   }
-}
-
-// Inverse of a lower-triangular n x n block (unit diagonal if unit != 0):
-// one thread per column solves L x = e_c by forward substitution.
-__global__ void trinv_lower_kernel(const double* L, int n, long lda, double* out, int unit) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  for (int i = 0; i < n; ++i) {
-    if (i < c) {
-      out[(long)i * n + c] = 0.0;
-      continue;
-    }
-    double acc = (i == c) ? 1.0 : 0.0;
-    for (int j = c; j < i; ++j) acc -= L[(long)i * lda + j] * out[(long)j * n + c];
-    out[(long)i * n + c] = unit ? acc : acc / L[(long)i * lda + i];
+  if (s_bad) return;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t / n, c = t % n;
+    if (c <= i) A[(long)i * lda + c] = As[i][c];
   }
 }
 
-// Inverse of an upper-triangular n x n block: one thread per column, back substitution.
-__global__ void trinv_upper_kernel(const double* U, int n, long lda, double* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  for (int i = n - 1; i >= 0; --i) {
-    if (i > c) {
-      out[(long)i * n + c] = 0.0;
-      continue;
-    }
+// Inverses of the n x n (n <= 32) diagonal blocks: one wave, one lane per
+// column of the inverse.  The block is staged in LDS (every lane reads the same
+// entry at a time: a broadcast) and each lane keeps its column in registers,
+// so the substitution is a chain of FMAs with no memory round trips.
+
+// lower triangular L (unit diagonal if unit != 0): forward substitution
+__global__ __launch_bounds__(64) void trinv_lower_kernel(const double* L, int n, long lda, double* out, int unit) {
+  __shared__ double Ls[kTriMax][kTriMax + 1];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) Ls[t / n][t % n] = L[(long)(t / n) * lda + t % n];
+  __syncthreads();
+  const int c = threadIdx.x;
+  double x[kTriMax];
+#pragma unroll
+  for (int i = 0; i < kTriMax; ++i) {
     double acc = (i == c) ? 1.0 : 0.0;
-    for (int j = i + 1; j <= c; ++j) acc -= U[(long)i * lda + j] * out[(long)j * n + c];
-    out[(long)i * n + c] = acc / U[(long)i * lda + i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) acc -= Ls[i][j] * x[j];
+    x[i] = (i < n) ? (unit ? acc : acc / Ls[i][i]) : 0.0;
   }
+  if (c < n)
+#pragma unroll
+    for (int i = 0; i < kTriMax; ++i)
+      if (i < n) out[(long)i * n + c] = x[i];
+}
+
+// upper triangular U: back substitution
+__global__ __launch_bounds__(64) void trinv_upper_kernel(const double* U, int n, long lda, double* out) {
+  __shared__ double Us[kTriMax][kTriMax + 1];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) Us[t / n][t % n] = U[(long)(t / n) * lda + t % n];
+  __syncthreads();
+  const int c = threadIdx.x;
+  double x[kTriMax];
+#pragma unroll
+  for (int i = kTriMax - 1; i >= 0; --i) {
+    double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = i + 1; j < kTriMax; ++j) acc -= (j < n ? Us[i][j] : 0.0) * x[j];
+    x[i] = (i < n) ? acc / Us[i][i] : 0.0;
+  }
+  if (c < n)
+#pragma unroll
+    for (int i = 0; i < kTriMax; ++i)
+      if (i < n) out[(long)i * n + c] = x[i];
 }
 
 // LU with partial pivoting of an m x nb panel (rows of a larger row-major
@@ -277,9 +298,10 @@ void chol_rec(double* A, int n, BlockedFactors& f, int j0, int len, int* st, Dev
   const int nb = f.nb;
   if (len <= nb) {
     double* Ajj = A + (long)j0 * n + j0;
+    TT_REQUIRE(len <= kTriMax, "diagonal block above 32");
     hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(BT), 0, c.s, Ajj, len, (long)n, st, j0);
-    hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(std::max(64, ((len + 63) / 64) * 64)), 0, c.s, Ajj, len,
-                       (long)n, const_cast<double*>(dblock(f.dinv, j0, nb)), 0);
+    hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(64), 0, c.s, Ajj, len, (long)n,
+                       const_cast<double*>(dblock(f.dinv, j0, nb)), 0);
     TT_HIP(hipGetLastError());
     return;
   }
@@ -308,10 +330,10 @@ void lu_rec(double* A, int n, BlockedFactors& f, int* piv, int j0, int w, int* s
     launch_prof(PK_PANEL_LU, pm * w * (double)w, 16.0 * pm * w, panel_lu_kernel, dim3(1), dim3(BT), 0, c.s,
                 A + (long)j0 * n + j0, n - j0, w, (long)n, piv + j0, j0, st);
     double* Ajj = A + (long)j0 * n + j0;
-    const unsigned tb = std::max(64, ((w + 63) / 64) * 64);
-    hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(tb), 0, c.s, Ajj, w, (long)n,
+    TT_REQUIRE(w <= kTriMax, "diagonal block above 32");
+    hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(64), 0, c.s, Ajj, w, (long)n,
                        const_cast<double*>(dblock(f.dinv, j0, nb)), 1);
-    hipLaunchKernelGGL(trinv_upper_kernel, dim3(1), dim3(tb), 0, c.s, Ajj, w, (long)n,
+    hipLaunchKernelGGL(trinv_upper_kernel, dim3(1), dim3(64), 0, c.s, Ajj, w, (long)n,
                        const_cast<double*>(dblock(f.uinv, j0, nb)));
     TT_HIP(hipGetLastError());
     return;
