@@ -41,6 +41,7 @@ struct Ctx {
   DevBuf dscr, dscr2, dscr3;  // dense factorisation scratch
   DevBuf ired;                // int scratch (status words)
   DevBuf dot_part, dot_out;
+  std::vector<DevBuf> gbuf;   // per-product stage buffers of grouped local products
   GemmPrec prec = GemmPrec::F64;
   double* hbuf = nullptr;     // pinned host staging
   size_t hbuf_n = 0;
