@@ -156,8 +156,8 @@ struct LocalKKT {
       g.C = gt2[a.o].get(); g.cm = s; g.cn = 1; g.sC = (long)4 * Rp * s;
       ++n;
     }
-    gemm_grouped(s1, n, c.s, &c.ws);
-    gemm_grouped(s2, n, c.s, &c.ws);
+    gemm_grouped(s1, n, c.s, &c.ws, c.prec);
+    gemm_grouped(s2, n, c.s, &c.ws, c.prec);
   }
 
   void stage3(std::initializer_list<Ap> aps, Ctx& c) {
@@ -175,7 +175,7 @@ struct LocalKKT {
       g.alpha = a.alpha; g.beta = a.beta;
       ++n;
     }
-    gemm_grouped(s3, n, c.s, &c.ws);
+    gemm_grouped(s3, n, c.s, &c.ws, c.prec);
   }
 
   // out = K u (u, out: [L][p])
@@ -183,7 +183,7 @@ struct LocalKKT {
     const double* x = u;
     const double* y = u + p;
     const double sg = sys->sense;
-    if (!sys->ineq && c.prec == GemmPrec::F64) {
+    if (!sys->ineq) {
       // Two levels of grouped stages: every operator applied to u, then L_X
       // applied to the eliminated dZ part.  K_Y's last stage waits for the
       // second level so that no launch has two products writing one row.

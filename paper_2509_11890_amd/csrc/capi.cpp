@@ -157,12 +157,12 @@ void check_local_op(const tt_local_op* K) {
 }
 
 // y = K x for the generic block description (chains of projected operators).
-// FP64: the blocks' projected products stage by stage, each stage of all of
-// them in grouped launches (first operators of every block, then the second
+// The blocks' projected products stage by stage, each stage of all of them in
+// grouped launches (first operators of every block, then the second
 // operators of the chained blocks).  A last-stage launch never holds two
 // products that add into the same block row, and the products of one row keep
 // the block order within each level.
-void generic_matvec_grouped(const tt_local_op* K, const double* x, double* y, Ctx& c) {
+void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c) {
   const long p = (long)K->r * K->m * K->rp;
   const int r = K->r, m = K->m, s = K->rp;
   fill((long)K->L * p, 0.0, y, c.s);
@@ -216,13 +216,13 @@ void generic_matvec_grouped(const tt_local_op* K, const double* x, double* y, Ct
       g.C = q.t2; g.cm = s; g.cn = 1; g.sC = (long)m * o.Rp * s;
       g2.push_back(g);
     }
-    for (size_t i = 0; i < g1.size(); i += 8) gemm_grouped(g1.data() + i, (int)std::min<size_t>(8, g1.size() - i), c.s, &c.ws);
-    for (size_t i = 0; i < g2.size(); i += 8) gemm_grouped(g2.data() + i, (int)std::min<size_t>(8, g2.size() - i), c.s, &c.ws);
+    for (size_t i = 0; i < g1.size(); i += 8) gemm_grouped(g1.data() + i, (int)std::min<size_t>(8, g1.size() - i), c.s, &c.ws, c.prec);
+    for (size_t i = 0; i < g2.size(); i += 8) gemm_grouped(g2.data() + i, (int)std::min<size_t>(8, g2.size() - i), c.s, &c.ws, c.prec);
     // last stage: y = alpha t2 phiR^T + beta y, launches cut where a row repeats
     std::vector<Gemm> g3;
     std::vector<int> rows;
     auto flush = [&]() {
-      if (!g3.empty()) gemm_grouped(g3.data(), (int)g3.size(), c.s, &c.ws);
+      if (!g3.empty()) gemm_grouped(g3.data(), (int)g3.size(), c.s, &c.ws, c.prec);
       g3.clear();
       rows.clear();
     };
@@ -239,42 +239,6 @@ void generic_matvec_grouped(const tt_local_op* K, const double* x, double* y, Ct
       if (q.row >= 0) rows.push_back(q.row);
     }
     flush();
-  }
-}
-
-void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c) {
-  if (c.prec == GemmPrec::F64) {
-    generic_matvec_grouped(K, x, y, c);
-    return;
-  }
-  const long p = (long)K->r * K->m * K->rp;
-  fill((long)K->L * p, 0.0, y, c.s);
-  // context-owned scratch: no allocation is released while kernels may still use it
-  DevBuf& perm0 = c.perm;
-  DevBuf& perm1 = c.perm2;
-  DevBuf& tmp = c.t3;
-  tmp.reserve(p);
-  for (int b = 0; b < K->nblocks; ++b) {
-    const tt_local_block& B = K->blocks[b];
-    const double* xin = x + (long)B.col * p;
-    double* yout = y + (long)B.row * p;
-    auto prep = [&](const tt_proj_op& o, DevBuf& buf) -> const double* {
-      if (!o.core) return nullptr;
-      buf.reserve((size_t)o.R * K->m * K->m * o.Rp);
-      permute_op_core(o.core, o.R, K->m, o.Rp, buf.get(), c.s);
-      return buf.get();
-    };
-    if (B.nchain == 1) {
-      const tt_proj_op& o = B.op[0];
-      local_apply(o.phiL, K->r, o.R, K->r, prep(o, perm0), K->m, o.phiR, K->rp, o.Rp, K->rp, xin, yout, B.coeff, 1.0, c);
-    } else {
-      const tt_proj_op& o0 = B.op[0];
-      const tt_proj_op& o1 = B.op[1];
-      local_apply(o0.phiL, K->r, o0.R, K->r, prep(o0, perm0), K->m, o0.phiR, K->rp, o0.Rp, K->rp, xin, tmp.get(), 1.0,
-                  0.0, c);
-      local_apply(o1.phiL, K->r, o1.R, K->r, prep(o1, perm1), K->m, o1.phiR, K->rp, o1.Rp, K->rp, tmp.get(), yout,
-                  B.coeff, 1.0, c);
-    }
   }
 }
 

@@ -227,15 +227,24 @@ struct GroupArgs {
   int n;
 };
 
-template <int WM, int WN, bool AKC, bool BKC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_grouped_kernel(GroupArgs ga) {
+// problem, output tile, batch entry and K slice of this workgroup
+struct GroupTile {
+  int i, tm, tn, bidx, slice;
+};
+__device__ __forceinline__ GroupTile group_tile(const GroupArgs& ga) {
   const int lin = blockIdx.x;
   int i = 0;
   while (i + 1 < ga.n && lin >= ga.end[i]) ++i;
   const int local = lin - (i ? ga.end[i - 1] : 0);
-  const KArgs& g = ga.g[i];
+  const int ks = ga.g[i].kslices;
   const int t = local % ga.tiles[i], z = local / ga.tiles[i];
-  gemm_f64_tile<WM, WN, AKC, BKC>(g, t / ga.gn[i], t % ga.gn[i], z / g.kslices, z % g.kslices);
+  return {i, t / ga.gn[i], t % ga.gn[i], z / ks, z % ks};
+}
+
+template <int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_grouped_kernel(GroupArgs ga) {
+  const GroupTile q = group_tile(ga);
+  gemm_f64_tile<WM, WN, AKC, BKC>(ga.g[q.i], q.tm, q.tn, q.bidx, q.slice);
 }
 
 // BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16): lane l supplies
@@ -250,7 +259,7 @@ constexpr int BK16 = 32;
 constexpr int P16 = 40;   // LDS row pitch in bf16 values
 
 template <int WM, int WN, bool AKC, bool BKC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_kernel(KArgs g) {
+__device__ __forceinline__ void gemm_bf16_tile(const KArgs& g, int tm, int tn, int bidx, int slice) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   constexpr int NA = TM * BK16 / 256, NB = BK16 * TN / 256;
   constexpr int ASTEP = AKC ? 256 / BK16 : 256 / TM;
@@ -259,18 +268,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][TN][P16];
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
-  const int gmt = gridDim.x, gnt = gridDim.y;
-  const int tiles = gmt * gnt;
-  const int lin = blockIdx.y * gmt + blockIdx.x;
-  int t = lin;
-  if (tiles >= 16) {
-    const int per = (tiles + 7) / 8;
-    const int cand = (lin % 8) * per + lin / 8;
-    t = (tiles % 8 == 0) ? cand : lin;
-  }
-  const int tm = t / gnt, tn = t % gnt;
   const int m0 = tm * TM, n0 = tn * TN;
-  const int bidx = blockIdx.z / g.kslices, slice = blockIdx.z % g.kslices;
   const int kbeg = slice * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
   const double* A = g.A + (long)bidx * g.sA;
   const double* B = g.B + (long)bidx * g.sB;
@@ -376,6 +374,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
           }
         }
       }
+}
+
+template <int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_kernel(KArgs g) {
+  const int gmt = gridDim.x, gnt = gridDim.y;
+  const int tiles = gmt * gnt;
+  const int lin = blockIdx.y * gmt + blockIdx.x;
+  int t = lin;
+  if (tiles >= 16) {
+    const int per = (tiles + 7) / 8;
+    const int cand = (lin % 8) * per + lin / 8;
+    t = (tiles % 8 == 0) ? cand : lin;
+  }
+  gemm_bf16_tile<WM, WN, AKC, BKC>(g, t / gnt, t % gnt, blockIdx.z / g.kslices, blockIdx.z % g.kslices);
+}
+
+template <int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_grouped_kernel(GroupArgs ga) {
+  const GroupTile q = group_tile(ga);
+  gemm_bf16_tile<WM, WN, AKC, BKC>(ga.g[q.i], q.tm, q.tn, q.bidx, q.slice);
 }
 
 __device__ __forceinline__ void splitk_reduce_one(const KArgs& g, long idx) {
@@ -549,6 +567,21 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
 }
 
 template <int WM, int WN>
+void launch_bf16_grouped(int blocks, hipStream_t stream, const GroupArgs& ga, bool akc, bool bkc, double flops,
+                         double bytes) {
+  const dim3 grid(blocks), blk(256);
+  if (akc && bkc)
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_grouped_kernel<WM, WN, true, true>, grid, blk, 0u, stream, ga);
+  else if (akc)
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_grouped_kernel<WM, WN, true, false>, grid, blk, 0u, stream, ga);
+  else if (bkc)
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_grouped_kernel<WM, WN, false, true>, grid, blk, 0u, stream, ga);
+  else
+    launch_prof(PK_GEMM_BF16, flops, bytes, gemm_bf16_grouped_kernel<WM, WN, false, false>, grid, blk, 0u, stream,
+                ga);
+}
+
+template <int WM, int WN>
 void launch_f64_grouped(int blocks, hipStream_t stream, const GroupArgs& ga, bool akc, bool bkc, double flops,
                         double bytes) {
   const dim3 grid(blocks), blk(256);
@@ -562,7 +595,8 @@ void launch_f64_grouped(int blocks, hipStream_t stream, const GroupArgs& ga, boo
     launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_grouped_kernel<WM, WN, false, false>, grid, blk, 0u, stream, ga);
 }
 
-void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws) {
+void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws, GemmPrec prec) {
+  const int kstep = (prec == GemmPrec::BF16) ? BK16 : BK;
   // problems that the grouped launch does not take go through gemm() one by one
   std::vector<const Gemm*> take;
   bool akc0 = false, bkc0 = false;
@@ -575,7 +609,7 @@ void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws) 
                       (double)(q.N - 1) * q.bn + (double)(q.K - 1 + BK16) * q.bk <= 536870911.0 &&
                       (take.empty() || (akc == akc0 && bkc == bkc0));
     if (!fits) {
-      gemm(q, stream, ws, GemmPrec::F64);
+      gemm(q, stream, ws, prec);
       continue;
     }
     if (take.empty()) { akc0 = akc; bkc0 = bkc; }
@@ -583,7 +617,7 @@ void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws) 
   }
   if (take.empty()) return;
   if (take.size() == 1) {
-    gemm(*take[0], stream, ws, GemmPrec::F64);
+    gemm(*take[0], stream, ws, prec);
     return;
   }
   // 64 x 64 tiles throughout (the products grouped here are small); K is
@@ -605,12 +639,12 @@ void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws) 
     const int gm = (q.M + BM - 1) / BM, gn = (q.N + BN - 1) / BN;
     const long tiles = (long)gm * gn * q.batch;
     int ks = 1;
-    if (tiles < 128 && q.K >= 16 * BK) {
-      ks = (int)std::min<long>((256 + tiles - 1) / tiles, (long)q.K / (8 * BK));
+    if (tiles < 128 && q.K >= 16 * kstep) {
+      ks = (int)std::min<long>((256 + tiles - 1) / tiles, (long)q.K / (8 * kstep));
       ks = std::max(1, std::min(ks, 64));
     }
     int chunk = (q.K + ks - 1) / ks;
-    chunk = ((chunk + BK - 1) / BK) * BK;
+    chunk = ((chunk + kstep - 1) / kstep) * kstep;
     ks = (q.K + chunk - 1) / chunk;
     g.kslices = ks;
     g.kchunk = chunk;
@@ -645,7 +679,10 @@ void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws) 
       ++red.n;
     }
   }
-  launch_f64_grouped<2, 2>((int)blocks, stream, ga, akc0, bkc0, flops, bytes);
+  if (prec == GemmPrec::BF16)
+    launch_bf16_grouped<2, 2>((int)blocks, stream, ga, akc0, bkc0, flops, bytes);
+  else
+    launch_f64_grouped<2, 2>((int)blocks, stream, ga, akc0, bkc0, flops, bytes);
   TT_HIP(hipGetLastError());
   if (split) {
     hipLaunchKernelGGL(splitk_reduce_grouped_kernel, dim3(nblocks((long)red.end[red.n - 1], 256)), dim3(256), 0,

@@ -24,10 +24,11 @@ struct Workspace {
 
 void gemm(const Gemm& g, hipStream_t stream, Workspace* ws = nullptr, GemmPrec prec = GemmPrec::F64);
 
-// Independent FP64 products in one launch (up to 8 with the same operand
-// layouts; the others go through gemm()).  Outputs must not overlap: the
-// problems run concurrently.
-void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws = nullptr);
+// Independent products in one launch (up to 8 with the same operand layouts;
+// the others go through gemm()), FP64 or BF16 operands.  Outputs must not
+// overlap: the problems run concurrently.
+void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws = nullptr,
+                  GemmPrec prec = GemmPrec::F64);
 
 // Helpers for the common row-major cases.
 inline Gemm gemm_nn(int M, int N, int K, const double* A, long lda, const double* B, long ldb, double* C,
