@@ -327,3 +327,20 @@ def test_krylov_local_solves_reach_gap_mark(precision):
     assert sum(l["krylov_iters"] for l in log) > 0
     assert res["status"] == P.TT_OK and res["time_to_gap"] > 0
     assert abs(res["pobj"] - 52.0) / 53.0 < 2.5e-4 and abs(res["dobj"] - 52.0) / 53.0 < 2.5e-4
+
+
+def test_solve_is_reproducible_run_to_run():
+    """The primal and dual phases run on two streams and every reduction has a
+    fixed order, so two solves of one instance from fresh states agree bit for
+    bit, iteration by iteration."""
+    P = _lib()
+    g = I.grid_4x8()
+    pr = P.Problem(P.TTIPM_MAXCUT, g.cores)
+    prm = P.Params(rank_cap=8, iter_rank_cap=8, stop_gap=1e-4, max_iter=40, direct_max=64,
+                   precond=P.TT_PREC_BJACOBI)
+    runs = []
+    for _ in range(2):
+        st = P.State(pr, prm)
+        res, log = P.ttipm_solve(pr, st, prm)
+        runs.append([(l["pobj"], l["dobj"], l["alpha_p"], l["alpha_d"], l["krylov_iters"]) for l in log])
+    assert len(runs[0]) > 3 and runs[0] == runs[1]
