@@ -273,7 +273,21 @@ __global__ void mdot_single(long n, const double* V, long ld, const double* w, d
   const int j = blockIdx.x;
   const double* v = V + (long)j * ld;
   double acc = 0.0;
-  for (long t = threadIdx.x; t < n; t += blockDim.x) acc += v[t] * w[t];
+  // four entries per thread at a time: the loads are issued before the first
+  // product waits on them, and the sum keeps the order of one entry at a time
+  constexpr int U = 4;
+  for (long t0 = threadIdx.x; t0 < n; t0 += (long)U * blockDim.x) {
+    double vs[U], ws[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long t = t0 + (long)u * blockDim.x;
+      vs[u] = t < n ? v[t] : 0.0;
+      ws[u] = t < n ? w[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (t0 + (long)u * blockDim.x < n) acc += vs[u] * ws[u];
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = acc;
