@@ -39,6 +39,26 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// v_j^T x over the rows j + lane, j + lane + 64, ... < m of one lane (v_j[j] = 1
+// implicit), summed in that order; four loads per operand are issued before
+// the first product waits on them.
+__device__ __forceinline__ double reflector_dot(const double* v, const double* x, int j, int m, int lane) {
+  double d = 0.0;
+  for (int i0 = j + lane; i0 < m; i0 += 256) {
+    double vs[4], xs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u;
+      vs[u] = i < m ? ((i == j) ? 1.0 : v[i]) : 0.0;
+      xs[u] = i < m ? x[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + 64 * u < m) d += vs[u] * xs[u];
+  }
+  return d;
+}
+
 // ---------------------------------------------------------------------------
 // Householder QR, column-major A (m x n, leading dimension lda), in place.
 // On exit R is in the upper triangle, the reflector vectors v_j (v_j[j] = 1
@@ -76,9 +96,7 @@ __global__ __launch_bounds__(DT) void qr_kernel(double* A, int m, int n, int lda
     if (tj != 0.0) {
       for (int c = j + 1 + w; c < n; c += NW) {
         double* cc = A + (long)c * lda;
-        double d = 0.0;
-        for (int i = j + lane; i < m; i += 64) d += ((i == j) ? 1.0 : col[i]) * cc[i];
-        d = wave_sum(d) * tj;
+        double d = wave_sum(reflector_dot(col, cc, j, m, lane)) * tj;
         for (int i = j + lane; i < m; i += 64) cc[i] -= d * ((i == j) ? 1.0 : col[i]);
       }
     }
@@ -102,9 +120,7 @@ __global__ __launch_bounds__(DT) void qr_form_q_kernel(const double* A, int m, i
     if (tj != 0.0) {
       for (int c = w; c < k; c += NW) {
         double* qc = Q + (long)c * ldq;
-        double d = 0.0;
-        for (int i = j + lane; i < m; i += 64) d += ((i == j) ? 1.0 : v[i]) * qc[i];
-        d = wave_sum(d) * tj;
+        double d = wave_sum(reflector_dot(v, qc, j, m, lane)) * tj;
         for (int i = j + lane; i < m; i += 64) qc[i] -= d * ((i == j) ? 1.0 : v[i]);
       }
     }
