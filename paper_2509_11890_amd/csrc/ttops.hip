@@ -217,8 +217,21 @@ void fill(long n, double v, double* y, hipStream_t s) {
 __global__ void gemv_t_kernel(long n, int k, const double* V, long ld, const double* coef, double sign, double* y) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
+  // four columns at a time: their loads are in flight together, and the sum
+  // keeps the order of one column at a time
   double acc = 0.0;
-  for (int j = 0; j < k; ++j) acc += coef[j] * V[(long)j * ld + t];
+  for (int j0 = 0; j0 < k; j0 += 4) {
+    double cs[4], vs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u;
+      cs[u] = j < k ? coef[j] : 0.0;
+      vs[u] = j < k ? V[(long)j * ld + t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + u < k) acc += cs[u] * vs[u];
+  }
   y[t] += sign * acc;
 }
 void gemv_update(long n, int k, const double* V, long ld, const double* coef, double sign, double* y,
