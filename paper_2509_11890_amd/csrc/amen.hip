@@ -69,28 +69,33 @@ struct Envs {
     }
   }
 
+  // the steps of all keys at one core share grouped launches
   void update_left(const BlockTT& W, int k, Ctx& c) {
+    std::vector<EnvStepArgs> st;
     for (size_t i = 0; i < keys.size(); ++i) {
       const EnvKey& e = keys[i];
       const int ra = W.r[k], ra2 = W.r[k + 1];
       const int R0 = op_rank(e, k), R1 = op_rank(e, k + 1);
       const int rc = trial_rank(e, W, k), rc2 = trial_rank(e, W, k + 1);
       L[i][k + 1].reserve((size_t)ra2 * R1 * rc2);
-      env_left_step(L[i][k].get(), ra, R0, rc, W.cores[k].get(), 4, ra2, e.op ? e.op->core(k) : nullptr, R1, 4,
-                    trial_core(e, W, k), rc2, L[i][k + 1].get(), c);
+      st.push_back({L[i][k].get(), ra, R0, rc, W.cores[k].get(), 4, ra2, e.op ? e.op->core(k) : nullptr, R1, 4,
+                    trial_core(e, W, k), rc2, L[i][k + 1].get()});
     }
+    env_steps(st, true, c);
   }
 
   void update_right(const BlockTT& W, int k, Ctx& c) {
+    std::vector<EnvStepArgs> st;
     for (size_t i = 0; i < keys.size(); ++i) {
       const EnvKey& e = keys[i];
       const int ra = W.r[k], ra2 = W.r[k + 1];
       const int R0 = op_rank(e, k), R1 = op_rank(e, k + 1);
       const int rc = trial_rank(e, W, k), rc2 = trial_rank(e, W, k + 1);
       R[i][k - 1].reserve((size_t)ra * R0 * rc);
-      env_right_step(R[i][k].get(), ra2, R1, rc2, W.cores[k].get(), 4, ra, e.op ? e.op->core(k) : nullptr, R0, 4,
-                     trial_core(e, W, k), rc, R[i][k - 1].get(), c);
+      st.push_back({R[i][k].get(), ra2, R1, rc2, W.cores[k].get(), 4, ra, e.op ? e.op->core(k) : nullptr, R0, 4,
+                    trial_core(e, W, k), rc, R[i][k - 1].get()});
     }
+    env_steps(st, false, c);
   }
 };
 

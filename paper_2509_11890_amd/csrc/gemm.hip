@@ -595,27 +595,41 @@ void launch_f64_grouped(int blocks, hipStream_t stream, const GroupArgs& ga, boo
     launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_grouped_kernel<WM, WN, false, false>, grid, blk, 0u, stream, ga);
 }
 
+// One grouped launch of up to kMaxGroup problems of one operand layout.
+static void gemm_group_launch(const std::vector<const Gemm*>& take, bool akc0, bool bkc0, hipStream_t stream,
+                              Workspace* ws, GemmPrec prec);
+
 void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws, GemmPrec prec) {
-  const int kstep = (prec == GemmPrec::BF16) ? BK16 : BK;
-  // problems that the grouped launch does not take go through gemm() one by one
-  std::vector<const Gemm*> take;
-  bool akc0 = false, bkc0 = false;
+  // Problems are sorted into the four operand layouts (which index of A and
+  // of B is unit stride) and launched in groups of up to kMaxGroup per
+  // layout; problems outside the 32-bit offset range or with K = 0 go
+  // through gemm() one by one.
+  std::vector<const Gemm*> cls[4];
   for (int i = 0; i < count; ++i) {
     const Gemm& q = qs[i];
     if (q.M <= 0 || q.N <= 0 || q.batch <= 0) continue;
     const bool akc = (q.ak == 1), bkc = (q.bk == 1 && q.bn != 1);
-    const bool fits = q.K > 0 && (int)take.size() < kMaxGroup && q.am >= 0 && q.ak >= 0 && q.bk >= 0 && q.bn >= 0 &&
+    const bool fits = q.K > 0 && q.am >= 0 && q.ak >= 0 && q.bk >= 0 && q.bn >= 0 &&
                       (double)(q.M - 1) * q.am + (double)(q.K - 1 + BK16) * q.ak <= 536870911.0 &&
-                      (double)(q.N - 1) * q.bn + (double)(q.K - 1 + BK16) * q.bk <= 536870911.0 &&
-                      (take.empty() || (akc == akc0 && bkc == bkc0));
+                      (double)(q.N - 1) * q.bn + (double)(q.K - 1 + BK16) * q.bk <= 536870911.0;
     if (!fits) {
       gemm(q, stream, ws, prec);
       continue;
     }
-    if (take.empty()) { akc0 = akc; bkc0 = bkc; }
-    take.push_back(&q);
+    std::vector<const Gemm*>& c = cls[(akc ? 2 : 0) + (bkc ? 1 : 0)];
+    c.push_back(&q);
+    if ((int)c.size() == kMaxGroup) {
+      gemm_group_launch(c, akc, bkc, stream, ws, prec);
+      c.clear();
+    }
   }
-  if (take.empty()) return;
+  for (int l = 0; l < 4; ++l)
+    if (!cls[l].empty()) gemm_group_launch(cls[l], l >= 2, l % 2 == 1, stream, ws, prec);
+}
+
+static void gemm_group_launch(const std::vector<const Gemm*>& take, bool akc0, bool bkc0, hipStream_t stream,
+                              Workspace* ws, GemmPrec prec) {
+  const int kstep = (prec == GemmPrec::BF16) ? BK16 : BK;
   if (take.size() == 1) {
     gemm(*take[0], stream, ws, prec);
     return;

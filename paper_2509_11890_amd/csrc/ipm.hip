@@ -311,20 +311,22 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
   auto upd_right = [&](int k) {
     const int ra = E.r[k], ra2 = E.r[k + 1];
     MR[k - 1].reserve((size_t)ra * M.r[k] * ra);
-    env_right_step(MR[k].get(), ra2, M.r[k + 1], ra2, E.cores[k].get(), 2, ra, M.core(k), M.r[k], 2,
-                   E.cores[k].get(), ra, MR[k - 1].get(), c);
     DR[k - 1].reserve((size_t)ra * dM.r[k] * ra);
-    env_right_step(DR[k].get(), ra2, dM.r[k + 1], ra2, E.cores[k].get(), 2, ra, dM.core(k), dM.r[k], 2,
-                   E.cores[k].get(), ra, DR[k - 1].get(), c);
+    env_steps({{MR[k].get(), ra2, M.r[k + 1], ra2, E.cores[k].get(), 2, ra, M.core(k), M.r[k], 2, E.cores[k].get(),
+                ra, MR[k - 1].get()},
+               {DR[k].get(), ra2, dM.r[k + 1], ra2, E.cores[k].get(), 2, ra, dM.core(k), dM.r[k], 2,
+                E.cores[k].get(), ra, DR[k - 1].get()}},
+              false, c);
   };
   auto upd_left = [&](int k) {
     const int ra = E.r[k], ra2 = E.r[k + 1];
     ML[k + 1].reserve((size_t)ra2 * M.r[k + 1] * ra2);
-    env_left_step(ML[k].get(), ra, M.r[k], ra, E.cores[k].get(), 2, ra2, M.core(k), M.r[k + 1], 2,
-                  E.cores[k].get(), ra2, ML[k + 1].get(), c);
     DL[k + 1].reserve((size_t)ra2 * dM.r[k + 1] * ra2);
-    env_left_step(DL[k].get(), ra, dM.r[k], ra, E.cores[k].get(), 2, ra2, dM.core(k), dM.r[k + 1], 2,
-                  E.cores[k].get(), ra2, DL[k + 1].get(), c);
+    env_steps({{ML[k].get(), ra, M.r[k], ra, E.cores[k].get(), 2, ra2, M.core(k), M.r[k + 1], 2, E.cores[k].get(),
+                ra2, ML[k + 1].get()},
+               {DL[k].get(), ra, dM.r[k], ra, E.cores[k].get(), 2, ra2, dM.core(k), dM.r[k + 1], 2,
+                E.cores[k].get(), ra2, DL[k + 1].get()}},
+              true, c);
   };
   for (int k = d - 1; k > 0; --k) upd_right(k);
   double lam_best = 1e300;

@@ -314,97 +314,168 @@ void permute_op_core(const double* O, int R, int m, int Rp, double* out, hipStre
   permute(O, out, {R, m, m, Rp}, {1, 3, 0, 2}, s);
 }
 
-void env_left_step(const double* phi, int ra, int R, int rc, const double* V, int mo, int ra2, const double* O,
-                   int Rp, int mi, const double* U, int rc2, double* out, Ctx& c) {
+namespace {
+
+// The GEMMs of one environment step, in order, with the scratch they use; the
+// left step with an operator permutes the operator core before its second GEMM.
+struct EnvPlan {
+  Gemm g[3];
+  int ng = 0;
+  bool permute_core = false;   // permute O into perm before g[1]
+  const double* O = nullptr;
+  int R = 0, mo = 0, mi = 0, Rp = 0;
+  double* perm = nullptr;
+};
+
+EnvPlan plan_left(const double* phi, int ra, int R, int rc, const double* V, int mo, int ra2, const double* O,
+                  int Rp, int mi, const double* U, int rc2, double* out, double* t1, double* t2, double* perm) {
+  EnvPlan P;
   if (O == nullptr) {
     TT_REQUIRE(R == 1 && Rp == 1 && mo == mi, "identity environment shapes");
     // t1[a][(i,c2)] = phi[a][c] U[c][(i,c2)];  out[a2][c2] = sum_(a,i) V[(a,i)][a2] t1[(a,i)][c2]
-    c.t1.reserve((size_t)ra * mi * rc2);
-    gemm(gemm_nn(ra, mi * rc2, rc, phi, rc, U, mi * rc2, c.t1.get(), mi * rc2), c.s, &c.ws, c.prec);
-    Gemm g;
+    P.g[0] = gemm_nn(ra, mi * rc2, rc, phi, rc, U, mi * rc2, t1, mi * rc2);
+    Gemm& g = P.g[1];
     g.M = ra2; g.N = rc2; g.K = ra * mo;
     g.A = V; g.am = 1; g.ak = ra2;
-    g.B = c.t1.get(); g.bk = rc2; g.bn = 1;
+    g.B = t1; g.bk = rc2; g.bn = 1;
     g.C = out; g.cm = rc2; g.cn = 1;
-    gemm(g, c.s, &c.ws, c.prec);
-    return;
+    P.ng = 2;
+    return P;
   }
   // stage 1: t1[(a,alpha)][(j,c2)] = phi[(a,alpha)][c] U[c][(j,c2)]
-  c.t1.reserve((size_t)ra * R * mi * rc2);
-  gemm(gemm_nn(ra * R, mi * rc2, rc, phi, rc, U, mi * rc2, c.t1.get(), mi * rc2), c.s, &c.ws, c.prec);
+  P.g[0] = gemm_nn(ra * R, mi * rc2, rc, phi, rc, U, mi * rc2, t1, mi * rc2);
   // stage 2: t2[a][(i,beta)][c2] = O'[(i,beta)][(alpha,j)] t1[a][(alpha,j)][c2]
-  c.perm.reserve((size_t)R * mo * mi * Rp);
-  permute(O, c.perm.get(), {R, mo, mi, Rp}, {1, 3, 0, 2}, c.s);
-  c.t2.reserve((size_t)ra * mo * Rp * rc2);
+  P.permute_core = true;
+  P.O = O; P.R = R; P.mo = mo; P.mi = mi; P.Rp = Rp; P.perm = perm;
   {
-    Gemm g;
+    Gemm& g = P.g[1];
     g.M = mo * Rp; g.N = rc2; g.K = R * mi; g.batch = ra;
-    g.A = c.perm.get(); g.am = R * mi; g.ak = 1; g.sA = 0;
-    g.B = c.t1.get(); g.bk = rc2; g.bn = 1; g.sB = (long)R * mi * rc2;
-    g.C = c.t2.get(); g.cm = rc2; g.cn = 1; g.sC = (long)mo * Rp * rc2;
-    gemm(g, c.s, &c.ws, c.prec);
+    g.A = perm; g.am = R * mi; g.ak = 1; g.sA = 0;
+    g.B = t1; g.bk = rc2; g.bn = 1; g.sB = (long)R * mi * rc2;
+    g.C = t2; g.cm = rc2; g.cn = 1; g.sC = (long)mo * Rp * rc2;
   }
   // stage 3: out[a2][(beta,c2)] = sum_(a,i) V[(a,i)][a2] t2[(a,i)][(beta,c2)]
   {
-    Gemm g;
+    Gemm& g = P.g[2];
     g.M = ra2; g.N = Rp * rc2; g.K = ra * mo;
     g.A = V; g.am = 1; g.ak = ra2;
-    g.B = c.t2.get(); g.bk = (long)Rp * rc2; g.bn = 1;
+    g.B = t2; g.bk = (long)Rp * rc2; g.bn = 1;
     g.C = out; g.cm = (long)Rp * rc2; g.cn = 1;
-    gemm(g, c.s, &c.ws, c.prec);
   }
+  P.ng = 3;
+  return P;
+}
+
+EnvPlan plan_right(const double* phi, int ra2, int Rp, int rc2, const double* V, int mo, int ra, const double* O,
+                   int R, int mi, const double* U, int rc, double* out, double* t1, double* t2) {
+  EnvPlan P;
+  if (O == nullptr) {
+    TT_REQUIRE(R == 1 && Rp == 1 && mo == mi, "identity environment shapes");
+    // t1[(c,i)][a2] = sum_c2 U[(c,i)][c2] phi[a2][c2]
+    Gemm& g1 = P.g[0];
+    g1.M = rc * mi; g1.N = ra2; g1.K = rc2;
+    g1.A = U; g1.am = rc2; g1.ak = 1;
+    g1.B = phi; g1.bk = 1; g1.bn = rc2;
+    g1.C = t1; g1.cm = ra2; g1.cn = 1;
+    // out[a][c] = sum_(i,a2) V[a][(i,a2)] t1[c][(i,a2)]
+    Gemm& g2 = P.g[1];
+    g2.M = ra; g2.N = rc; g2.K = mo * ra2;
+    g2.A = V; g2.am = (long)mo * ra2; g2.ak = 1;
+    g2.B = t1; g2.bk = 1; g2.bn = (long)mi * ra2;
+    g2.C = out; g2.cm = rc; g2.cn = 1;
+    P.ng = 2;
+    return P;
+  }
+  // stage 1 (batched over a2): t1[a2][(c,j)][beta] = sum_c2 U[(c,j)][c2] phi[a2][beta][c2]
+  {
+    Gemm& g = P.g[0];
+    g.M = rc * mi; g.N = Rp; g.K = rc2; g.batch = ra2;
+    g.A = U; g.am = rc2; g.ak = 1; g.sA = 0;
+    g.B = phi; g.bk = 1; g.bn = rc2; g.sB = (long)Rp * rc2;
+    g.C = t1; g.cm = Rp; g.cn = 1; g.sC = (long)rc * mi * Rp;
+  }
+  // stage 2: t2[(alpha,i)][(a2,c)] = sum_(j,beta) O[(alpha,i)][(j,beta)] t1[(a2,c)][(j,beta)]
+  {
+    Gemm& g = P.g[1];
+    g.M = R * mo; g.N = ra2 * rc; g.K = mi * Rp;
+    g.A = O; g.am = (long)mi * Rp; g.ak = 1;
+    g.B = t1; g.bk = 1; g.bn = (long)mi * Rp;
+    g.C = t2; g.cm = (long)ra2 * rc; g.cn = 1;
+  }
+  // stage 3 (batched over alpha): out[a][alpha][c] = sum_(i,a2) V[a][(i,a2)] t2[alpha][(i,a2)][c]
+  {
+    Gemm& g = P.g[2];
+    g.M = ra; g.N = rc; g.K = mo * ra2; g.batch = R;
+    g.A = V; g.am = (long)mo * ra2; g.ak = 1; g.sA = 0;
+    g.B = t2; g.bk = rc; g.bn = 1; g.sB = (long)mo * ra2 * rc;
+    g.C = out; g.cm = (long)R * rc; g.cn = 1; g.sC = rc;
+  }
+  P.ng = 3;
+  return P;
+}
+
+// The plans' GEMMs level by level: the k-th GEMMs of all plans are independent
+// (each plan owns its scratch and output), so each level is grouped launches.
+void run_plans(std::vector<EnvPlan>& plans, Ctx& c) {
+  for (int lv = 0; lv < 3; ++lv) {
+    std::vector<Gemm> gs;
+    for (EnvPlan& P : plans) {
+      if (lv >= P.ng) continue;
+      if (lv == 1 && P.permute_core) permute(P.O, P.perm, {P.R, P.mo, P.mi, P.Rp}, {1, 3, 0, 2}, c.s);
+      gs.push_back(P.g[lv]);
+    }
+    if (!gs.empty()) gemm_grouped(gs.data(), (int)gs.size(), c.s, &c.ws, c.prec);
+  }
+}
+
+}  // namespace
+
+void env_left_step(const double* phi, int ra, int R, int rc, const double* V, int mo, int ra2, const double* O,
+                   int Rp, int mi, const double* U, int rc2, double* out, Ctx& c) {
+  c.t1.reserve((size_t)ra * R * mi * rc2);
+  if (O) {
+    c.perm.reserve((size_t)R * mo * mi * Rp);
+    c.t2.reserve((size_t)ra * mo * Rp * rc2);
+  }
+  std::vector<EnvPlan> plans{plan_left(phi, ra, R, rc, V, mo, ra2, O, Rp, mi, U, rc2, out, c.t1.get(), c.t2.get(),
+                                       c.perm.get())};
+  run_plans(plans, c);
 }
 
 void env_right_step(const double* phi, int ra2, int Rp, int rc2, const double* V, int mo, int ra,
                     const double* O, int R, int mi, const double* U, int rc, double* out, Ctx& c) {
-  if (O == nullptr) {
-    TT_REQUIRE(R == 1 && Rp == 1 && mo == mi, "identity environment shapes");
-    // t1[(c,i)][a2] = sum_c2 U[(c,i)][c2] phi[a2][c2]
-    c.t1.reserve((size_t)rc * mi * ra2);
-    Gemm g1;
-    g1.M = rc * mi; g1.N = ra2; g1.K = rc2;
-    g1.A = U; g1.am = rc2; g1.ak = 1;
-    g1.B = phi; g1.bk = 1; g1.bn = rc2;
-    g1.C = c.t1.get(); g1.cm = ra2; g1.cn = 1;
-    gemm(g1, c.s, &c.ws, c.prec);
-    // out[a][c] = sum_(i,a2) V[a][(i,a2)] t1[c][(i,a2)]
-    Gemm g2;
-    g2.M = ra; g2.N = rc; g2.K = mo * ra2;
-    g2.A = V; g2.am = (long)mo * ra2; g2.ak = 1;
-    g2.B = c.t1.get(); g2.bk = 1; g2.bn = (long)mi * ra2;
-    g2.C = out; g2.cm = rc; g2.cn = 1;
-    gemm(g2, c.s, &c.ws, c.prec);
-    return;
-  }
-  // stage 1 (batched over a2): t1[a2][(c,j)][beta] = sum_c2 U[(c,j)][c2] phi[a2][beta][c2]
   c.t1.reserve((size_t)ra2 * rc * mi * Rp);
-  {
-    Gemm g;
-    g.M = rc * mi; g.N = Rp; g.K = rc2; g.batch = ra2;
-    g.A = U; g.am = rc2; g.ak = 1; g.sA = 0;
-    g.B = phi; g.bk = 1; g.bn = rc2; g.sB = (long)Rp * rc2;
-    g.C = c.t1.get(); g.cm = Rp; g.cn = 1; g.sC = (long)rc * mi * Rp;
-    gemm(g, c.s, &c.ws, c.prec);
+  if (O) c.t2.reserve((size_t)R * mo * ra2 * rc);
+  std::vector<EnvPlan> plans{plan_right(phi, ra2, Rp, rc2, V, mo, ra, O, R, mi, U, rc, out, c.t1.get(), c.t2.get())};
+  run_plans(plans, c);
+}
+
+void env_steps(const std::vector<EnvStepArgs>& steps, bool left, Ctx& c) {
+  std::vector<EnvPlan> plans;
+  plans.reserve(steps.size());
+  size_t nb = 0;
+  auto buf = [&](size_t n) {
+    if (c.gbuf.size() <= nb) c.gbuf.resize(nb + 1);
+    c.gbuf[nb].reserve(n);
+    return c.gbuf[nb++].get();
+  };
+  for (const EnvStepArgs& a : steps) {
+    if (left) {
+      double* t1 = buf((size_t)a.ra * a.R * a.mi * a.rc2);
+      double* t2 = a.O ? buf((size_t)a.ra * a.mo * a.Rp * a.rc2) : nullptr;
+      double* perm = a.O ? buf((size_t)a.R * a.mo * a.mi * a.Rp) : nullptr;
+      plans.push_back(plan_left(a.phi, a.ra, a.R, a.rc, a.V, a.mo, a.ra2, a.O, a.Rp, a.mi, a.U, a.rc2, a.out, t1, t2,
+                                perm));
+    } else {
+      // the fields hold env_right_step's arguments in its order:
+      // (phi, ra2, Rp, rc2, V, mo, ra, O, R, mi, U, rc, out)
+      const int ra2 = a.ra, Rp = a.R, rc2 = a.rc, ra = a.ra2, R = a.Rp, rc = a.rc2;
+      double* t1 = buf((size_t)ra2 * rc * a.mi * Rp);
+      double* t2 = a.O ? buf((size_t)R * a.mo * ra2 * rc) : nullptr;
+      plans.push_back(plan_right(a.phi, ra2, Rp, rc2, a.V, a.mo, ra, a.O, R, a.mi, a.U, rc, a.out, t1, t2));
+    }
   }
-  // stage 2: t2[(alpha,i)][(a2,c)] = sum_(j,beta) O[(alpha,i)][(j,beta)] t1[(a2,c)][(j,beta)]
-  c.t2.reserve((size_t)R * mo * ra2 * rc);
-  {
-    Gemm g;
-    g.M = R * mo; g.N = ra2 * rc; g.K = mi * Rp;
-    g.A = O; g.am = (long)mi * Rp; g.ak = 1;
-    g.B = c.t1.get(); g.bk = 1; g.bn = (long)mi * Rp;
-    g.C = c.t2.get(); g.cm = (long)ra2 * rc; g.cn = 1;
-    gemm(g, c.s, &c.ws, c.prec);
-  }
-  // stage 3 (batched over alpha): out[a][alpha][c] = sum_(i,a2) V[a][(i,a2)] t2[alpha][(i,a2)][c]
-  {
-    Gemm g;
-    g.M = ra; g.N = rc; g.K = mo * ra2; g.batch = R;
-    g.A = V; g.am = (long)mo * ra2; g.ak = 1; g.sA = 0;
-    g.B = c.t2.get(); g.bk = rc; g.bn = 1; g.sB = (long)mo * ra2 * rc;
-    g.C = out; g.cm = (long)R * rc; g.cn = 1; g.sC = rc;
-    gemm(g, c.s, &c.ws, c.prec);
-  }
+  run_plans(plans, c);
 }
 
 void local_apply(const double* phiL, int r, int R, int rc, const double* Operm, int m, const double* phiR, int s,

@@ -86,6 +86,22 @@ void env_left_step(const double* phi, int ra, int R, int rc, const double* V, in
                    int Rp, int mi, const double* U, int rc2, double* out, Ctx& c);
 void env_right_step(const double* phi, int ra2, int Rp, int rc2, const double* V, int mo, int ra,
                     const double* O, int R, int mi, const double* U, int rc, double* out, Ctx& c);
+// Several environment steps of one direction at once (their k-th GEMMs share
+// grouped launches).  The fields hold the arguments of env_left_step, or of
+// env_right_step, in that function's order (for a right step: phi, ra2, Rp,
+// rc2, V, mo, ra, O, R, mi, U, rc, out).  Outputs must be distinct.
+struct EnvStepArgs {
+  const double* phi;
+  int ra, R, rc;
+  const double* V;
+  int mo, ra2;
+  const double* O;
+  int Rp, mi;
+  const double* U;
+  int rc2;
+  double* out;
+};
+void env_steps(const std::vector<EnvStepArgs>& steps, bool left, Ctx& c);
 // y = alpha * P x + beta * y with P the projected operator between a test
 // frame (ranks r, s) and a trial TT core x [rc][m][rd]:
 //   y[a][i][b] = sum phiL[a][al][c] O[al][i][j][be] x[c][j][e] phiR[b][be][e]
