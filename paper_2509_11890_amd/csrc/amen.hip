@@ -812,6 +812,10 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
         Rhat[q].reserve(p);
         fill(p, 0.0, Rhat[q].get(), c.s);
       }
+      // the terms' projections in grouped stage launches (terms of one block
+      // residual keep their order)
+      std::vector<DevBuf> operms(sys.terms.size());
+      std::vector<LocalApplyArgs> proj;
       for (size_t t = 0; t < sys.terms.size(); ++t) {
         const Term& tm = sys.terms[t];
         const int key = key_of_term[t];
@@ -819,16 +823,16 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
         const int R0 = envs.op_rank(e, k), R1 = envs.op_rank(e, k + 1);
         const int rc = e.trial->r[k], rd = e.trial->r[k + 1];
         const double* Op = nullptr;
-        DevBuf operm;
         if (e.op) {
-          operm.reserve((size_t)e.op->core_size(k));
-          permute_op_core(e.op->core(k), R0, 4, R1, operm.get(), c.s);
-          Op = operm.get();
+          operms[t].reserve((size_t)e.op->core_size(k));
+          permute_op_core(e.op->core(k), R0, 4, R1, operms[t].get(), c.s);
+          Op = operms[t].get();
         }
-        local_apply(envs.L[key][k].get(), r, R0, rc, Op, 4, envs.R[key][k].get(), s, R1, rd, e.trial->core(k),
-                    Rhat[tm.res].get(), tm.coef, 1.0, c);
-        c.sync();   // operm is released at scope end
+        proj.push_back({envs.L[key][k].get(), r, R0, rc, Op, 4, envs.R[key][k].get(), s, R1, rd, e.trial->core(k),
+                        Rhat[tm.res].get(), tm.coef, 1.0});
       }
+      local_apply_many(proj, c);
+      c.sync();   // the permuted cores are released at scope end
       // local right-hand side f = [-Rp; (-Rt;) -Rc + LX^ Rd]
       f.reserve(n);
       axpby(p, -1.0, Rhat[RES_P].get(), 0.0, f.get(), c.s);

@@ -157,89 +157,43 @@ void check_local_op(const tt_local_op* K) {
 }
 
 // y = K x for the generic block description (chains of projected operators).
-// The blocks' projected products stage by stage, each stage of all of them in
-// grouped launches (first operators of every block, then the second
-// operators of the chained blocks).  A last-stage launch never holds two
-// products that add into the same block row, and the products of one row keep
-// the block order within each level.
+// The blocks' projected products in grouped stage launches: first operators
+// of every block, then the second operators of the chained blocks; the
+// products of one block row keep the block order within each level.
 void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c) {
   const long p = (long)K->r * K->m * K->rp;
-  const int r = K->r, m = K->m, s = K->rp;
   fill((long)K->L * p, 0.0, y, c.s);
-  struct Prod {
-    const tt_proj_op* o;
-    const double* x;
-    double* y;
-    double alpha, beta;
-    int row;          // output block row, or -1 for a private buffer
-    double *perm, *t1, *t2;
-  };
-  std::vector<Prod> lv[2];
-  int nbuf = 0;
+  // context-owned permuted cores and chain buffers: no allocation is released
+  // while kernels may still use it
+  size_t nb = 0;
   auto buf = [&](size_t n) {
-    if ((int)c.gbuf.size() <= nbuf) c.gbuf.resize(nbuf + 1);
-    c.gbuf[nbuf].reserve(n);
-    return c.gbuf[nbuf++].get();
+    if (c.lbuf.size() <= nb) c.lbuf.resize(nb + 1);
+    c.lbuf[nb].reserve(n);
+    return c.lbuf[nb++].get();
   };
-  auto prod = [&](const tt_proj_op& o, const double* xin, double* yout, double alpha, double beta, int row) {
-    Prod q{&o, xin, yout, alpha, beta, row, nullptr, nullptr, nullptr};
+  auto args = [&](const tt_proj_op& o, const double* xin, double* yout, double alpha, double beta) {
+    double* perm = nullptr;
     if (o.core) {
-      q.perm = buf((size_t)o.R * m * m * o.Rp);
-      permute_op_core(o.core, o.R, m, o.Rp, q.perm, c.s);
-      q.t2 = buf((size_t)r * m * o.Rp * s);
+      perm = buf((size_t)o.R * K->m * K->m * o.Rp);
+      permute_op_core(o.core, o.R, K->m, o.Rp, perm, c.s);
     }
-    q.t1 = buf((size_t)r * o.R * m * s);
-    return q;
+    return LocalApplyArgs{o.phiL, K->r, o.R, K->r, perm, K->m, o.phiR, K->rp, o.Rp, K->rp, xin, yout, alpha, beta};
   };
+  std::vector<LocalApplyArgs> lv0, lv1;
   for (int b = 0; b < K->nblocks; ++b) {
     const tt_local_block& B = K->blocks[b];
     const double* xin = x + (long)B.col * p;
     double* yout = y + (long)B.row * p;
     if (B.nchain == 1) {
-      lv[0].push_back(prod(B.op[0], xin, yout, B.coeff, 1.0, B.row));
+      lv0.push_back(args(B.op[0], xin, yout, B.coeff, 1.0));
     } else {
       double* tb = buf((size_t)p);
-      lv[0].push_back(prod(B.op[0], xin, tb, 1.0, 0.0, -1));
-      lv[1].push_back(prod(B.op[1], tb, yout, B.coeff, 1.0, B.row));
+      lv0.push_back(args(B.op[0], xin, tb, 1.0, 0.0));
+      lv1.push_back(args(B.op[1], tb, yout, B.coeff, 1.0));
     }
   }
-  for (const auto& L : lv) {
-    std::vector<Gemm> g1, g2;
-    for (const Prod& q : L) {
-      const tt_proj_op& o = *q.o;
-      g1.push_back(gemm_nn(r * o.R, m * s, r, o.phiL, r, q.x, (long)m * s, q.t1, (long)m * s));
-      if (!o.core) continue;
-      Gemm g;   // batched over a: t2[a] = O' t1[a]
-      g.M = m * o.Rp; g.N = s; g.K = o.R * m; g.batch = r;
-      g.A = q.perm; g.am = (long)o.R * m; g.ak = 1; g.sA = 0;
-      g.B = q.t1; g.bk = s; g.bn = 1; g.sB = (long)o.R * m * s;
-      g.C = q.t2; g.cm = s; g.cn = 1; g.sC = (long)m * o.Rp * s;
-      g2.push_back(g);
-    }
-    for (size_t i = 0; i < g1.size(); i += 8) gemm_grouped(g1.data() + i, (int)std::min<size_t>(8, g1.size() - i), c.s, &c.ws, c.prec);
-    for (size_t i = 0; i < g2.size(); i += 8) gemm_grouped(g2.data() + i, (int)std::min<size_t>(8, g2.size() - i), c.s, &c.ws, c.prec);
-    // last stage: y = alpha t2 phiR^T + beta y, launches cut where a row repeats
-    std::vector<Gemm> g3;
-    std::vector<int> rows;
-    auto flush = [&]() {
-      if (!g3.empty()) gemm_grouped(g3.data(), (int)g3.size(), c.s, &c.ws, c.prec);
-      g3.clear();
-      rows.clear();
-    };
-    for (const Prod& q : L) {
-      const tt_proj_op& o = *q.o;
-      if (g3.size() == 8 || (q.row >= 0 && std::find(rows.begin(), rows.end(), q.row) != rows.end())) flush();
-      Gemm g;
-      g.M = r * m; g.N = s; g.K = o.Rp * s;
-      g.A = o.core ? q.t2 : q.t1; g.am = (long)o.Rp * s; g.ak = 1;
-      g.B = o.phiR; g.bk = 1; g.bn = (long)o.Rp * s;
-      g.C = q.y; g.cm = s; g.cn = 1;
-      g.alpha = q.alpha; g.beta = q.beta;
-      g3.push_back(g);
-      if (q.row >= 0) rows.push_back(q.row);
-    }
-    flush();
-  }
+  local_apply_many(lv0, c);
+  local_apply_many(lv1, c);
 }
 
 }  // namespace

@@ -519,6 +519,56 @@ void local_apply(const double* phiL, int r, int R, int rc, const double* Operm, 
   }
 }
 
+void local_apply_many(const std::vector<LocalApplyArgs>& v, Ctx& c) {
+  if (v.empty()) return;
+  size_t nb = 0;
+  auto buf = [&](size_t n) {
+    if (c.gbuf.size() <= nb) c.gbuf.resize(nb + 1);
+    c.gbuf[nb].reserve(n);
+    return c.gbuf[nb++].get();
+  };
+  std::vector<Gemm> g1, g2, g3;
+  for (const LocalApplyArgs& a : v) {
+    double* t1 = buf((size_t)a.r * a.R * a.m * a.rd);
+    // stage 1: t1[(a,alpha)][(j,e)] = phiL[(a,alpha)][c] x[c][(j,e)]
+    g1.push_back(gemm_nn(a.r * a.R, a.m * a.rd, a.rc, a.phiL, a.rc, a.x, (long)a.m * a.rd, t1, (long)a.m * a.rd));
+    const double* last = t1;
+    if (a.Operm) {
+      // stage 2 (batched over a): t2[a][(i,beta)][e] = O'[(i,beta)][(alpha,j)] t1[a][(alpha,j)][e]
+      double* t2 = buf((size_t)a.r * a.m * a.Rp * a.rd);
+      Gemm g;
+      g.M = a.m * a.Rp; g.N = a.rd; g.K = a.R * a.m; g.batch = a.r;
+      g.A = a.Operm; g.am = (long)a.R * a.m; g.ak = 1; g.sA = 0;
+      g.B = t1; g.bk = a.rd; g.bn = 1; g.sB = (long)a.R * a.m * a.rd;
+      g.C = t2; g.cm = a.rd; g.cn = 1; g.sC = (long)a.m * a.Rp * a.rd;
+      g2.push_back(g);
+      last = t2;
+    } else {
+      TT_REQUIRE(a.R == 1 && a.Rp == 1, "identity local operator");
+    }
+    // stage 3: y[(a,i)][b] = alpha sum_(beta,e) t2[(a,i)][(beta,e)] phiR[b][(beta,e)] + beta y
+    Gemm g;
+    g.M = a.r * a.m; g.N = a.s; g.K = a.Rp * a.rd;
+    g.A = last; g.am = (long)a.Rp * a.rd; g.ak = 1;
+    g.B = a.phiR; g.bk = 1; g.bn = (long)a.Rp * a.rd;
+    g.C = a.y; g.cm = a.s; g.cn = 1;
+    g.alpha = a.alpha; g.beta = a.beta;
+    g3.push_back(g);
+  }
+  gemm_grouped(g1.data(), (int)g1.size(), c.s, &c.ws, c.prec);
+  gemm_grouped(g2.data(), (int)g2.size(), c.s, &c.ws, c.prec);
+  // last stages in list order, a launch cut wherever an output repeats
+  size_t b = 0;
+  for (size_t e = 0; e <= g3.size(); ++e) {
+    bool cut = e == g3.size();
+    for (size_t q = b; q < e && !cut; ++q) cut = g3[q].C == g3[e].C;
+    if (cut && e > b) {
+      gemm_grouped(g3.data() + b, (int)(e - b), c.s, &c.ws, c.prec);
+      b = e;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // SVD and orthogonalisation
 // ---------------------------------------------------------------------------

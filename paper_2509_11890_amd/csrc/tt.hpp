@@ -42,6 +42,7 @@ struct Ctx {
   DevBuf ired;                // int scratch (status words)
   DevBuf dot_part, dot_out;
   std::vector<DevBuf> gbuf;   // per-product stage buffers of grouped local products
+  std::vector<DevBuf> lbuf;   // callers' operands of grouped local products
   GemmPrec prec = GemmPrec::F64;
   double* hbuf = nullptr;     // pinned host staging
   size_t hbuf_n = 0;
@@ -108,6 +109,21 @@ void env_steps(const std::vector<EnvStepArgs>& steps, bool left, Ctx& c);
 // Operm is O permuted to [i][be][al][j] (permute_op_core), nullptr = identity.
 void local_apply(const double* phiL, int r, int R, int rc, const double* Operm, int m, const double* phiR, int s,
                  int Rp, int rd, const double* x, double* y, double alpha, double beta, Ctx& c);
+// Several local_apply calls with grouped stage launches: the same result as
+// calling local_apply for each element in order (outputs may repeat; the
+// contributions to one output keep the list order).  Operm as local_apply.
+struct LocalApplyArgs {
+  const double* phiL;
+  int r, R, rc;
+  const double* Operm;
+  int m;
+  const double* phiR;
+  int s, Rp, rd;
+  const double* x;
+  double* y;
+  double alpha, beta;
+};
+void local_apply_many(const std::vector<LocalApplyArgs>& v, Ctx& c);
 void permute_op_core(const double* O, int R, int m, int Rp, double* out, hipStream_t s);
 
 // ---- orthogonalisation and rounding --------------------------------------------
