@@ -117,8 +117,9 @@ __global__ __launch_bounds__(DT) void qr_form_q_kernel(const double* A, int m, i
   for (int j = kmax - 1; j >= 0; --j) {
     const double* v = A + (long)j * lda;
     const double tj = tau[j];
+    // columns c < j are still e_c, which H_j leaves unchanged
     if (tj != 0.0) {
-      for (int c = w; c < k; c += NW) {
+      for (int c = j + w; c < k; c += NW) {
         double* qc = Q + (long)c * ldq;
         double d = wave_sum(reflector_dot(v, qc, j, m, lane)) * tj;
         for (int i = j + lane; i < m; i += 64) qc[i] -= d * ((i == j) ? 1.0 : v[i]);
