@@ -59,6 +59,23 @@ __device__ __forceinline__ double reflector_dot(const double* v, const double* x
   return d;
 }
 
+// x -= d v_j over the rows of one lane (v_j[j] = 1 implicit), four rows at a
+// time with their loads issued first.
+__device__ __forceinline__ void reflector_update(const double* v, double* x, int j, int m, int lane, double d) {
+  for (int i0 = j + lane; i0 < m; i0 += 256) {
+    double vs[4], xs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u;
+      vs[u] = i < m ? ((i == j) ? 1.0 : v[i]) : 0.0;
+      xs[u] = i < m ? x[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + 64 * u < m) x[i0 + 64 * u] = xs[u] - d * vs[u];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Householder QR, column-major A (m x n, leading dimension lda), in place.
 // On exit R is in the upper triangle, the reflector vectors v_j (v_j[j] = 1
@@ -97,7 +114,7 @@ __global__ __launch_bounds__(DT) void qr_kernel(double* A, int m, int n, int lda
       for (int c = j + 1 + w; c < n; c += NW) {
         double* cc = A + (long)c * lda;
         double d = wave_sum(reflector_dot(col, cc, j, m, lane)) * tj;
-        for (int i = j + lane; i < m; i += 64) cc[i] -= d * ((i == j) ? 1.0 : col[i]);
+        reflector_update(col, cc, j, m, lane, d);
       }
     }
     __syncthreads();
@@ -122,7 +139,7 @@ __global__ __launch_bounds__(DT) void qr_form_q_kernel(const double* A, int m, i
       for (int c = j + w; c < k; c += NW) {
         double* qc = Q + (long)c * ldq;
         double d = wave_sum(reflector_dot(v, qc, j, m, lane)) * tj;
-        for (int i = j + lane; i < m; i += 64) qc[i] -= d * ((i == j) ? 1.0 : v[i]);
+        reflector_update(v, qc, j, m, lane, d);
       }
     }
     __syncthreads();
