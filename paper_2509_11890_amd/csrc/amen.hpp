@@ -91,8 +91,9 @@ struct AmenInfo {
   double t_env = 0, t_solve = 0, t_svd = 0;
 };
 
-// Solve the Newton system starting from W (block at position 0).  On return
-// the block is back at position 0 (warm start for the next call).
+// Solve the Newton system starting from W, whose block sits at an end core
+// (0 or d-1).  On return the block is at the end core where the last
+// half-sweep left it, which is the warm start of the next call.
 void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInfo& info, Ctx& c);
 
 // Build an initial block TT (block at 0) from a frame TT (e.g. the identity).
