@@ -227,35 +227,48 @@ __global__ void diag_scatter_kernel(const double* D, int r, int m, int s, int L,
 
 // In-place Gauss-Jordan inversion with partial pivoting, one thread per block
 // (n <= 16); W is per-block scratch of n * n doubles.  Singular blocks become I.
-__global__ void block_inverse_kernel(double* blk, double* W, int nblk, int n) {
+// One thread per block, Gauss-Jordan with partial pivoting on the block and
+// the identity beside it.  Both sit in LDS, entry-major and thread-minor
+// (entry e of thread t at e * blockDim.x + t), so that the threads' dependent
+// accesses are LDS round trips, conflict-free, instead of global ones.
+__global__ void block_inverse_kernel(double* blk, int nblk, int n) {
+  extern __shared__ double lds[];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nblk) return;
-  double* A = blk + (long)t * n * n;
-  double* B = W + (long)t * n * n;
-  for (int i = 0; i < n * n; ++i) B[i] = (i / n == i % n) ? 1.0 : 0.0;
+  const int T = blockDim.x, nn = n * n;
+  double* A = lds + threadIdx.x;            // entry e at A[e * T]
+  double* B = lds + (long)nn * T + threadIdx.x;
+  double* G = blk + (long)t * nn;
+  for (int i = 0; i < nn; ++i) {
+    A[i * T] = G[i];
+    B[i * T] = (i / n == i % n) ? 1.0 : 0.0;
+  }
   double amax = 0.0;
-  for (int i = 0; i < n * n; ++i) amax = fmax(amax, fabs(A[i]));
+  for (int i = 0; i < nn; ++i) amax = fmax(amax, fabs(A[i * T]));
   bool ok = amax > 0.0;
   for (int k = 0; k < n && ok; ++k) {
     int p = k;
     for (int i = k + 1; i < n; ++i)
-      if (fabs(A[i * n + k]) > fabs(A[p * n + k])) p = i;
-    if (!(fabs(A[p * n + k]) > 1e-14 * amax)) { ok = false; break; }
+      if (fabs(A[(i * n + k) * T]) > fabs(A[(p * n + k) * T])) p = i;
+    if (!(fabs(A[(p * n + k) * T]) > 1e-14 * amax)) { ok = false; break; }
     if (p != k)
       for (int j = 0; j < n; ++j) {
-        double x = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = x;
-        x = B[k * n + j]; B[k * n + j] = B[p * n + j]; B[p * n + j] = x;
+        double x = A[(k * n + j) * T]; A[(k * n + j) * T] = A[(p * n + j) * T]; A[(p * n + j) * T] = x;
+        x = B[(k * n + j) * T]; B[(k * n + j) * T] = B[(p * n + j) * T]; B[(p * n + j) * T] = x;
       }
-    const double d = 1.0 / A[k * n + k];
-    for (int j = 0; j < n; ++j) { A[k * n + j] *= d; B[k * n + j] *= d; }
+    const double d = 1.0 / A[(k * n + k) * T];
+    for (int j = 0; j < n; ++j) { A[(k * n + j) * T] *= d; B[(k * n + j) * T] *= d; }
     for (int i = 0; i < n; ++i) {
       if (i == k) continue;
-      const double f = A[i * n + k];
+      const double f = A[(i * n + k) * T];
       if (f == 0.0) continue;
-      for (int j = 0; j < n; ++j) { A[i * n + j] -= f * A[k * n + j]; B[i * n + j] -= f * B[k * n + j]; }
+      for (int j = 0; j < n; ++j) {
+        A[(i * n + j) * T] -= f * A[(k * n + j) * T];
+        B[(i * n + j) * T] -= f * B[(k * n + j) * T];
+      }
     }
   }
-  for (int i = 0; i < n * n; ++i) A[i] = ok ? B[i] : ((i / n == i % n) ? 1.0 : 0.0);
+  for (int i = 0; i < nn; ++i) G[i] = ok ? B[i * T] : ((i / n == i % n) ? 1.0 : 0.0);
 }
 
 // y[l][a][i][b] = sum_{l', j} inv[(a,b)][l m + i][l' m + j] x[l'][a][j][b]
@@ -338,8 +351,13 @@ void BlockJacobi::invert(Ctx& c) {
   const int n = L * m;
   TT_REQUIRE(n <= 16, "block-Jacobi blocks are limited to 16 x 16");
   const int nb = r * s;
-  tmp.reserve((size_t)nb * n * n);
-  hipLaunchKernelGGL(block_inverse_kernel, dim3(nblocks(nb, 64)), dim3(64), 0, c.s, blk.get(), tmp.get(), nb, n);
+  // threads per workgroup: up to 64, as many as keep both n x n arrays of every
+  // thread within the 64 KiB of LDS a workgroup gets without opting in
+  int T = 64;
+  while (T > 1 && (size_t)2 * n * n * T * sizeof(double) > 65536) T /= 2;
+  TT_REQUIRE((size_t)2 * n * n * T * sizeof(double) <= 65536, "block-Jacobi block too large");
+  hipLaunchKernelGGL(block_inverse_kernel, dim3(nblocks(nb, T)), dim3(T), (size_t)2 * n * n * T * sizeof(double),
+                     c.s, blk.get(), nb, n);
   TT_HIP(hipGetLastError());
 }
 

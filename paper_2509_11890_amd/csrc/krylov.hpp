@@ -41,7 +41,6 @@ void gmres_solve(long n, const KrylovOps& ops, const double* f, double* u, const
 struct BlockJacobi {
   int r = 0, s = 0, m = 0, L = 0;
   DevBuf blk;   // [(a, b)][L m][L m]: assembled blocks, then their inverses
-  DevBuf tmp, tmp2;
   void init(int r_, int s_, int m_, int L_, Ctx& c);
   void copy_from(const BlockJacobi& o, Ctx& c);
   // blocks[row][col] += coeff * D, D the diagonal block of the chain (applied first to last)
