@@ -697,31 +697,42 @@ __global__ void stack_dz_kernel(double* dz, const double* tmp, const double* rd,
 // ---------------------------------------------------------------------------
 // dense projected operator (for the direct solve and the public ABI)
 // ---------------------------------------------------------------------------
+void local_dense_ops(const std::vector<DenseOpArgs>& v, Ctx& c) {
+  std::vector<DevBuf> T1(v.size()), T2(v.size());
+  std::vector<Gemm> g1, g2;
+  for (size_t q = 0; q < v.size(); ++q) {
+    const DenseOpArgs& a = v[q];
+    // T1[a][c][(i,j,beta)] = sum_alpha phiL[a][alpha][c] O[alpha][(i,j,beta)]
+    const long w = (long)a.m * a.m * a.Rp;
+    T1[q].reserve((size_t)a.r * a.r * w);
+    T2[q].reserve((size_t)a.r * a.r * a.m * a.m * a.s * a.s);
+    Gemm g;
+    g.M = a.r; g.N = (int)w; g.K = a.R; g.batch = a.r;
+    g.A = a.phiL; g.am = 1; g.ak = a.r; g.sA = (long)a.R * a.r;
+    g.B = a.O; g.bk = w; g.bn = 1; g.sB = 0;
+    g.C = T1[q].get(); g.cm = w; g.cn = 1; g.sC = (long)a.r * w;
+    g1.push_back(g);
+    // T2[(a,c,i,j)][b][e] = sum_beta T1[(a,c,i,j)][beta] phiR[b][beta][e]
+    Gemm h;
+    h.M = a.r * a.r * a.m * a.m; h.N = a.s; h.K = a.Rp; h.batch = a.s;
+    h.A = T1[q].get(); h.am = a.Rp; h.ak = 1; h.sA = 0;
+    h.B = a.phiR; h.bk = a.s; h.bn = 1; h.sB = (long)a.Rp * a.s;
+    h.C = T2[q].get(); h.cm = (long)a.s * a.s; h.cn = 1; h.sC = a.s;
+    g2.push_back(h);
+  }
+  gemm_grouped(g1.data(), (int)g1.size(), c.s, &c.ws, GemmPrec::F64);
+  gemm_grouped(g2.data(), (int)g2.size(), c.s, &c.ws, GemmPrec::F64);
+  // [a][c][i][j][b][e] -> [a][i][b][c][j][e]
+  for (size_t q = 0; q < v.size(); ++q) {
+    const DenseOpArgs& a = v[q];
+    permute(T2[q].get(), a.out, {a.r, a.r, a.m, a.m, a.s, a.s}, {0, 2, 4, 1, 3, 5}, c.s);
+  }
+  c.sync();   // the stage buffers are released at scope end
+}
+
 void local_dense_op(const double* phiL, int r, int R, const double* O, int m, const double* phiR, int s, int Rp,
                     double* out, Ctx& c) {
-  // T1[a][c][(i,j,beta)] = sum_alpha phiL[a][alpha][c] O[alpha][(i,j,beta)]
-  const long w = (long)m * m * Rp;
-  DevBuf T1((size_t)r * r * w), T2((size_t)r * r * m * m * s * s);
-  {
-    Gemm g;
-    g.M = r; g.N = (int)w; g.K = R; g.batch = r;
-    g.A = phiL; g.am = 1; g.ak = r; g.sA = (long)R * r;
-    g.B = O; g.bk = w; g.bn = 1; g.sB = 0;
-    g.C = T1.get(); g.cm = w; g.cn = 1; g.sC = (long)r * w;
-    gemm(g, c.s, &c.ws, GemmPrec::F64);
-  }
-  // T2[(a,c,i,j)][b][e] = sum_beta T1[(a,c,i,j)][beta] phiR[b][beta][e]
-  {
-    Gemm g;
-    g.M = r * r * m * m; g.N = s; g.K = Rp; g.batch = s;
-    g.A = T1.get(); g.am = Rp; g.ak = 1; g.sA = 0;
-    g.B = phiR; g.bk = s; g.bn = 1; g.sB = (long)Rp * s;
-    g.C = T2.get(); g.cm = (long)s * s; g.cn = 1; g.sC = s;
-    gemm(g, c.s, &c.ws, GemmPrec::F64);
-  }
-  // [a][c][i][j][b][e] -> [a][i][b][c][j][e]
-  permute(T2.get(), out, {r, r, m, m, s, s}, {0, 2, 4, 1, 3, 5}, c.s);
-  c.sync();
+  local_dense_ops({{phiL, r, R, O, m, phiR, s, Rp, out}}, c);
 }
 
 TT BlockTT::component(int l, Ctx& c) const {

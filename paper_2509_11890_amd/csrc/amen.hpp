@@ -103,5 +103,16 @@ BlockTT block_from_frame(const TT& frame, int Lp, Ctx& c);
 // Dense projected operator [(a,i,b)][(c,j,e)] (p x p) from environments.
 void local_dense_op(const double* phiL, int r, int R, const double* O, int m, const double* phiR, int s, int Rp,
                     double* out, Ctx& c);
+// Several dense projected operators at once (grouped GEMM launches, one sync).
+struct DenseOpArgs {
+  const double* phiL;
+  int r, R;
+  const double* O;
+  int m;
+  const double* phiR;
+  int s, Rp;
+  double* out;
+};
+void local_dense_ops(const std::vector<DenseOpArgs>& v, Ctx& c);
 
 }  // namespace ttipm

@@ -343,8 +343,9 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
         merge_pair(dM, k, D2, c);
         Ml.reserve((size_t)p * p);
         Dl.reserve((size_t)p * p);
-        local_dense_op(ML[k].get(), r, M.r[k], M2.get(), 4, MR[k + 1].get(), s, M.r[k + 2], Ml.get(), c);
-        local_dense_op(DL[k].get(), r, dM.r[k], D2.get(), 4, DR[k + 1].get(), s, dM.r[k + 2], Dl.get(), c);
+        local_dense_ops({{ML[k].get(), r, M.r[k], M2.get(), 4, MR[k + 1].get(), s, M.r[k + 2], Ml.get()},
+                         {DL[k].get(), r, dM.r[k], D2.get(), 4, DR[k + 1].get(), s, dM.r[k + 2], Dl.get()}},
+                        c);
         e.reserve(p);
         // warm start: the current E on this pair's frame (the non-orthogonal
         // core carries the singular values of the last split)
