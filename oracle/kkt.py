@@ -18,10 +18,21 @@ correlation-clustering formulation (Sec. 4.3), and the residuals
 AHO: L_Z = I x Z + Z x I, L_X = I x X + X x I; XZ: L_Z = Z x I, L_X = I x X
 (per-core Kronecker products, Def. "Kronecker product of TT matrices", so that
 (A x B) vec_TT(M) = vec_TT(A M B^T)).  The dense solve is by LU.
+
+Also here, for a frame matrix W (N x p, orthonormal columns):
+  * reduced_system: the projected system of eq. (reduced_kkt_system), dZ
+    eliminated before the solve, with the chained products
+    (W^T L_X W)(W^T Aeq^T W) kept as products of projections;
+  * block_elimination: the solve of that system by the Cholesky factor of
+    W^T L_Z W, the LU of Phi and of the Schur complement S, and the
+    triangular solves in the order dY -> dT -> dX of Sec. 3.3;
+  * dz_local: the elimination formula for dZ_k of Sec. 3.3.
+With W = I the reduced system is the full system with dZ substituted.
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg as sla
 
 from . import tt
 
@@ -79,38 +90,134 @@ def residuals_dense(prob, X, Y, Z, T, mu, direction, sigma_mu=None):
     return Rd, Rp, Rt, Rc
 
 
+def system_blocks(prob, X, Y, Z, T, mu, direction, Rc_override=None, sigma_mu=None, Rt_override=None):
+    """Dense operator blocks and residuals of eq. (tt-kkt-newton-system).
+
+    Returns a dict with Aeq, AeqT, KY, LZ, LX (N x N), the residuals Rd, Rp,
+    Rc (and Rt), and for inequalities Ai, AiT, TA (= diag_TT(vec T) Aineq),
+    DK (= D_ineq(X) + K_T) and the sense s."""
+    f = tt.full
+    B = dict(ineq="Aineq" in prob)
+    B["Aeq"], B["AeqT"] = tt.full_mat(prob["Aeq"]), tt.full_mat(prob["AeqT"])
+    B["KY"] = tt.full_mat(prob["KY"])
+    LZ, LX = L_ops(X, Z, direction)
+    B["LZ"], B["LX"] = tt.full_mat(LZ), tt.full_mat(LX)
+    Rd, Rp, Rt, Rc = residuals_dense(prob, X, Y, Z, T, mu, direction, sigma_mu)
+    B["Rd"], B["Rp"] = Rd, Rp
+    B["Rc"] = Rc if Rc_override is None else Rc_override
+    if B["ineq"]:
+        s = prob["sense"]
+        B["s"] = s
+        B["Ai"], B["AiT"] = tt.full_mat(prob["Aineq"]), tt.full_mat(prob["AineqT"])
+        B["TA"] = np.diag(f(T)) @ B["Ai"]
+        slack = s * (f(prob["Bineq"]) - B["Ai"] @ f(X))
+        B["DK"] = np.diag(slack) + tt.full_mat(prob["KT"])
+        B["Rt"] = Rt if Rt_override is None else Rt_override
+    return B
+
+
+def assemble(B):
+    """The unreduced block matrix K and right-hand side -R (unknowns dX, dY, [dT,] dZ)."""
+    N = B["Aeq"].shape[0]
+    I = np.eye(N)
+    O = np.zeros((N, N))
+    if not B["ineq"]:
+        K = np.block([[O, -B["AeqT"], I], [-B["Aeq"], B["KY"], O], [B["LZ"], O, B["LX"]]])
+        R = np.concatenate([B["Rd"], B["Rp"], B["Rc"]])
+        return K, -R
+    s = B["s"]
+    K = np.block([[O, -B["AeqT"], -s * B["AiT"], I],
+                  [-B["Aeq"], B["KY"], O, O],
+                  [-s * B["TA"], O, B["DK"], O],
+                  [B["LZ"], O, O, B["LX"]]])
+    R = np.concatenate([B["Rd"], B["Rp"], B["Rt"], B["Rc"]])
+    return K, -R
+
+
 def newton_dense(prob, X, Y, Z, T, mu, direction, Rc_override=None, sigma_mu=None, Rt_override=None):
     """Solve the dense block Newton system; returns dense (dX, dY, dT, dZ)."""
-    f = tt.full
-    N2 = 4 ** prob["d"]
-    Aeq, AeqT = tt.full_mat(prob["Aeq"]), tt.full_mat(prob["AeqT"])
-    KY = tt.full_mat(prob["KY"])
-    LZ, LX = L_ops(X, Z, direction)
-    LZd, LXd = tt.full_mat(LZ), tt.full_mat(LX)
-    Rd, Rp, Rt, Rc = residuals_dense(prob, X, Y, Z, T, mu, direction, sigma_mu)
-    if Rc_override is not None:
-        Rc = Rc_override
-    if Rt_override is not None:
-        Rt = Rt_override
-    I = np.eye(N2)
-    O = np.zeros((N2, N2))
-    if "Aineq" not in prob:
-        K = np.block([[O, -AeqT, I], [-Aeq, KY, O], [LZd, O, LXd]])
-        rhs = -np.concatenate([Rd, Rp, Rc])
-        sol = np.linalg.solve(K, rhs)
+    B = system_blocks(prob, X, Y, Z, T, mu, direction, Rc_override, sigma_mu, Rt_override)
+    K, rhs = assemble(B)
+    sol = np.linalg.solve(K, rhs)
+    if not B["ineq"]:
         dX, dY, dZ = np.split(sol, 3)
         return dX, dY, None, dZ
-    s = prob["sense"]
-    Ai, AiT, KT = tt.full_mat(prob["Aineq"]), tt.full_mat(prob["AineqT"]), tt.full_mat(prob["KT"])
-    t = f(T)
-    slack = s * (f(prob["Bineq"]) - Ai @ f(X))
-    TA = np.diag(t) @ Ai
-    D = np.diag(slack)
-    K = np.block([[O, -AeqT, -s * AiT, I],
-                  [-Aeq, KY, O, O],
-                  [-s * TA, O, D + KT, O],
-                  [LZd, O, O, LXd]])
-    rhs = -np.concatenate([Rd, Rp, Rt, Rc])
-    sol = np.linalg.solve(K, rhs)
     dX, dY, dT, dZ = np.split(sol, 4)
+    return dX, dY, dT, dZ
+
+
+def _proj(W, A):
+    return W.T @ A @ W
+
+
+def reduced_system(B, W):
+    """Eq. (reduced_kkt_system) for the frame W: matrix and right-hand side in
+    the unknowns (dX_k, dY_k[, dT_k]); dZ_k has been eliminated."""
+    Ah, ATh, KYh = _proj(W, B["Aeq"]), _proj(W, B["AeqT"]), _proj(W, B["KY"])
+    LZh, LXh = _proj(W, B["LZ"]), _proj(W, B["LX"])
+    Rdh, Rph, Rch = W.T @ B["Rd"], W.T @ B["Rp"], W.T @ B["Rc"]
+    p = W.shape[1]
+    O = np.zeros((p, p))
+    if not B["ineq"]:
+        K = np.block([[-Ah, KYh], [LZh, LXh @ ATh]])
+        rhs = -np.concatenate([Rph, Rch - LXh @ Rdh])
+        return K, rhs
+    s = B["s"]
+    TAh, DKh, AiTh = _proj(W, B["TA"]), _proj(W, B["DK"]), _proj(W, B["AiT"])
+    Rth = W.T @ B["Rt"]
+    # the inequality blocks carry the sense s of the >= convention exactly as
+    # in the unreduced system (-s T Aineq in row t, -s Aineq^T in row d)
+    K = np.block([[-Ah, KYh, O], [-s * TAh, O, DKh], [LZh, LXh @ ATh, s * (LXh @ AiTh)]])
+    rhs = -np.concatenate([Rph, Rth, Rch - LXh @ Rdh])
+    return K, rhs
+
+
+def dz_local(B, W, dY, dT=None):
+    """dZ_k = W^T Aeq^T W dY_k (+ s W^T Aineq^T W dT_k) - W^T R_d (Sec. 3.3)."""
+    dz = _proj(W, B["AeqT"]) @ dY - W.T @ B["Rd"]
+    if B["ineq"]:
+        dz = dz + B["s"] * (_proj(W, B["AiT"]) @ dT)
+    return dz
+
+
+def block_elimination(B, W):
+    """Sec. 3.3 block elimination on the frame W: Cholesky of L_Z^, LU of Phi
+    and of the Schur complement S, then dY, dT, dX by triangular solves.
+    Returns (dX_k, dY_k, dT_k or None, dZ_k)."""
+    Ah, ATh, KYh = _proj(W, B["Aeq"]), _proj(W, B["AeqT"]), _proj(W, B["KY"])
+    LZh, LXh = _proj(W, B["LZ"]), _proj(W, B["LX"])
+    Rdh, Rph, Rch = W.T @ B["Rd"], W.T @ B["Rp"], W.T @ B["Rc"]
+    cz = sla.cho_factor(0.5 * (LZh + LZh.T), lower=True)
+    LZinv = lambda M: sla.cho_solve(cz, M)
+    # g = L_Z^{-1} (L_X^ R_d^ - R_c^)
+    g = LZinv(LXh @ Rdh - Rch)
+    if not B["ineq"]:
+        S = Ah @ LZinv(LXh @ ATh) + KYh
+        dY = sla.lu_solve(sla.lu_factor(S), Ah @ g - Rph)
+        dT = None
+        dZ = dz_local(B, W, dY)
+    else:
+        s = B["s"]
+        TAh, DKh, AiTh = _proj(W, B["TA"]), _proj(W, B["DK"]), _proj(W, B["AiT"])
+        Rth = W.T @ B["Rt"]
+        # With the sense s the t row reads -s TA^ dX + DK^ dT = -R_t^ and the
+        # chained block is s L_X^ Aineq^T^; eliminating dX = -L_Z^{-1}(L_X^ Aeq^T^ dY
+        # + s L_X^ Aineq^T^ dT) + g gives
+        #   Phi dT = s TA^ (g - L_Z^{-1} L_X^ Aeq^T^ dY) - R_t^,
+        #   Phi    = DK^ + s^2 TA^ L_Z^{-1} L_X^ Aineq^T^,
+        # and for dY the Schur complement of Phi in the (y, t) system.
+        G_y = LZinv(LXh @ ATh)
+        G_t = LZinv(LXh @ AiTh)
+        Phi = DKh + (s * s) * TAh @ G_t
+        luP = sla.lu_factor(Phi)
+        Pinv = lambda M: sla.lu_solve(luP, M)
+        # y row: -A^ dX + KY^ dY = -R_p^ with dX as above:
+        #   (A^ G_y + KY^) dY + s A^ G_t dT = A^ g - R_p^
+        # t row: Phi dT + s TA^ G_y dY = s TA^ g - R_t^
+        S = Ah @ G_y + KYh - (s * s) * Ah @ G_t @ Pinv(TAh @ G_y)
+        rhs_y = Ah @ g - Rph - s * Ah @ G_t @ Pinv(s * TAh @ g - Rth)
+        dY = sla.lu_solve(sla.lu_factor(S), rhs_y)
+        dT = Pinv(s * TAh @ (g - G_y @ dY) - Rth)
+        dZ = dz_local(B, W, dY, dT)
+    dX = -LZinv(Rch + LXh @ dZ)
     return dX, dY, dT, dZ
