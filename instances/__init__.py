@@ -31,6 +31,7 @@ import numpy as np
 __all__ = [
     "Graph", "grid_4x8", "kron_sum_products", "hypercube", "signed_kron",
     "kron_sum_noise", "complete", "odd_cycle_plus_isolated", "c5_plus_3k1",
+    "binary_tt_adjacency", "tt_matrix_ranks",
     "config", "CONFIG_NAMES",
 ]
 
@@ -331,6 +332,133 @@ def c5_plus_3k1() -> Graph:
     for u, v in edges:
         dense[u, v] = dense[v, u] = 1.0
     return Graph("c5_plus_3k1", d, cores, dense, {"theta": 3.0 + np.sqrt(5.0)})
+
+
+def tt_matrix_ranks(cores, rtol=1e-10):
+    """TT ranks of a TT matrix after compression (right-to-left QR, then
+    left-to-right SVD keeping singular values above rtol times the largest)."""
+    G = [np.asarray(c, dtype=np.float64) for c in cores]
+    d = len(G)
+    for k in range(d - 1, 0, -1):
+        R0, m1, m2, R1 = G[k].shape
+        Q, Rt = np.linalg.qr(G[k].reshape(R0, -1).T)
+        G[k] = Q.T.reshape(-1, m1, m2, R1)
+        G[k - 1] = np.tensordot(G[k - 1], Rt.T, axes=(3, 0))
+    ranks = [1]
+    for k in range(d - 1):
+        R0, m1, m2, R1 = G[k].shape
+        U, sv, Vt = np.linalg.svd(G[k].reshape(R0 * m1 * m2, R1), full_matrices=False)
+        keep = max(1, int(np.sum(sv > rtol * sv[0]))) if sv.size and sv[0] > 0 else 1
+        G[k] = U[:, :keep].reshape(R0, m1, m2, keep)
+        G[k + 1] = np.tensordot(sv[:keep, None] * Vt[:keep], G[k + 1], axes=(1, 0))
+        ranks.append(keep)
+    return ranks + [1]
+
+
+def binary_tt_adjacency(d, r, seed=0, bias=0.0, max_tries=500) -> Graph:
+    """Random simple graph (symmetric 0/1 adjacency, zero diagonal) of TT rank r
+    on 2^d vertices, by the construction of the paper's App. A ("Sampling
+    Binary TT Matrices", "Sampling Adjacency TT Matrices without
+    Self-Connections").
+
+    An orthonormal basis q_0..q_{r-1} (rows of Q, QR of a Gaussian matrix)
+    carries a path state through the cores.  The first core puts basis row
+    q_i(alpha, beta) on mode pair (alpha, beta); each middle core applies, per
+    mode pair, P = I + sum_i q_i (q_sigma(i) - q_i)^T, which sends q_i to
+    q_sigma(i) (sigma a random map of the basis indices); the last core reads
+    the state against q_j(alpha, beta), giving 1 for the same basis vector and
+    0 for an orthogonal one.  Entries are therefore 0/1 and the TT rank is at
+    most r.  Symmetry: the (alpha, beta) and (beta, alpha) slices of every
+    core are equal.  Zero diagonal: the diagonal slice of the second core
+    drops the states that all-diagonal prefixes can reach (the term
+    - sum_{i in D} q_i q_i^T of the paper), so every diagonal entry is 0 (for
+    d = 2 the last core avoids those states instead).  The indices i, sigma(i),
+    j are drawn with weights exp(-bias * index) (bias = 0: uniform; a larger
+    bias gives fewer orthogonal combinations and denser graphs).  Samples are
+    rejected until the TT rank is exactly r and the graph has an edge.
+
+    Reading: the paper does not state the pair distribution, the number of
+    pairs or the rejection details; sigma is a full random map here, so
+    instances match the paper's in distribution type, not sample by sample."""
+    if d < 2 or r < 1:
+        raise ValueError("need d >= 2 and r >= 1")
+    rng = np.random.default_rng(seed)
+    pairs = [(0, 0), (0, 1), (1, 1)]
+    for _ in range(max_tries):
+        Q, _ = np.linalg.qr(rng.standard_normal((r, r)))
+        w = np.exp(-bias * np.arange(r))
+        w /= w.sum()
+        first = {}
+        for a, b in pairs:
+            first[(a, b)] = first[(b, a)] = int(rng.choice(r, p=w))
+        diag_states = {first[(0, 0)], first[(1, 1)]}
+        maps = []
+        for _k in range(1, d - 1):
+            m = {}
+            for a, b in pairs:
+                sigma = rng.choice(r, size=r, p=w).astype(np.int64)
+                if a == b:
+                    for i in diag_states:
+                        sigma[i] = -1          # cancelled: all-diagonal prefixes end here
+                m[(a, b)] = m[(b, a)] = sigma
+            maps.append(m)
+            diag_states = set()
+        last = {}
+        for a, b in pairs:
+            choices = [j for j in range(r) if a != b or j not in diag_states]
+            if not choices:
+                last[(a, b)] = last[(b, a)] = -1
+                continue
+            ww = w[choices] / w[choices].sum()
+            last[(a, b)] = last[(b, a)] = int(choices[int(rng.choice(len(choices), p=ww))])
+        # TT cores
+        cores = []
+        G = np.zeros((1, 2, 2, r))
+        for (a, b), i in first.items():
+            G[0, a, b, :] = Q[i]
+        cores.append(G)
+        for m in maps:
+            G = np.zeros((r, 2, 2, r))
+            for (a, b), sigma in m.items():
+                for i in range(r):
+                    if sigma[i] >= 0:
+                        G[:, a, b, :] += np.outer(Q[i], Q[sigma[i]])
+            cores.append(G)
+        G = np.zeros((r, 2, 2, 1))
+        for (a, b), j in last.items():
+            if j >= 0:
+                G[:, a, b, 0] = Q[j]
+        cores.append(G)
+        # dense adjacency by following the path states (independent of the TT contraction)
+        dense = None
+        if d <= 12:
+            n = 2 ** d
+            u = np.arange(n)[:, None] + np.zeros((1, n), dtype=np.int64)
+            v = np.arange(n)[None, :] + np.zeros((n, 1), dtype=np.int64)
+            bit = lambda x, k: (x >> (d - 1 - k)) & 1
+            ua, vb = bit(u, 0), bit(v, 0)
+            state = np.zeros((n, n), dtype=np.int64)
+            for (a, b), i in first.items():
+                state[(ua == a) & (vb == b)] = i
+            for k, m in enumerate(maps, start=1):
+                ua, vb = bit(u, k), bit(v, k)
+                new = np.full((n, n), -1, dtype=np.int64)
+                for (a, b), sigma in m.items():
+                    sel = (ua == a) & (vb == b) & (state >= 0)
+                    new[sel] = sigma[state[sel]]
+                state = new
+            ua, vb = bit(u, d - 1), bit(v, d - 1)
+            dense = np.zeros((n, n))
+            for (a, b), j in last.items():
+                sel = (ua == a) & (vb == b) & (state >= 0) & (state == j)
+                dense[sel] = 1.0
+            if dense.sum() == 0:
+                continue
+        if max(tt_matrix_ranks(cores)) != r:
+            continue
+        return Graph(f"binary_tt_d{d}_r{r}_s{seed}", d, cores, dense,
+                     {"seed": seed, "tt_rank": r, "bias": bias})
+    raise RuntimeError(f"no graph of TT rank {r} on 2^{d} vertices after {max_tries} draws")
 
 
 # ----------------------------------------------------------------------------
