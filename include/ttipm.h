@@ -333,6 +333,17 @@ typedef struct {
                            solve ends at the rank cap above its residual target, or admits a
                            step below 1e-3 (Sec. 3.5); not with inequalities (0)            */
   int32_t eig_kick;     /* random kick ranks per core split of the step-length DMRG (2)   */
+  int32_t g4_window;    /* M of the windowed residual control (Sec. 3.3, (G4)): once the XZ
+                           warm-up is over, an update whose residual measure
+                           Psi = ||R_p|| + ||R_d|| + mu exceeds the largest Psi of the last
+                           M + 1 iterates by more than the rounding budget is damped (both
+                           step lengths halved) and retried; 0 = off (4)                 */
+  int32_t g4_retries;   /* damped retries of the windowed control per iteration (3); after
+                           the last one the trial with the smallest Psi is taken          */
+  int32_t shift_mode;   /* Cor. 1 shift of the rounded X, Z, T: 1 = the whole rounding error
+                           zeta (keeps positive definiteness also when iter_rank_cap forces
+                           a larger truncation than the tolerance; default), 0 = only the
+                           part within the tolerance budget                               */
 } ttipm_params;
 
 TTIPM_API void ttipm_params_default(ttipm_params* p);
@@ -353,6 +364,13 @@ typedef struct {
   int32_t mlp_used, mlp_fallbacks;  /* local solves with the MLP preconditioner kept / replaced by
                                        block Jacobi under the fallback rule */
   int32_t xz_fallback;              /* 1 when this iteration fell back from AHO to XZ */
+  int32_t g4_retries;               /* damped retries of the windowed residual control */
+  double psi;                       /* residual measure ||R_p|| + ||R_d|| + mu of the accepted update
+                                       (of the entry iterate when the control is off) */
+  double zeta_x, zeta_x_cap;        /* rounding error ||X - X~||_F of the accepted update and its
+                                       part forced by iter_rank_cap (only the rest, within the
+                                       tolerance budget, is added as the Cor. 1 shift) */
+  double zeta_z, zeta_z_cap;        /* the same for Z */
   double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration */
 } ttipm_step_info;
 

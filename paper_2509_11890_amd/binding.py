@@ -88,7 +88,8 @@ class ttipm_params(C.Structure):
                 ("precond", C.c_int32), ("mlp", C.c_void_p), ("eig_rank", C.c_int32),
                 ("eig_sweeps", C.c_int32), ("verbose", C.c_int32), ("kick", C.c_int32), ("seed", C.c_int32),
                 ("kick_sweeps", C.c_int32), ("collect_probes", C.c_int32), ("collect_cap", C.c_int64),
-                ("xz_fallback", C.c_int32), ("eig_kick", C.c_int32)]
+                ("xz_fallback", C.c_int32), ("eig_kick", C.c_int32), ("g4_window", C.c_int32),
+                ("g4_retries", C.c_int32), ("shift_mode", C.c_int32)]
 
 
 class ttipm_step_info(C.Structure):
@@ -98,7 +99,8 @@ class ttipm_step_info(C.Structure):
                                           "alpha_p", "alpha_d", "sigma", "eta", "alpha_p_max",
                                           "alpha_d_max")] + \
                [("backtracks", C.c_int32), ("mlp_used", C.c_int32), ("mlp_fallbacks", C.c_int32),
-                ("xz_fallback", C.c_int32)] + \
+                ("xz_fallback", C.c_int32), ("g4_retries", C.c_int32)] + \
+               [(n, C.c_double) for n in ("psi", "zeta_x", "zeta_x_cap", "zeta_z", "zeta_z_cap")] + \
                [(n, C.c_double) for n in ("t_env", "t_solve", "t_svd", "t_step", "t_round", "t_total")]
 
     def as_dict(self):

@@ -376,6 +376,9 @@ void ttipm_params_default(ttipm_params* p) {
   p->collect_cap = 1 << 20;
   p->xz_fallback = 0;
   p->eig_kick = 2;
+  p->g4_window = 4;
+  p->g4_retries = 3;
+  p->shift_mode = 1;
 }
 
 int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {
@@ -481,10 +484,11 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
       if (prm->verbose)
         std::fprintf(stderr,
                      "it %2d %s mu %.2e pobj %+.10e dobj %+.10e gap %.2e ep %.1e ed %.1e ap %.3e/%.3e ad %.3e/%.3e "
-                     "bt %d rX %d rY %d rZ %d rW %d sw %d/%d kr %d sig %.2e eta %.1e t %.3fs\n",
+                     "bt %d g4 %d psi %.2e zx %.1e/%.1e zz %.1e/%.1e rX %d rY %d rZ %d rW %d sw %d/%d kr %d sig %.2e "
+                     "eta %.1e t %.3fs\n",
                      inf.iter, inf.direction ? "aho" : (inf.xz_fallback ? "xz*" : "xz "), inf.mu, inf.pobj, inf.dobj, inf.rel_gap, inf.eps_p,
                      inf.eps_d, inf.alpha_p, inf.alpha_p_max, inf.alpha_d, inf.alpha_d_max, inf.backtracks,
-                     inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w, inf.sweeps_pred, inf.sweeps_corr,
+                     inf.g4_retries, inf.psi, inf.zeta_x, inf.zeta_x_cap, inf.zeta_z, inf.zeta_z_cap, inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w, inf.sweeps_pred, inf.sweeps_corr,
                      inf.krylov_iters, inf.sigma, inf.eta, inf.t_total);
       if (!std::isfinite(inf.pobj)) throw Error(TT_ERR_NUMERIC, "non-finite objective");
     }

@@ -49,17 +49,36 @@ __global__ void symmetrize_kernel(double* A, int n) {
   A[(long)j * n + i] = v;
 }
 
-// Rounding with the spectral shift of Cor. 1: round at tol / (1 + ||S||_F),
+// Rounding with the spectral shift of Cor. 1: round at tol / (1 + ||S||_F) and
 // add zeta S; keep the unrounded tensor if the rank does not drop (and is
-// within the cap).
-TT round_shift(TT v, double tol, const TT* shift, int cap, Ctx& c, double* zeta_out) {
+// within the cap).  Cor. 1 budgets the error the tolerance allows
+// (zeta <= tol / (1 + ||S||_F)); a binding rank cap discards more.  The
+// eigenvalue bound of Cor. 1 (Weyl) holds for any zeta, so with shift_all the
+// whole zeta is added and positive definiteness is kept; its cap-forced part
+// then moves every affine residual by up to zeta_cap ||A S|| (for MaxCut every
+// diagonal entry of X), which the windowed residual control of the update
+// watches.  Without shift_all only the tolerance part is added.
+struct ShiftInfo {
+  double zeta = 0.0;      // ||M - M~||_F of the rounding (0 if the tensor was kept)
+  double zeta_tol = 0.0;  // the part within the tolerance budget
+};
+
+TT round_shift(TT v, double tol, const TT* shift, int cap, Ctx& c, ShiftInfo* si, bool shift_all = true) {
   const double nS = shift ? tt_norm(*shift, c) : 0.0;
   const int r0 = v.max_rank();
   TT vt = tt_clone(v, c);
-  const double zeta = tt_round_abs(vt, tol / (1.0 + nS), cap, c);
-  if (zeta_out) *zeta_out = zeta;
-  if (vt.max_rank() >= r0 && r0 <= cap) return v;
-  if (shift && zeta > 0) return tt_add({&vt, shift}, {1.0, zeta}, c);
+  double zeta_tol = 0.0;
+  const double zeta = tt_round_abs(vt, tol / (1.0 + nS), cap, c, nullptr, &zeta_tol);
+  if (vt.max_rank() >= r0 && r0 <= cap) {
+    if (si) *si = ShiftInfo{};
+    return v;
+  }
+  if (si) {
+    si->zeta = zeta;
+    si->zeta_tol = zeta_tol;
+  }
+  const double z = shift_all ? zeta : zeta_tol;
+  if (shift && z > 0) return tt_add({&vt, shift}, {1.0, z}, c);
   return vt;
 }
 
@@ -541,6 +560,26 @@ void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& 
   info.rank_z = S.Z.max_rank();
 }
 
+// Psi = ||R_p|| + ||R_d|| + mu of an iterate (the residual measure watched by the
+// windowed control).  Reading: the complementarity block of R_mu enters through
+// mu; its exact norm needs the rank-product TT X Z, which is never formed.
+double residual_measure(const Problem& P, const TT& X, const TT& Y, const TT& Z, const TT* T, Ctx& c) {
+  TT AY = tt_matvec(P.AeqT, Y, c);
+  TT Rd = tt_add({&Z, &P.C, &AY}, {1.0, 1.0, -1.0}, c);
+  if (P.ineq) {
+    TT AT = tt_matvec(P.AineqT, *T, c);
+    Rd = tt_add({&Rd, &AT}, {1.0, -P.sense}, c);
+  }
+  TT AX = tt_matvec(P.Aeq, X, c);
+  TT Rp = tt_add({&P.Beq, &AX}, {1.0, -1.0}, c);
+  double xz = tt_dot(X, Z, c);
+  if (P.ineq) {
+    TT sx = ineq_slack(P, X, false, c);
+    xz += tt_dot(*T, sx, c);
+  }
+  return tt_norm(Rp, c) + tt_norm(Rd, c) + xz / (P.n + P.q);
+}
+
 namespace {
 
 // L_Z = I kron Z + Z kron I (AHO) or Z kron I (XZ); L_X = I kron X + X kron I
@@ -756,6 +795,12 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   // from above, so the step can overshoot; the updated X and Z are checked
   // with a DMRG estimate of lambda_min against the identity, and a step whose
   // estimate is not positive is halved and retried.
+  //
+  // Windowed residual control (Sec. 3.3, condition (G4) of the safeguarded
+  // TT-IPM theorem): the residual measure Psi of the rounded, shifted update is
+  // compared with the largest Psi of the last M + 1 accepted iterates; a step
+  // that exceeds it by more than the rounding budget of the update is damped
+  // (both step lengths halved) and retried.
   t1 = now();
   const int cap = prm.iter_rank_cap > 0 ? prm.iter_rank_cap : 4 * prm.rank_cap;
   {
@@ -763,53 +808,108 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
       return min_gen_eig(P.Ivec, M, E, have, std::max(1, prm.eig_rank), std::max(1, prm.eig_sweeps),
                          std::max(0, prm.eig_kick), sd + 11, cx);
     };
+    const int M = std::max(0, prm.g4_window);
+    const double psi_k = info.eps_p * (1.0 + P.normB) + info.eps_d * (1.0 + P.normC) + mu;
+    S.psi_hist.push_back(psi_k);
+    while ((int)S.psi_hist.size() > M + 1) S.psi_hist.erase(S.psi_hist.begin());
+    const double theta = *std::max_element(S.psi_hist.begin(), S.psi_hist.end());
+    // reading: the control applies once the XZ warm-up is over and the window
+    // is full ("for all sufficiently large k" in (G4)); the allowed perturbation
+    // is the Cor. 1 budget of the X and Z roundings
+    const bool g4_on = M > 0 && S.iter >= prm.n_xz && (int)S.psi_hist.size() == M + 1;
+    const double rho = tolp + told;
+    struct Trial {
+      TT X, Y, Z, T;
+      double a_p = 0, a_d = 0, psi = 0;
+      ShiftInfo sx, sz;
+      int bt = 0;
+    };
     // X + a_p dX and Z + a_d dZ: rounding, shift and safeguard, one stream each
     // (the dual step a_d is final once the Z branch ends, so Y follows it)
-    TT Xn, Zn;
-    int bt_p = 0, bt_d = 0;
-    auto primal = [&](Ctx& cx) {
-      for (int tries = 0;; ++tries) {
-        if (tries > 6) {           // no acceptable step: keep the iterate
-          a_p = 0.0;
-          Xn = tt_clone(S.X, cx);
-          break;
+    auto attempt = [&](double ap, double ad) {
+      Trial t;
+      int bt_p = 0, bt_d = 0;
+      auto primal = [&](Ctx& cx) {
+        for (int tries = 0;; ++tries) {
+          if (tries > 6) {           // no acceptable step: keep the iterate
+            ap = 0.0;
+            t.X = tt_clone(S.X, cx);
+            t.sx = ShiftInfo{};
+            break;
+          }
+          TT Xs = tt_add({&S.X, &dX2}, {1.0, ap}, cx);
+          t.X = round_shift(std::move(Xs), tolp, &P.Ivec, cap, cx, &t.sx, prm.shift_mode != 0);
+          if (pd_min(t.X, S.EXc, S.has_EXc, cx) > 0.0) break;
+          ap *= 0.5;
+          bt_p++;
         }
-        TT Xs = tt_add({&S.X, &dX2}, {1.0, a_p}, cx);
-        Xn = round_shift(std::move(Xs), tolp, &P.Ivec, cap, cx, nullptr);
-        if (pd_min(Xn, S.EXc, S.has_EXc, cx) > 0.0) break;
-        a_p *= 0.5;
-        bt_p++;
-      }
-    };
-    auto dual = [&](Ctx& cx) {
-      for (int tries = 0;; ++tries) {
-        if (tries > 6) {
-          a_d = 0.0;
-          Zn = tt_clone(S.Z, cx);
-          break;
+      };
+      auto dual = [&](Ctx& cx) {
+        for (int tries = 0;; ++tries) {
+          if (tries > 6) {
+            ad = 0.0;
+            t.Z = tt_clone(S.Z, cx);
+            t.sz = ShiftInfo{};
+            break;
+          }
+          TT Zs = tt_add({&S.Z, &dZ2}, {1.0, ad}, cx);
+          t.Z = round_shift(std::move(Zs), told, &P.Ivec, cap, cx, &t.sz, prm.shift_mode != 0);
+          if (pd_min(t.Z, S.EZc, S.has_EZc, cx) > 0.0) break;
+          ad *= 0.5;
+          bt_d++;
         }
-        TT Zs = tt_add({&S.Z, &dZ2}, {1.0, a_d}, cx);
-        Zn = round_shift(std::move(Zs), told, &P.Ivec, cap, cx, nullptr);
-        if (pd_min(Zn, S.EZc, S.has_EZc, cx) > 0.0) break;
-        a_d *= 0.5;
-        bt_d++;
+        TT Yn = tt_add({&S.Y, &dY2}, {1.0, ad}, cx);
+        t.Y = round_shift(std::move(Yn), told, nullptr, cap, cx, nullptr);
+      };
+      run_concurrent(c, {primal, dual});
+      if (P.ineq) {
+        TT dT2 = S.W.component(2, c);
+        TT Tn = tt_add({&S.T, &dT2}, {1.0, ad}, c);
+        t.T = round_shift(std::move(Tn), told, &P.oneT, cap, c, nullptr, prm.shift_mode != 0);
       }
-      TT Yn = tt_add({&S.Y, &dY2}, {1.0, a_d}, cx);
-      S.Y = round_shift(std::move(Yn), told, nullptr, cap, cx, nullptr);
+      t.a_p = ap;
+      t.a_d = ad;
+      t.bt = bt_p + bt_d;
+      return t;
     };
-    run_concurrent(c, {primal, dual});
-    info.backtracks += bt_p + bt_d;
-    S.X = std::move(Xn);
-    S.Z = std::move(Zn);
+    Trial best;
+    bool have_best = false;
+    for (int g = 0;; ++g) {
+      Trial t = attempt(a_p, a_d);
+      info.backtracks += t.bt;
+      if (!g4_on) {
+        best = std::move(t);
+        break;
+      }
+      t.psi = residual_measure(P, t.X, t.Y, t.Z, P.ineq ? &t.T : nullptr, c);
+      const bool ok = t.psi <= theta + rho;
+      const double ap_next = 0.5 * t.a_p, ad_next = 0.5 * t.a_d;
+      if (!have_best || t.psi < best.psi) {
+        best = std::move(t);
+        have_best = true;
+      }
+      // after the last damping the trial with the smallest Psi is taken, so
+      // that the iteration never stands still on a repeated direction
+      if (ok || g >= std::max(0, prm.g4_retries) || (ap_next == 0.0 && ad_next == 0.0)) break;
+      info.g4_retries++;
+      a_p = ap_next;
+      a_d = ad_next;
+    }
+    a_p = best.a_p;
+    a_d = best.a_d;
+    info.psi = g4_on ? best.psi : psi_k;
+    info.zeta_x = best.sx.zeta;
+    info.zeta_x_cap = std::sqrt(std::max(0.0, best.sx.zeta * best.sx.zeta - best.sx.zeta_tol * best.sx.zeta_tol));
+    info.zeta_z = best.sz.zeta;
+    info.zeta_z_cap = std::sqrt(std::max(0.0, best.sz.zeta * best.sz.zeta - best.sz.zeta_tol * best.sz.zeta_tol));
+    S.X = std::move(best.X);
+    S.Z = std::move(best.Z);
+    S.Y = std::move(best.Y);
+    if (P.ineq) S.T = std::move(best.T);
     S.dX = tt_clone(dX2, c);
     S.dY = tt_clone(dY2, c);
     S.dZ = tt_clone(dZ2, c);
     if (P.ineq) S.dT = S.W.component(2, c);
-    if (P.ineq) {
-      TT dT2 = S.W.component(2, c);
-      TT Tn = tt_add({&S.T, &dT2}, {1.0, a_d}, c);
-      S.T = round_shift(std::move(Tn), told, &P.oneT, cap, c, nullptr);
-    }
   }
   info.t_round += now() - t1;
   info.alpha_p = a_p;

@@ -35,6 +35,7 @@ struct State {
   double eta = 1e-3;
   int iter = 0;
   bool frame_capped = false;         // a Newton frame has reached the rank cap: enrichment is off
+  std::vector<double> psi_hist;      // residual measures of the last accepted iterates (windowed control)
   unsigned long long seed = 12345;
 };
 

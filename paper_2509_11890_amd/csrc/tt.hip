@@ -742,13 +742,14 @@ void tt_orth_right(TT& t, int downto, Ctx& c) {
   }
 }
 
-double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped) {
+double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped, double* zeta_tol) {
   if (capped) *capped = false;
+  if (zeta_tol) *zeta_tol = 0.0;
   if (t.d == 1) return 0.0;
   tt_orth_right(t, 0, c);
   const double eps_k = eps / std::sqrt((double)(t.d - 1));
   const long mid = (long)t.mo * t.mi;
-  double zeta2 = 0.0;
+  double zeta2 = 0.0, zeta_tol2 = 0.0;
   for (int k = 0; k < t.d - 1; ++k) {
     const int rows = (int)(t.r[k] * mid), cols = t.r[k + 1];
     SvdOut sv;
@@ -761,6 +762,8 @@ double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped) {
     for (int j = 1; j <= kk; ++j)
       if (std::sqrt(tail[j]) <= eps_k) { rk = j; break; }
     rk = std::max(1, rk);
+    // the tolerance alone would discard tail[rk]; a binding cap discards more
+    zeta_tol2 += tail[rk];
     if (rk > max_rank) {
       rk = max_rank;
       if (capped) *capped = true;
@@ -790,6 +793,7 @@ double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped) {
     TT_HIP(hipMemcpyAsync(t.core(k + 1), nn.get(), sizeof(double) * (size_t)rk * ncols, hipMemcpyDeviceToDevice, c.s));
     c.sync();
   }
+  if (zeta_tol) *zeta_tol = std::sqrt(zeta_tol2);
   return std::sqrt(zeta2);
 }
 

@@ -132,7 +132,9 @@ void orth_rows(double* G, int q, int len, Ctx& c);
 // Right-orthogonalise cores d-1 .. downto+1 (ranks may shrink).
 void tt_orth_right(TT& t, int downto, Ctx& c);
 // TT rounding (abs tolerance eps, per-bond eps/sqrt(d-1)); returns zeta = ||t - t~||_F.
-double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped = nullptr);
+// zeta_tol receives the part the tolerance alone discards (<= eps); the rest of
+// zeta (zeta^2 - zeta_tol^2) is forced by max_rank.
+double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped = nullptr, double* zeta_tol = nullptr);
 
 // SVD of a row-major matrix M (rows x cols) on the device: U row-major
 // (rows x k), sigma (host, k values), Vt row-major (k x cols), k = min(rows, cols).
