@@ -146,6 +146,23 @@ typedef struct {
  * enqueued on the stream (scratch is owned by the per-stream context). */
 TTIPM_API int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stream);
 
+/*
+ * y = K x exactly as tt_local_matvec (same kernels, same results), for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Every intermediate (the
+ * permuted operator cores, chain buffers, the three GEMM stages' buffers and
+ * the split-K partial sums) lives in one static device array of 64 MiB per
+ * GPU, held from the first call on that GPU until the process ends; the call
+ * never allocates or frees memory.  The caller still owns x and y.  The device
+ * of the call is the current device; the stream must belong to it.  If the
+ * call would need more than the 64 MiB (for one operator block about
+ * r = 64, R = 128), it returns TT_ERR_ARG with the required size in
+ * tt_last_error() and launches nothing.  All calls on one GPU share the array:
+ * calls that overlap on one GPU (other streams, other threads) race and must
+ * be serialised by the caller.  No synchronisation.
+ */
+TTIPM_API int tt_local_matvec_noalloc(const tt_local_op* K, const double* x, double* y, void* stream);
+
 /* DIRECT: blocked LU with partial pivoting of the assembled dense K.
  * CHOLESKY: blocked Cholesky of the symmetric part of the assembled K, for
  * symmetric positive definite local operators; TT_ERR_NUMERIC if a pivot is

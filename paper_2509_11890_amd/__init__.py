@@ -9,6 +9,6 @@ from .binding import (  # noqa: F401
     lib, LibraryMissing, TTError, TT_OK, TT_LEFT, TT_RIGHT, TT_TOL_ABS, TT_TOL_REL,
     TTIPM_MAXCUT, TTIPM_THETA, TTIPM_CC, TTIPM_F64, TTIPM_MIXED,
     TT_SOLVE_AUTO, TT_SOLVE_DIRECT, TT_SOLVE_GMRES, TT_SOLVE_CHOLESKY, TT_PREC_NONE, TT_PREC_BJACOBI, TT_PREC_MLP,
-    contract_interfaces, local_matvec, local_solve, tt_round, ProjOp, LocalBlock, LocalOp,
+    contract_interfaces, local_matvec, local_matvec_noalloc, local_solve, tt_round, ProjOp, LocalBlock, LocalOp,
     Params, Problem, State, ttipm_step, ttipm_solve, version, profile_start, profile_stop, MLP,
 )

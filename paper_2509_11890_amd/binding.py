@@ -122,6 +122,7 @@ lib.tt_version.restype = C.c_char_p
 lib.tt_contract_interfaces.argtypes = [C.POINTER(tt_view), C.POINTER(tt_view), C.POINTER(tt_view),
                                        C.c_int32, C.c_int32, _P, _P, _P]
 lib.tt_local_matvec.argtypes = [C.POINTER(tt_local_op), _P, _P, _P]
+lib.tt_local_matvec_noalloc.argtypes = [C.POINTER(tt_local_op), _P, _P, _P]
 lib.tt_local_solve.argtypes = [C.POINTER(tt_local_op), _P, _P, C.POINTER(tt_solve_params),
                                C.POINTER(tt_solve_info), _P]
 lib.tt_round.argtypes = [C.POINTER(tt_view), C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_double), _P]
@@ -249,6 +250,11 @@ class LocalOp:
 
 def local_matvec(K: LocalOp, x, y):
     _check(lib.tt_local_matvec(C.byref(K.op), _dev(x), _dev(y), _stream()))
+
+
+def local_matvec_noalloc(K: LocalOp, x, y):
+    """y = K x with every intermediate in the library's static scratch array."""
+    _check(lib.tt_local_matvec_noalloc(C.byref(K.op), _dev(x), _dev(y), _stream()))
 
 
 def local_solve(K: LocalOp, rhs, x, method=TT_SOLVE_AUTO, rtol=1e-12, restart=40, maxit=1000,

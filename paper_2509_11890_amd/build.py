@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libttipm.so")
 ARCH = os.environ.get("TTIPM_ARCH", "gfx950")
 
-SOURCES = ["common.cpp", "gemm.hip", "dense.hip", "blocked.hip", "krylov.hip", "mlp.hip", "ttops.hip", "tt.hip", "amen.hip", "ipm.hip", "capi.cpp"]
+SOURCES = ["common.cpp", "gemm.hip", "dense.hip", "blocked.hip", "krylov.hip", "mlp.hip", "ttops.hip", "tt.hip", "amen.hip", "ipm.hip", "noalloc.hip", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

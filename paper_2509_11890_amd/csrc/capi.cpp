@@ -14,6 +14,7 @@
 #include "blocked.hpp"
 #include "krylov.hpp"
 #include "mlp.hpp"
+#include "noalloc.hpp"
 #include "dense.hpp"
 #include "ipm.hpp"
 #include "ttops.hpp"
@@ -160,13 +161,20 @@ void check_local_op(const tt_local_op* K) {
 // The blocks' projected products in grouped stage launches: first operators
 // of every block, then the second operators of the chained blocks; the
 // products of one block row keep the block order within each level.
-void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c) {
+// y = K x.  With arena, the permuted cores, chain buffers, stage buffers and
+// split-K partials come from it; with dry as well nothing is launched and
+// arena->used / *ws_need receive the scratch the call needs (a dry run takes
+// an arena whose base is a placeholder address: its pointers are compared,
+// never dereferenced, so the launch grouping is that of the real call).
+void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c, Arena* arena = nullptr,
+                    bool dry = false, size_t* ws_need = nullptr) {
   const long p = (long)K->r * K->m * K->rp;
-  fill((long)K->L * p, 0.0, y, c.s);
+  if (!dry) fill((long)K->L * p, 0.0, y, c.s);
   // context-owned permuted cores and chain buffers: no allocation is released
   // while kernels may still use it
   size_t nb = 0;
   auto buf = [&](size_t n) {
+    if (arena) return arena->take(n);
     if (c.lbuf.size() <= nb) c.lbuf.resize(nb + 1);
     c.lbuf[nb].reserve(n);
     return c.lbuf[nb++].get();
@@ -175,7 +183,7 @@ void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c) {
     double* perm = nullptr;
     if (o.core) {
       perm = buf((size_t)o.R * K->m * K->m * o.Rp);
-      permute_op_core(o.core, o.R, K->m, o.Rp, perm, c.s);
+      if (!dry) permute_op_core(o.core, o.R, K->m, o.Rp, perm, c.s);
     }
     return LocalApplyArgs{o.phiL, K->r, o.R, K->r, perm, K->m, o.phiR, K->rp, o.Rp, K->rp, xin, yout, alpha, beta};
   };
@@ -192,8 +200,10 @@ void generic_matvec(const tt_local_op* K, const double* x, double* y, Ctx& c) {
       lv1.push_back(args(B.op[1], tb, yout, B.coeff, 1.0));
     }
   }
-  local_apply_many(lv0, c);
-  local_apply_many(lv1, c);
+  // the two levels run one after the other on the stream; with an arena the
+  // second level's stage buffers follow the first level's
+  local_apply_many(lv0, c, arena, dry, ws_need);
+  local_apply_many(lv1, c, arena, dry, ws_need);
 }
 
 }  // namespace
@@ -206,6 +216,37 @@ int tt_local_matvec(const tt_local_op* K, const double* x, double* y, void* stre
     c.prec = K->precision == TTIPM_MIXED ? GemmPrec::BF16 : GemmPrec::F64;
     generic_matvec(K, x, y, c);
     c.prec = GemmPrec::F64;
+    return TT_OK;
+  });
+}
+
+int tt_local_matvec_noalloc(const tt_local_op* K, const double* x, double* y, void* stream) {
+  return guarded([&]() -> int {
+    check_local_op(K);
+    if (!x || !y) throw Error(TT_ERR_ARG, "NULL vector");
+    size_t cap = 0;
+    double* scratch = noalloc_scratch(&cap);
+    // a context of the caller's stream that never reserves memory: every
+    // buffer of the call comes from the static scratch array
+    Ctx c;
+    c.s = as_stream(stream);
+    c.prec = K->precision == TTIPM_MIXED ? GemmPrec::BF16 : GemmPrec::F64;
+    Arena plan;
+    plan.base = reinterpret_cast<double*>(uintptr_t(1) << 20);   // placeholder, never dereferenced
+    plan.cap = size_t(1) << 56;
+    size_t ws_need = 0;
+    generic_matvec(K, x, y, c, &plan, true, &ws_need);
+    const size_t need = ((plan.used + 31) & ~size_t(31)) + ws_need;
+    if (need > cap) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "tt_local_matvec_noalloc: the call needs %.1f MiB of scratch, the limit is %.1f MiB",
+                    need * 8.0 / (1 << 20), cap * 8.0 / (1 << 20));
+      throw Error(TT_ERR_ARG, msg);
+    }
+    Arena run;
+    run.base = scratch;
+    run.cap = cap;
+    generic_matvec(K, x, y, c, &run, false, nullptr);
     return TT_OK;
   });
 }

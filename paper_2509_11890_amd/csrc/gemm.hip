@@ -447,6 +447,42 @@ __global__ void scale_c_kernel(double* C, long cm, long cn, long sC, int M, int 
 
 static Workspace g_default_ws;
 
+double* Workspace::take(size_t n) {
+  if (fixed) {
+    if (n > fixed_n) throw Error(TT_ERR_ARG, "split-K partials exceed the fixed workspace");
+    return fixed;
+  }
+  buf.reserve(n);
+  return buf.get();
+}
+
+// Slice count of the split-K rule for `tiles` output tiles.
+static int splitk_slices(long tiles, int K, int kstep) {
+  int ks = 1;
+  if (tiles < 128 && K >= 16 * kstep) {
+    ks = (int)std::min<long>((256 + tiles - 1) / tiles, (long)K / (8 * kstep));
+    ks = std::max(1, std::min(ks, 64));
+  }
+  int chunk = (K + ks - 1) / ks;
+  chunk = ((chunk + kstep - 1) / kstep) * kstep;
+  return (K + chunk - 1) / chunk;
+}
+
+size_t gemm_splitk_need(const Gemm& q, GemmPrec prec) {
+  if (q.M <= 0 || q.N <= 0 || q.batch <= 0 || q.K <= 0) return 0;
+  const int kstep = (prec == GemmPrec::BF16) ? BK16 : BK;
+  // the single launch picks tiles of at least 64 x 64, the grouped one 64 x 64:
+  // 64 x 64 tiles give the most output tiles and the fewest slices, 128 x 128
+  // the fewest tiles and the most slices; both bound the slice count
+  size_t need = 0;
+  for (int t = 64; t <= 128; t *= 2) {
+    const long tiles = (long)((q.M + t - 1) / t) * ((q.N + t - 1) / t) * q.batch;
+    const int ks = splitk_slices(tiles, q.K, kstep);
+    if (ks > 1) need = std::max(need, (size_t)q.batch * ks * q.M * q.N);
+  }
+  return need;
+}
+
 template <int WM, int WN>
 void launch_bf16(dim3 grid, hipStream_t stream, const KArgs& g, double flops, double bytes) {
   const bool akc = (g.ak == 1), bkc = (g.bk == 1 && g.bn != 1);
@@ -535,8 +571,7 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   if (ks > 1) {
     Workspace* w = ws ? ws : &g_default_ws;
     size_t need = (size_t)q.batch * ks * q.M * q.N;
-    w->buf.reserve(need);
-    g.P = w->buf.get();
+    g.P = w->take(need);
   }
   dim3 grid(gm, gn, q.batch * ks);
   const double flops = 2.0 * q.M * q.N * (double)q.K * q.batch;
@@ -678,13 +713,13 @@ static void gemm_group_launch(const std::vector<const Gemm*>& take, bool akc0, b
   GroupArgs red{};
   if (split) {
     Workspace* w = ws ? ws : &g_default_ws;
-    w->buf.reserve((size_t)part);
+    double* P0 = w->take((size_t)part);
     long off = 0, outs = 0;
     for (int i = 0; i < ga.n; ++i) {
       KArgs& g = ga.g[i];
       if (g.kslices <= 1) continue;
       const Gemm& q = *take[i];
-      g.P = w->buf.get() + off;
+      g.P = P0 + off;
       off += (long)q.batch * g.kslices * q.M * q.N;
       red.g[red.n] = g;
       outs += (long)q.batch * q.M * q.N;

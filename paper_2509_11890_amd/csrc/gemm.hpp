@@ -17,10 +17,19 @@ struct Gemm {
 
 enum class GemmPrec { F64, BF16 };
 
-// Scratch for split-K partial sums; grows on demand.
+// Scratch for split-K partial sums; grows on demand, or (fixed != nullptr) a
+// caller-provided region of fixed_n doubles that is never grown.
 struct Workspace {
   DevBuf buf;
+  double* fixed = nullptr;
+  size_t fixed_n = 0;
+  double* take(size_t n);
 };
+
+// Upper bound (doubles) of the split-K partials one problem needs in gemm()
+// or in a grouped launch; a gemm_grouped call needs at most the sum over its
+// problems.
+size_t gemm_splitk_need(const Gemm& q, GemmPrec prec);
 
 void gemm(const Gemm& g, hipStream_t stream, Workspace* ws = nullptr, GemmPrec prec = GemmPrec::F64);
 

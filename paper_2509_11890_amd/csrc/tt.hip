@@ -519,10 +519,11 @@ void local_apply(const double* phiL, int r, int R, int rc, const double* Operm, 
   }
 }
 
-void local_apply_many(const std::vector<LocalApplyArgs>& v, Ctx& c) {
+void local_apply_many(const std::vector<LocalApplyArgs>& v, Ctx& c, Arena* arena, bool dry, size_t* ws_need) {
   if (v.empty()) return;
   size_t nb = 0;
   auto buf = [&](size_t n) {
+    if (arena) return arena->take(n);
     if (c.gbuf.size() <= nb) c.gbuf.resize(nb + 1);
     c.gbuf[nb].reserve(n);
     return c.gbuf[nb++].get();
@@ -555,18 +556,42 @@ void local_apply_many(const std::vector<LocalApplyArgs>& v, Ctx& c) {
     g.alpha = a.alpha; g.beta = a.beta;
     g3.push_back(g);
   }
-  gemm_grouped(g1.data(), (int)g1.size(), c.s, &c.ws, c.prec);
-  gemm_grouped(g2.data(), (int)g2.size(), c.s, &c.ws, c.prec);
   // last stages in list order, a launch cut wherever an output repeats
-  size_t b = 0;
-  for (size_t e = 0; e <= g3.size(); ++e) {
-    bool cut = e == g3.size();
-    for (size_t q = b; q < e && !cut; ++q) cut = g3[q].C == g3[e].C;
-    if (cut && e > b) {
-      gemm_grouped(g3.data() + b, (int)(e - b), c.s, &c.ws, c.prec);
-      b = e;
+  std::vector<std::pair<size_t, size_t>> cuts;
+  {
+    size_t b = 0;
+    for (size_t e = 0; e <= g3.size(); ++e) {
+      bool cut = e == g3.size();
+      for (size_t q = b; q < e && !cut; ++q) cut = g3[q].C == g3[e].C;
+      if (cut && e > b) {
+        cuts.push_back({b, e});
+        b = e;
+      }
     }
   }
+  if (dry) {
+    // every grouped call reuses the partials region from its start
+    auto need = [&](const Gemm* q, size_t n) {
+      size_t t = 0;
+      for (size_t i = 0; i < n; ++i) t += gemm_splitk_need(q[i], c.prec);
+      return t;
+    };
+    size_t w = std::max(need(g1.data(), g1.size()), need(g2.data(), g2.size()));
+    for (const auto& ct : cuts) w = std::max(w, need(g3.data() + ct.first, ct.second - ct.first));
+    if (ws_need) *ws_need = std::max(*ws_need, w);
+    return;
+  }
+  Workspace fixed_ws;
+  Workspace* ws = &c.ws;
+  if (arena) {
+    double* rest = arena->take(0);
+    fixed_ws.fixed = rest;
+    fixed_ws.fixed_n = arena->cap > arena->used ? arena->cap - arena->used : 0;
+    ws = &fixed_ws;
+  }
+  gemm_grouped(g1.data(), (int)g1.size(), c.s, ws, c.prec);
+  gemm_grouped(g2.data(), (int)g2.size(), c.s, ws, c.prec);
+  for (const auto& ct : cuts) gemm_grouped(g3.data() + ct.first, (int)(ct.second - ct.first), c.s, ws, c.prec);
 }
 
 // ---------------------------------------------------------------------------

@@ -123,7 +123,24 @@ struct LocalApplyArgs {
   double* y;
   double alpha, beta;
 };
-void local_apply_many(const std::vector<LocalApplyArgs>& v, Ctx& c);
+// A bump allocator over caller-provided device memory (base == nullptr:
+// count only).  Offsets are rounded to 256 bytes.
+struct Arena {
+  double* base = nullptr;
+  size_t cap = 0, used = 0;
+  double* take(size_t n) {
+    const size_t off = (used + 31) & ~size_t(31);
+    used = off + n;
+    TT_REQUIRE(!base || used <= cap, "scratch arena overflow");
+    return base ? base + off : nullptr;
+  }
+};
+// With arena: stage buffers are taken from it and split-K partials use the
+// rest of it (never grown); with dry as well nothing is launched and
+// *ws_need receives the split-K partials the launches would need (a dry run
+// takes operand pointers only as markers: Operm != nullptr means an operator).
+void local_apply_many(const std::vector<LocalApplyArgs>& v, Ctx& c, Arena* arena = nullptr, bool dry = false,
+                      size_t* ws_need = nullptr);
 void permute_op_core(const double* O, int R, int m, int Rp, double* out, hipStream_t s);
 
 // ---- orthogonalisation and rounding --------------------------------------------
