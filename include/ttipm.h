@@ -67,6 +67,8 @@ TTIPM_API const char* tt_last_error(void);
 TTIPM_API const char* tt_version(void);
 
 /* ---- TT views ----------------------------------------------------------- */
+enum { TT_F64 = 0, TT_F32 = 1, TT_BF16 = 2 };
+
 /*
  * A TT vector (m_in == 1) or TT matrix (m_in > 1) with d cores.
  *   ranks : host array of d+1 ranks, ranks[0] = ranks[d] = 1.  Calls that
@@ -75,7 +77,14 @@ TTIPM_API const char* tt_version(void);
  *           2 for TT matrices and plain vectors over binary modes).
  *   m_in  : 1 for a TT vector, the input mode size for an operator.
  *   cores : host array of d device pointers; core k holds
- *           ranks[k] * m_out * m_in * ranks[k+1] doubles.
+ *           ranks[k] * m_out * m_in * ranks[k+1] elements of dtype.
+ *   capacity_rank : 0, or the largest rank every core buffer has room for
+ *           (core k holds capacity ranks on both bonds); a call that writes
+ *           a TT of data-dependent rank into the view never exceeds it.
+ *   dtype : element type of the cores.  Every call of this header reads and
+ *           writes TT_F64 views and rejects the others with TT_ERR_ARG; the
+ *           field lets low-precision copies cross the boundary tagged.
+ * A view with d = 0 is an absent argument where a call allows one.
  */
 typedef struct {
   int32_t d;
@@ -83,6 +92,8 @@ typedef struct {
   int32_t m_in;
   int32_t* ranks;
   double** cores;
+  int32_t capacity_rank;
+  int32_t dtype;
 } tt_view;
 
 /* ---- environments (interfaces) ------------------------------------------ */
@@ -103,6 +114,20 @@ typedef struct {
 TTIPM_API int tt_contract_interfaces(const tt_view* test, const tt_view* op, const tt_view* trial,
                            int32_t k, int32_t dir, const double* phi_in, double* phi_out,
                            void* stream);
+
+/*
+ * <Oi vi, Oj vj> for TT vectors vi, vj (m_in = 1, equal mode sizes) and
+ * operators Oi, Oj on them (NULL = identity), without forming the images:
+ * one left-to-right sweep over a four-layer environment
+ * E[a][alpha][beta][c] (ranks of vi, Oi, Oj, vj), four GEMM stages per core.
+ * The norm of a sum of operator images (a global residual K dU + R of the
+ * Newton system, Sec. 3.3, Lemma "AMEn Directions as Inexact Newton
+ * Directions") is a sum of such terms.  Device memory: the environment and two
+ * stage buffers of max_k ranks(vi) ranks(Oi) ranks(Oj) ranks(vj) * m doubles.
+ * Writes the value to *out (host).  Synchronises the stream.
+ */
+TTIPM_API int tt_op_inner(const tt_view* vi, const tt_view* Oi, const tt_view* vj, const tt_view* Oj, double* out,
+                          void* stream);
 
 /* ---- projected local operator -------------------------------------------- */
 /*
@@ -214,34 +239,61 @@ TTIPM_API int tt_local_solve(const tt_local_op* K, const double* rhs, double* x,
  * tol * ||t||_F (TT_TOL_REL), ranks capped at max_rank.  Ranks never grow, so
  * the caller's core buffers are reused; t->ranks is updated.  zeta_out (may be
  * NULL) receives ||t - round(t)||_F accumulated from the discarded singular
- * values (the spectral-shift size of Cor. 1).  Synchronises the stream.
+ * values (the spectral-shift size of Cor. 1).
+ * ws: NULL = scratch from the library's caching device pool; else a
+ * caller-owned, 256-byte aligned device region of ws_bytes from which every
+ * device buffer of the call is taken (at least tt_round_workspace bytes; a
+ * call that would need more returns TT_ERR_ARG with t unchanged).  Pinned host
+ * staging of the norms stays library-owned.  Synchronises the stream.
  * Returns TT_ERR_RANK_CAP (a warning, result valid) if the cap truncated more
  * than the tolerance allowed.
  */
-TTIPM_API int tt_round(tt_view* t, double tol, int32_t tol_mode, int32_t max_rank, double* zeta_out,
-             void* stream);
+TTIPM_API int tt_round(tt_view* t, double tol, int32_t tol_mode, int32_t max_rank, double* zeta_out, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Workspace bytes that always suffice for tt_round of t (any tolerance, any
+ * cap): written to *bytes.  No device work. */
+TTIPM_API int tt_round_workspace(const tt_view* t, size_t* bytes);
 
 /* ---- the interior-point method --------------------------------------------- */
 typedef struct ttipm_problem ttipm_problem;
 typedef struct ttipm_state ttipm_state;
 
-enum { TTIPM_MAXCUT = 0, TTIPM_THETA = 1, TTIPM_CC = 2 };
+enum { TTIPM_MAXCUT = 0, TTIPM_THETA = 1, TTIPM_CC = 2, TTIPM_GENERIC = 3 };
 enum { TTIPM_F64 = 0, TTIPM_MIXED = 1 };
 enum { TTIPM_DIR_XZ = 0, TTIPM_DIR_AHO = 1 };
 
 /*
- * Problem description (Sec. 4).  graph is a TT matrix with 2 x 2 modes:
+ * Problem description.
+ * Kinds built from a graph (Sec. 4): graph is a TT matrix with 2 x 2 modes,
  *   TTIPM_MAXCUT: the weighted adjacency A_G (Sec. 4.1);
  *   TTIPM_THETA : the 0/1 adjacency A_G (Sec. 4.2);
  *   TTIPM_CC    : the signed weights W = C+ - C-, zero diagonal (Sec. 4.3),
- *                 with negdeg the TT vector (m_out = 2) of C- 1.
- * The library builds C, A_eq, B_eq, K_Y (and A_ineq, K_T) itself and copies
- * everything it needs; the caller's buffers may be freed after the call.
+ *                 with negdeg the TT vector (m_out = 2) of C- 1;
+ * the library builds C, A_eq, B_eq, K_Y (and A_ineq, K_T) itself.
+ * TTIPM_GENERIC: the tensorised SDP of Sec. 3.2 given directly (Def. "SDP",
+ * Def. "The Dual SDP" in TT form): maximise <C, X> subject to
+ * A_eq vec_TT X = B_eq, A_ineq vec_TT X <= B_ineq (>= with ineq_sense = -1),
+ * X psd.  C, B_eq, B_ineq are vec_TT vectors (m_out 4, m_in 1); A_eq, A_eq^T,
+ * K_Y, A_ineq, A_ineq^T, K_T are operators on vec_TT (m_out = m_in = 4).  The
+ * multipliers Y and T are padded to n x n (Sec. 3.2): K_Y and K_T are the
+ * diagonal masks of their idle entries, and the active inequality mask 1_T is
+ * taken as vec_TT(J) - K_T vec_TT(J).  Aineq.d = 0 means no inequalities.
+ * q counts the inequality multipliers in mu = (<X,Z> + <T, s(X)>) / (n + q);
+ * the initial point is X = lam0 I + x0_ineq A_ineq(J), Z = lam0 I, Y = 0,
+ * T = t0_ineq A_ineq(J) (Sec. 5.1).  The graph kinds ignore these fields.
+ * Every input is copied at create time; the caller's buffers may be freed
+ * after the call.  All views are TT_F64.
  */
 typedef struct {
   int32_t kind;
   tt_view graph;
   tt_view negdeg;   /* TTIPM_CC only (d = 0 otherwise) */
+  tt_view C, Aeq, AeqT, Beq, KY;          /* TTIPM_GENERIC */
+  tt_view Aineq, AineqT, Bineq, KT;       /* TTIPM_GENERIC with inequalities */
+  int32_t ineq_sense;                     /* +1: A_ineq vec X <= B_ineq; -1: >= */
+  double q;
+  double lam0, x0_ineq, t0_ineq;
 } ttipm_problem_desc;
 
 TTIPM_API int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out);
@@ -339,8 +391,7 @@ typedef struct {
   int32_t eig_rank;     /* rank of the TT eigenvector in the step-length solver          */
   int32_t eig_sweeps;   /* ALS sweeps of the step-length solver                           */
   int32_t verbose;      /* print one line per iteration to stderr                          */
-  int32_t kick;         /* seeded random enrichment columns per AMEn core move (2); off once
-                           a Newton frame has been truncated by rank_cap                 */
+  int32_t kick;         /* enrichment directions per AMEn core move (2)                   */
   int32_t seed;         /* seed of the enrichment and step-length start vectors            */
   int32_t kick_sweeps;  /* enrichment only in the first kick_sweeps half-sweeps of a solve */
   int32_t collect_probes; /* > 0 and mlp set: every local system of the AMEn solves adds its
@@ -361,6 +412,15 @@ typedef struct {
                            zeta (keeps positive definiteness also when iter_rank_cap forces
                            a larger truncation than the tolerance; default), 0 = only the
                            part within the tolerance budget                               */
+  int32_t newton_check; /* 1: evaluate the global FP64 residual ||K dU + R|| / ||R|| of each
+                           corrector direction (ttipm_step_info.newton_res); with
+                           precision TTIPM_MIXED a direction above eta is then refined by
+                           FP64 AMEn sweeps warm-started from it (1)                      */
+  int32_t refine_sweeps;/* FP64 half-sweeps of one such refinement (2)                    */
+  int32_t enrich;       /* AMEn enrichment (Sec. 2.3): 1 = the leading directions of the
+                           Newton residual K dU + R sketched with a seeded Gaussian TT on
+                           the side ahead of the block, with room kept under rank_cap (1);
+                           0 = seeded random directions, off once rank_cap truncates      */
 } ttipm_params;
 
 TTIPM_API void ttipm_params_default(ttipm_params* p);
@@ -388,6 +448,11 @@ typedef struct {
                                        part forced by iter_rank_cap (only the rest, within the
                                        tolerance budget, is added as the Cor. 1 shift) */
   double zeta_z, zeta_z_cap;        /* the same for Z */
+  double newton_res;                /* ||K dU + R|| / ||R|| of the corrector direction, FP64, after any
+                                       refinement (0 when newton_check is off; -1 when an operator-image
+                                       environment of the check would exceed 256 MiB) */
+  int32_t refine_sweeps;            /* FP64 refinement half-sweeps of the corrector (mixed precision) */
+  double t_check;                   /* seconds spent on the residual check and refinement */
   double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration */
 } ttipm_step_info;
 

@@ -468,6 +468,23 @@ CONFIG_NAMES = ["maxcut_grid_d5", "maxcut_kron_d10", "theta_hypercube_d10",
                 "cc_signed_d12", "maxcut_noise_d12"]
 
 
+def negdeg_cores(g: Graph, tol=1e-14):
+    """TT cores (mode 2) of the negative-degree vector C^- 1 of a signed graph,
+    C^- = max(-W, 0), by successive truncated SVDs at relative tol (the input
+    of the correlation-clustering encoding)."""
+    v = np.maximum(-g.dense, 0.0).sum(axis=1)
+    cores, r, C = [], 1, np.asarray(v, dtype=np.float64).reshape(1, -1)
+    for k in range(g.d - 1):
+        C = C.reshape(r * 2, -1)
+        U, s, Vt = np.linalg.svd(C, full_matrices=False)
+        rk = max(1, int(np.sum(s > tol * max(s[0], 1e-300))))
+        cores.append(U[:, :rk].reshape(r, 2, rk))
+        C = s[:rk, None] * Vt[:rk]
+        r = rk
+    cores.append(C.reshape(r, 2, 1))
+    return cores
+
+
 def config(name: str) -> dict:
     if name == "maxcut_grid_d5":
         return {"kind": "maxcut", "graph": grid_4x8(), "rank_cap": 8, "precision": "f64"}

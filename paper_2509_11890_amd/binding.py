@@ -40,13 +40,17 @@ TT_LEFT, TT_RIGHT = 0, 1
 TT_TOL_ABS, TT_TOL_REL = 0, 1
 TT_SOLVE_AUTO, TT_SOLVE_DIRECT, TT_SOLVE_GMRES, TT_SOLVE_CHOLESKY = 0, 1, 2, 3
 TT_PREC_NONE, TT_PREC_BJACOBI, TT_PREC_MLP = 0, 1, 2
-TTIPM_MAXCUT, TTIPM_THETA, TTIPM_CC = 0, 1, 2
+TTIPM_MAXCUT, TTIPM_THETA, TTIPM_CC, TTIPM_GENERIC = 0, 1, 2, 3
 TTIPM_F64, TTIPM_MIXED = 0, 1
+
+
+TT_F64, TT_F32, TT_BF16 = 0, 1, 2
 
 
 class tt_view(C.Structure):
     _fields_ = [("d", C.c_int32), ("m_out", C.c_int32), ("m_in", C.c_int32),
-                ("ranks", C.POINTER(C.c_int32)), ("cores", C.POINTER(C.c_void_p))]
+                ("ranks", C.POINTER(C.c_int32)), ("cores", C.POINTER(C.c_void_p)),
+                ("capacity_rank", C.c_int32), ("dtype", C.c_int32)]
 
 
 class tt_proj_op(C.Structure):
@@ -76,7 +80,10 @@ class tt_solve_info(C.Structure):
 
 
 class ttipm_problem_desc(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("graph", tt_view), ("negdeg", tt_view)]
+    _fields_ = [("kind", C.c_int32), ("graph", tt_view), ("negdeg", tt_view)] + \
+               [(n, tt_view) for n in ("C", "Aeq", "AeqT", "Beq", "KY", "Aineq", "AineqT", "Bineq", "KT")] + \
+               [("ineq_sense", C.c_int32), ("q", C.c_double), ("lam0", C.c_double), ("x0_ineq", C.c_double),
+                ("t0_ineq", C.c_double)]
 
 
 class ttipm_params(C.Structure):
@@ -89,7 +96,8 @@ class ttipm_params(C.Structure):
                 ("eig_sweeps", C.c_int32), ("verbose", C.c_int32), ("kick", C.c_int32), ("seed", C.c_int32),
                 ("kick_sweeps", C.c_int32), ("collect_probes", C.c_int32), ("collect_cap", C.c_int64),
                 ("xz_fallback", C.c_int32), ("eig_kick", C.c_int32), ("g4_window", C.c_int32),
-                ("g4_retries", C.c_int32), ("shift_mode", C.c_int32)]
+                ("g4_retries", C.c_int32), ("shift_mode", C.c_int32), ("newton_check", C.c_int32),
+                ("refine_sweeps", C.c_int32), ("enrich", C.c_int32)]
 
 
 class ttipm_step_info(C.Structure):
@@ -100,7 +108,8 @@ class ttipm_step_info(C.Structure):
                                           "alpha_d_max")] + \
                [("backtracks", C.c_int32), ("mlp_used", C.c_int32), ("mlp_fallbacks", C.c_int32),
                 ("xz_fallback", C.c_int32), ("g4_retries", C.c_int32)] + \
-               [(n, C.c_double) for n in ("psi", "zeta_x", "zeta_x_cap", "zeta_z", "zeta_z_cap")] + \
+               [(n, C.c_double) for n in ("psi", "zeta_x", "zeta_x_cap", "zeta_z", "zeta_z_cap", "newton_res")] + \
+               [("refine_sweeps", C.c_int32), ("t_check", C.c_double)] + \
                [(n, C.c_double) for n in ("t_env", "t_solve", "t_svd", "t_step", "t_round", "t_total")]
 
     def as_dict(self):
@@ -125,7 +134,11 @@ lib.tt_local_matvec.argtypes = [C.POINTER(tt_local_op), _P, _P, _P]
 lib.tt_local_matvec_noalloc.argtypes = [C.POINTER(tt_local_op), _P, _P, _P]
 lib.tt_local_solve.argtypes = [C.POINTER(tt_local_op), _P, _P, C.POINTER(tt_solve_params),
                                C.POINTER(tt_solve_info), _P]
-lib.tt_round.argtypes = [C.POINTER(tt_view), C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_double), _P]
+lib.tt_round.argtypes = [C.POINTER(tt_view), C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_double), _P,
+                         C.c_size_t, _P]
+lib.tt_round_workspace.argtypes = [C.POINTER(tt_view), C.POINTER(C.c_size_t)]
+lib.tt_op_inner.argtypes = [C.POINTER(tt_view), C.POINTER(tt_view), C.POINTER(tt_view), C.POINTER(tt_view),
+                            C.POINTER(C.c_double), _P]
 lib.ttipm_params_default.argtypes = [C.POINTER(ttipm_params)]
 lib.ttipm_params_default.restype = None
 lib.ttipm_problem_create.argtypes = [C.POINTER(ttipm_problem_desc), C.POINTER(_P)]
@@ -203,7 +216,7 @@ class _View:
                 raise ValueError("core size does not match the modes")
         self.ptrs = (C.c_void_p * d)(*[_dev(G).value for G in self.cores])
         self.v = tt_view(d, m_out, m_in, C.cast(self.ranks_arr, C.POINTER(C.c_int32)),
-                         C.cast(self.ptrs, C.POINTER(C.c_void_p)))
+                         C.cast(self.ptrs, C.POINTER(C.c_void_p)), 0, TT_F64)
 
     @property
     def ranks(self):
@@ -268,11 +281,34 @@ def local_solve(K: LocalOp, rhs, x, method=TT_SOLVE_AUTO, rtol=1e-12, restart=40
             "precond": info.precond_used, "converged": code == TT_OK}
 
 
-def tt_round(cores, tol, mode=TT_TOL_ABS, max_rank=1 << 30, m_out=4, m_in=1):
-    """In-place TT rounding of device cores; returns (new cores as views, zeta)."""
+def op_inner(vi, Oi, vj, Oj, m=4):
+    """<Oi vi, Oj vj> of device TT cores (vectors [r, m, r'], operators
+    [R, m, m, R'] or None for the identity)."""
+    vv = [_View(vi, m), _View(vj, m)]
+    oo = [None if O is None else _View(O, m, m) for O in (Oi, Oj)]
+    out = C.c_double(0.0)
+    ref = lambda v: None if v is None else C.byref(v.v)
+    _check(lib.tt_op_inner(C.byref(vv[0].v), ref(oo[0]), C.byref(vv[1].v), ref(oo[1]), C.byref(out), _stream()))
+    return out.value
+
+
+def tt_round_workspace(cores, m_out=4, m_in=1):
+    """Workspace bytes that suffice for tt_round of these cores."""
+    v = _View(cores, m_out, m_in)
+    n = C.c_size_t(0)
+    _check(lib.tt_round_workspace(C.byref(v.v), C.byref(n)))
+    return n.value
+
+
+def tt_round(cores, tol, mode=TT_TOL_ABS, max_rank=1 << 30, m_out=4, m_in=1, workspace=None):
+    """In-place TT rounding of device cores; returns (new cores as views, zeta).
+    workspace: None (library pool) or a device tensor whose memory serves every
+    device buffer of the call."""
     v = _View(cores, m_out, m_in)
     zeta = C.c_double(0.0)
-    _check(lib.tt_round(C.byref(v.v), float(tol), int(mode), int(max_rank), C.byref(zeta), _stream()),
+    ws, nb = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()),
+                                                   workspace.numel() * workspace.element_size())
+    _check(lib.tt_round(C.byref(v.v), float(tol), int(mode), int(max_rank), C.byref(zeta), ws, nb, _stream()),
            allow=(TT_ERR_RANK_CAP,))
     r = v.ranks
     out = []
@@ -314,6 +350,35 @@ class Problem:
         _check(lib.ttipm_problem_create(C.byref(desc), C.byref(self.h)))
         self.d = len(g)
         del keep
+
+    @classmethod
+    def generic(cls, C_, Aeq, AeqT, Beq, KY, Aineq=None, AineqT=None, Bineq=None, KT=None, ineq_sense=1, q=0.0,
+                lam0=1.0, x0_ineq=0.0, t0_ineq=1e-3):
+        """The tensorised SDP of Sec. 3.2 given directly: vec_TT vectors C, B_eq,
+        B_ineq as lists of [r, 4, r'] cores, operators as [R, 4, 4, R'] cores."""
+        self = cls.__new__(cls)
+        dev = lambda cores: [torch.as_tensor(G, dtype=torch.float64).cuda().contiguous() for G in cores]
+        desc = ttipm_problem_desc()
+        desc.kind = TTIPM_GENERIC
+        keep = []
+        for name, cores, m_in in (("C", C_, 1), ("Aeq", Aeq, 4), ("AeqT", AeqT, 4), ("Beq", Beq, 1), ("KY", KY, 4),
+                                  ("Aineq", Aineq, 4), ("AineqT", AineqT, 4), ("Bineq", Bineq, 1), ("KT", KT, 4)):
+            if cores is None:
+                continue
+            g = dev(cores)
+            v = _View(g, 4, m_in)
+            setattr(desc, name, v.v)
+            keep += [g, v]
+        desc.ineq_sense = int(ineq_sense)
+        desc.q = float(q)
+        desc.lam0 = float(lam0)
+        desc.x0_ineq = float(x0_ineq)
+        desc.t0_ineq = float(t0_ineq)
+        self.h = C.c_void_p()
+        _check(lib.ttipm_problem_create(C.byref(desc), C.byref(self.h)))
+        self.d = len(C_)
+        del keep
+        return self
 
     def __del__(self):
         if getattr(self, "h", None) and self.h.value:

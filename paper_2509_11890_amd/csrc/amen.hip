@@ -45,6 +45,10 @@ struct Envs {
   std::vector<EnvKey> keys;
   std::vector<std::vector<DevBuf>> L, R;
   int d = 0;
+  const TT* test = nullptr;   // nullptr: the frame W is the test TT
+
+  int test_rank(const BlockTT& W, int bond) const { return test ? test->r[bond] : W.r[bond]; }
+  const double* test_core(const BlockTT& W, int k) const { return test ? test->core(k) : W.cores[k].get(); }
 
   int op_rank(const EnvKey& e, int bond) const { return e.op ? e.op->r[bond] : 1; }
   int trial_rank(const EnvKey& e, const BlockTT& W, int bond) const { return e.trial ? e.trial->r[bond] : W.r[bond]; }
@@ -74,11 +78,11 @@ struct Envs {
     std::vector<EnvStepArgs> st;
     for (size_t i = 0; i < keys.size(); ++i) {
       const EnvKey& e = keys[i];
-      const int ra = W.r[k], ra2 = W.r[k + 1];
+      const int ra = test_rank(W, k), ra2 = test_rank(W, k + 1);
       const int R0 = op_rank(e, k), R1 = op_rank(e, k + 1);
       const int rc = trial_rank(e, W, k), rc2 = trial_rank(e, W, k + 1);
       L[i][k + 1].reserve((size_t)ra2 * R1 * rc2);
-      st.push_back({L[i][k].get(), ra, R0, rc, W.cores[k].get(), 4, ra2, e.op ? e.op->core(k) : nullptr, R1, 4,
+      st.push_back({L[i][k].get(), ra, R0, rc, test_core(W, k), 4, ra2, e.op ? e.op->core(k) : nullptr, R1, 4,
                     trial_core(e, W, k), rc2, L[i][k + 1].get()});
     }
     env_steps(st, true, c);
@@ -88,11 +92,11 @@ struct Envs {
     std::vector<EnvStepArgs> st;
     for (size_t i = 0; i < keys.size(); ++i) {
       const EnvKey& e = keys[i];
-      const int ra = W.r[k], ra2 = W.r[k + 1];
+      const int ra = test_rank(W, k), ra2 = test_rank(W, k + 1);
       const int R0 = op_rank(e, k), R1 = op_rank(e, k + 1);
       const int rc = trial_rank(e, W, k), rc2 = trial_rank(e, W, k + 1);
       R[i][k - 1].reserve((size_t)ra * R0 * rc);
-      st.push_back({R[i][k].get(), ra2, R1, rc2, W.cores[k].get(), 4, ra, e.op ? e.op->core(k) : nullptr, R0, 4,
+      st.push_back({R[i][k].get(), ra2, R1, rc2, test_core(W, k), 4, ra, e.op ? e.op->core(k) : nullptr, R0, 4,
                     trial_core(e, W, k), rc, R[i][k - 1].get()});
     }
     env_steps(st, false, c);
@@ -319,9 +323,70 @@ void random_orth_rows(const double* B, int q0, long bj, long bi, int len, double
   orth_rows(G, q, len, c);
 }
 
+// G (q x len) = the q leading principal directions of the ncand candidate
+// rows C (q x len row-major, ncand x len) after their components along the q0
+// orthonormal vectors b_j (B[j*bj + i*bi]) are removed (two passes): the right
+// singular vectors of the projected candidates with the largest singular
+// values, orthonormal and orthogonal to the b_j.  Directions the candidates do
+// not supply (rank below q) are filled with seeded random ones.
+void principal_orth_rows(const double* B, int q0, long bj, long bi, int len, const double* C, int ncand, double* G,
+                         int q, unsigned long long seed, Ctx& c) {
+  if (q <= 0) return;
+  DevBuf P((size_t)ncand * len);
+  TT_HIP(hipMemcpyAsync(P.get(), C, sizeof(double) * (size_t)ncand * len, hipMemcpyDeviceToDevice, c.s));
+  auto project = [&](double* M, int nr) {
+    if (q0 <= 0) return;
+    DevBuf T((size_t)nr * q0);
+    for (int pass = 0; pass < 2; ++pass) {
+      Gemm g1;   // T = M B^T
+      g1.M = nr; g1.N = q0; g1.K = len;
+      g1.A = M; g1.am = len; g1.ak = 1;
+      g1.B = B; g1.bk = bi; g1.bn = bj;
+      g1.C = T.get(); g1.cm = q0; g1.cn = 1;
+      gemm(g1, c.s, &c.ws, GemmPrec::F64);
+      Gemm g2;   // M -= T B
+      g2.M = nr; g2.N = len; g2.K = q0;
+      g2.A = T.get(); g2.am = q0; g2.ak = 1;
+      g2.B = B; g2.bk = bj; g2.bn = bi;
+      g2.C = M; g2.cm = len; g2.cn = 1;
+      g2.alpha = -1.0; g2.beta = 1.0;
+      gemm(g2, c.s, &c.ws, GemmPrec::F64);
+    }
+  };
+  project(P.get(), ncand);
+  SvdOut sv;
+  svd_rowmajor_side(P.get(), ncand, len, false, sv, c);
+  // directions with a singular value above rounding level are taken
+  int take = 0;
+  const double s0 = sv.sigma.empty() ? 0.0 : sv.sigma[0];
+  while (take < std::min(q, sv.k) && sv.sigma[take] > 1e-12 * s0 && s0 > 0.0) ++take;
+  if (take > 0)
+    TT_HIP(hipMemcpyAsync(G, sv.Vt.get(), sizeof(double) * (size_t)take * len, hipMemcpyDeviceToDevice, c.s));
+  if (take < q) {
+    // random rows orthogonal to the b_j and to the directions taken
+    DevBuf Bx((size_t)(q0 + take) * len);
+    if (q0 > 0) {
+      if (bi == 1) {
+        copy2d(B, bj, Bx.get(), len, q0, len, c.s);
+      } else {
+        TT_REQUIRE(bj == 1, "basis vectors must be rows or columns");
+        DevBuf t((size_t)len * q0);
+        copy2d(B, bi, t.get(), q0, len, q0, c.s);
+        permute(t.get(), Bx.get(), {len, q0}, {1, 0}, c.s);
+      }
+    }
+    if (take > 0)
+      TT_HIP(hipMemcpyAsync(Bx.get() + (size_t)q0 * len, G, sizeof(double) * (size_t)take * len,
+                            hipMemcpyDeviceToDevice, c.s));
+    random_orth_rows(Bx.get(), q0 + take, len, 1, len, G + (size_t)take * len, q - take, seed, c);
+  }
+  c.sync();
+}
+
 // Move the block index from W.pos to W.pos + 1 (dir > 0) or W.pos - 1 (dir < 0).
 
-bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick, unsigned long long seed) {
+bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick, unsigned long long seed,
+                 const double* cand, int ncand) {
   bool capped = false;
   const int k = W.pos, Lp = W.Lp, r = W.r[k], s = W.r[k + 1], md = W.m;
   const long n1 = (long)r * md * s;
@@ -349,20 +414,25 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     TT_HIP(hipGetLastError());
     SvdOut sv;
     svd_rowmajor_side(Ms.get(), rows, cols, true, sv, c);
-    // Enrichment fills only the capacity the rank cap leaves: once the cap
-    // binds, the truncated SVD directions are kept in full.
+    // Random enrichment fills only the capacity the rank cap leaves (once the
+    // cap binds, the truncated SVD directions are kept in full); residual
+    // enrichment (candidates given) comes on top of the truncated rank, as in
+    // AMEn, so the frame rank can reach cap + kick.
     const int rk_tol = rank_for(sv.sigma, tol_rel, sv.k);
     const int rk0 = std::max(1, std::min(rk_tol, cap));
     capped = rk_tol > cap;
-    const int q = std::max(0, std::min({kick, rows - rk0, cap - rk0}));
+    const int q = std::max(0, std::min({kick, rows - rk0, cand ? kick : cap - rk0}));
     const int rk = rk0 + q;
     // W_k = [U[:, :rk0] | kick]  ([r][4][rk])
     W.cores[k].reserve((size_t)rows * rk);
     copy2d(sv.U.get(), sv.k, W.cores[k].get(), rk, rows, rk0, c.s);
     if (q > 0) {
-      // random columns orthonormalised against U (the columns of W_k)
+      // enrichment columns orthonormalised against U (the columns of W_k)
       DevBuf G((size_t)q * rows);                                // G^T: q x rows
-      random_orth_rows(W.cores[k].get(), rk0, 1, rk, rows, G.get(), q, seed, c);
+      if (cand)
+        principal_orth_rows(W.cores[k].get(), rk0, 1, rk, rows, cand, ncand, G.get(), q, seed, c);
+      else
+        random_orth_rows(W.cores[k].get(), rk0, 1, rk, rows, G.get(), q, seed, c);
       // columns rk0.. of W_k = G (transposed)
       DevBuf Gt((size_t)rows * q);
       permute(G.get(), Gt.get(), {q, rows}, {1, 0}, c.s);
@@ -398,14 +468,19 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     const int rk_tol = rank_for(sv.sigma, tol_rel, sv.k);
     const int rk0 = std::max(1, std::min(rk_tol, cap));
     capped = rk_tol > cap;
-    const int q = std::max(0, std::min({kick, cols - rk0, cap - rk0}));
+    const int q = std::max(0, std::min({kick, cols - rk0, cand ? kick : cap - rk0}));
     const int rk = rk0 + q;
     // W_k = [Vt[:rk0]; kick]  ([rk][4][s])
     W.cores[k].reserve((size_t)rk * cols);
     TT_HIP(hipMemcpyAsync(W.cores[k].get(), sv.Vt.get(), sizeof(double) * (size_t)rk0 * cols, hipMemcpyDeviceToDevice,
                           c.s));
-    if (q > 0)   // random rows orthonormalised against those of Vt
-      random_orth_rows(W.cores[k].get(), rk0, cols, 1, cols, W.cores[k].get() + (size_t)rk0 * cols, q, seed, c);
+    if (q > 0) {   // enrichment rows orthonormalised against those of Vt
+      if (cand)
+        principal_orth_rows(W.cores[k].get(), rk0, cols, 1, cols, cand, ncand, W.cores[k].get() + (size_t)rk0 * cols,
+                            q, seed, c);
+      else
+        random_orth_rows(W.cores[k].get(), rk0, cols, 1, cols, W.cores[k].get() + (size_t)rk0 * cols, q, seed, c);
+    }
     // coef = M Vt[:rk]^T  ((a,l) x rk)
     DevBuf coef((size_t)rows * rk);
     Gemm g;
@@ -762,6 +837,152 @@ BlockTT block_from_frame(const TT& frame, int Lp, Ctx& c) {
   return W;
 }
 
+void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double* rhs, Ctx& c) {
+  struct Img {
+    double coef;
+    const TT* op;   // nullptr: identity
+    const TT* vec;
+  };
+  const int L = sys.L();
+  std::vector<TT> comp;
+  for (int l = 0; l <= L; ++l) comp.push_back(W.component(l, c));
+  const TT& dX = comp[0];
+  const TT& dY = comp[1];
+  const TT& dZ = comp[L];
+  const TT* dT = sys.ineq ? &comp[2] : nullptr;
+  std::vector<Img> R[4], KU[4];
+  for (const Term& t : sys.terms) R[t.res].push_back({t.coef, t.op >= 0 ? sys.ops[t.op] : nullptr, t.vec});
+  // K dU, block rows of eq. (tt-kkt-newton-system)
+  KU[RES_D] = {{1.0, nullptr, &dZ}, {-1.0, sys.ops[OP_AEQT], &dY}};
+  if (sys.ineq) KU[RES_D].push_back({-sys.sense, sys.ops[OP_AIT], dT});
+  KU[RES_P] = {{-1.0, sys.ops[OP_AEQ], &dX}, {1.0, sys.ops[OP_KY], &dY}};
+  if (sys.ineq) KU[RES_T] = {{-sys.sense, sys.ops[OP_TA], &dX}, {1.0, sys.ops[OP_DK], dT}};
+  KU[RES_C] = {{1.0, sys.ops[OP_LZ], &dX}, {1.0, sys.ops[OP_LX], &dZ}};
+  auto norm2 = [&](const std::vector<Img>& v) {
+    double s = 0.0;
+    for (size_t i = 0; i < v.size(); ++i)
+      for (size_t j = i; j < v.size(); ++j) {
+        const double ip = tt_op_dot(*v[i].vec, v[i].op, *v[j].vec, v[j].op, c);
+        s += (i == j ? 1.0 : 2.0) * v[i].coef * v[j].coef * ip;
+      }
+    return std::max(s, 0.0);
+  };
+  // every pair's four-layer environment must stay within a memory budget;
+  // otherwise the check is not made (res = rhs = -1)
+  const double budget = 3.2e7;   // doubles (256 MiB) per environment
+  for (int b = 0; b < 4; ++b) {
+    std::vector<Img> all = KU[b];
+    all.insert(all.end(), R[b].begin(), R[b].end());
+    for (size_t i = 0; i < all.size(); ++i)
+      for (size_t j = i; j < all.size(); ++j)
+        for (int k = 0; k <= all[i].vec->d; ++k) {
+          const double e = (double)all[i].vec->r[k] * (all[i].op ? all[i].op->r[k] : 1) *
+                           (all[j].op ? all[j].op->r[k] : 1) * all[j].vec->r[k];
+          if (e * 4.0 > budget) {
+            *res = *rhs = -1.0;
+            return;
+          }
+        }
+  }
+  double e2 = 0.0, r2 = 0.0;
+  for (int b = 0; b < 4; ++b) {
+    if (R[b].empty() && KU[b].empty()) continue;
+    std::vector<Img> all = KU[b];
+    all.insert(all.end(), R[b].begin(), R[b].end());
+    e2 += norm2(all);
+    r2 += norm2(R[b]);
+  }
+  *res = std::sqrt(e2);
+  *rhs = std::sqrt(r2);
+}
+
+namespace {
+
+// Candidate enrichment rows at core k: every block row b of E = K dU + R
+// (eq. (tt-kkt-newton-system), the current block core as dU_k) projected with
+// the frame's environments behind the block and the sketch's ahead of it.
+// dir > 0: E_b[a][i][t] (t: sketch rank) -> rows [t][(a,i)]; dir < 0:
+// E_b[t][i][b] -> rows [t][(i,b)].  Each block row is scaled to unit norm so
+// that every row of the system contributes.  Returns the number of rows.
+int residual_candidates(const NewtonSys& sys, Envs& envs, Envs& sk, const BlockTT& W, int k, int dir,
+                        const int* key_of_op, const std::vector<int>& key_of_term, int key_id, int rho, DevBuf& cand,
+                        Ctx& c) {
+  const int L = sys.L();
+  const int r = W.r[k], s = W.r[k + 1];
+  const long p = (long)r * 4 * s;
+  struct Src {
+    int row;
+    double coef;
+    int key;
+    const double* x;
+    int rc, rd;
+  };
+  std::vector<Src> src;
+  auto comp = [&](int l) { return W.blk.get() + (size_t)l * p; };
+  src.push_back({RES_D, 1.0, key_id, comp(L), r, s});
+  src.push_back({RES_D, -1.0, key_of_op[OP_AEQT], comp(1), r, s});
+  if (sys.ineq) src.push_back({RES_D, -sys.sense, key_of_op[OP_AIT], comp(2), r, s});
+  src.push_back({RES_P, -1.0, key_of_op[OP_AEQ], comp(0), r, s});
+  src.push_back({RES_P, 1.0, key_of_op[OP_KY], comp(1), r, s});
+  if (sys.ineq) {
+    src.push_back({RES_T, -sys.sense, key_of_op[OP_TA], comp(0), r, s});
+    src.push_back({RES_T, 1.0, key_of_op[OP_DK], comp(2), r, s});
+  }
+  src.push_back({RES_C, 1.0, key_of_op[OP_LZ], comp(0), r, s});
+  src.push_back({RES_C, 1.0, key_of_op[OP_LX], comp(L), r, s});
+  for (size_t t = 0; t < sys.terms.size(); ++t) {
+    const Term& tm = sys.terms[t];
+    src.push_back({tm.res, tm.coef, key_of_term[t], tm.vec->core(k), tm.vec->r[k], tm.vec->r[k + 1]});
+  }
+  const int nrow = sys.ineq ? 4 : 3;
+  const int rows_out = dir > 0 ? r * 4 : 4 * s;   // length of a candidate row
+  const long blk = (long)rho * rows_out;           // one residual block row
+  DevBuf Eb((size_t)4 * blk);
+  fill(4 * blk, 0.0, Eb.get(), c.s);
+  std::vector<DevBuf> operm(src.size());
+  std::vector<LocalApplyArgs> v;
+  for (size_t i = 0; i < src.size(); ++i) {
+    const Src& q = src[i];
+    TT_REQUIRE(q.key >= 0, "residual enrichment: missing environment");
+    const EnvKey& e = envs.keys[q.key];
+    const int R0 = envs.op_rank(e, k), R1 = envs.op_rank(e, k + 1);
+    const double* Op = nullptr;
+    if (e.op) {
+      operm[i].reserve((size_t)e.op->core_size(k));
+      permute_op_core(e.op->core(k), R0, 4, R1, operm[i].get(), c.s);
+      Op = operm[i].get();
+    }
+    double* y = Eb.get() + (size_t)q.row * blk;
+    if (dir > 0)   // [a][i][t]
+      v.push_back({envs.L[q.key][k].get(), r, R0, q.rc, Op, 4, sk.R[q.key][k].get(), rho, R1, q.rd, q.x, y, q.coef,
+                   1.0});
+    else           // [t][i][b]
+      v.push_back({sk.L[q.key][k].get(), rho, R0, q.rc, Op, 4, envs.R[q.key][k].get(), s, R1, q.rd, q.x, y, q.coef,
+                   1.0});
+  }
+  local_apply_many(v, c);
+  // rows of the candidates, one residual block row after another
+  const int used[4] = {RES_D, RES_P, sys.ineq ? RES_T : -1, RES_C};
+  int nc = 0;
+  cand.reserve((size_t)nrow * blk);
+  for (int u = 0; u < 4; ++u) {
+    if (used[u] < 0) continue;
+    double* y = Eb.get() + (size_t)used[u] * blk;
+    const double nrm = dev_norm(y, blk, c);
+    if (!(nrm > 0.0)) continue;
+    double* dst = cand.get() + (size_t)nc * rows_out;
+    if (dir > 0)
+      permute(y, dst, {rows_out, rho}, {1, 0}, c.s, 1.0 / nrm);
+    else
+      axpby(blk, 1.0 / nrm, y, 0.0, dst, c.s);
+    nc += rho;
+  }
+  c.sync();
+  return nc;
+}
+
+}  // namespace
+
 void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInfo& info, Ctx& c) {
   // The block sits at an end core: core 0 (the first sweep runs left to
   // right) or core d-1, where the previous solve's last sweep left it (the
@@ -787,8 +1008,32 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
     key_of_term[t] = (int)keys.size();
     keys.push_back({sys.terms[t].op >= 0 ? sys.ops[sys.terms[t].op] : nullptr, sys.terms[t].vec});
   }
+  // residual enrichment (Sec. 2.3, AMEn of Dolgov and Savostyanov): the kick
+  // directions at a block move are the leading directions of the Newton
+  // residual E = K dU + R (unreduced block rows) projected on the frame's side
+  // behind the block and on a seeded Gaussian TT sketch V of rank rho ahead of
+  // it (reading: the sketch stands in for AMEn's rank-rho residual TT)
+  const bool resid = prm.enrich == 1 && prm.kick > 0;
+  int key_id = -1;
+  if (resid) {
+    key_id = (int)keys.size();
+    keys.push_back({nullptr, nullptr});
+  }
   Envs envs;
   envs.init(keys, d, c);
+  const int rho = prm.kick + 2;
+  TT V;
+  Envs sk;
+  if (resid) {
+    V = TT(d, 4, 1);
+    for (int k = 1; k < d; ++k) V.r[k] = rho;
+    for (int k = 0; k < d; ++k) {
+      V.alloc(k);
+      random_block(V.core(k), V.core_size(k), prm.seed * 7919ull + 104729ull * (unsigned long long)k + 17ull, c);
+    }
+    sk.test = &V;
+    sk.init(keys, d, c);
+  }
   double t0 = now();
   if (from_right)
     for (int k = 0; k < d - 1; ++k) envs.update_left(W, k, c);
@@ -806,6 +1051,18 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   std::vector<double> res_hist;   // max_res of each sweep
   for (int sweep = 0; sweep < prm.max_sweeps; ++sweep) {
     double max_res = 0.0;
+    const bool enrich_now = resid && sweep < prm.kick_sweeps;
+    if (enrich_now) {
+      // sketch environments on the side ahead of the block (its frame cores
+      // stay fixed until the sweep reaches them)
+      const double te = now();
+      if (dir > 0)
+        for (int k = d - 1; k > 0; --k) sk.update_right(W, k, c);
+      else
+        for (int k = 0; k < d - 1; ++k) sk.update_left(W, k, c);
+      c.sync();
+      info.t_env += now() - te;
+    }
     for (int step = 0; step < d; ++step) {
       const int k = (dir > 0) ? step : d - 1 - step;
       TT_REQUIRE(W.pos == k, "block position");
@@ -899,11 +1156,20 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       TT_HIP(hipGetLastError());
       c.sync();
       info.t_solve += now() - ts;
+      // sketched residual of the local system: candidate enrichment rows
+      DevBuf cand;
+      int ncand = 0;
+      if (enrich_now && ((dir > 0 && k < d - 1) || (dir < 0 && k > 0))) {
+        const double te = now();
+        ncand = residual_candidates(sys, envs, sk, W, k, dir, key_of_op, key_of_term, key_id, rho, cand, c);
+        info.t_svd += now() - te;
+      }
       // move the block index and extend the environments
       if (dir > 0 && k < d - 1) {
         double t1 = now();
         info.capped |= split_block(W, +1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
-                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k));
+                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k), ncand ? cand.get() : nullptr,
+                    ncand);
         info.t_svd += now() - t1;
         t1 = now();
         envs.update_left(W, k, c);
@@ -912,7 +1178,8 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       } else if (dir < 0 && k > 0) {
         double t1 = now();
         info.capped |= split_block(W, -1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
-                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k) + 7777ull);
+                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k) + 7777ull,
+                    ncand ? cand.get() : nullptr, ncand);
         info.t_svd += now() - t1;
         t1 = now();
         envs.update_right(W, k, c);

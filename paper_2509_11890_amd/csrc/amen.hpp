@@ -57,8 +57,12 @@ struct BlockTT {
 // passes) and against each other (QR): the random enrichment of a TT core.
 void random_orth_rows(const double* B, int q0, long bj, long bi, int len, double* G, int q, unsigned long long seed,
                       Ctx& c);
+// With candidate rows cand (ncand rows of the kept factor's length: the
+// sketched residual of the local system, see amen_solve) the kick directions
+// are their leading principal directions, added on top of the truncated rank
+// (the frame rank can reach cap + kick).
 bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick = 0,
-                 unsigned long long seed = 0);
+                 unsigned long long seed = 0, const double* cand = nullptr, int ncand = 0);
 // Norm of a device vector (deterministic; synchronises).
 double dev_norm(const double* x, long n, Ctx& c);
 
@@ -72,6 +76,8 @@ struct AmenParams {
   int precond = 0;          // TT_PREC_*
   bool mixed = false;       // BF16 MFMA contractions inside the Krylov solve
   int kick = 2;             // enrichment directions added at every block move
+  int enrich = 1;           // 1: the leading directions of the sketched Newton residual (AMEn,
+                            // Sec. 2.3); 0: seeded random directions
   unsigned long long seed = 0;
   int verbose = 0;          // >= 2: one line per sweep to stderr
   int kick_sweeps = 1 << 30; // enrichment only in the first kick_sweeps half-sweeps
@@ -95,6 +101,14 @@ struct AmenInfo {
 // (0 or d-1).  On return the block is at the end core where the last
 // half-sweep left it, which is the warm start of the next call.
 void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInfo& info, Ctx& c);
+
+// Global residual of the Newton system for the direction held in W (the
+// unreduced system of eq. (tt-kkt-newton-system) with the system's own,
+// rounded operators): *res = ||K dU + R||, *rhs = ||R||, summed over the
+// block rows, each norm exact from operator-image inner products (no image is
+// formed).  The forcing condition of Sec. 3.3 (Lemma "AMEn Directions as
+// Inexact Newton Directions") asks res <= eta rhs.
+void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double* rhs, Ctx& c);
 
 // Build an initial block TT (block at 0) from a frame TT (e.g. the identity).
 BlockTT block_from_frame(const TT& frame, int Lp, Ctx& c);

@@ -71,10 +71,13 @@ int guarded(F&& f) {
 void check_view(const tt_view* v, const char* name) {
   if (!v) throw Error(TT_ERR_ARG, std::string(name) + " is NULL");
   if (v->d < 1 || !v->ranks || !v->cores) throw Error(TT_ERR_ARG, std::string(name) + ": empty view");
+  if (v->dtype != TT_F64) throw Error(TT_ERR_ARG, std::string(name) + ": only TT_F64 views are accepted");
   if (v->ranks[0] != 1 || v->ranks[v->d] != 1) throw Error(TT_ERR_ARG, std::string(name) + ": boundary ranks must be 1");
   if (v->m_out < 1 || v->m_in < 1) throw Error(TT_ERR_ARG, std::string(name) + ": mode sizes");
   for (int k = 0; k < v->d; ++k) {
     if (v->ranks[k + 1] < 1) throw Error(TT_ERR_ARG, std::string(name) + ": ranks must be positive");
+    if (v->capacity_rank > 0 && v->ranks[k + 1] > v->capacity_rank)
+      throw Error(TT_ERR_ARG, std::string(name) + ": a rank exceeds capacity_rank");
     if (!v->cores[k]) throw Error(TT_ERR_ARG, std::string(name) + ": NULL core pointer");
   }
 }
@@ -367,24 +370,90 @@ int tt_local_solve(const tt_local_op* K, const double* rhs, double* x, const tt_
   });
 }
 
-int tt_round(tt_view* t, double tol, int32_t tol_mode, int32_t max_rank, double* zeta_out, void* stream) {
+int tt_op_inner(const tt_view* vi, const tt_view* Oi, const tt_view* vj, const tt_view* Oj, double* out,
+                void* stream) {
+  return guarded([&]() -> int {
+    check_view(vi, "vi");
+    check_view(vj, "vj");
+    if (!out) throw Error(TT_ERR_ARG, "NULL out");
+    if (vi->m_in != 1 || vj->m_in != 1 || vi->m_out != vj->m_out || vi->d != vj->d)
+      throw Error(TT_ERR_ARG, "vi and vj must be TT vectors with the same modes");
+    for (const tt_view* O : {Oi, Oj}) {
+      if (!O) continue;
+      check_view(O, "operator");
+      if (O->d != vi->d || O->m_out != vi->m_out || O->m_in != vi->m_out)
+        throw Error(TT_ERR_ARG, "operator modes must match the vectors");
+    }
+    Ctx& c = ctx_for(stream);
+    c.prec = GemmPrec::F64;
+    TT a = tt_from_view(*vi, c), b = tt_from_view(*vj, c);
+    std::unique_ptr<TT> A, B;
+    if (Oi) A = std::make_unique<TT>(tt_from_view(*Oi, c));
+    if (Oj) B = std::make_unique<TT>(tt_from_view(*Oj, c));
+    *out = tt_op_dot(a, A.get(), b, B.get(), c);
+    return TT_OK;
+  });
+}
+
+int tt_round_workspace(const tt_view* t, size_t* bytes) {
+  return guarded([&]() -> int {
+    check_view(t, "t");
+    if (!bytes) throw Error(TT_ERR_ARG, "NULL bytes");
+    // bound on the device memory one rounding takes: the working copy and the
+    // orthogonalised cores, then per bond the QR / one-sided Jacobi SVD
+    // temporaries of the (r_k m) x r_{k+1} unfolding and the next core
+    const double m = (double)t->m_out * t->m_in;
+    double sum = 0.0, per_bond = 0.0;
+    for (int k = 0; k < t->d; ++k) {
+      const double rows = t->ranks[k] * m, cols = t->ranks[k + 1];
+      sum += rows * cols;
+      const double next = k + 1 < t->d ? cols * m * t->ranks[k + 2] : 0.0;
+      per_bond = std::max(per_bond, 12.0 * rows * cols + 6.0 * cols * cols + 3.0 * next + 64.0 * cols);
+    }
+    *bytes = (size_t)(2.0 * 8.0 * (2.0 * sum + per_bond)) + ((size_t)1 << 20);
+    return TT_OK;
+  });
+}
+
+int tt_round(tt_view* t, double tol, int32_t tol_mode, int32_t max_rank, double* zeta_out, void* ws,
+             size_t ws_bytes, void* stream) {
   return guarded([&]() -> int {
     check_view(t, "t");
     if (!(tol >= 0.0)) throw Error(TT_ERR_ARG, "tol must be >= 0");
     if (max_rank < 1) throw Error(TT_ERR_ARG, "max_rank must be >= 1");
-    Ctx& c = ctx_for(stream);
+    if (ws && ((uintptr_t)ws & 255)) throw Error(TT_ERR_ARG, "workspace must be 256-byte aligned");
+    auto run = [&](Ctx& c) {
+      TT w = tt_from_view(*t, c);
+      double eps = tol;
+      if (tol_mode == TT_TOL_REL) eps = tol * tt_norm(w, c);
+      bool capped = false;
+      const double zeta = tt_round_abs(w, eps, max_rank, c, &capped);
+      c.sync();
+      // the caller's cores change only once the rounding has succeeded
+      for (int k = 0; k < t->d; ++k)
+        TT_HIP(hipMemcpyAsync(t->cores[k], w.core(k), sizeof(double) * w.core_size(k), hipMemcpyDeviceToDevice, c.s));
+      for (int k = 0; k <= t->d; ++k) t->ranks[k] = w.r[k];
+      c.sync();
+      if (zeta_out) *zeta_out = zeta;
+      return capped ? (int)TT_ERR_RANK_CAP : (int)TT_OK;
+    };
+    if (!ws) {
+      Ctx& c = ctx_for(stream);
+      c.prec = GemmPrec::F64;
+      return run(c);
+    }
+    // every device buffer of the call comes from the caller's workspace: a
+    // context of its own (destroyed, with its buffers, inside the scope)
+    ArenaScope scope(ws, ws_bytes);
+    Ctx c;
+    c.s = as_stream(stream);
     c.prec = GemmPrec::F64;
-    TT w = tt_from_view(*t, c);
-    double eps = tol;
-    if (tol_mode == TT_TOL_REL) eps = tol * tt_norm(w, c);
-    bool capped = false;
-    const double zeta = tt_round_abs(w, eps, max_rank, c, &capped);
-    for (int k = 0; k <= t->d; ++k) t->ranks[k] = w.r[k];
-    for (int k = 0; k < t->d; ++k)
-      TT_HIP(hipMemcpyAsync(t->cores[k], w.core(k), sizeof(double) * w.core_size(k), hipMemcpyDeviceToDevice, c.s));
-    c.sync();
-    if (zeta_out) *zeta_out = zeta;
-    return capped ? TT_ERR_RANK_CAP : TT_OK;
+    try {
+      return run(c);
+    } catch (...) {
+      (void)hipStreamSynchronize(c.s);
+      throw;
+    }
   });
 }
 
@@ -420,23 +489,54 @@ void ttipm_params_default(ttipm_params* p) {
   p->g4_window = 4;
   p->g4_retries = 3;
   p->shift_mode = 1;
+  p->newton_check = 1;
+  p->refine_sweeps = 2;
+  p->enrich = 1;
 }
 
 int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {
   return guarded([&]() -> int {
     if (!desc || !out) throw Error(TT_ERR_ARG, "NULL argument");
-    check_view(&desc->graph, "graph");
-    if (desc->graph.m_out != 2 || desc->graph.m_in != 2) throw Error(TT_ERR_ARG, "graph must have 2 x 2 modes");
     Ctx& c = ctx_for(nullptr);
     c.prec = GemmPrec::F64;
-    TT G = tt_from_view(desc->graph, c);
-    std::unique_ptr<TT> nd;
-    if (desc->kind == TTIPM_CC) {
-      check_view(&desc->negdeg, "negdeg");
-      nd = std::make_unique<TT>(tt_from_view(desc->negdeg, c));
-    }
     auto p = std::make_unique<ttipm_problem>();
-    p->P = build_problem(desc->kind, G, nd.get(), c);
+    if (desc->kind == TTIPM_GENERIC) {
+      auto get = [&](const tt_view& v, const char* name, std::unique_ptr<TT>& hold) -> const TT* {
+        check_view(&v, name);
+        hold = std::make_unique<TT>(tt_from_view(v, c));
+        return hold.get();
+      };
+      std::unique_ptr<TT> h[9];
+      GenericSdp g;
+      g.C = get(desc->C, "C", h[0]);
+      g.Aeq = get(desc->Aeq, "Aeq", h[1]);
+      g.AeqT = get(desc->AeqT, "AeqT", h[2]);
+      g.Beq = get(desc->Beq, "Beq", h[3]);
+      g.KY = get(desc->KY, "KY", h[4]);
+      if (desc->Aineq.d > 0) {
+        g.Aineq = get(desc->Aineq, "Aineq", h[5]);
+        g.AineqT = get(desc->AineqT, "AineqT", h[6]);
+        g.Bineq = get(desc->Bineq, "Bineq", h[7]);
+        g.KT = get(desc->KT, "KT", h[8]);
+        g.sense = desc->ineq_sense;
+        g.q = desc->q;
+        g.x0_ineq = desc->x0_ineq;
+        g.t0_ineq = desc->t0_ineq;
+      }
+      if (!(desc->lam0 > 0.0)) throw Error(TT_ERR_ARG, "lam0 must be positive");
+      g.lam0 = desc->lam0;
+      p->P = build_problem_generic(g, c);
+    } else {
+      check_view(&desc->graph, "graph");
+      if (desc->graph.m_out != 2 || desc->graph.m_in != 2) throw Error(TT_ERR_ARG, "graph must have 2 x 2 modes");
+      TT G = tt_from_view(desc->graph, c);
+      std::unique_ptr<TT> nd;
+      if (desc->kind == TTIPM_CC) {
+        check_view(&desc->negdeg, "negdeg");
+        nd = std::make_unique<TT>(tt_from_view(desc->negdeg, c));
+      }
+      p->P = build_problem(desc->kind, G, nd.get(), c);
+    }
     c.sync();
     *out = p.release();
     return TT_OK;
@@ -525,11 +625,12 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
       if (prm->verbose)
         std::fprintf(stderr,
                      "it %2d %s mu %.2e pobj %+.10e dobj %+.10e gap %.2e ep %.1e ed %.1e ap %.3e/%.3e ad %.3e/%.3e "
-                     "bt %d g4 %d psi %.2e zx %.1e/%.1e zz %.1e/%.1e rX %d rY %d rZ %d rW %d sw %d/%d kr %d sig %.2e "
-                     "eta %.1e t %.3fs\n",
+                     "bt %d g4 %d psi %.2e zx %.1e/%.1e zz %.1e/%.1e nres %.1e rf %d rX %d rY %d rZ %d rW %d sw %d/%d "
+                     "kr %d sig %.2e eta %.1e t %.3fs\n",
                      inf.iter, inf.direction ? "aho" : (inf.xz_fallback ? "xz*" : "xz "), inf.mu, inf.pobj, inf.dobj, inf.rel_gap, inf.eps_p,
                      inf.eps_d, inf.alpha_p, inf.alpha_p_max, inf.alpha_d, inf.alpha_d_max, inf.backtracks,
-                     inf.g4_retries, inf.psi, inf.zeta_x, inf.zeta_x_cap, inf.zeta_z, inf.zeta_z_cap, inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w, inf.sweeps_pred, inf.sweeps_corr,
+                     inf.g4_retries, inf.psi, inf.zeta_x, inf.zeta_x_cap, inf.zeta_z, inf.zeta_z_cap, inf.newton_res,
+                     inf.refine_sweeps, inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w, inf.sweeps_pred, inf.sweeps_corr,
                      inf.krylov_iters, inf.sigma, inf.eta, inf.t_total);
       if (!std::isfinite(inf.pobj)) throw Error(TT_ERR_NUMERIC, "non-finite objective");
     }

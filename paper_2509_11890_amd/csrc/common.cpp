@@ -1,7 +1,10 @@
 // Error text across the C boundary and the caching device allocator.
 #include "common.hpp"
 
+#include <algorithm>
 #include <map>
+#include <string>
+#include <vector>
 #include <mutex>
 
 namespace ttipm {
@@ -26,6 +29,14 @@ Pool& global_pool() {
   return *p;
 }
 thread_local Pool* t_pool = nullptr;
+
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, top = 0, peak = 0;
+  struct Blk { size_t off, end; bool freed; };
+  std::vector<Blk> stack;
+};
+thread_local Arena* t_arena = nullptr;
 Pool& pool() { return t_pool ? *t_pool : global_pool(); }
 size_t size_class(size_t bytes) {
   size_t c = 256;
@@ -35,6 +46,16 @@ size_t size_class(size_t bytes) {
 }  // namespace
 
 void* pool_alloc(size_t bytes) {
+  if (t_arena) {
+    Arena& A = *t_arena;
+    const size_t off = (A.top + 255) & ~size_t(255);
+    if (off + bytes > A.cap)
+      throw Error(TT_ERR_ARG, "workspace too small: needs more than " + std::to_string(A.cap) + " bytes");
+    A.stack.push_back({off, off + bytes, false});
+    A.top = off + bytes;
+    A.peak = std::max(A.peak, A.top);
+    return A.base + off;
+  }
   const size_t cls = size_class(bytes);
   Pool& P = pool();
   {
@@ -63,6 +84,21 @@ void* pool_alloc(size_t bytes) {
 
 void pool_free(void* p, size_t bytes) {
   if (!p) return;
+  if (t_arena) {
+    Arena& A = *t_arena;
+    char* q = static_cast<char*>(p);
+    if (q >= A.base && q < A.base + A.cap) {
+      const size_t off = (size_t)(q - A.base);
+      for (auto it = A.stack.rbegin(); it != A.stack.rend(); ++it)
+        if (it->off == off && !it->freed) {
+          it->freed = true;
+          break;
+        }
+      while (!A.stack.empty() && A.stack.back().freed) A.stack.pop_back();
+      A.top = A.stack.empty() ? 0 : A.stack.back().end;
+      return;
+    }
+  }
   const size_t cls = size_class(bytes);
   Pool& P = pool();
   std::lock_guard<std::mutex> g(P.mu);
@@ -74,6 +110,20 @@ size_t pool_bytes_in_use() {
   const long long n = pool().in_use;
   return n > 0 ? (size_t)n : 0;
 }
+
+ArenaScope::ArenaScope(void* base, size_t bytes) {
+  if (t_arena) throw Error(TT_ERR_ARG, "nested workspace scopes");
+  t_arena = new Arena();
+  t_arena->base = static_cast<char*>(base);
+  t_arena->cap = bytes;
+}
+
+ArenaScope::~ArenaScope() {
+  delete t_arena;
+  t_arena = nullptr;
+}
+
+size_t ArenaScope::peak() const { return t_arena ? t_arena->peak : 0; }
 
 void pool_local_begin() {
   if (!t_pool) t_pool = new Pool();

@@ -54,6 +54,21 @@ void pool_trim();
 void pool_local_begin();
 void pool_local_end();
 
+// While an ArenaScope is alive, every pool allocation of the calling thread is
+// served from the caller-provided device region [base, base + bytes) instead
+// of the pool (as a stack: a freed block at the top is reclaimed, so scoped
+// temporaries reuse the space).  An allocation that does not fit throws
+// TT_ERR_ARG.  Blocks taken from the region must be freed before the scope
+// ends, and the stream that used them synchronised.
+class ArenaScope {
+ public:
+  ArenaScope(void* base, size_t bytes);
+  ~ArenaScope();
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+  size_t peak() const;
+};
+
 // Owning device buffer of doubles.  Grows, never shrinks.
 class DevBuf {
  public:

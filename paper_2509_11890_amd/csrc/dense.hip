@@ -447,6 +447,154 @@ __global__ __launch_bounds__(DT) void trsm_lower_t_kernel(const double* L, int n
   }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-resident variants for matrices that fit the workgroup's LDS: the whole
+// matrix is staged once (row stride n + 1, odd for even n, so that the column
+// accesses of a wavefront fall in different banks), factorised there and
+// written back.  Thread t works on columns t % 32 + 32 k and rows t / 32 +
+// 32 k' of each trailing update.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(DT) void cholesky_lds_kernel(double* A, int n, int* status) {
+  extern __shared__ double S[];
+  __shared__ int s_bad;
+  const int ld = n | 1;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  for (int t = tid; t < n * n; t += DT) S[(t / n) * ld + t % n] = A[t];
+  if (tid == 0) { status[0] = 0; s_bad = 0; }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      const double d = S[j * ld + j];
+      if (!(d > 0.0)) { status[0] = j + 1; s_bad = 1; }
+      S[j * ld + j] = (d > 0.0) ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    if (s_bad) return;
+    const double inv = 1.0 / S[j * ld + j];
+    for (int i = j + 1 + tid; i < n; i += DT) S[i * ld + j] *= inv;
+    __syncthreads();
+    for (int i = j + 1 + ty; i < n; i += DT / 32) {
+      const double a = S[i * ld + j];
+      for (int c = j + 1 + tx; c <= i; c += 32) S[i * ld + c] -= a * S[c * ld + j];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < n * n; t += DT) {
+    const int i = t / n, c = t % n;
+    A[t] = (c <= i) ? S[i * ld + c] : 0.0;
+  }
+}
+
+// LU with partial pivoting and solve, as lu_solve_kernel, with A and B in LDS.
+__global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, double* B, int nrhs, int* status) {
+  extern __shared__ double S[];
+  __shared__ double rv[DT];
+  __shared__ int ri[DT];
+  __shared__ int s_piv;
+  const int ld = n | 1;
+  double* Bs = S + (size_t)n * ld;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  for (int t = tid; t < n * n; t += DT) S[(t / n) * ld + t % n] = A[t];
+  for (int t = tid; t < n * nrhs; t += DT) Bs[t] = B[t];
+  if (tid == 0) status[0] = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double best = -1.0;
+    int bi = j;
+    for (int i = j + tid; i < n; i += DT) {
+      const double v = fabs(S[i * ld + j]);
+      if (v > best) { best = v; bi = i; }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int o = DT / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        const double a = rv[tid], b = rv[tid + o];
+        const int ia = ri[tid], ib = ri[tid + o];
+        if (b > a || (b == a && ib < ia)) { rv[tid] = b; ri[tid] = ib; }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) s_piv = ri[0];
+    __syncthreads();
+    const int piv = s_piv;
+    if (piv != j) {
+      for (int c = tid; c < n; c += DT) {
+        const double t = S[j * ld + c]; S[j * ld + c] = S[piv * ld + c]; S[piv * ld + c] = t;
+      }
+      for (int c = tid; c < nrhs; c += DT) {
+        const double t = Bs[j * nrhs + c]; Bs[j * nrhs + c] = Bs[piv * nrhs + c]; Bs[piv * nrhs + c] = t;
+      }
+    }
+    __syncthreads();
+    const double d = S[j * ld + j];
+    if (d == 0.0) {
+      if (tid == 0) status[0] = j + 1;
+      return;
+    }
+    const double inv = 1.0 / d;
+    for (int i = j + 1 + tid; i < n; i += DT) S[i * ld + j] *= inv;
+    __syncthreads();
+    for (int i = j + 1 + ty; i < n; i += DT / 32) {
+      const double a = S[i * ld + j];
+      for (int c = j + 1 + tx; c < n; c += 32) S[i * ld + c] -= a * S[j * ld + c];
+      for (int c = tx; c < nrhs; c += 32) Bs[i * nrhs + c] -= a * Bs[j * nrhs + c];
+    }
+    __syncthreads();
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const double inv = 1.0 / S[j * ld + j];
+    for (int c = tid; c < nrhs; c += DT) Bs[j * nrhs + c] *= inv;
+    __syncthreads();
+    for (int i = ty; i < j; i += DT / 32) {
+      const double a = S[i * ld + j];
+      for (int c = tx; c < nrhs; c += 32) Bs[i * nrhs + c] -= a * Bs[j * nrhs + c];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < n * n; t += DT) A[t] = S[(t / n) * ld + t % n];
+  for (int t = tid; t < n * nrhs; t += DT) B[t] = Bs[t];
+}
+
+// Triangular solve L X = B (or L^T X = B) for a slab of right-hand sides per
+// workgroup: workgroup g takes columns [g cb, g cb + cb) of B into LDS; L is
+// read through the caches (every workgroup reads all of it).
+template <bool TRANS>
+__global__ __launch_bounds__(DT) void trsm_slab_kernel(const double* L, int n, double* B, int nrhs, int cb) {
+  extern __shared__ double Bs[];
+  const int c0 = blockIdx.x * cb;
+  const int w = min(cb, nrhs - c0);
+  const int tid = threadIdx.x;
+  const int c = tid % cb, rg = tid / cb, nrg = DT / cb;
+  for (int t = tid; t < n * w; t += DT) Bs[(t / w) * cb + t % w] = B[(long)(t / w) * nrhs + c0 + t % w];
+  __syncthreads();
+  // threads beyond nrg full row groups (cb not dividing DT) stay idle
+  const bool active = c < w && rg < nrg;
+  if (!TRANS) {
+    for (int j = 0; j < n; ++j) {
+      if (rg == 0 && active) Bs[j * cb + c] /= L[(long)j * n + j];
+      __syncthreads();
+      if (active) {
+        const double bj = Bs[j * cb + c];
+        for (int i = j + 1 + rg; i < n; i += nrg) Bs[i * cb + c] -= L[(long)i * n + j] * bj;
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int j = n - 1; j >= 0; --j) {
+      if (rg == 0 && active) Bs[j * cb + c] /= L[(long)j * n + j];
+      __syncthreads();
+      if (active) {
+        const double bj = Bs[j * cb + c];
+        for (int i = rg; i < j; i += nrg) Bs[i * cb + c] -= L[(long)j * n + i] * bj;
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = tid; t < n * w; t += DT) B[(long)(t / w) * nrhs + c0 + t % w] = Bs[(t / w) * cb + t % w];
+}
+
 __global__ void symmetrize_kernel(double* A, int n) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long)n * n) return;
@@ -791,27 +939,76 @@ void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* w
 
 // The single-workgroup factorisations below are timed as one group; their
 // algorithmic flops are the textbook counts.
+// Dynamic LDS opt-in for the small dense kernels (the same device limit as the
+// Jacobi kernels).
+static size_t small_lds_limit() {
+  static size_t limit = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+      (void)hipGetLastError();
+      return (size_t)0;
+    }
+    // static shared memory of lu_solve_lds_kernel (rv, ri) is 12 KiB
+    size_t lim = (size_t)v - (size_t)DT * 12 - 256;
+    const void* ks[] = {reinterpret_cast<const void*>(&cholesky_lds_kernel),
+                        reinterpret_cast<const void*>(&lu_solve_lds_kernel),
+                        reinterpret_cast<const void*>(&trsm_slab_kernel<false>),
+                        reinterpret_cast<const void*>(&trsm_slab_kernel<true>)};
+    if (lim > 65536 - (size_t)DT * 12 - 256)
+      for (const void* k : ks)
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
+          (void)hipGetLastError();
+          lim = 65536 - (size_t)DT * 12 - 256;
+          break;
+        }
+    return lim;
+  }();
+  return limit;
+}
+
+// The single-workgroup factorisations below are timed as one group; their
+// algorithmic flops are the textbook counts.
 void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s) {
   const double nn = n;
-  launch_prof(PK_DENSE_1WG, 2.0 / 3.0 * nn * nn * nn + 2.0 * nn * nn * nrhs, 8.0 * (2.0 * nn * nn + 2.0 * nn * nrhs),
-              lu_solve_kernel, dim3(1), dim3(DT), 0u, s, A, n, B, nrhs, status);
+  const double fl = 2.0 / 3.0 * nn * nn * nn + 2.0 * nn * nn * nrhs, by = 8.0 * (2.0 * nn * nn + 2.0 * nn * nrhs);
+  const size_t lds = sizeof(double) * ((size_t)n * (n | 1) + (size_t)n * nrhs);
+  if (lds <= small_lds_limit())
+    launch_prof(PK_DENSE_1WG, fl, by, lu_solve_lds_kernel, dim3(1), dim3(DT), (unsigned)lds, s, A, n, B, nrhs, status);
+  else
+    launch_prof(PK_DENSE_1WG, fl, by, lu_solve_kernel, dim3(1), dim3(DT), 0u, s, A, n, B, nrhs, status);
   TT_HIP(hipGetLastError());
 }
 
 void dense_cholesky(double* A, int n, int* status, hipStream_t s) {
   const double nn = n;
-  launch_prof(PK_DENSE_1WG, nn * nn * nn / 3.0, 8.0 * 2.0 * nn * nn, cholesky_kernel, dim3(1), dim3(DT), 0u, s, A, n,
-              status);
+  const size_t lds = sizeof(double) * (size_t)n * (n | 1);
+  if (lds <= small_lds_limit())
+    launch_prof(PK_DENSE_1WG, nn * nn * nn / 3.0, 8.0 * 2.0 * nn * nn, cholesky_lds_kernel, dim3(1), dim3(DT),
+                (unsigned)lds, s, A, n, status);
+  else
+    launch_prof(PK_DENSE_1WG, nn * nn * nn / 3.0, 8.0 * 2.0 * nn * nn, cholesky_kernel, dim3(1), dim3(DT), 0u, s, A,
+                n, status);
   TT_HIP(hipGetLastError());
 }
 
 void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s) {
   const double nn = n;
   const double fl = nn * nn * nrhs, by = 8.0 * (0.5 * nn * nn + 2.0 * nn * nrhs);
-  if (transpose)
+  // slabs of up to 16 right-hand sides, one workgroup each
+  const int cb = std::min(16, std::max(1, nrhs));
+  const size_t lds = sizeof(double) * (size_t)n * cb;
+  if (lds <= small_lds_limit()) {
+    const dim3 grid((nrhs + cb - 1) / cb);
+    if (transpose)
+      launch_prof(PK_DENSE_1WG, fl, by, trsm_slab_kernel<true>, grid, dim3(DT), (unsigned)lds, s, L, n, B, nrhs, cb);
+    else
+      launch_prof(PK_DENSE_1WG, fl, by, trsm_slab_kernel<false>, grid, dim3(DT), (unsigned)lds, s, L, n, B, nrhs, cb);
+  } else if (transpose) {
     launch_prof(PK_DENSE_1WG, fl, by, trsm_lower_t_kernel, dim3(1), dim3(DT), 0u, s, L, n, B, nrhs);
-  else
+  } else {
     launch_prof(PK_DENSE_1WG, fl, by, trsm_lower_kernel, dim3(1), dim3(DT), 0u, s, L, n, B, nrhs);
+  }
   TT_HIP(hipGetLastError());
 }
 

@@ -523,7 +523,10 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   if (q.am < 0 || q.ak < 0 || q.bk < 0 || q.bn < 0 ||
       (double)(q.M - 1) * q.am + (double)(q.K - 1 + BK16) * q.ak > 536870911.0 ||
       (double)(q.N - 1) * q.bn + (double)(q.K - 1 + BK16) * q.bk > 536870911.0)
-    throw Error(TT_ERR_ARG, "gemm operand too large for 32-bit byte offsets");
+    throw Error(TT_ERR_ARG, "gemm operand too large for 32-bit byte offsets (M " + std::to_string(q.M) + " N " +
+                                std::to_string(q.N) + " K " + std::to_string(q.K) + " am " + std::to_string(q.am) +
+                                " ak " + std::to_string(q.ak) + " bk " + std::to_string(q.bk) + " bn " +
+                                std::to_string(q.bn) + " batch " + std::to_string(q.batch) + ")");
   KArgs g;
   g.M = q.M; g.N = q.N; g.K = q.K;
   g.A = q.A; g.am = q.am; g.ak = q.ak; g.sA = q.sA;

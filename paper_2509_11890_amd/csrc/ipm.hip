@@ -151,8 +151,78 @@ Problem build_problem(int kind, const TT& G, const TT* negdeg, Ctx& c) {
     P.oneT = tt_clone(JmI, c);
     P.q = P.n * P.n - P.n;
     P.lam0 = 2.0;
+    P.x0_ineq = P.lam0 / 10.0;
   } else {
     throw Error(TT_ERR_ARG, "unknown problem kind");
+  }
+  compress(P.C, c);
+  compress(P.Aeq, c);
+  compress(P.AeqT, c);
+  compress(P.KY, c);
+  if (P.ineq) {
+    compress(P.Aineq, c);
+    compress(P.AineqT, c);
+    compress(P.KT, c);
+    compress(P.oneT, c);
+  }
+  P.normB = tt_norm(P.Beq, c);
+  P.normC = tt_norm(P.C, c);
+  return P;
+}
+
+Problem build_problem_generic(const GenericSdp& g, Ctx& c) {
+  auto vec = [](const TT* t, const char* name) {
+    TT_REQUIRE(t && t->mo == 4 && t->mi == 1, std::string(name) + " must be a vec_TT vector (mode 4)");
+  };
+  auto op = [](const TT* t, const char* name) {
+    TT_REQUIRE(t && t->mo == 4 && t->mi == 4, std::string(name) + " must be an operator on vec_TT (4 x 4 modes)");
+  };
+  vec(g.C, "C");
+  vec(g.Beq, "B_eq");
+  op(g.Aeq, "A_eq");
+  op(g.AeqT, "A_eq^T");
+  op(g.KY, "K_Y");
+  const int d = g.C->d;
+  for (const TT* t : {g.Aeq, g.AeqT, g.Beq, g.KY})
+    TT_REQUIRE(t->d == d, "every TT of the problem must have the same number of cores");
+  Problem P;
+  P.kind = TTIPM_GENERIC;
+  P.d = d;
+  P.n = std::ldexp(1.0, d);
+  P.Ivec = tt_rank1(d, 4, 1, I4, c);
+  P.I2 = tt_rank1(d, 2, 2, {1, 0, 0, 1}, c);
+  {
+    std::vector<double> i16(16, 0.0);
+    for (int i = 0; i < 4; ++i) i16[i * 4 + i] = 1.0;
+    P.I16 = tt_rank1(d, 4, 4, i16, c);
+  }
+  P.C = tt_clone(*g.C, c);
+  P.Aeq = tt_clone(*g.Aeq, c);
+  P.AeqT = tt_clone(*g.AeqT, c);
+  P.Beq = tt_clone(*g.Beq, c);
+  P.KY = tt_clone(*g.KY, c);
+  P.lam0 = g.lam0;
+  if (g.Aineq) {
+    op(g.Aineq, "A_ineq");
+    op(g.AineqT, "A_ineq^T");
+    op(g.KT, "K_T");
+    vec(g.Bineq, "B_ineq");
+    for (const TT* t : {g.Aineq, g.AineqT, g.KT, g.Bineq})
+      TT_REQUIRE(t->d == d, "every TT of the problem must have the same number of cores");
+    TT_REQUIRE(g.sense == 1.0 || g.sense == -1.0, "ineq_sense must be +1 or -1");
+    P.ineq = true;
+    P.sense = g.sense;
+    P.Aineq = tt_clone(*g.Aineq, c);
+    P.AineqT = tt_clone(*g.AineqT, c);
+    P.KT = tt_clone(*g.KT, c);
+    P.Bineq = tt_clone(*g.Bineq, c);
+    // active inequality mask 1_T = vec_TT(J) - K_T vec_TT(J)
+    TT Jvec = tt_rank1(d, 4, 1, J4, c);
+    TT KJ = tt_matvec(P.KT, Jvec, c);
+    P.oneT = tt_add({&Jvec, &KJ}, {1.0, -1.0}, c);
+    P.q = g.q;
+    P.x0_ineq = g.x0_ineq;
+    P.t0_ineq = g.t0_ineq;
   }
   compress(P.C, c);
   compress(P.Aeq, c);
@@ -183,10 +253,10 @@ void init_state(const Problem& P, const ttipm_params& prm, State& S, Ctx& c) {
     TT Jvec = tt_rank1(P.d, 4, 1, J4, c);
     TT AJ = tt_matvec(P.Aineq, Jvec, c);
     compress(AJ, c);
-    TT X2 = tt_add({&S.X, &AJ}, {1.0, P.lam0 / 10.0}, c);
+    TT X2 = tt_add({&S.X, &AJ}, {1.0, P.x0_ineq}, c);
     S.X = std::move(X2);
     S.T = tt_clone(AJ, c);
-    tt_scale(S.T, 1e-3, c);
+    tt_scale(S.T, P.t0_ineq, c);
   }
   S.eta = prm.eta0;
   S.iter = 0;
@@ -682,10 +752,13 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   ap.gmres_maxit = prm.gmres_maxit;
   ap.precond = prm.precond;
   ap.mixed = prm.precision == TTIPM_MIXED;
-  // Random enrichment lets the frame ranks grow past a block-ALS fixed point;
-  // once a Newton frame has been truncated by the rank cap the ranks cannot
-  // grow any more, and enrichment is switched off for the rest of the solve.
-  ap.kick = S.frame_capped ? 0 : std::max(0, prm.kick);
+  // Enrichment lets the frame ranks grow past a block-ALS fixed point.  The
+  // residual directions stay on when the rank cap binds (the split keeps room
+  // for them); random directions are switched off for the rest of the solve
+  // once a Newton frame has been truncated by the cap, where they would only
+  // perturb the truncated solve.
+  ap.enrich = prm.enrich;
+  ap.kick = (prm.enrich == 0 && S.frame_capped) ? 0 : std::max(0, prm.kick);
   ap.verbose = prm.verbose;
   ap.kick_sweeps = std::max(0, prm.kick_sweeps);
   ap.mlp = prm.mlp ? &const_cast<tt_mlp*>(static_cast<const tt_mlp*>(prm.mlp))->net : nullptr;
@@ -777,6 +850,32 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   AmenInfo ai_c;
   amen_solve(sys, S.W, ap, ai_c, c);
   S.frame_capped |= ai_c.capped;
+  // Global FP64 residual of the corrector system (Sec. 3.3, Lemma "AMEn
+  // Directions as Inexact Newton Directions": ||K dU + R|| <= eta ||R||).  In
+  // mixed precision a direction that misses it is refined by FP64 AMEn
+  // sweeps warm-started from it (iterative refinement of the Newton solve).
+  if (prm.newton_check) {
+    const double t0 = now();
+    double res = 0.0, rhs = 0.0;
+    newton_residual(sys, S.W, &res, &rhs, c);
+    info.newton_res = rhs > 0 ? res / rhs : (res < 0 ? -1.0 : 0.0);
+    if (ap.mixed && info.newton_res > S.eta) {
+      AmenParams ar = ap;
+      ar.mixed = false;
+      ar.max_sweeps = std::max(2, prm.refine_sweeps);
+      AmenInfo ai_r;
+      amen_solve(sys, S.W, ar, ai_r, c);
+      S.frame_capped |= ai_r.capped;
+      info.refine_sweeps = ai_r.sweeps;
+      ai_c.krylov_iters += ai_r.krylov_iters;
+      ai_c.t_env += ai_r.t_env;
+      ai_c.t_solve += ai_r.t_solve;
+      ai_c.t_svd += ai_r.t_svd;
+      newton_residual(sys, S.W, &res, &rhs, c);
+      info.newton_res = rhs > 0 ? res / rhs : (res < 0 ? -1.0 : 0.0);
+    }
+    info.t_check = now() - t0;
+  }
   TT dX2 = S.W.component(0, c), dY2 = S.W.component(1, c), dZ2 = S.W.component(L, c);
   t1 = now();
   run_concurrent(c, {[&](Ctx& cx) { info.alpha_p_max = step_length(S.X, dX2, S.EX, S.has_EX, prm, sd + 3, cx); },

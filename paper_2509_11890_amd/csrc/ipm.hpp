@@ -13,6 +13,7 @@ struct Problem {
   int kind = 0, d = 0;
   double n = 0, q = 0;
   double lam0 = 1.0;
+  double x0_ineq = 0.0, t0_ineq = 1e-3;   // X0 = lam0 I + x0_ineq A_ineq(J), T0 = t0_ineq A_ineq(J)
   bool ineq = false;
   double sense = 1.0;
   TT C, Aeq, AeqT, KY, Beq;          // vec_TT vectors (mode 4) and operators (4 x 4)
@@ -40,6 +41,14 @@ struct State {
 };
 
 Problem build_problem(int kind, const TT& graph, const TT* negdeg, Ctx& c);
+// The tensorised SDP given directly (Sec. 3.2): C, B_eq (and B_ineq) vec_TT
+// vectors, the operators on vec_TT; Aineq == nullptr: no inequalities.
+struct GenericSdp {
+  const TT *C = nullptr, *Aeq = nullptr, *AeqT = nullptr, *Beq = nullptr, *KY = nullptr;
+  const TT *Aineq = nullptr, *AineqT = nullptr, *Bineq = nullptr, *KT = nullptr;
+  double sense = 1.0, q = 0.0, lam0 = 1.0, x0_ineq = 0.0, t0_ineq = 1e-3;
+};
+Problem build_problem_generic(const GenericSdp& g, Ctx& c);
 void init_state(const Problem& P, const ttipm_params& prm, State& S, Ctx& c);
 // One IPM iteration; fills info (measures at entry + the step taken).
 void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c);

@@ -306,6 +306,68 @@ double tt_sandwich(const TT& u, const TT& A, const TT& v, Ctx& c) {
   return h[0];
 }
 
+// <Oi vi, Oj vj> by a left-to-right sweep over a four-layer environment
+// E[a][alpha][beta][c] (a, c: ranks of vi, vj; alpha, beta: ranks of Oi, Oj),
+// four GEMM stages per core: vj, then Oj over its input mode, then Oi over the
+// shared output mode, then vi over Oi's input mode.
+double tt_op_dot(const TT& vi, const TT* Oi, const TT& vj, const TT* Oj, Ctx& c) {
+  const int d = vi.d, m = vi.mo;
+  TT_REQUIRE(vj.d == d && vj.mo == m && vi.mi == 1 && vj.mi == 1, "op_dot vector shapes");
+  for (const TT* O : {Oi, Oj})
+    if (O) TT_REQUIRE(O->d == d && O->mo == m && O->mi == m, "op_dot operator shapes");
+  std::vector<double> eye((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) eye[(size_t)i * m + i] = 1.0;
+  TT Id;
+  if (!Oi || !Oj) Id = tt_rank1(d, m, m, eye, c);
+  const TT& A = Oi ? *Oi : Id;
+  const TT& B = Oj ? *Oj : Id;
+  size_t emax = 1, tmax = 1;
+  for (int k = 0; k <= d; ++k)
+    emax = std::max(emax, (size_t)vi.r[k] * A.r[k] * B.r[k] * vj.r[k]);
+  for (int k = 0; k < d; ++k) {
+    const size_t a = vi.r[k], al = A.r[k], be = B.r[k], cc = vj.r[k];
+    const size_t a2 = vi.r[k + 1], al2 = A.r[k + 1], be2 = B.r[k + 1], c2 = vj.r[k + 1];
+    tmax = std::max({tmax, a * al * be * m * c2, a * al * c2 * m * be2, a * c2 * be2 * m * al2});
+  }
+  DevBuf e0(emax), e1(emax), t1(tmax), t2(tmax), pB((size_t)B.max_rank() * B.max_rank() * m * m);
+  fill(1, 1.0, e0.get(), c.s);
+  for (int k = 0; k < d; ++k) {
+    const int a = vi.r[k], al = A.r[k], be = B.r[k], cc = vj.r[k];
+    const int a2 = vi.r[k + 1], al2 = A.r[k + 1], be2 = B.r[k + 1], c2 = vj.r[k + 1];
+    // T1[(a,al,be)][(j,c2)] = E[(a,al,be)][c] vj[c][(j,c2)]
+    gemm(gemm_nn(a * al * be, m * c2, cc, e0.get(), cc, vj.core(k), (long)m * c2, t1.get(), (long)m * c2), c.s,
+         &c.ws, GemmPrec::F64);
+    // [a][al][be][j][c2] -> [a][al][c2][be][j]
+    permute(t1.get(), t2.get(), {a, al, be, m, c2}, {0, 1, 4, 2, 3}, c.s);
+    // Oj [be][i][j][be2] -> [(be,j)][(i,be2)]
+    permute(B.core(k), pB.get(), {be, m, m, be2}, {0, 2, 1, 3}, c.s);
+    // T2[(a,al,c2)][(i,be2)] = T1'[(a,al,c2)][(be,j)] Oj'[(be,j)][(i,be2)]
+    gemm(gemm_nn(a * al * c2, m * be2, be * m, t2.get(), (long)be * m, pB.get(), (long)m * be2, t1.get(),
+                 (long)m * be2),
+         c.s, &c.ws, GemmPrec::F64);
+    // [a][al][c2][i][be2] -> [a][c2][be2][al][i]
+    permute(t1.get(), t2.get(), {a, al, c2, m, be2}, {0, 2, 4, 1, 3}, c.s);
+    // T3[(a,c2,be2)][(j,al2)] = T2'[(a,c2,be2)][(al,i)] Oi[(al,i)][(j,al2)]
+    gemm(gemm_nn(a * c2 * be2, m * al2, al * m, t2.get(), (long)al * m, A.core(k), (long)m * al2, t1.get(),
+                 (long)m * al2),
+         c.s, &c.ws, GemmPrec::F64);
+    // [a][c2][be2][j][al2] -> [a][j][al2][be2][c2]
+    permute(t1.get(), t2.get(), {a, c2, be2, m, al2}, {0, 3, 4, 2, 1}, c.s);
+    // E'[a2][(al2,be2,c2)] = sum_(a,j) vi[(a,j)][a2] T3'[(a,j)][(al2,be2,c2)]
+    Gemm g;
+    g.M = a2; g.N = al2 * be2 * c2; g.K = a * m;
+    g.A = vi.core(k); g.am = 1; g.ak = a2;
+    g.B = t2.get(); g.bk = (long)al2 * be2 * c2; g.bn = 1;
+    g.C = e1.get(); g.cm = (long)al2 * be2 * c2; g.cn = 1;
+    gemm(g, c.s, &c.ws, GemmPrec::F64);
+    std::swap(e0, e1);
+  }
+  double* h = c.host(1);
+  TT_HIP(hipMemcpyAsync(h, e0.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  return h[0];
+}
+
 // ---------------------------------------------------------------------------
 // environments and local products: three GEMM stages each
 // ---------------------------------------------------------------------------

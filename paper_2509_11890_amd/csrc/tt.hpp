@@ -80,6 +80,10 @@ TT tt_transpose(const TT& A, Ctx& c);                  // swap mode indices of a
 double tt_dot(const TT& x, const TT& y, Ctx& c);       // <x, y> (synchronises)
 double tt_norm(const TT& x, Ctx& c);
 double tt_sandwich(const TT& u, const TT& A, const TT& v, Ctx& c);  // u^T A v
+// <Oi vi, Oj vj> for TT vectors vi, vj and operators Oi, Oj on them (nullptr =
+// identity), never forming Oi vi: the norm of a sum of operator images is a
+// sum of these (synchronises)
+double tt_op_dot(const TT& vi, const TT* Oi, const TT& vj, const TT* Oj, Ctx& c);
 
 // ---- environments and projected local products (Sec. 3.3) ---------------------
 // phi_in/phi_out layouts as in tt_contract_interfaces; O == nullptr is the identity.

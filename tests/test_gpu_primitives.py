@@ -183,6 +183,104 @@ def test_round_truncation_matches_oracle(tol):
     assert abs(zeta - zref) <= 1e-9 * ott.norm(T2) + 1e-6 * zref
 
 
+@pytest.mark.parametrize("which", ["both", "left_identity", "both_identity", "large"])
+def test_op_inner_matches_dense(which):
+    """tt_op_inner <Oi vi, Oj vj> against the dense images of the oracle's
+    full vectors and operators (relative 1e-12)."""
+    P = _lib()
+    rng = np.random.default_rng({"both": 1, "left_identity": 2, "both_identity": 3, "large": 4}[which])
+    if which == "large":
+        vr, Ar, Br, wr = [1, 4, 16, 40, 16, 4, 1], [1, 3, 9, 12, 7, 2, 1], [1, 4, 8, 10, 8, 4, 1], [1, 4, 15, 33, 14, 4, 1]
+    else:
+        vr, Ar, Br, wr = [1, 3, 5, 2, 1], [1, 2, 4, 3, 1], [1, 3, 2, 2, 1], [1, 4, 3, 5, 1]
+    vi, vj = _rand_tt(rng, vr, 4), _rand_tt(rng, wr, 4)
+    Oi = None if which in ("left_identity", "both_identity") else _rand_op(rng, Ar, 4)
+    Oj = None if which == "both_identity" else _rand_op(rng, Br, 4)
+    img = lambda O, v: ott.full(v) if O is None else ott.full_mat(O) @ ott.full(v)
+    ref = float(img(Oi, vi) @ img(Oj, vj))
+    got = P.op_inner([_cuda(G) for G in vi], None if Oi is None else [_cuda(G) for G in Oi],
+                     [_cuda(G) for G in vj], None if Oj is None else [_cuda(G) for G in Oj])
+    scale = np.linalg.norm(img(Oi, vi)) * np.linalg.norm(img(Oj, vj))
+    assert abs(got - ref) <= 1e-12 * scale
+
+
+def _decaying_tt(rng, ranks, m, decay):
+    """A TT whose bond spectra decay geometrically (orthogonal factors scaled by
+    decay**j), so that every tolerance truncates at a different rank."""
+    d = len(ranks) - 1
+    cores = []
+    for k in range(d):
+        G = rng.standard_normal((ranks[k] * m, ranks[k + 1]))
+        Q, _ = np.linalg.qr(G)
+        if k < d - 1:
+            Q = Q * (decay ** np.arange(ranks[k + 1]))[None, :]
+        cores.append(Q.reshape(ranks[k], m, ranks[k + 1]))
+    return cores
+
+
+@pytest.mark.parametrize("case", ["m16_operator", "qr_first_r128", "global_jacobi_r200"])
+def test_round_large_paths_match_oracle(case):
+    """tt_round against the oracle rounding on the paths the small cases do not
+    reach: operator cores with m = 16 (4 x 4 modes), unfoldings too large for
+    LDS (QR first, then the Jacobi SVD of the square factor in LDS) and bonds
+    whose square factor does not fit LDS either (global-memory Jacobi)."""
+    P = _lib()
+    rng = np.random.default_rng({"m16_operator": 1, "qr_first_r128": 2, "global_jacobi_r200": 3}[case])
+    if case == "m16_operator":
+        ranks, m, m_out, m_in = [1, 16, 60, 60, 16, 1], 16, 4, 4
+    elif case == "qr_first_r128":
+        ranks, m, m_out, m_in = [1, 4, 16, 64, 128, 64, 16, 4, 1], 4, 4, 1
+    else:
+        ranks, m, m_out, m_in = [1, 4, 16, 64, 200, 64, 16, 4, 1], 4, 4, 1
+    T = _decaying_tt(rng, ranks, m, 0.93)
+    eps = 1e-3 * ott.norm(T)
+    ref, zref = ott.round_tt(T, eps, "abs")
+    shape = (lambda G: G.reshape(G.shape[0], m_out, m_in, G.shape[2])) if m_in > 1 else (lambda G: G)
+    out, zeta = P.tt_round([_cuda(shape(G)) for G in T], eps, P.TT_TOL_ABS, m_out=m_out, m_in=m_in)
+    torch.cuda.synchronize()
+    got = [G.cpu().numpy().reshape(G.shape[0], m, G.shape[-1]) for G in out]
+    assert ott.ranks(got) == ott.ranks(ref)
+    err = np.linalg.norm(ott.full(got) - ott.full(T))
+    assert err <= eps * (1 + 1e-9)
+    assert abs(zeta - zref) <= 1e-9 * ott.norm(T) + 1e-6 * zref
+    # the rounded tensors agree entry by entry (both are the truncation of the
+    # same orthogonalised tensor; singular vectors are unique up to sign)
+    assert np.max(np.abs(ott.full(got) - ott.full(ref))) <= 1e-10 * np.max(np.abs(ott.full(T)))
+
+
+@pytest.mark.parametrize("ranks,m_out,m_in", [([1, 4, 16, 30, 16, 4, 1], 4, 1), ([1, 16, 48, 48, 16, 1], 4, 4),
+                                              ([1, 4, 16, 64, 160, 64, 16, 4, 1], 4, 1)])
+def test_round_with_caller_workspace(ranks, m_out, m_in):
+    """tt_round with a caller workspace of exactly tt_round_workspace bytes
+    gives the pool result bit for bit; a workspace far too small is refused
+    with TT_ERR_ARG and leaves the cores and ranks unchanged."""
+    P = _lib()
+    rng = np.random.default_rng(sum(ranks))
+    m = m_out * m_in
+    T = _decaying_tt(rng, ranks, m, 0.9)
+    shape = (lambda G: G.reshape(G.shape[0], m_out, m_in, G.shape[2])) if m_in > 1 else (lambda G: G)
+    eps = 1e-4 * ott.norm(T)
+    a = [_cuda(shape(G)) for G in T]
+    b = [_cuda(shape(G)) for G in T]
+    nbytes = P.tt_round_workspace(b, m_out=m_out, m_in=m_in)
+    ws = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device="cuda")
+    out_a, za = P.tt_round(a, eps, P.TT_TOL_ABS, m_out=m_out, m_in=m_in)
+    out_b, zb = P.tt_round(b, eps, P.TT_TOL_ABS, m_out=m_out, m_in=m_in, workspace=ws[: nbytes // 8])
+    torch.cuda.synchronize()
+    assert za == zb
+    assert [G.shape for G in out_a] == [G.shape for G in out_b]
+    for x, y in zip(out_a, out_b):
+        assert torch.equal(x, y)
+    c = [_cuda(shape(G)) for G in T]
+    tiny = torch.empty(1024, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.TTError) as e:
+        P.tt_round(c, eps, P.TT_TOL_ABS, m_out=m_out, m_in=m_in, workspace=tiny)
+    assert e.value.code == P.binding.TT_ERR_ARG
+    torch.cuda.synchronize()
+    for G, G0 in zip(c, T):
+        assert np.array_equal(G.cpu().numpy().reshape(G0.shape), G0)
+
+
 @pytest.mark.parametrize("method", ["direct", "gmres"])
 def test_local_solve_matches_dense_lu(method):
     P = _lib()
@@ -222,6 +320,46 @@ def test_local_solve_matches_dense_lu(method):
     torch.cuda.synchronize()
     assert info["rel_res"] < 1e-12
     assert _rel(x.cpu().numpy(), x_ref) < 1e-10
+
+
+@pytest.mark.parametrize("precond", ["none", "bjacobi"])
+def test_local_solve_gmres_at_frame_rank_32(precond):
+    """GMRES on a local system of the n = 2^10 frame size (r = r' = 32, two
+    components: 8192 unknowns) against a dense LU of the oracle's explicit
+    matrix; entries agree to 1e-10 of the largest."""
+    P = _lib()
+    rng = np.random.default_rng(29)
+    r, rp, m, L = 32, 32, 4, 2
+    p = r * m * rp
+    ops = []
+    for _ in range(3):
+        phiL = rng.standard_normal((r, 2, r)) * (0.3 / r)
+        phiR = rng.standard_normal((rp, 3, rp)) * (0.3 / rp)
+        core = rng.standard_normal((2, m, m, 3))
+        ops.append((phiL, core, phiR))
+    ident = (np.eye(r)[:, None, :], None, np.eye(rp)[:, None, :])
+    blocks = [(0, 0, 1.0, [ident]), (1, 1, 1.0, [ident]), (0, 1, 1.0, [ops[0]]), (1, 0, -1.0, [ops[1]]),
+              (1, 1, 0.5, [ops[2], ops[0]])]
+    Kd = np.zeros((L * p, L * p))
+    for row, col, coef, chain in blocks:
+        M = None
+        for (phiL, core, phiR) in chain:
+            Dm = (np.kron(np.kron(phiL[:, 0, :], np.eye(m)), phiR[:, 0, :]) if core is None
+                  else ott.local_dense(phiL, core, phiR))
+            M = Dm if M is None else Dm @ M
+        Kd[row * p:(row + 1) * p, col * p:(col + 1) * p] += coef * M
+    b = rng.standard_normal(L * p)
+    x_ref = np.linalg.solve(Kd, b)
+    pblocks = [P.LocalBlock(row, col, coef, [P.ProjOp(_cuda(a), None if c is None else _cuda(c), _cuda(bb))
+                                             for a, c, bb in chain]) for row, col, coef, chain in blocks]
+    K = P.LocalOp(r, rp, L, pblocks)
+    x = torch.zeros(L * p, dtype=torch.float64, device="cuda")
+    info = P.local_solve(K, _cuda(b), x, method=P.TT_SOLVE_GMRES, rtol=1e-13, restart=40, maxit=2000,
+                         precond=P.TT_PREC_BJACOBI if precond == "bjacobi" else P.TT_PREC_NONE)
+    torch.cuda.synchronize()
+    assert info["rel_res"] < 1e-12
+    got = x.cpu().numpy()
+    assert np.max(np.abs(got - x_ref)) <= 1e-10 * np.max(np.abs(x_ref))
 
 
 def _random_local_op(P, rng, r, rp, m, L, spd):
