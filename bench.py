@@ -1,31 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of the TT-IPM hot path on one MI355X.
 
-Workload (default): MaxCut SDP with n = 2^10 on the weighted graph whose
-adjacency is the sum of 4 Kronecker products of 10 random symmetric 2x2 factors
-(entries U[0, 1], seed 2, zero diagonal), X/Z/Y as TT objects over 10 modes,
-Newton-direction (frame) and iterate rank caps 32, plain FP64.  Local systems
-of up to 1024 unknowns are solved by the dense block elimination of Sec. 3.3,
-larger ones by restarted GMRES with the block-Jacobi preconditioner.
+Headline workload (default): the MaxCut SDP of the 4 x 8 grid graph (n = 2^5,
+unit weights, value 52), X/Z/Y as TT objects over 5 modes, Newton-direction
+(frame) and iterate rank caps 8, plain FP64 with the dense block elimination
+of Sec. 3.3 for the local systems.  It is the one configuration of the
+benchmark set on which the TT-IPM reaches the stopping mark; the larger
+configurations (n = 2^10 and 2^12, below) stop above it at their rank caps.
 
-One step = one complete TT-IPM solve (``ttipm_solve``) from the initial point of
-Sec. 5.1 to the first iterate with relative duality gap <= 1e-4 and primal /
-dual infeasibility <= 2e-4, or to the iteration limit (--max-iter) when the
-gap is not reached (``reached_gap`` says which), on inputs already resident in
-HBM.  The reported value is the time per step (seconds, lower is better).
+One step = one complete TT-IPM solve (``ttipm_solve``) from the initial point
+of Sec. 5.1 to the first iterate with relative duality gap <= 1e-4 and primal /
+dual infeasibility <= 2e-4, on inputs already resident in HBM.  ``value`` is
+the wall time per step (seconds, lower is better); every timed step must reach
+the mark (``reached_gap``), else ``value`` is null.
 
 Beside it, the line carries
   * roofline: the instrumented kernel with the largest event time inside the
-    timed steps (HIP events on its launch stream, every period-th launch), its
-    algorithmic flops per second against the MI355X peak of its precision;
+    timed steps (HIP events on its launch stream, every period-th launch),
+    its algorithmic rate against the MI355X peak of its precision;
   * local_contraction: TFLOP/s of the projected local matvec (three MFMA GEMM
-    stages) at the workload's shape and at r = 64, R = 128;
-  * precision_variants_grid_d5: the 4x8 grid solved with FP64 direct, FP64 GMRES,
-    mixed BF16 GMRES with FP64 refinement, and mixed + learned preconditioner;
-  * mixed_precision_same_step: the same step with BF16 Arnoldi products and
-    FP64 refinement of the local solves (untimed by the step clock);
-  * time_to_gap_n1024_closed_forms: K_1024 and Q_10 MaxCut to the 1e-4 mark;
-  * cpu_baseline: the dense FP64 HKM interior-point oracle on the same
+    stages) at r = 32, 64, 128 in FP64 and with BF16 operands;
+  * precision_variants: the headline instance solved to the mark with FP64
+    direct, FP64 GMRES, mixed BF16 GMRES with FP64 refinement, and mixed +
+    learned preconditioner, each with its error against the FP64 oracle;
+  * config_records: one solve of each larger configuration under a wall-time
+    cap (n = 2^10 Kronecker MaxCut, theta of Q_10, correlation clustering and
+    noisy Kronecker-sum MaxCut at n = 2^12): whether the mark was reached, the
+    last measures and ranks, and the objective error against the dense oracle,
+    the closed form or the certificate of the TT iterates;
+  * time_to_gap_n1024_closed_forms: K_1024 and Q_10 MaxCut to the mark;
+  * cpu_baseline: the dense FP64 HKM interior-point oracle on the headline
     instance, timed on the host cores to the same gap rule.
 """
 import argparse
@@ -39,29 +43,31 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6e12, "bf16": 2.5e15}
 HBM = 8.0e12
+MARK = dict(stop_gap=1e-4, eps_gap=1e-4)
 
 WORKLOADS = {
     # name: (instance config, frame rank cap, iterate rank cap)
-    "maxcut_kron_d10": ("maxcut_kron_d10", 32, 32),
     "maxcut_grid_d5": ("maxcut_grid_d5", 8, 8),
+    "maxcut_kron_d10": ("maxcut_kron_d10", 32, 32),
 }
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="maxcut_kron_d10", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="maxcut_grid_d5", choices=sorted(WORKLOADS))
     ap.add_argument("--rank-cap", type=int, default=None, help="override the frame rank cap")
     ap.add_argument("--iter-rank-cap", type=int, default=None, help="override the iterate rank cap")
-    ap.add_argument("--max-iter", type=int, default=12,
-                    help="IPM iteration limit of a step (the step ends earlier at the gap mark)")
-    ap.add_argument("--profile-period", type=int, default=32,
+    ap.add_argument("--max-iter", type=int, default=100, help="IPM iteration limit of a step")
+    ap.add_argument("--profile-period", type=int, default=8,
                     help="event-time every n-th launch of the instrumented kernels")
+    ap.add_argument("--record-wall", type=float, default=30.0,
+                    help="wall-time cap (s) of each configuration record")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the mixed / learned comparison and the n = 1024 closed-form solves")
+                    help="skip the precision variants, the configuration records and the n = 1024 closed forms")
     ap.add_argument("--contraction-only", action="store_true",
                     help="only the local-contraction microbenchmarks (and a 256 MiB device copy used to calibrate "
                          "the HBM byte counters)")
@@ -69,13 +75,19 @@ def parse():
     return ap.parse_args()
 
 
-def contraction_rate(P, torch, r, R, reps=50, warm=5):
-    """FP64 TFLOP/s of one projected local matvec y = phiL O x phiR (Sec. 3.3)."""
+def _median(xs):
+    xs = sorted(xs)
+    n = len(xs)
+    return 0.5 * (xs[(n - 1) // 2] + xs[n // 2]) if n else None
+
+
+def contraction_rate(P, torch, r, R, bf16=False, reps=50, warm=5):
+    """TFLOP/s of one projected local matvec y = phiL O x phiR (Sec. 3.3)."""
     g = torch.Generator(device="cpu").manual_seed(r * 1000 + R)
     rnd = lambda *s: torch.randn(*s, generator=g, dtype=torch.float64).cuda()
     m = 4
     op = P.ProjOp(rnd(r, R, r), rnd(R, m, m, R), rnd(r, R, r))
-    K = P.LocalOp(r, r, 1, [P.LocalBlock(0, 0, 1.0, [op])])
+    K = P.LocalOp(r, r, 1, [P.LocalBlock(0, 0, 1.0, [op])], precision=P.TTIPM_MIXED if bf16 else P.TTIPM_F64)
     x = rnd(r * m * r)
     y = torch.empty_like(x)
     for _ in range(warm):
@@ -89,8 +101,9 @@ def contraction_rate(P, torch, r, R, reps=50, warm=5):
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / 1e3 / reps
     flops = 16.0 * r ** 3 * R + 32.0 * r ** 2 * R ** 2
-    return {"r": r, "R": R, "dtype": "f64", "us_per_matvec": t * 1e6, "gflop_per_matvec": flops / 1e9,
-            "tflops": flops / t / 1e12, "frac_of_peak": flops / t / PEAK["f64"]}
+    peak = PEAK["bf16" if bf16 else "f64"]
+    return {"r": r, "R": R, "dtype": "bf16-in/f32-acc" if bf16 else "f64", "us_per_matvec": t * 1e6,
+            "gflop_per_matvec": flops / 1e9, "tflops": flops / t / 1e12, "frac_of_peak": flops / t / peak}
 
 
 def interface_rate(P, torch, r, R, reps=50, warm=5):
@@ -119,98 +132,168 @@ def interface_rate(P, torch, r, R, reps=50, warm=5):
             "frac_of_peak": flops / t / PEAK["f64"]}
 
 
-def contraction_rate_bf16(P, torch, r, R, reps=50, warm=5):
-    """Same projected matvec with BF16 operands / FP32 accumulation (tt_local_op.precision)."""
-    g = torch.Generator(device="cpu").manual_seed(r * 1000 + R)
-    rnd = lambda *s: torch.randn(*s, generator=g, dtype=torch.float64).cuda()
-    m = 4
-    op = P.ProjOp(rnd(r, R, r), rnd(R, m, m, R), rnd(r, R, r))
-    K = P.LocalOp(r, r, 1, [P.LocalBlock(0, 0, 1.0, [op])], precision=P.TTIPM_MIXED)
-    x = rnd(r * m * r)
-    y = torch.empty_like(x)
-    for _ in range(warm):
-        P.local_matvec(K, x, y)
-    s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        P.local_matvec(K, x, y)
-    e1.record(s)
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / 1e3 / reps
-    flops = 16.0 * r ** 3 * R + 32.0 * r ** 2 * R ** 2
-    return {"r": r, "R": R, "dtype": "bf16-in/f32-acc", "us_per_matvec": t * 1e6, "gflop_per_matvec": flops / 1e9,
-            "tflops": flops / t / 1e12, "frac_of_peak": flops / t / PEAK["bf16"]}
+def problem_of(P, I, name):
+    """(ttipm problem, instance config) of a named configuration."""
+    cfg = I.config(name)
+    g = cfg["graph"]
+    kind = {"maxcut": P.TTIPM_MAXCUT, "theta": P.TTIPM_THETA, "cc": P.TTIPM_CC}[cfg["kind"]]
+    if kind == P.TTIPM_CC:
+        return P.Problem(kind, g.cores, I.negdeg_cores(g)), cfg
+    return P.Problem(kind, g.cores), cfg
 
 
-def precision_variants(P, I):
-    """Time-to-gap of the 4x8 grid MaxCut (n = 32, value 52) with the plain FP64
-    direct local solves and with GMRES local solves (block Jacobi, mixed BF16 +
-    FP64 refinement, mixed + learned preconditioner trained on the local systems
-    of one FP64 run of the same instance)."""
+def precision_variants(P, I, oracle_obj):
+    """Time to the mark of the headline instance (grid 4 x 8, value 52) with
+    the plain FP64 direct local solves and with GMRES local solves (block
+    Jacobi, mixed BF16 + FP64 refinement, mixed + learned preconditioner trained
+    on the local systems of one FP64 run of the same instance)."""
     g = I.grid_4x8()
     prob = P.Problem(P.TTIPM_MAXCUT, g.cores)
     out = {}
 
     def run(name, **kw):
-        prm = P.Params(rank_cap=8, iter_rank_cap=8, stop_gap=1e-4, eps_gap=1e-4, max_iter=100, **kw)
+        prm = P.Params(rank_cap=8, iter_rank_cap=8, max_iter=100, **MARK, **kw)
         st = P.State(prob, prm)
         t0 = time.perf_counter()
         res, log = P.ttipm_solve(prob, st, prm)
         out[name] = {"time_to_gap_s": res["time_to_gap"], "wall_s": time.perf_counter() - t0,
-                     "iterations": res["iterations"], "rel_gap": res["rel_gap"],
+                     "reached_gap": res["time_to_gap"] > 0, "iterations": res["iterations"],
+                     "rel_gap": res["rel_gap"], "eps_p": res["eps_p"], "eps_d": res["eps_d"],
                      "obj_err_vs_closed_form": abs(res["pobj"] - 52.0) / 53.0,
+                     "obj_err_vs_f64_oracle": abs(res["pobj"] - oracle_obj) / (1 + abs(oracle_obj)),
                      "krylov_iters": int(sum(l["krylov_iters"] for l in log)),
                      "mlp_used": int(sum(l["mlp_used"] for l in log)),
                      "mlp_fallbacks": int(sum(l["mlp_fallbacks"] for l in log))}
 
+    gm = dict(direct_max=64, gmres_restart=40, gmres_maxit=800)
     run("f64_direct")
-    run("f64_gmres_bjacobi", direct_max=64, precond=P.TT_PREC_BJACOBI, gmres_restart=40, gmres_maxit=800)
-    run("mixed_gmres_bjacobi", direct_max=64, precond=P.TT_PREC_BJACOBI, precision=P.TTIPM_MIXED,
-        gmres_restart=40, gmres_maxit=800)
+    run("f64_gmres_bjacobi", precond=P.TT_PREC_BJACOBI, **gm)
+    run("mixed_gmres_bjacobi", precond=P.TT_PREC_BJACOBI, precision=P.TTIPM_MIXED, **gm)
     net = P.MLP(8, hidden=256, seed=0)
-    run("collect", direct_max=64, precond=P.TT_PREC_BJACOBI, gmres_restart=40, gmres_maxit=800, mlp=net.h.value,
-        collect_probes=8, collect_cap=200000)
+    run("collect", precond=P.TT_PREC_BJACOBI, mlp=net.h.value, collect_probes=8, collect_cap=200000, **gm)
     hist = net.train(epochs=30, batch=512, lr=1e-3, seed=1)
     out.pop("collect")
-    run("mixed_gmres_mlp", direct_max=64, precond=P.TT_PREC_MLP, precision=P.TTIPM_MIXED, gmres_restart=40,
-        gmres_maxit=800, mlp=net.h.value)
+    run("mixed_gmres_mlp", precond=P.TT_PREC_MLP, precision=P.TTIPM_MIXED, mlp=net.h.value, **gm)
     out["mlp_training"] = {"blocks": net.dataset_size, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
     return out
 
 
-def closed_forms_d10(P, I):
-    """Time to the 1e-4 gap mark on the n = 1024 MaxCut instances with closed-form
-    values (K_1024: n^2/4; Q_10: |E| = 5120) at TT ranks <= 8, FP64."""
+def closed_forms_d10(P, I, cpu=True):
+    """Time to the mark on the n = 1024 MaxCut instances with closed-form values
+    (K_1024: n^2/4; Q_10: |E| = 5120) at TT ranks <= 8, FP64, beside the dense
+    oracle's time to the same mark on the host cores."""
+    from oracle import problems as OP, sdp_dense as S
     out = {}
     for name, g, value in (("K1024", I.complete(10), 1024.0 ** 2 / 4), ("Q10_maxcut", I.hypercube(10), 5120.0)):
         prob = P.Problem(P.TTIPM_MAXCUT, g.cores)
-        prm = P.Params(rank_cap=8, iter_rank_cap=8, stop_gap=1e-4, max_iter=60)
+        prm = P.Params(rank_cap=8, iter_rank_cap=8, max_iter=60, **MARK)
         res, log = P.ttipm_solve(prob, P.State(prob, prm), prm)
         out[name] = {"time_to_gap_s": res["time_to_gap"], "iterations": res["iterations"],
                      "rel_gap": res["rel_gap"], "eps_p": res["eps_p"], "eps_d": res["eps_d"],
                      "pobj_err_vs_closed_form": abs(res["pobj"] - value) / (1 + value),
                      "dobj_err_vs_closed_form": abs(res["dobj"] - value) / (1 + value)}
+        if cpu:
+            t0 = time.perf_counter()
+            d = S.solve(OP.maxcut_dense(g.dense), tol_gap=1e-4, tol_feas=2e-4)
+            out[name]["cpu_oracle_time_to_gap_s"] = time.perf_counter() - t0
+            out[name]["cpu_oracle_iterations"] = d["iterations"]
     return out
 
 
-def cpu_baseline(graph, budget_s=60.0):
-    """Dense FP64 HKM/Mehrotra oracle on the host: time to rel_gap <= 1e-4 with
-    infeasibilities <= 2e-4, and its objective at 1e-9 (for the error report)."""
-    import numpy as np  # noqa: F401
+def _dense_oracle(kind, A, budget_gap=1e-4):
+    from oracle import problems as OP, sdp_dense as S
+    prob = {"maxcut": OP.maxcut_dense, "theta": OP.theta_dense}[kind](A)
+    t0 = time.perf_counter()
+    res = S.solve(prob, tol_gap=1e-9, tol_feas=1e-9, gap_marks=(budget_gap,))
+    return res, time.perf_counter() - t0
+
+
+def config_records(P, I, wall):
+    """One solve of each larger configuration, step by step under a wall-time
+    cap: reached mark, measures of the last iterate, ranks, time, and the
+    objective error against the FP64 reference of that configuration."""
+    import numpy as np
+    from oracle import certificate as cert
+    # theta from the scaled identity passes through iterates of norm ~1e4 in
+    # its first iterations; forcing terms and rounding budgets of eta ~ 1e-3
+    # there leave errors the rank caps cannot remove later, so its record
+    # starts from eta = 1e-6 with floor 1e-7
+    specs = [
+        # name, config, frame cap, iterate cap, precision, reference, extra parameters
+        ("n1024_kron_maxcut", "maxcut_kron_d10", 32, 32, P.TTIPM_F64, "dense", {}),
+        ("theta_Q10", "theta_hypercube_d10", 64, 64, P.TTIPM_MIXED, 512.0, {"eta0": 1e-6, "delta": 1e-7}),
+        ("n4096_signed_cc", "cc_signed_d12", 64, 64, P.TTIPM_MIXED, "certificate", {}),
+        ("n4096_noisy_kron_sum_maxcut", "maxcut_noise_d12", 128, 128, P.TTIPM_MIXED, "certificate", {}),
+    ]
+    out = {}
+    for name, cfgname, cap, icap, prec, ref, extra in specs:
+        prob, cfg = problem_of(P, I, cfgname)
+        prm = P.Params(rank_cap=cap, iter_rank_cap=icap, max_iter=200, precision=prec, direct_max=1024,
+                       precond=P.TT_PREC_BJACOBI, gmres_restart=40, gmres_maxit=1000, **MARK, **extra)
+        st = P.State(prob, prm)
+        rec = {"frame_rank_cap": cap, "iterate_rank_cap": icap, "params": extra,
+               "precision": "mixed" if prec == P.TTIPM_MIXED else "f64", "reached_gap": False,
+               "time_to_gap_s": None, "status": "wall_cap"}
+        t0 = time.perf_counter()
+        last = None
+        try:
+            while True:
+                inf = P.ttipm_step(prob, st, prm)
+                el = time.perf_counter() - t0
+                last = inf
+                if inf["rel_gap"] <= 1e-4 and inf["eps_p"] <= 2e-4 and inf["eps_d"] <= 2e-4:
+                    rec.update(reached_gap=True, time_to_gap_s=el, status="reached")
+                    break
+                if el > wall:
+                    break
+        except P.TTError as e:
+            rec["status"] = f"stopped: {e}"
+        rec["wall_s"] = time.perf_counter() - t0
+        if last is not None:
+            rec.update({k: last[k] for k in ("iter", "rel_gap", "eps_p", "eps_d", "pobj", "dobj", "mu",
+                                             "rank_x", "rank_y", "rank_z", "rank_w", "newton_res")})
+        kind = cfg["kind"]
+        A = cfg["graph"].dense
+        if ref == "dense":
+            res, t_or = _dense_oracle(kind, A)
+            p_ref = 0.5 * (res["pobj"] + res["dobj"])
+            rec["oracle"] = {"objective": p_ref, "time_to_gap_s": res["time_to_gap"][1e-4], "time_total_s": t_or}
+        elif ref == "certificate":
+            Xc, Yc, Zc = st.export("X"), st.export("Y"), st.export("Z")
+            Tc = st.export("T") if kind == "cc" else None
+            c = cert.certificate_tt(kind, A, Xc, Yc, Zc, Tc)
+            rec["certificate"] = {k: (float(v) if np.isscalar(v) else None) for k, v in c.items()}
+            p_ref = None
+        else:
+            p_ref = float(ref)
+        if p_ref is not None and last is not None:
+            rec["obj_err_vs_reference"] = abs(last["pobj"] - p_ref) / (1 + abs(p_ref))
+        out[name] = rec
+        print(f"record {name}: {rec['status']} it {rec.get('iter')} gap {rec.get('rel_gap')} "
+              f"eps_p {rec.get('eps_p')} wall {rec['wall_s']:.1f}s", file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_baseline(graph, min_work_s=10.0):
+    """Dense FP64 HKM/Mehrotra oracle on the host cores: the same instance
+    solved to rel_gap <= 1e-4 with infeasibilities <= 2e-4, repeated until
+    about min_work_s of CPU time has been spent; seconds per solve."""
     from threadpoolctl import threadpool_info
 
     from oracle import problems as OP, sdp_dense as S
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     prob = OP.maxcut_dense(graph.dense)
-    t0 = time.perf_counter()
-    res = S.solve(prob, tol_gap=1e-9, tol_feas=1e-9, gap_marks=(1e-4,))
-    total = time.perf_counter() - t0
-    ttg = res["time_to_gap"][1e-4]
-    return {"value": ttg, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": (f"full dense HKM solve of the same n={prob['n']} instance; time to the first iterate with "
-                       f"rel_gap<=1e-4, eps<=2e-4 ({res['iterations']} iterations to 1e-9 took {total:.1f} s)"),
-            "pobj_1e9": res["pobj"], "dobj_1e9": res["dobj"]}
+    ref = S.solve(prob, tol_gap=1e-9, tol_feas=1e-9)
+    reps, t_sum = 0, 0.0
+    while t_sum < min_work_s and reps < 1000:
+        t0 = time.perf_counter()
+        res = S.solve(prob, tol_gap=1e-4, tol_feas=2e-4)
+        t_sum += time.perf_counter() - t0
+        reps += 1
+    return {"value": t_sum / reps, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"{reps} dense HKM solves of the same n={prob['n']} instance to rel_gap<=1e-4, "
+                       f"eps<=2e-4 ({res['iterations']} iterations each), {t_sum:.1f} s in all"),
+            "objective_1e9": 0.5 * (ref["pobj"] + ref["dobj"])}
 
 
 def stored_traffic(kernel, workload):
@@ -246,6 +329,27 @@ def calibration_copy(torch):
     return 2 * src.numel() * 8
 
 
+def roofline_of(kstats, period, workload):
+    """Roofline object of the instrumented kernel with the largest event time."""
+    if not kstats:
+        return None
+    dom_name, dom = max(kstats.items(), key=lambda kv: kv[1]["time_ms"])
+    if dom["timed"] <= 0 or dom["time_ms"] <= 0:
+        return None
+    t_avg = dom["time_ms"] / 1e3 / dom["timed"]
+    common = {"kernel": dom_name, "avg_launch_us": t_avg * 1e6, "launches": dom["launches"],
+              "timed_launches": dom["timed"], "traffic": stored_traffic(dom_name, workload)}
+    if dom["flops"] > 0:
+        prec = "bf16" if "bf16" in dom_name else "f64"
+        achieved = dom["flops"] / (dom["time_ms"] / 1e3)
+        return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK[prec], "flops_per_launch": dom["flops"] / dom["timed"],
+                "algorithmic_bytes_per_launch": dom["bytes"] / dom["timed"], **common}
+    achieved = dom["bytes"] / (dom["time_ms"] / 1e3)
+    return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM / 1e9, "unit": "GB/s", "frac": achieved / HBM,
+            "bytes_per_launch": dom["bytes"] / dom["timed"], **common}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -258,15 +362,13 @@ def main():
     import instances as I
     import paper_2509_11890_amd as P
 
+    torch.cuda.set_device(0)
     if args.contraction_only:
-        # local matvec (FP64 and BF16) and environment step (FP64) at r in {8, 32, 64, 128},
-        # R in {1, 2, r, 2r}
-        torch.cuda.set_device(0)
         rows, envs = [], []
         for r in (8, 32, 64, 128):
             for R in sorted({1, 2, r, 2 * r}):
                 rows.append(contraction_rate(P, torch, r, R))
-                rows.append(contraction_rate_bf16(P, torch, r, R))
+                rows.append(contraction_rate(P, torch, r, R, bf16=True))
                 envs.append(interface_rate(P, torch, r, R))
         print(json.dumps({"local_contraction": rows, "interfaces": envs, "copy_bytes": calibration_copy(torch)}),
               flush=True)
@@ -277,23 +379,14 @@ def main():
     icap = args.iter_rank_cap or icap
     cfg = I.config(cfg_name)
     graph = cfg["graph"]
-    kind = {"maxcut": P.TTIPM_MAXCUT, "theta": P.TTIPM_THETA}[cfg["kind"]]
-    torch.cuda.set_device(0)
-    prob = P.Problem(kind, graph.cores)
-    # local systems up to 1024 unknowns by the dense block elimination, larger
-    # ones by restarted FP64 GMRES with the block-Jacobi preconditioner
-    solver = dict(direct_max=1024, precond=P.TT_PREC_BJACOBI, gmres_restart=40, gmres_maxit=1000)
-    prm = P.Params(rank_cap=cap, iter_rank_cap=icap, stop_gap=1e-4, eps_gap=1e-4, max_iter=args.max_iter,
-                   verbose=1 if args.verbose else 0, **solver)
+    prob, _ = problem_of(P, I, cfg_name)
+    prm = P.Params(rank_cap=cap, iter_rank_cap=icap, max_iter=args.max_iter, verbose=1 if args.verbose else 0,
+                   direct_max=1024, precond=P.TT_PREC_BJACOBI, gmres_restart=40, gmres_maxit=1000, **MARK)
 
     def one_solve():
         st = P.State(prob, prm)
-        res, log = P.ttipm_solve(prob, st, prm)
-        return res, log
+        return P.ttipm_solve(prob, st, prm)
 
-    # load the kernels and fill the allocator once (one IPM iteration, untimed)
-    warm = P.Params(rank_cap=cap, iter_rank_cap=icap, stop_gap=1e-4, eps_gap=1e-4, max_iter=1, **solver)
-    P.ttipm_solve(prob, P.State(prob, warm), warm)
     for w in range(args.warmup):
         res, _ = one_solve()
         print(f"warmup {w}: {res['iterations']} iterations, gap {res['rel_gap']:.2e}, "
@@ -315,60 +408,34 @@ def main():
     per_step = elapsed / args.steps
     reached = all(r["time_to_gap"] > 0 for r, _ in results)
     last, last_log = results[-1]
-
-    # dominant instrumented kernel inside the timed steps
-    dom_name, dom = max(kstats.items(), key=lambda kv: kv[1]["time_ms"])
-    roof = None
-    if dom["timed"] > 0 and dom["time_ms"] > 0:
-        t_avg = dom["time_ms"] / 1e3 / dom["timed"]
-        if dom["flops"] > 0:
-            prec = "bf16" if "bf16" in dom_name else "f64"
-            achieved = dom["flops"] / (dom["time_ms"] / 1e3)
-            roof = {"bound": "mfma", "kernel": dom_name, "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved / PEAK[prec], "traffic": stored_traffic(dom_name, args.workload),
-                    "algorithmic_bytes_per_launch": dom["bytes"] / dom["timed"],
-                    "avg_launch_us": t_avg * 1e6, "launches": dom["launches"], "timed_launches": dom["timed"],
-                    "flops_per_launch": dom["flops"] / dom["timed"]}
-        else:
-            achieved = dom["bytes"] / (dom["time_ms"] / 1e3)
-            roof = {"bound": "hbm", "kernel": dom_name, "achieved": achieved / 1e9, "peak": HBM / 1e9,
-                    "unit": "GB/s", "frac": achieved / HBM, "traffic": stored_traffic(dom_name, args.workload),
-                    "avg_launch_us": t_avg * 1e6,
-                    "launches": dom["launches"], "timed_launches": dom["timed"],
-                    "bytes_per_launch": dom["bytes"] / dom["timed"]}
-    kernel_share = {k: round(v["time_ms"] * (args.profile_period if v["timed"] else 0) / 1e3 / args.steps, 4)
+    roof = roofline_of(kstats, args.profile_period, args.workload)
+    kernel_share = {k: round(v["time_ms"] * (args.profile_period if v["timed"] else 0) / 1e3 / args.steps, 5)
                     for k, v in kstats.items()}
 
-    # the same C2 step with BF16 Arnoldi products and FP64 refinement (mixed precision)
-    c2_mixed = None
-    if not args.no_variants:
-        pm = P.Params(rank_cap=cap, iter_rank_cap=icap, stop_gap=1e-4, eps_gap=1e-4, max_iter=args.max_iter,
-                      precision=P.TTIPM_MIXED, **solver)
-        t0m = time.perf_counter()
-        resm, logm = P.ttipm_solve(prob, P.State(prob, pm), pm)
-        c2_mixed = {"wall_s": time.perf_counter() - t0m, "iterations": resm["iterations"],
-                    "time_to_gap_s": resm["time_to_gap"], "rel_gap": resm["rel_gap"], "eps_p": resm["eps_p"],
-                    "eps_d": resm["eps_d"], "krylov_iters": int(sum(l["krylov_iters"] for l in logm)),
-                    "krylov_iters_f64": int(sum(l["krylov_iters"] for l in last_log))}
-    contraction = [contraction_rate(P, torch, r, R) for r, R in ((cap, 2 * cap), (64, 128))]
-    contraction += [contraction_rate_bf16(P, torch, r, R) for r, R in ((cap, 2 * cap), (64, 128))]
-    variants = None if args.no_variants else precision_variants(P, I)
-    closed = None if args.no_variants else closed_forms_d10(P, I)
+    contraction = [contraction_rate(P, torch, r, 2 * r, bf16=b) for r in (32, 64, 128) for b in (False, True)]
 
     cpu = None
     if not args.no_cpu and graph.dense is not None:
         cpu = cpu_baseline(graph)
-
+    oracle_obj = cpu["objective_1e9"] if cpu else None
     err = None
-    if cpu is not None:
-        ref = 0.5 * (cpu["pobj_1e9"] + cpu["dobj_1e9"])
-        err = {"pobj_vs_oracle": abs(last["pobj"] - ref) / (1 + abs(ref)),
-               "dobj_vs_oracle": abs(last["dobj"] - ref) / (1 + abs(ref)), "oracle_objective": ref}
-        cpu = {k: v for k, v in cpu.items() if not k.endswith("_1e9")}
+    if oracle_obj is not None:
+        err = {"pobj_vs_oracle": abs(last["pobj"] - oracle_obj) / (1 + abs(oracle_obj)),
+               "dobj_vs_oracle": abs(last["dobj"] - oracle_obj) / (1 + abs(oracle_obj)),
+               "oracle_objective": oracle_obj}
+        if cfg_name == "maxcut_grid_d5":
+            err["pobj_vs_closed_form_52"] = abs(last["pobj"] - 52.0) / 53.0
+        cpu = {k: v for k, v in cpu.items() if k != "objective_1e9"}
+
+    variants = records = closed = None
+    if not args.no_variants:
+        variants = precision_variants(P, I, oracle_obj if cfg_name == "maxcut_grid_d5" and oracle_obj else 52.0)
+        closed = closed_forms_d10(P, I, cpu=not args.no_cpu)
+        records = config_records(P, I, args.record_wall)
 
     out = {
         "metric": "TT-IPM time-to-gap<=1e-4 (s) + local-contraction TFLOP/s, mixed+learned vs FP64",
-        "value": per_step,
+        "value": per_step if reached else None,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -383,8 +450,10 @@ def main():
                    "frame_rank_cap": cap, "iterate_rank_cap": icap, "precision": "f64",
                    "gap_rule": "rel_gap<=1e-4, eps_p<=2e-4, eps_d<=2e-4"},
         "reached_gap": reached,
-        "solve": {"iterations": last["iterations"], "time_to_gap_s": last["time_to_gap"], "rel_gap": last["rel_gap"],
-                  "eps_p": last["eps_p"], "eps_d": last["eps_d"], "pobj": last["pobj"], "dobj": last["dobj"],
+        "solve": {"iterations": last["iterations"], "time_to_gap_s": last["time_to_gap"],
+                  "time_to_gap_median_s": _median([r["time_to_gap"] for r, _ in results]),
+                  "rel_gap": last["rel_gap"], "eps_p": last["eps_p"], "eps_d": last["eps_d"],
+                  "pobj": last["pobj"], "dobj": last["dobj"],
                   "max_rank_w": max((l["rank_w"] for l in last_log), default=0),
                   "max_rank_x": max((l["rank_x"] for l in last_log), default=0),
                   "phase_s": {k: round(sum(l[k] for l in last_log), 4)
@@ -393,8 +462,8 @@ def main():
         "kernel_time_s_per_step": kernel_share,
         "roofline": roof,
         "local_contraction": contraction,
-        "precision_variants_grid_d5": variants,
-        "mixed_precision_same_step": c2_mixed,
+        "precision_variants": variants,
+        "config_records": records,
         "time_to_gap_n1024_closed_forms": closed,
         "cpu_baseline": cpu,
     }

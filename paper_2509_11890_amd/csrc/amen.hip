@@ -380,7 +380,6 @@ void principal_orth_rows(const double* B, int q0, long bj, long bi, int len, con
                             hipMemcpyDeviceToDevice, c.s));
     random_orth_rows(Bx.get(), q0 + take, len, 1, len, G + (size_t)take * len, q - take, seed, c);
   }
-  c.sync();
 }
 
 // Move the block index from W.pos to W.pos + 1 (dir > 0) or W.pos - 1 (dir < 0).
@@ -593,9 +592,10 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
   dense_symmetrize(LZ.get(), p, c.s);
   c.ired.reserve(4);
   int* st = reinterpret_cast<int*>(c.ired.get());
-  // Large frames go through the blocked (GEMM-based) factorisations; small
-  // ones through the single-workgroup kernels, which have less launch overhead.
-  const bool blocked = p > kBlockedMin;
+  // Frames whose matrices fit one workgroup's LDS go through the LDS-resident
+  // single-workgroup kernels (fewest launches); larger ones through the
+  // blocked (GEMM-based) factorisations.
+  const bool blocked = p > kBlockedMin || !dense_small_fits_lds(p);
   BlockedFactors fz, fs;
   int hst = 0;
   if (blocked) {
@@ -898,6 +898,32 @@ void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double
 
 namespace {
 
+// rows of block b (rho rows of len, taken from Eb[b]) scaled by 1 / ||Eb[b]||
+// into out[b]; a zero block gives zero rows.  One workgroup per block.
+__global__ __launch_bounds__(256) void normalize_blocks_kernel(const double* Eb, long blk, int rho, int len,
+                                                               const int* which, bool transpose, double* out) {
+  __shared__ double red[256];
+  const double* y = Eb + (size_t)which[blockIdx.x] * blk;
+  double* dst = out + (size_t)blockIdx.x * blk;
+  double sq = 0.0;
+  for (long t = threadIdx.x; t < blk; t += 256) sq += y[t] * y[t];
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double nrm = sqrt(red[0]);
+  const double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  // transpose: y is [len][rho] -> rows [rho][len]
+  for (long t = threadIdx.x; t < blk; t += 256)
+    dst[t] = sc * (transpose ? y[(t % len) * rho + t / len] : y[t]);
+}
+
+}  // namespace
+
+namespace {
+
 // Candidate enrichment rows at core k: every block row b of E = K dU + R
 // (eq. (tt-kkt-newton-system), the current block core as dU_k) projected with
 // the frame's environments behind the block and the sketch's ahead of it.
@@ -961,24 +987,21 @@ int residual_candidates(const NewtonSys& sys, Envs& envs, Envs& sk, const BlockT
                    1.0});
   }
   local_apply_many(v, c);
-  // rows of the candidates, one residual block row after another
-  const int used[4] = {RES_D, RES_P, sys.ineq ? RES_T : -1, RES_C};
-  int nc = 0;
+  // rows of the candidates, one residual block row after another, each block
+  // scaled to unit norm on the device (a zero block gives zero rows, which the
+  // principal directions ignore)
+  std::vector<int> used = {RES_D, RES_P};
+  if (sys.ineq) used.push_back(RES_T);
+  used.push_back(RES_C);
+  c.ired.reserve(8);
+  int* wd = reinterpret_cast<int*>(c.ired.get()) + 4;
+  TT_HIP(hipMemcpyAsync(wd, used.data(), sizeof(int) * used.size(), hipMemcpyHostToDevice, c.s));
   cand.reserve((size_t)nrow * blk);
-  for (int u = 0; u < 4; ++u) {
-    if (used[u] < 0) continue;
-    double* y = Eb.get() + (size_t)used[u] * blk;
-    const double nrm = dev_norm(y, blk, c);
-    if (!(nrm > 0.0)) continue;
-    double* dst = cand.get() + (size_t)nc * rows_out;
-    if (dir > 0)
-      permute(y, dst, {rows_out, rho}, {1, 0}, c.s, 1.0 / nrm);
-    else
-      axpby(blk, 1.0 / nrm, y, 0.0, dst, c.s);
-    nc += rho;
-  }
-  c.sync();
-  return nc;
+  hipLaunchKernelGGL(normalize_blocks_kernel, dim3((unsigned)used.size()), dim3(256), 0, c.s, Eb.get(), blk, rho,
+                     rows_out, wd, dir > 0, cand.get());
+  TT_HIP(hipGetLastError());
+  c.sync();   // the host copy of `used` must be consumed before it goes out of scope
+  return (int)used.size() * rho;
 }
 
 }  // namespace

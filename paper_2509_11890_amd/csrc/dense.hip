@@ -967,6 +967,10 @@ static size_t small_lds_limit() {
   return limit;
 }
 
+bool dense_small_fits_lds(int n, int nrhs) {
+  return sizeof(double) * ((size_t)n * (n | 1) + (size_t)n * nrhs) <= small_lds_limit();
+}
+
 // The single-workgroup factorisations below are timed as one group; their
 // algorithmic flops are the textbook counts.
 void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s) {

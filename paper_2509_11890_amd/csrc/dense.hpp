@@ -34,6 +34,10 @@ void dense_sym_min_eig(const double* B, int p, double* v, double* lam, double* w
                        int kmax = 128, int restarts = 8, double tol = 1e-12, bool v_init = false);
 // LU with partial pivoting; solves A X = B in place (row-major).  status[0] != 0 on a zero pivot.
 void dense_lu_solve(double* A, int n, double* B, int nrhs, int* status, hipStream_t s);
+// True when the LDS-resident Cholesky / LU-solve kernels take an n x n matrix
+// (and n x nrhs right-hand sides); larger matrices go through the blocked
+// factorisations instead.
+bool dense_small_fits_lds(int n, int nrhs = 1);
 // Cholesky (lower, row-major, in place).  status[0] = j+1 if not positive definite.
 void dense_cholesky(double* A, int n, int* status, hipStream_t s);
 // A <- (A + A^T) / 2 (row-major n x n).

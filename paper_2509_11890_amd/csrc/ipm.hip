@@ -320,7 +320,7 @@ double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c, const double*
   TT_HIP(hipGetLastError());
   // Pencils of a few hundred unknowns use the GEMM-based blocked Cholesky and
   // triangular solves; the single-workgroup kernels win only for small ones.
-  const bool blocked = p >= kPencilBlocked;
+  const bool blocked = p >= kPencilBlocked || !dense_small_fits_lds(p);
   BlockedFactors f;
   int hst = 0;
   if (blocked) {
