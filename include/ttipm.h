@@ -417,10 +417,15 @@ typedef struct {
                            precision TTIPM_MIXED a direction above eta is then refined by
                            FP64 AMEn sweeps warm-started from it (1)                      */
   int32_t refine_sweeps;/* FP64 half-sweeps of one such refinement (2)                    */
+  int32_t combine_multipliers; /* 1: with inequalities whose masks are disjoint
+                           ((I - K_Y)(I - K_T) = 0), Y and T updates share one padded block
+                           dL of the Newton system (Sec. 3.5, Combined Multiplier Storage):
+                           two block rows and columns instead of three (1)               */
   int32_t enrich;       /* AMEn enrichment (Sec. 2.3): 1 = the leading directions of the
                            Newton residual K dU + R sketched with a seeded Gaussian TT on
-                           the side ahead of the block, with room kept under rank_cap (1);
-                           0 = seeded random directions, off once rank_cap truncates      */
+                           the side ahead of the block (1); 0 = seeded random directions,
+                           off once rank_cap truncates.  Both fill only capacity left
+                           under rank_cap                                                 */
 } ttipm_params;
 
 TTIPM_API void ttipm_params_default(ttipm_params* p);

@@ -97,7 +97,7 @@ class ttipm_params(C.Structure):
                 ("kick_sweeps", C.c_int32), ("collect_probes", C.c_int32), ("collect_cap", C.c_int64),
                 ("xz_fallback", C.c_int32), ("eig_kick", C.c_int32), ("g4_window", C.c_int32),
                 ("g4_retries", C.c_int32), ("shift_mode", C.c_int32), ("newton_check", C.c_int32),
-                ("refine_sweeps", C.c_int32), ("enrich", C.c_int32)]
+                ("refine_sweeps", C.c_int32), ("combine_multipliers", C.c_int32), ("enrich", C.c_int32)]
 
 
 class ttipm_step_info(C.Structure):

@@ -413,14 +413,12 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     TT_HIP(hipGetLastError());
     SvdOut sv;
     svd_rowmajor_side(Ms.get(), rows, cols, true, sv, c);
-    // Random enrichment fills only the capacity the rank cap leaves (once the
-    // cap binds, the truncated SVD directions are kept in full); residual
-    // enrichment (candidates given) comes on top of the truncated rank, as in
-    // AMEn, so the frame rank can reach cap + kick.
+    // Enrichment fills only the capacity the rank cap leaves: once the cap
+    // binds, the truncated SVD directions are kept in full.
     const int rk_tol = rank_for(sv.sigma, tol_rel, sv.k);
     const int rk0 = std::max(1, std::min(rk_tol, cap));
     capped = rk_tol > cap;
-    const int q = std::max(0, std::min({kick, rows - rk0, cand ? kick : cap - rk0}));
+    const int q = std::max(0, std::min({kick, rows - rk0, cap - rk0}));
     const int rk = rk0 + q;
     // W_k = [U[:, :rk0] | kick]  ([r][4][rk])
     W.cores[k].reserve((size_t)rows * rk);
@@ -467,7 +465,7 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     const int rk_tol = rank_for(sv.sigma, tol_rel, sv.k);
     const int rk0 = std::max(1, std::min(rk_tol, cap));
     capped = rk_tol > cap;
-    const int q = std::max(0, std::min({kick, cols - rk0, cand ? kick : cap - rk0}));
+    const int q = std::max(0, std::min({kick, cols - rk0, cap - rk0}));
     const int rk = rk0 + q;
     // W_k = [Vt[:rk0]; kick]  ([rk][4][s])
     W.cores[k].reserve((size_t)rk * cols);

@@ -14,7 +14,12 @@
 namespace ttipm {
 
 // Indices of the system operators (all TT matrices with 4 x 4 modes).
-enum SysOpId { OP_AEQ = 0, OP_AEQT, OP_KY, OP_LZ, OP_LX, OP_TA, OP_DK, OP_AIT, OP_EXTRA0, OP_EXTRA1, OP_COUNT };
+enum SysOpId {
+  OP_AEQ = 0, OP_AEQT, OP_KY, OP_LZ, OP_LX, OP_TA, OP_DK, OP_AIT,
+  // operators used only by right-hand-side terms
+  OP_EXTRA0, OP_EXTRA1, OP_EXTRA2, OP_EXTRA3, OP_EXTRA4, OP_EXTRA5, OP_EXTRA6, OP_EXTRA7, OP_EXTRA8, OP_EXTRA9,
+  OP_COUNT
+};
 
 // Residual blocks of eq. (tt-kkt-newton-system).
 enum ResId { RES_D = 0, RES_P = 1, RES_C = 2, RES_T = 3 };
@@ -59,8 +64,8 @@ void random_orth_rows(const double* B, int q0, long bj, long bi, int len, double
                       Ctx& c);
 // With candidate rows cand (ncand rows of the kept factor's length: the
 // sketched residual of the local system, see amen_solve) the kick directions
-// are their leading principal directions, added on top of the truncated rank
-// (the frame rank can reach cap + kick).
+// are their leading principal directions.  Either kind fills only capacity
+// left under the cap.
 bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick = 0,
                  unsigned long long seed = 0, const double* cand = nullptr, int ncand = 0);
 // Norm of a device vector (deterministic; synchronises).

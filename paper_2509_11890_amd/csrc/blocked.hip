@@ -163,6 +163,91 @@ __global__ __launch_bounds__(BT) void panel_lu_kernel(double* A, int m, int nb, 
   }
 }
 
+// The same panel factorisation with the panel staged in LDS (row stride
+// nb + 1): for panels of up to a few hundred rows, where every step of the
+// global-memory version waits on L2 latency.
+__global__ __launch_bounds__(BT) void panel_lu_lds_kernel(double* A, int m, int nb, long lda, int* piv, int row_base,
+                                                          int* status) {
+  extern __shared__ double P[];
+  __shared__ double rv[BT];
+  __shared__ int ri[BT];
+  __shared__ int s_piv;
+  const int ld = nb + 1;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < m * nb; t += BT) P[(t / nb) * ld + t % nb] = A[(long)(t / nb) * lda + t % nb];
+  __syncthreads();
+  for (int j = 0; j < nb && j < m; ++j) {
+    double best = -1.0;
+    int bi = j;
+    for (int i = j + tid; i < m; i += BT) {
+      const double v = fabs(P[i * ld + j]);
+      if (v > best) { best = v; bi = i; }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int o = BT / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        const double a = rv[tid], b = rv[tid + o];
+        const int ia = ri[tid], ib = ri[tid + o];
+        if (b > a || (b == a && ib < ia)) { rv[tid] = b; ri[tid] = ib; }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      s_piv = ri[0];
+      piv[j] = row_base + ri[0];
+    }
+    __syncthreads();
+    const int pv = s_piv;
+    if (pv != j)
+      for (int c = tid; c < nb; c += BT) {
+        const double t = P[j * ld + c];
+        P[j * ld + c] = P[pv * ld + c];
+        P[pv * ld + c] = t;
+      }
+    __syncthreads();
+    const double d = P[j * ld + j];
+    if (d == 0.0) {
+      if (tid == 0 && status[0] == 0) status[0] = row_base + j + 1;
+      __syncthreads();
+      continue;
+    }
+    for (int i = j + 1 + tid; i < m; i += BT) P[i * ld + j] /= d;
+    __syncthreads();
+    const int cols = nb - j - 1;
+    if (cols > 0)
+      for (int t = tid; t < (m - j - 1) * cols; t += BT) {
+        const int i = j + 1 + t / cols, c = j + 1 + t % cols;
+        P[i * ld + c] -= P[i * ld + j] * P[j * ld + c];
+      }
+    __syncthreads();
+  }
+  for (int t = tid; t < m * nb; t += BT) A[(long)(t / nb) * lda + t % nb] = P[(t / nb) * ld + t % nb];
+}
+
+// Dynamic LDS available to the LDS panel kernel (device limit minus its
+// static reduction arrays), opted in above the 64 KiB default.
+static size_t panel_lds_limit() {
+  static size_t limit = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+      (void)hipGetLastError();
+      return (size_t)0;
+    }
+    size_t lim = (size_t)v - (size_t)BT * 12 - 256;
+    if (lim > 65536 - (size_t)BT * 12 - 256 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&panel_lu_lds_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
+      (void)hipGetLastError();
+      lim = 65536 - (size_t)BT * 12 - 256;
+    }
+    return lim;
+  }();
+  return limit;
+}
+
 // Apply the row swaps of one panel (rows j0 .. j0+nb-1 swapped with piv[t])
 // to the columns [c0, c1): one thread per column, swaps in order.
 __global__ void apply_swaps_kernel(double* A, long lda, const int* piv, int j0, int nb, int c0, int c1) {
@@ -327,8 +412,13 @@ void lu_rec(double* A, int n, BlockedFactors& f, int* piv, int j0, int w, int* s
   const int nb = f.nb;
   if (w <= nb) {
     const double pm = n - j0;
-    launch_prof(PK_PANEL_LU, pm * w * (double)w, 16.0 * pm * w, panel_lu_kernel, dim3(1), dim3(BT), 0, c.s,
-                A + (long)j0 * n + j0, n - j0, w, (long)n, piv + j0, j0, st);
+    const size_t lds = sizeof(double) * (size_t)(n - j0) * (w + 1);
+    if (lds <= panel_lds_limit())
+      launch_prof(PK_PANEL_LU, pm * w * (double)w, 16.0 * pm * w, panel_lu_lds_kernel, dim3(1), dim3(BT),
+                  (unsigned)lds, c.s, A + (long)j0 * n + j0, n - j0, w, (long)n, piv + j0, j0, st);
+    else
+      launch_prof(PK_PANEL_LU, pm * w * (double)w, 16.0 * pm * w, panel_lu_kernel, dim3(1), dim3(BT), 0, c.s,
+                  A + (long)j0 * n + j0, n - j0, w, (long)n, piv + j0, j0, st);
     double* Ajj = A + (long)j0 * n + j0;
     TT_REQUIRE(w <= kTriMax, "diagonal block above 32");
     hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(64), 0, c.s, Ajj, w, (long)n,

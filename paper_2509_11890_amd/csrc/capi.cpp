@@ -492,6 +492,7 @@ void ttipm_params_default(ttipm_params* p) {
   p->newton_check = 1;
   p->refine_sweeps = 2;
   p->enrich = 1;
+  p->combine_multipliers = 1;
 }
 
 int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {

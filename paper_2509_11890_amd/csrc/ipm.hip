@@ -5,6 +5,7 @@
 #include "mlp.hpp"
 
 #include <algorithm>
+#include <deque>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -87,6 +88,20 @@ TT round_shift(TT v, double tol, const TT* shift, int cap, Ctx& c, ShiftInfo* si
 // ---------------------------------------------------------------------------
 // problem encodings (Sec. 4)
 // ---------------------------------------------------------------------------
+// Non-idle multiplier masks P_Y = I - K_Y, P_T = I - K_T and whether they are
+// disjoint (P_Y P_T = 0, checked on the diagonal P_Y P_T vec_TT(J) of the two
+// diagonal masks): the condition of the combined multiplier storage of Sec. 3.5.
+void multiplier_masks(Problem& P, Ctx& c) {
+  P.PY = tt_add({&P.I16, &P.KY}, {1.0, -1.0}, c);
+  P.PT = tt_add({&P.I16, &P.KT}, {1.0, -1.0}, c);
+  compress(P.PY, c);
+  compress(P.PT, c);
+  TT Jvec = tt_rank1(P.d, 4, 1, J4, c);
+  TT t = tt_matvec(P.PT, Jvec, c);
+  TT b = tt_matvec(P.PY, t, c);
+  P.masks_disjoint = tt_norm(b, c) <= 1e-12 * tt_norm(Jvec, c);
+}
+
 Problem build_problem(int kind, const TT& G, const TT* negdeg, Ctx& c) {
   TT_REQUIRE(G.mo == 2 && G.mi == 2, "graph must be a TT matrix with 2 x 2 modes");
   Problem P;
@@ -164,6 +179,7 @@ Problem build_problem(int kind, const TT& G, const TT* negdeg, Ctx& c) {
     compress(P.AineqT, c);
     compress(P.KT, c);
     compress(P.oneT, c);
+    multiplier_masks(P, c);
   }
   P.normB = tt_norm(P.Beq, c);
   P.normC = tt_norm(P.C, c);
@@ -233,6 +249,7 @@ Problem build_problem_generic(const GenericSdp& g, Ctx& c) {
     compress(P.AineqT, c);
     compress(P.KT, c);
     compress(P.oneT, c);
+    multiplier_masks(P, c);
   }
   P.normB = tt_norm(P.Beq, c);
   P.normC = tt_norm(P.C, c);
@@ -663,6 +680,81 @@ TT L_op(const Problem& P, const TT& Mv, bool aho, bool left_identity, Ctx& c) {
   return left_identity ? tt_kron(P.I2, Mm, c) : tt_kron(Mm, P.I2, c);
 }
 
+// The Newton system with the multiplier updates dY and dT stored in one padded
+// block dL (Sec. 3.5, Combined Multiplier Storage; masks disjoint): the dual
+// column becomes -(A_eq^T P_Y + s A_ineq^T P_T) dL, the two multiplier rows
+// become -(P_Y A_eq + s P_T T A_ineq) dX + (P_Y K_Y P_Y + P_T (D_ineq + K_T) P_T) dL
+// with right-hand side P_Y R_p + P_T R_t, and the dX, dZ rows are unchanged.
+// The operators of the block are built once per iteration (ops); the masked
+// right-hand-side terms per solve, their operators kept in `store`.
+struct CombinedOps {
+  TT Aeq, AeqT, KY;
+};
+
+CombinedOps combined_ops(const Problem& P, const TT& TA, const TT& DK, double tol, Ctx& c) {
+  CombinedOps o;
+  const double s = P.sense;
+  TT a1 = tt_matmat(P.PY, P.Aeq, c), a2 = tt_matmat(P.PT, TA, c);
+  o.Aeq = tt_add({&a1, &a2}, {1.0, s}, c);
+  TT b1 = tt_matmat(P.AeqT, P.PY, c), b2 = tt_matmat(P.AineqT, P.PT, c);
+  o.AeqT = tt_add({&b1, &b2}, {1.0, s}, c);
+  TT k1 = tt_matmat(P.PY, P.KY, c), k2 = tt_matmat(P.PT, DK, c);
+  TT k1p = tt_matmat(k1, P.PY, c), k2p = tt_matmat(k2, P.PT, c);
+  o.KY = tt_add({&k1p, &k2p}, {1.0, 1.0}, c);
+  tt_round_abs(o.Aeq, tol, 1 << 30, c);
+  tt_round_abs(o.AeqT, tol, 1 << 30, c);
+  tt_round_abs(o.KY, tol, 1 << 30, c);
+  return o;
+}
+
+NewtonSys combined_system(const NewtonSys& s0, const Problem& P, const CombinedOps& co, std::deque<TT>& store,
+                          double tol, Ctx& c) {
+  NewtonSys sc;
+  sc.ineq = false;
+  sc.sense = 1.0;
+  for (int o = 0; o < OP_COUNT; ++o) sc.ops[o] = nullptr;
+  sc.ops[OP_AEQ] = &co.Aeq;
+  sc.ops[OP_AEQT] = &co.AeqT;
+  sc.ops[OP_KY] = &co.KY;
+  sc.ops[OP_LZ] = s0.ops[OP_LZ];
+  sc.ops[OP_LX] = s0.ops[OP_LX];
+  sc.ops[OP_EXTRA0] = s0.ops[OP_EXTRA0];
+  // masked term operators in the free slots OP_EXTRA2.., one per (mask, operator)
+  std::vector<std::pair<std::pair<int, int>, int>> memo;
+  int next = OP_EXTRA2;
+  auto masked = [&](int mask, int op) {
+    for (const auto& m : memo)
+      if (m.first.first == mask && m.first.second == op) return m.second;
+    TT_REQUIRE(next < OP_COUNT, "combined multipliers: out of operator slots");
+    const TT& M = mask == 0 ? P.PY : P.PT;
+    if (op < 0) {
+      store.push_back(tt_clone(M, c));
+    } else {
+      store.push_back(tt_matmat(M, *s0.ops[op], c));
+      tt_round_abs(store.back(), tol, 1 << 30, c);
+    }
+    sc.ops[next] = &store.back();
+    memo.push_back({{mask, op}, next});
+    return next++;
+  };
+  // an unmasked term whose operator the combined system does not carry (A_ineq^T
+  // on T in R_d) gets a slot of its own
+  auto carried = [&](int op) {
+    if (op < 0 || sc.ops[op] == s0.ops[op]) return op;
+    for (int o = OP_EXTRA2; o < next; ++o)
+      if (sc.ops[o] == s0.ops[op]) return o;
+    TT_REQUIRE(next < OP_COUNT, "combined multipliers: out of operator slots");
+    sc.ops[next] = s0.ops[op];
+    return next++;
+  };
+  for (const Term& t : s0.terms) {
+    if (t.res == RES_P) sc.terms.push_back({RES_P, t.coef, masked(0, t.op), t.vec});
+    else if (t.res == RES_T) sc.terms.push_back({RES_P, t.coef, masked(1, t.op), t.vec});
+    else sc.terms.push_back({t.res, t.coef, carried(t.op), t.vec});
+  }
+  return sc;
+}
+
 }  // namespace
 
 void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c) {
@@ -719,6 +811,19 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     sys.ops[OP_DK] = &DK;
     sys.ops[OP_AIT] = &P.AineqT;
   }
+  // combined multiplier storage (Sec. 3.5) when the masks are disjoint
+  const bool comb = P.ineq && P.masks_disjoint && prm.combine_multipliers != 0;
+  CombinedOps cops;
+  if (comb) cops = combined_ops(P, TA, DK, told, c);
+  std::deque<TT> cstore;
+  NewtonSys sysc;
+  // the system the AMEn solves: the combined one is rebuilt from sys's terms
+  auto solve_sys = [&]() -> const NewtonSys& {
+    if (!comb) return sys;
+    cstore.clear();
+    sysc = combined_system(sys, P, cops, cstore, told, c);
+    return sysc;
+  };
   // residual terms: R_d = Z + C - Aeq^T Y (- s Aineq^T T), R_p = B - Aeq X,
   // R_t = T o s(X) - mu 1_T = -s diag(T) A_ineq X (+ s diag(T) B_ineq) - mu 1_T
   //
@@ -740,7 +845,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   }
   if (P.ineq) base.push_back({RES_T, -P.sense, OP_TA, &S.X});
   if (!S.has_W) {
-    S.W = block_from_frame(P.Ivec, sys.Lp(), c);
+    S.W = block_from_frame(P.Ivec, comb ? 3 : sys.Lp(), c);
     S.has_W = true;
   }
   AmenParams ap;
@@ -752,11 +857,11 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   ap.gmres_maxit = prm.gmres_maxit;
   ap.precond = prm.precond;
   ap.mixed = prm.precision == TTIPM_MIXED;
-  // Enrichment lets the frame ranks grow past a block-ALS fixed point.  The
-  // residual directions stay on when the rank cap binds (the split keeps room
-  // for them); random directions are switched off for the rest of the solve
-  // once a Newton frame has been truncated by the cap, where they would only
-  // perturb the truncated solve.
+  // Enrichment lets the frame ranks grow past a block-ALS fixed point; it
+  // fills capacity left under the rank cap.  Random directions are switched
+  // off for the rest of the solve once a Newton frame has been truncated by
+  // the cap, where they would only perturb the truncated solve; residual
+  // directions stay on wherever a split leaves capacity.
   ap.enrich = prm.enrich;
   ap.kick = (prm.enrich == 0 && S.frame_capped) ? 0 : std::max(0, prm.kick);
   ap.verbose = prm.verbose;
@@ -767,7 +872,21 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   ap.mu = std::max(mu, 1e-300);
   ap.seed = S.seed + 31ull * (unsigned long long)S.iter;
   // --- predictor: affine direction (target mu = 0) ---
-  const int L = sys.L();
+  const int L = comb ? 2 : sys.L();   // solved components; dZ is component L
+  // components of the direction: dX = 0, dZ = L; dY = 1 and dT = 2, or with
+  // combined storage dY = P_Y dL and dT = P_T dL with dL = 1
+  auto comp_y = [&]() {
+    if (!comb) return S.W.component(1, c);
+    TT dl = S.W.component(1, c);
+    return tt_matvec(P.PY, dl, c);
+  };
+  auto comp_t = [&]() {
+    if (!comb) return S.W.component(2, c);
+    TT dl = S.W.component(1, c);
+    TT t = tt_matvec(P.PT, dl, c);
+    tt_round_abs(t, 1e-14 * std::max(tt_norm(t, c), 1e-300), 1 << 30, c);
+    return t;
+  };
   const unsigned long long sd = S.seed + 7919ull * (unsigned long long)S.iter;
   AmenInfo ai_p;
   TT dX, dZ, dT, sx, dsx;
@@ -776,7 +895,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     sys.terms = base;
     sys.terms.push_back({RES_C, 1.0, OP_LZ, &S.X});   // (R_t keeps its mu term only in the corrector)
     ai_p = AmenInfo{};
-    amen_solve(sys, S.W, ap, ai_p, c);
+    amen_solve(solve_sys(), S.W, ap, ai_p, c);
     S.frame_capped |= ai_p.capped;
     dX = S.W.component(0, c);
     dZ = S.W.component(L, c);
@@ -788,7 +907,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     run_concurrent(c, {[&](Ctx& cx) { a_p = std::min(1.0, step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, cx)); },
                        [&](Ctx& cx) { a_d = std::min(1.0, step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, cx)); }});
     if (P.ineq) {
-      dT = S.W.component(2, c);
+      dT = comp_t();
       sx = ineq_slack(P, S.X, false, c);
       dsx = ineq_slack(P, dX, true, c);
       a_p = std::min(a_p, ratio_step(sx, dsx, P.oneT, c));
@@ -848,7 +967,8 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     sys.terms.push_back({RES_T, 1.0, OP_EXTRA1, &dsx});
   }
   AmenInfo ai_c;
-  amen_solve(sys, S.W, ap, ai_c, c);
+  const NewtonSys& sys_c = solve_sys();
+  amen_solve(sys_c, S.W, ap, ai_c, c);
   S.frame_capped |= ai_c.capped;
   // Global FP64 residual of the corrector system (Sec. 3.3, Lemma "AMEn
   // Directions as Inexact Newton Directions": ||K dU + R|| <= eta ||R||).  In
@@ -857,31 +977,32 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   if (prm.newton_check) {
     const double t0 = now();
     double res = 0.0, rhs = 0.0;
-    newton_residual(sys, S.W, &res, &rhs, c);
+    newton_residual(sys_c, S.W, &res, &rhs, c);
     info.newton_res = rhs > 0 ? res / rhs : (res < 0 ? -1.0 : 0.0);
     if (ap.mixed && info.newton_res > S.eta) {
       AmenParams ar = ap;
       ar.mixed = false;
       ar.max_sweeps = std::max(2, prm.refine_sweeps);
       AmenInfo ai_r;
-      amen_solve(sys, S.W, ar, ai_r, c);
+      amen_solve(sys_c, S.W, ar, ai_r, c);
       S.frame_capped |= ai_r.capped;
       info.refine_sweeps = ai_r.sweeps;
       ai_c.krylov_iters += ai_r.krylov_iters;
       ai_c.t_env += ai_r.t_env;
       ai_c.t_solve += ai_r.t_solve;
       ai_c.t_svd += ai_r.t_svd;
-      newton_residual(sys, S.W, &res, &rhs, c);
+      newton_residual(sys_c, S.W, &res, &rhs, c);
       info.newton_res = rhs > 0 ? res / rhs : (res < 0 ? -1.0 : 0.0);
     }
     info.t_check = now() - t0;
   }
-  TT dX2 = S.W.component(0, c), dY2 = S.W.component(1, c), dZ2 = S.W.component(L, c);
+  TT dX2 = S.W.component(0, c), dY2 = comp_y(), dZ2 = S.W.component(L, c);
+  TT dT2;
+  if (P.ineq) dT2 = comp_t();
   t1 = now();
   run_concurrent(c, {[&](Ctx& cx) { info.alpha_p_max = step_length(S.X, dX2, S.EX, S.has_EX, prm, sd + 3, cx); },
                      [&](Ctx& cx) { info.alpha_d_max = step_length(S.Z, dZ2, S.EZ, S.has_EZ, prm, sd + 4, cx); }});
   if (P.ineq) {
-    TT dT2 = S.W.component(2, c);
     TT ds2 = ineq_slack(P, dX2, true, c);
     info.alpha_p_max = std::min(info.alpha_p_max, ratio_step(sx, ds2, P.oneT, c));
     info.alpha_d_max = std::min(info.alpha_d_max, ratio_step(S.T, dT2, P.oneT, c));
@@ -962,7 +1083,6 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
       };
       run_concurrent(c, {primal, dual});
       if (P.ineq) {
-        TT dT2 = S.W.component(2, c);
         TT Tn = tt_add({&S.T, &dT2}, {1.0, ad}, c);
         t.T = round_shift(std::move(Tn), told, &P.oneT, cap, c, nullptr, prm.shift_mode != 0);
       }
@@ -1008,7 +1128,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     S.dX = tt_clone(dX2, c);
     S.dY = tt_clone(dY2, c);
     S.dZ = tt_clone(dZ2, c);
-    if (P.ineq) S.dT = S.W.component(2, c);
+    if (P.ineq) S.dT = tt_clone(dT2, c);
   }
   info.t_round += now() - t1;
   info.alpha_p = a_p;

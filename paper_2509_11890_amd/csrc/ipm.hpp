@@ -19,6 +19,8 @@ struct Problem {
   TT C, Aeq, AeqT, KY, Beq;          // vec_TT vectors (mode 4) and operators (4 x 4)
   TT Aineq, AineqT, KT, Bineq, oneT;
   TT Ivec;                           // vec_TT(I)
+  TT PY, PT;                         // non-idle multiplier masks I - K_Y, I - K_T (inequalities)
+  bool masks_disjoint = false;       // P_Y P_T = 0: Y and T can share one padded block (Sec. 3.5)
   TT I2;                             // identity TT matrix, 2 x 2 modes
   TT I16;                            // identity operator I kron I, 4 x 4 modes
   double normB = 0, normC = 0;
