@@ -66,6 +66,14 @@ TTIPM_API const char* tt_last_error(void);
 /* Library version string. */
 TTIPM_API const char* tt_version(void);
 
+/* sizeof of the caller-visible structs, in this order: tt_view, tt_proj_op,
+   tt_local_block, tt_local_op, tt_solve_params, tt_solve_info,
+   ttipm_problem_desc, tt_mlp_batch, tt_kernel_stat, ttipm_params,
+   ttipm_step_info, ttipm_result.  Writes min(n, 12) values to out (host
+   memory) and returns how many there are (12); a binding compares them with
+   its own mirrors of the structs before any call.  Needs no GPU. */
+TTIPM_API int tt_abi_sizes(size_t* out, int32_t n);
+
 /* ---- TT views ----------------------------------------------------------- */
 enum { TT_F64 = 0, TT_F32 = 1, TT_BF16 = 2 };
 
@@ -421,6 +429,17 @@ typedef struct {
                            ((I - K_Y)(I - K_T) = 0), Y and T updates share one padded block
                            dL of the Newton system (Sec. 3.5, Combined Multiplier Storage):
                            two block rows and columns instead of three (1)               */
+  int32_t finish;       /* 1: finishing phase (Sec. 3.5, Relaxing the Positive Definiteness
+                           Barrier): once the relative stopping criteria hold, ttipm_solve
+                           goes on until ||R_p||_F, ||R_d||_F, <X, Z> < finish_abs; in that
+                           phase the step lengths and the PD safeguard use M + nu I >= 0
+                           and an update is accepted only if ||R_p|| + ||R_d|| + |<X, Z>|
+                           decreases with eps_p, eps_d and rel_gap within max(current, the
+                           relative bound); after damped retries a rejected iteration keeps
+                           the iterate and raises nu (1e-7, then x10, at most
+                           finish_nu_max).  The result meets the relative criteria (0)    */
+  double finish_abs;    /* absolute targets of the finishing phase (1e-3)                 */
+  double finish_nu_max; /* largest relaxation nu of the finishing phase (1e-3)            */
   int32_t enrich;       /* AMEn enrichment (Sec. 2.3): 1 = the leading directions of the
                            Newton residual K dU + R sketched with a seeded Gaussian TT on
                            the side ahead of the block (1); 0 = seeded random directions,
@@ -439,6 +458,7 @@ typedef struct {
   int32_t iter, direction, sweeps_pred, sweeps_corr, krylov_iters;
   int32_t rank_x, rank_y, rank_z, rank_w;
   double mu, pobj, dobj, rel_gap, eps_p, eps_d, eps_c;
+  double norm_rp, norm_rd, xz;      /* ||R_p||_F, ||R_d||_F and <X, Z> (+ <T, slack>) of the entry iterate */
   double alpha_p, alpha_d, sigma, eta;
   double alpha_p_max, alpha_d_max;  /* Thm. 1 step bounds from the TT eigen-solver, before tau and
                                        the PD check (1e6 when the direction has no bound) */
@@ -458,6 +478,9 @@ typedef struct {
                                        environment of the check would exceed 256 MiB) */
   int32_t refine_sweeps;            /* FP64 refinement half-sweeps of the corrector (mixed precision) */
   double t_check;                   /* seconds spent on the residual check and refinement */
+  int32_t finishing;                /* 1 in the finishing phase */
+  int32_t finish_rejected;          /* 1 when the finishing phase kept the iterate (no acceptable step) */
+  double nu;                        /* barrier relaxation nu of this iteration (finishing phase) */
   double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration */
 } ttipm_step_info;
 
@@ -472,14 +495,21 @@ TTIPM_API int ttipm_step(ttipm_problem* p, ttipm_state* s, const ttipm_params* p
                void* stream);
 
 typedef struct {
-  int32_t status;       /* TT_OK: stop_gap reached; TT_ERR_NOT_CONVERGED: max_iter or a
-                           stall (both step lengths < 1e-3 twice in a row); TT_ERR_NOT_PD:
-                           an iterate lost positive definiteness.  The other fields
-                           describe the last accepted iterate in every case. */
+  int32_t status;       /* TT_OK: the relative criteria (stop_gap) hold; with the finishing
+                           phase on, the solve went on from there until the absolute ones,
+                           max_iter or a stall, and the result still meets the relative
+                           ones.  TT_ERR_NOT_CONVERGED: max_iter or a stall (both step
+                           lengths < 1e-3 in five consecutive iterations) before the
+                           relative criteria; TT_ERR_NOT_PD: an iterate lost positive
+                           definiteness.  The other fields describe the last accepted
+                           iterate in every case. */
   int32_t iterations;
   double time_to_gap;   /* seconds to the eps_gap mark (-1 if not reached)          */
   double time_total;
   double pobj, dobj, rel_gap, eps_p, eps_d;
+  double norm_rp, norm_rd, xz;  /* ||R_p||_F, ||R_d||_F, <X, Z> (+ <T, slack>) */
+  int32_t finish_iterations;    /* iterations spent in the finishing phase */
+  int32_t absolute_met;         /* 1 when ||R_p||_F, ||R_d||_F, <X, Z> < finish_abs */
 } ttipm_result;
 
 /*

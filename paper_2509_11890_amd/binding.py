@@ -97,19 +97,21 @@ class ttipm_params(C.Structure):
                 ("kick_sweeps", C.c_int32), ("collect_probes", C.c_int32), ("collect_cap", C.c_int64),
                 ("xz_fallback", C.c_int32), ("eig_kick", C.c_int32), ("g4_window", C.c_int32),
                 ("g4_retries", C.c_int32), ("shift_mode", C.c_int32), ("newton_check", C.c_int32),
-                ("refine_sweeps", C.c_int32), ("combine_multipliers", C.c_int32), ("enrich", C.c_int32)]
+                ("refine_sweeps", C.c_int32), ("combine_multipliers", C.c_int32), ("finish", C.c_int32),
+                ("finish_abs", C.c_double), ("finish_nu_max", C.c_double), ("enrich", C.c_int32)]
 
 
 class ttipm_step_info(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("iter", "direction", "sweeps_pred", "sweeps_corr",
                                          "krylov_iters", "rank_x", "rank_y", "rank_z", "rank_w")] + \
                [(n, C.c_double) for n in ("mu", "pobj", "dobj", "rel_gap", "eps_p", "eps_d", "eps_c",
-                                          "alpha_p", "alpha_d", "sigma", "eta", "alpha_p_max",
+                                          "norm_rp", "norm_rd", "xz", "alpha_p", "alpha_d", "sigma", "eta", "alpha_p_max",
                                           "alpha_d_max")] + \
                [("backtracks", C.c_int32), ("mlp_used", C.c_int32), ("mlp_fallbacks", C.c_int32),
                 ("xz_fallback", C.c_int32), ("g4_retries", C.c_int32)] + \
                [(n, C.c_double) for n in ("psi", "zeta_x", "zeta_x_cap", "zeta_z", "zeta_z_cap", "newton_res")] + \
-               [("refine_sweeps", C.c_int32), ("t_check", C.c_double)] + \
+               [("refine_sweeps", C.c_int32), ("t_check", C.c_double), ("finishing", C.c_int32),
+                ("finish_rejected", C.c_int32), ("nu", C.c_double)] + \
                [(n, C.c_double) for n in ("t_env", "t_solve", "t_svd", "t_step", "t_round", "t_total")]
 
     def as_dict(self):
@@ -119,7 +121,9 @@ class ttipm_step_info(C.Structure):
 class ttipm_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("time_to_gap", C.c_double),
                 ("time_total", C.c_double), ("pobj", C.c_double), ("dobj", C.c_double),
-                ("rel_gap", C.c_double), ("eps_p", C.c_double), ("eps_d", C.c_double)]
+                ("rel_gap", C.c_double), ("eps_p", C.c_double), ("eps_d", C.c_double),
+                ("norm_rp", C.c_double), ("norm_rd", C.c_double), ("xz", C.c_double),
+                ("finish_iterations", C.c_int32), ("absolute_met", C.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -535,3 +539,23 @@ class MLP:
         loss = C.c_double(0.0)
         _check(lib.tt_mlp_eval(self.h, b, C.byref(loss), _stream()))
         return loss.value
+
+
+# ---- struct layout check ---------------------------------------------------------
+lib.tt_abi_sizes.argtypes = [C.POINTER(C.c_size_t), C.c_int32]
+ABI_STRUCTS = (tt_view, tt_proj_op, tt_local_block, tt_local_op, tt_solve_params, tt_solve_info,
+               ttipm_problem_desc, tt_mlp_batch, tt_kernel_stat, ttipm_params, ttipm_step_info, ttipm_result)
+
+
+def abi_mismatches():
+    """(name, library sizeof, mirror sizeof) of every struct whose mirror differs."""
+    out = (C.c_size_t * len(ABI_STRUCTS))()
+    count = lib.tt_abi_sizes(out, len(ABI_STRUCTS))
+    if count != len(ABI_STRUCTS):
+        return [("struct count", count, len(ABI_STRUCTS))]
+    return [(t.__name__, out[i], C.sizeof(t)) for i, t in enumerate(ABI_STRUCTS) if out[i] != C.sizeof(t)]
+
+
+_bad = abi_mismatches()
+if _bad:
+    raise ImportError(f"{LIB_PATH}: struct layouts differ from the Python mirrors: {_bad}")

@@ -94,6 +94,16 @@ const char* tt_last_error(void) { return ttipm::last_error(); }
 
 const char* tt_version(void) { return "ttipm-mi355x 0.1 (gfx950)"; }
 
+int tt_abi_sizes(size_t* out, int32_t n) {
+  const size_t sz[] = {sizeof(tt_view),         sizeof(tt_proj_op),     sizeof(tt_local_block),
+                       sizeof(tt_local_op),     sizeof(tt_solve_params), sizeof(tt_solve_info),
+                       sizeof(ttipm_problem_desc), sizeof(tt_mlp_batch), sizeof(tt_kernel_stat),
+                       sizeof(ttipm_params),    sizeof(ttipm_step_info), sizeof(ttipm_result)};
+  const int count = (int)(sizeof(sz) / sizeof(sz[0]));
+  for (int i = 0; out && i < n && i < count; ++i) out[i] = sz[i];
+  return count;
+}
+
 int tt_profile_start(int32_t period) {
   return guarded([&]() -> int {
     if (period < 1) throw Error(TT_ERR_ARG, "period must be >= 1");
@@ -493,6 +503,9 @@ void ttipm_params_default(ttipm_params* p) {
   p->refine_sweeps = 2;
   p->enrich = 1;
   p->combine_multipliers = 1;
+  p->finish = 0;
+  p->finish_abs = 1e-3;
+  p->finish_nu_max = 1e-3;
 }
 
 int ttipm_problem_create(const ttipm_problem_desc* desc, ttipm_problem** out) {
@@ -597,11 +610,16 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
       r.rel_gap = m.rel_gap;
       r.eps_p = m.eps_p;
       r.eps_d = m.eps_d;
-      const bool done = m.rel_gap <= prm->stop_gap && m.eps_p <= 2 * prm->stop_gap && m.eps_d <= 2 * prm->stop_gap;
-      if (done) {
-        r.status = TT_OK;
-        break;
-      }
+      r.norm_rp = m.norm_rp;
+      r.norm_rd = m.norm_rd;
+      r.xz = m.xz;
+      r.absolute_met = ipm_absolute_done(m, *prm) ? 1 : 0;
+      // relative criteria; with the finishing phase on, the solve goes on
+      // from there to the absolute ones and any later stop returns the last
+      // accepted iterate, which still meets the relative criteria
+      const bool rel_done = ipm_relative_done(m, *prm);
+      if (rel_done) r.status = TT_OK;
+      if (rel_done && (!prm->finish || ipm_absolute_done(m, *prm))) break;
       if (it >= prm->max_iter) break;
       // Stall: the TT direction no longer admits a step (both step lengths
       // below 1e-3 in five consecutive iterations: from the scaled identity
@@ -609,7 +627,7 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
       // the iteration recovers), or an iterate lost positive definiteness in
       // the step-length test; the last accepted iterate is the result.
       if (short_steps >= 5) {
-        r.status = TT_ERR_NOT_CONVERGED;
+        if (!rel_done) r.status = TT_ERR_NOT_CONVERGED;
         break;
       }
       ttipm_step_info inf{};
@@ -622,15 +640,16 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
         break;
       }
       short_steps = (inf.alpha_p < 1e-3 && inf.alpha_d < 1e-3) ? short_steps + 1 : 0;
+      r.finish_iterations += inf.finishing;
       if (log && it < log_cap) log[it] = inf;
       if (prm->verbose)
         std::fprintf(stderr,
                      "it %2d %s mu %.2e pobj %+.10e dobj %+.10e gap %.2e ep %.1e ed %.1e ap %.3e/%.3e ad %.3e/%.3e "
-                     "bt %d g4 %d psi %.2e zx %.1e/%.1e zz %.1e/%.1e nres %.1e rf %d rX %d rY %d rZ %d rW %d sw %d/%d "
+                     "bt %d g4 %d fin %d nu %.0e psi %.2e zx %.1e/%.1e zz %.1e/%.1e nres %.1e rf %d rX %d rY %d rZ %d rW %d sw %d/%d "
                      "kr %d sig %.2e eta %.1e t %.3fs\n",
                      inf.iter, inf.direction ? "aho" : (inf.xz_fallback ? "xz*" : "xz "), inf.mu, inf.pobj, inf.dobj, inf.rel_gap, inf.eps_p,
                      inf.eps_d, inf.alpha_p, inf.alpha_p_max, inf.alpha_d, inf.alpha_d_max, inf.backtracks,
-                     inf.g4_retries, inf.psi, inf.zeta_x, inf.zeta_x_cap, inf.zeta_z, inf.zeta_z_cap, inf.newton_res,
+                     inf.g4_retries, inf.finishing + inf.finish_rejected, inf.nu, inf.psi, inf.zeta_x, inf.zeta_x_cap, inf.zeta_z, inf.zeta_z_cap, inf.newton_res,
                      inf.refine_sweeps, inf.rank_x, inf.rank_y, inf.rank_z, inf.rank_w, inf.sweeps_pred, inf.sweeps_corr,
                      inf.krylov_iters, inf.sigma, inf.eta, inf.t_total);
       if (!std::isfinite(inf.pobj)) throw Error(TT_ERR_NUMERIC, "non-finite objective");

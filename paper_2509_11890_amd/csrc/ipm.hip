@@ -612,39 +612,53 @@ TT ineq_slack(const Problem& P, const TT& X, bool homogeneous, Ctx& c) {
 }
 
 // mu = (<X, Z> + <T, s(X)>) / (n + q)  (Sec. 3.2)
-double ipm_mu(const Problem& P, const State& S, Ctx& c) {
-  double xz = tt_dot(S.X, S.Z, c);
+// Measures of the iterate (X, Y, Z, T): objectives, residual norms, the
+// complementarity <X, Z> (+ <T, slack(X)>) and mu = that / (n + q).
+void iterate_measures(const Problem& P, const TT& X, const TT& Y, const TT& Z, const TT* T, ttipm_step_info& info,
+                      Ctx& c) {
+  double xz = tt_dot(X, Z, c);
   if (P.ineq) {
-    TT sx = ineq_slack(P, S.X, false, c);
-    xz += tt_dot(S.T, sx, c);
+    TT sx = ineq_slack(P, X, false, c);
+    xz += tt_dot(*T, sx, c);
   }
-  return xz / (P.n + P.q);
-}
-
-void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& c) {
-  const double mu = ipm_mu(P, S, c);
-  TT AY = tt_matvec(P.AeqT, S.Y, c);
-  TT Rd = tt_add({&S.Z, &P.C, &AY}, {1.0, 1.0, -1.0}, c);
-  TT AX = tt_matvec(P.Aeq, S.X, c);
+  const double mu = xz / (P.n + P.q);
+  TT AY = tt_matvec(P.AeqT, Y, c);
+  TT Rd = tt_add({&Z, &P.C, &AY}, {1.0, 1.0, -1.0}, c);
+  TT AX = tt_matvec(P.Aeq, X, c);
   TT Rp = tt_add({&P.Beq, &AX}, {1.0, -1.0}, c);
-  const double pobj = tt_dot(P.C, S.X, c);
-  const double dobj = tt_dot(P.Beq, S.Y, c);
+  const double pobj = tt_dot(P.C, X, c);
+  const double dobj = tt_dot(P.Beq, Y, c);
   info.mu = mu;
+  info.xz = xz;
   info.pobj = pobj;
   info.dobj = dobj;
-  info.eps_p = tt_norm(Rp, c) / (1.0 + P.normB);
+  info.norm_rp = tt_norm(Rp, c);
+  info.eps_p = info.norm_rp / (1.0 + P.normB);
   double rdn2 = tt_dot(Rd, Rd, c);
   if (P.ineq) {
-    TT AT = tt_matvec(P.AineqT, S.T, c);
+    TT AT = tt_matvec(P.AineqT, *T, c);
     TT Rd2 = tt_add({&Rd, &AT}, {1.0, -P.sense}, c);
     rdn2 = tt_dot(Rd2, Rd2, c);
   }
-  info.eps_d = std::sqrt(std::max(rdn2, 0.0)) / (1.0 + P.normC);
+  info.norm_rd = std::sqrt(std::max(rdn2, 0.0));
+  info.eps_d = info.norm_rd / (1.0 + P.normC);
   info.rel_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
   info.eps_c = mu / (1.0 + std::fabs(pobj));
-  info.rank_x = S.X.max_rank();
-  info.rank_y = S.Y.max_rank();
-  info.rank_z = S.Z.max_rank();
+  info.rank_x = X.max_rank();
+  info.rank_y = Y.max_rank();
+  info.rank_z = Z.max_rank();
+}
+
+void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& c) {
+  iterate_measures(P, S.X, S.Y, S.Z, P.ineq ? &S.T : nullptr, info, c);
+}
+
+bool ipm_relative_done(const ttipm_step_info& m, const ttipm_params& prm) {
+  return m.rel_gap <= prm.stop_gap && m.eps_p <= 2 * prm.stop_gap && m.eps_d <= 2 * prm.stop_gap;
+}
+
+bool ipm_absolute_done(const ttipm_step_info& m, const ttipm_params& prm) {
+  return m.norm_rp < prm.finish_abs && m.norm_rd < prm.finish_abs && m.xz < prm.finish_abs;
 }
 
 // Psi = ||R_p|| + ||R_d|| + mu of an iterate (the residual measure watched by the
@@ -763,6 +777,26 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   info.iter = S.iter;
   ipm_measures(P, S, info, c);
   const double mu = info.mu;
+  // Finishing phase (Sec. 3.5, Relaxing the Positive Definiteness Barrier):
+  // once the relative stopping criteria hold, the iteration goes on towards
+  // the absolute ones with the PD barrier relaxed to M + nu I >= 0 (nu grows
+  // from 0 only after rejected updates, up to finish_nu_max), and updates are
+  // accepted on a merit test.
+  if (prm.finish && !S.finishing && ipm_relative_done(info, prm)) {
+    S.finishing = true;
+    S.nu = 0.0;
+  }
+  info.finishing = S.finishing ? 1 : 0;
+  info.nu = S.nu;
+  const double nu = S.finishing ? S.nu : 0.0;
+  // the matrices whose definiteness bounds the steps: M + nu I
+  TT Xb, Zb;
+  if (nu > 0.0) {
+    Xb = tt_add({&S.X, &P.Ivec}, {1.0, nu}, c);
+    Zb = tt_add({&S.Z, &P.Ivec}, {1.0, nu}, c);
+  }
+  const TT& Xs = nu > 0.0 ? Xb : S.X;
+  const TT& Zs = nu > 0.0 ? Zb : S.Z;
   // XZ warm-up iterations (Sec. 5.1), then AHO.  With inequality constraints the
   // warm-up is skipped (reading): the nonsymmetric XZ direction breaks the
   // symmetry of X against the mirrored multipliers T, and the iteration stalls
@@ -828,10 +862,11 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   // R_t = T o s(X) - mu 1_T = -s diag(T) A_ineq X (+ s diag(T) B_ineq) - mu 1_T
   //
   // Zero blocks (Sec. 3.5): a feasibility residual that already meets its
-  // stopping threshold (relative 2 stop_gap) is set to zero in the Newton
-  // system, so its terms are neither projected nor contracted.
-  const bool zero_p = info.eps_p <= 2.0 * prm.stop_gap;
-  const bool zero_d = info.eps_d <= 2.0 * prm.stop_gap;
+  // stopping threshold (relative 2 stop_gap; in the finishing phase the
+  // absolute target) is set to zero in the Newton system, so its terms are
+  // neither projected nor contracted.
+  const bool zero_p = S.finishing ? info.norm_rp < prm.finish_abs : info.eps_p <= 2.0 * prm.stop_gap;
+  const bool zero_d = S.finishing ? info.norm_rd < prm.finish_abs : info.eps_d <= 2.0 * prm.stop_gap;
   std::vector<Term> base;
   if (!zero_d) {
     base.push_back({RES_D, 1.0, -1, &S.Z});
@@ -904,8 +939,8 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     // inequalities also s(X + a_p dX) >= 0 and T + a_d dT >= 0 on the active
     // mask (Sec. 3.4: the diagonal pencils reduce to entry ratios)
     // the primal and dual eigen-solves are independent: one stream each
-    run_concurrent(c, {[&](Ctx& cx) { a_p = std::min(1.0, step_length(S.X, dX, S.EX, S.has_EX, prm, sd + 1, cx)); },
-                       [&](Ctx& cx) { a_d = std::min(1.0, step_length(S.Z, dZ, S.EZ, S.has_EZ, prm, sd + 2, cx)); }});
+    run_concurrent(c, {[&](Ctx& cx) { a_p = std::min(1.0, step_length(Xs, dX, S.EX, S.has_EX, prm, sd + 1, cx)); },
+                       [&](Ctx& cx) { a_d = std::min(1.0, step_length(Zs, dZ, S.EZ, S.has_EZ, prm, sd + 2, cx)); }});
     if (P.ineq) {
       dT = comp_t();
       sx = ineq_slack(P, S.X, false, c);
@@ -1000,8 +1035,8 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   TT dT2;
   if (P.ineq) dT2 = comp_t();
   t1 = now();
-  run_concurrent(c, {[&](Ctx& cx) { info.alpha_p_max = step_length(S.X, dX2, S.EX, S.has_EX, prm, sd + 3, cx); },
-                     [&](Ctx& cx) { info.alpha_d_max = step_length(S.Z, dZ2, S.EZ, S.has_EZ, prm, sd + 4, cx); }});
+  run_concurrent(c, {[&](Ctx& cx) { info.alpha_p_max = step_length(Xs, dX2, S.EX, S.has_EX, prm, sd + 3, cx); },
+                     [&](Ctx& cx) { info.alpha_d_max = step_length(Zs, dZ2, S.EZ, S.has_EZ, prm, sd + 4, cx); }});
   if (P.ineq) {
     TT ds2 = ineq_slack(P, dX2, true, c);
     info.alpha_p_max = std::min(info.alpha_p_max, ratio_step(sx, ds2, P.oneT, c));
@@ -1059,7 +1094,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
           }
           TT Xs = tt_add({&S.X, &dX2}, {1.0, ap}, cx);
           t.X = round_shift(std::move(Xs), tolp, &P.Ivec, cap, cx, &t.sx, prm.shift_mode != 0);
-          if (pd_min(t.X, S.EXc, S.has_EXc, cx) > 0.0) break;
+          if (pd_min(t.X, S.EXc, S.has_EXc, cx) > -nu) break;
           ap *= 0.5;
           bt_p++;
         }
@@ -1074,7 +1109,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
           }
           TT Zs = tt_add({&S.Z, &dZ2}, {1.0, ad}, cx);
           t.Z = round_shift(std::move(Zs), told, &P.Ivec, cap, cx, &t.sz, prm.shift_mode != 0);
-          if (pd_min(t.Z, S.EZc, S.has_EZc, cx) > 0.0) break;
+          if (pd_min(t.Z, S.EZc, S.has_EZc, cx) > -nu) break;
           ad *= 0.5;
           bt_d++;
         }
@@ -1093,7 +1128,54 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     };
     Trial best;
     bool have_best = false;
-    for (int g = 0;; ++g) {
+    const double a_p0 = a_p, a_d0 = a_d;
+    if (S.finishing) {
+      // merit acceptance: the merit ||R_p|| + ||R_d|| + |<X, Z>| (the
+      // quantities of the absolute criteria) must decrease while neither
+      // residual rises above max(current, its absolute target) and eps_p,
+      // eps_d and the gap stay within max(current, the relative stopping
+      // bound), so that every accepted iterate still meets the relative
+      // criteria; damped retries, else the iterate is kept
+      const double phi0 = info.norm_rp + info.norm_rd + std::fabs(info.xz);
+      const double lim_p = std::max(info.eps_p, 2.0 * prm.stop_gap), lim_d = std::max(info.eps_d, 2.0 * prm.stop_gap);
+      const double lim_g = std::max(info.rel_gap, prm.stop_gap);
+      const double lim_rp = std::max(info.norm_rp, prm.finish_abs), lim_rd = std::max(info.norm_rd, prm.finish_abs);
+      bool accepted = false;
+      for (int g = 0;; ++g) {
+        Trial t = attempt(a_p, a_d);
+        info.backtracks += t.bt;
+        ttipm_step_info tm{};
+        iterate_measures(P, t.X, t.Y, t.Z, P.ineq ? &t.T : nullptr, tm, c);
+        t.psi = tm.norm_rp + tm.norm_rd + std::fabs(tm.xz);
+        if (t.psi < phi0 && tm.eps_p <= lim_p && tm.eps_d <= lim_d && tm.rel_gap <= lim_g && tm.norm_rp <= lim_rp &&
+            tm.norm_rd <= lim_rd && (t.a_p > 0.0 || t.a_d > 0.0)) {
+          best = std::move(t);
+          accepted = true;
+          break;
+        }
+        const double ap_next = 0.5 * t.a_p, ad_next = 0.5 * t.a_d;
+        if (g >= std::max(0, prm.g4_retries) || (ap_next == 0.0 && ad_next == 0.0)) break;
+        info.g4_retries++;
+        a_p = ap_next;
+        a_d = ad_next;
+      }
+      if (!accepted) {
+        best = Trial{};
+        best.X = tt_clone(S.X, c);
+        best.Y = tt_clone(S.Y, c);
+        best.Z = tt_clone(S.Z, c);
+        if (P.ineq) best.T = tt_clone(S.T, c);
+        best.a_p = best.a_d = 0.0;
+        // the direction is recomputed next iteration: with a more relaxed
+        // barrier when the PD bounds held the step short, and in every case
+        // with a tenfold tighter forcing term (solve and rounding tolerances)
+        if (std::min(a_p0, a_d0) < 0.1) S.nu = std::min(std::max(10.0 * S.nu, 1e-7), prm.finish_nu_max);
+        S.eta = std::max(0.1 * S.eta, 1e-12);
+        info.finish_rejected = 1;
+      }
+      have_best = true;
+    }
+    for (int g = 0; !have_best; ++g) {
       Trial t = attempt(a_p, a_d);
       info.backtracks += t.bt;
       if (!g4_on) {
@@ -1116,7 +1198,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
     }
     a_p = best.a_p;
     a_d = best.a_d;
-    info.psi = g4_on ? best.psi : psi_k;
+    info.psi = (g4_on || S.finishing) ? best.psi : psi_k;
     info.zeta_x = best.sx.zeta;
     info.zeta_x_cap = std::sqrt(std::max(0.0, best.sx.zeta * best.sx.zeta - best.sx.zeta_tol * best.sx.zeta_tol));
     info.zeta_z = best.sz.zeta;
@@ -1144,7 +1226,12 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   info.t_env = ai_p.t_env + ai_c.t_env;
   info.t_solve = ai_p.t_solve + ai_c.t_solve;
   info.t_svd = ai_p.t_svd + ai_c.t_svd;
-  S.eta = std::max(std::min(S.eta, prm.cmu * mu), prm.delta);
+  // in the finishing phase the floor delta of the forcing term gives way to
+  // one that keeps the rounding tolerances (eta (1 + ||b||) / 10, eta (1 +
+  // ||C||) / 10) below a tenth of the absolute targets
+  const double floor = S.finishing ? std::min(prm.delta, prm.finish_abs / (1.0 + std::max(P.normB, P.normC)))
+                                   : prm.delta;
+  S.eta = std::max(std::min(S.eta, prm.cmu * mu), std::min(floor, S.eta));
   S.iter += 1;
   info.t_total = now() - t_begin;
 }

@@ -39,6 +39,8 @@ struct State {
   int iter = 0;
   bool frame_capped = false;         // a Newton frame has reached the rank cap: enrichment is off
   std::vector<double> psi_hist;      // residual measures of the last accepted iterates (windowed control)
+  bool finishing = false;            // in the finishing phase (PD barrier relaxation, merit acceptance)
+  double nu = 0.0;                   // current relaxation M + nu I >= 0 of the finishing phase
   unsigned long long seed = 12345;
 };
 
@@ -56,6 +58,10 @@ void init_state(const Problem& P, const ttipm_params& prm, State& S, Ctx& c);
 void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c);
 // Measures of the current iterate (mu, objectives, relative errors, gap).
 void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& c);
+// The relative stopping criteria rel_gap <= stop_gap, eps_p, eps_d <= 2 stop_gap,
+// and the absolute ones of the finishing phase ||R_p||, ||R_d||, <X, Z> < finish_abs.
+bool ipm_relative_done(const ttipm_step_info& m, const ttipm_params& prm);
+bool ipm_absolute_done(const ttipm_step_info& m, const ttipm_params& prm);
 
 // Smallest generalised eigenvalue of (dM, M) over TT vectors of the given rank
 // (two-site DMRG with Cholesky reduction of the projected pencil and `kick`

@@ -397,3 +397,62 @@ def test_generic_problem_matches_built_kind(which):
     assert abs(r0["pobj"] - r1["pobj"]) <= 1e-8 * (1 + abs(r0["pobj"]))
     assert abs(r0["dobj"] - r1["dobj"]) <= 1e-8 * (1 + abs(r0["dobj"]))
     assert np.linalg.norm(X0 - X1) <= 1e-7 * np.linalg.norm(X0)
+
+
+def _merit(l):
+    return l["norm_rp"] + l["norm_rd"] + abs(l["xz"])
+
+
+@pytest.mark.parametrize("d,seed", [(4, 3), (3, 7)])
+def test_finishing_phase_reaches_absolute_targets_cc(d, seed):
+    """Finishing phase (Sec. 3.5, relaxing the PD barrier): on the
+    correlation-clustering instances at full TT rank, the solve continues past
+    the relative criteria (1e-4) to the absolute targets ||R_p||, ||R_d||,
+    <X, Z> < 1e-6 under merit-based acceptance.  The merit of the entry
+    iterates never rises, every finishing iterate still meets the relative
+    criteria, and both objectives land within 1e-6 of the dense IPM oracle;
+    without the phase the same run stops with ||R_d|| far above the target."""
+    P = _lib()
+    g = I.signed_kron(d, 2, seed)
+    dense = S.solve(OP.cc_dense(g.dense))
+    pr = P.Problem(P.TTIPM_CC, g.cores, _tt_vector_exact(np.maximum(-g.dense, 0.0).sum(axis=1), d))
+    runs = {}
+    for fin in (0, 1):
+        prm = P.Params(rank_cap=64, stop_gap=1e-4, eps_gap=1e-4, max_iter=60, finish=fin, finish_abs=1e-6)
+        runs[fin] = P.ttipm_solve(pr, P.State(pr, prm), prm)
+    res0, _ = runs[0]
+    res, log = runs[1]
+    print("finish", d, {k: res[k] for k in ("iterations", "finish_iterations", "norm_rp", "norm_rd", "xz",
+                                           "pobj", "dobj")}, dense["pobj"])
+    assert res0["status"] == 0 and res0["absolute_met"] == 0 and res0["finish_iterations"] == 0
+    assert res["status"] == 0 and res["absolute_met"] == 1 and res["finish_iterations"] > 0
+    assert res["norm_rp"] < 1e-6 and res["norm_rd"] < 1e-6 and res["xz"] < 1e-6
+    for key in ("pobj", "dobj"):
+        assert abs(res[key] - dense["pobj"]) / (1 + abs(dense["pobj"])) < 1e-6
+    fin = [l for l in log if l["finishing"]]
+    assert fin
+    for a, b in zip(fin, fin[1:]):
+        assert _merit(b) <= _merit(a) * (1 + 1e-12)
+        if a["finish_rejected"]:
+            assert _merit(b) == _merit(a)
+    for l in fin:
+        assert l["rel_gap"] <= 1e-4 and l["eps_p"] <= 2e-4 and l["eps_d"] <= 2e-4
+
+
+def test_finishing_phase_keeps_relative_criteria_when_capped():
+    """With rank caps that keep the absolute targets out of reach (4 x 8 grid
+    MaxCut, caps 8/8), the finishing phase stops on its own (rejections or
+    max_iter), and the result still meets the relative criteria with an
+    objective no further from the closed form (52) than the relative
+    criteria allow."""
+    P = _lib()
+    g = I.grid_4x8()
+    pr = P.Problem(P.TTIPM_MAXCUT, g.cores)
+    prm = P.Params(rank_cap=8, iter_rank_cap=8, stop_gap=1e-4, eps_gap=1e-4, max_iter=40, finish=1)
+    res, log = P.ttipm_solve(pr, P.State(pr, prm), prm)
+    assert res["status"] == 0 and res["finish_iterations"] > 0
+    assert res["rel_gap"] <= 1e-4 and res["eps_p"] <= 2e-4 and res["eps_d"] <= 2e-4
+    assert abs(res["pobj"] - 52.0) / 53.0 < 3e-4
+    fin = [l for l in log if l["finishing"]]
+    for a, b in zip(fin, fin[1:]):
+        assert _merit(b) <= _merit(a) * (1 + 1e-12)

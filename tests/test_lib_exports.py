@@ -49,3 +49,14 @@ def test_binding_structs_match_header_fields():
     assert fields("ttipm_params") == [f[0] for f in B.ttipm_params._fields_]
     assert fields("ttipm_step_info") == [f[0] for f in B.ttipm_step_info._fields_]
     assert fields("ttipm_result") == [f[0] for f in B.ttipm_result._fields_]
+
+
+def test_struct_sizes_match_library():
+    """sizeof of every caller-visible struct agrees between the compiled library
+    and the ctypes mirrors (a field of the wrong type or in the wrong place
+    changes the size or the padding)."""
+    import paper_2509_11890_amd.binding as B
+    assert B.abi_mismatches() == []
+    out = (ctypes.c_size_t * 2)()
+    assert B.lib.tt_abi_sizes(out, 2) == len(B.ABI_STRUCTS)
+    assert out[0] == ctypes.sizeof(B.tt_view)
