@@ -20,6 +20,12 @@ Local systems are solved densely (numpy.linalg.solve) so that every local
 solution is exact; this is the slow, obviously correct counterpart of the
 library's Krylov solver.  Readings of points the paper leaves open are marked
 "reading:" in the comments.
+
+Pins: at full TT rank the solve reaches the closed-form SDP values of K_8 and
+C_7 + K_1 (MaxCut) and of C_5 + 3 K_1 (theta), tests/test_oracle_ttipm_ref.py.
+Under binding rank caps nothing pins it: its enrichment and its capped
+rounding with the Cor. 1 shift follow the same readings as the library, so it
+cannot tell a defect of those readings from behaviour of the method.
 """
 from __future__ import annotations
 
