@@ -613,8 +613,7 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
       trsm_blocked(LZ.get(), p, fz, B, nrhs, false, c);
       trsm_blocked(LZ.get(), p, fz, B, nrhs, true, c);
     } else {
-      dense_trsm_lower(LZ.get(), p, B, nrhs, false, c.s);
-      dense_trsm_lower(LZ.get(), p, B, nrhs, true, c.s);
+      dense_chol_solve(LZ.get(), p, B, nrhs, c.s);
     }
   };
   // G = L_Z^{-1} L_X^ Aeq^T^ ; S = Aeq^ G + K_Y^
@@ -856,15 +855,6 @@ void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double
   KU[RES_P] = {{-1.0, sys.ops[OP_AEQ], &dX}, {1.0, sys.ops[OP_KY], &dY}};
   if (sys.ineq) KU[RES_T] = {{-sys.sense, sys.ops[OP_TA], &dX}, {1.0, sys.ops[OP_DK], dT}};
   KU[RES_C] = {{1.0, sys.ops[OP_LZ], &dX}, {1.0, sys.ops[OP_LX], &dZ}};
-  auto norm2 = [&](const std::vector<Img>& v) {
-    double s = 0.0;
-    for (size_t i = 0; i < v.size(); ++i)
-      for (size_t j = i; j < v.size(); ++j) {
-        const double ip = tt_op_dot(*v[i].vec, v[i].op, *v[j].vec, v[j].op, c);
-        s += (i == j ? 1.0 : 2.0) * v[i].coef * v[j].coef * ip;
-      }
-    return std::max(s, 0.0);
-  };
   // every pair's four-layer environment must stay within a memory budget;
   // otherwise the check is not made (res = rhs = -1)
   const double budget = 3.2e7;   // doubles (256 MiB) per environment
@@ -882,16 +872,39 @@ void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double
           }
         }
   }
-  double e2 = 0.0, r2 = 0.0;
+  // ||sum_i coef_i O_i v_i||^2 of every block row from the pairwise inner
+  // products, all pairs of all rows in one batched evaluation; the pairs of
+  // the right-hand-side terms alone (||R||) are a subset of them
+  std::vector<OpDotPair> pairs;
+  struct PairUse {
+    int b;
+    double w;    // weight in ||K dU + R||^2
+    bool in_r;   // also a pair of ||R||^2
+  };
+  std::vector<PairUse> use;
   for (int b = 0; b < 4; ++b) {
-    if (R[b].empty() && KU[b].empty()) continue;
+    const int nk = (int)KU[b].size();
     std::vector<Img> all = KU[b];
     all.insert(all.end(), R[b].begin(), R[b].end());
-    e2 += norm2(all);
-    r2 += norm2(R[b]);
+    for (size_t i = 0; i < all.size(); ++i)
+      for (size_t j = i; j < all.size(); ++j) {
+        pairs.push_back({all[i].vec, all[i].op, all[j].vec, all[j].op});
+        use.push_back({b, (i == j ? 1.0 : 2.0) * all[i].coef * all[j].coef, (int)i >= nk && (int)j >= nk});
+      }
   }
-  *res = std::sqrt(e2);
-  *rhs = std::sqrt(r2);
+  const std::vector<double> ip = tt_op_dots(pairs, c);
+  double e2[4] = {0.0, 0.0, 0.0, 0.0}, r2[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t q = 0; q < ip.size(); ++q) {
+    e2[use[q].b] += use[q].w * ip[q];
+    if (use[q].in_r) r2[use[q].b] += use[q].w * ip[q];
+  }
+  double es = 0.0, rs = 0.0;
+  for (int b = 0; b < 4; ++b) {
+    es += std::max(e2[b], 0.0);
+    rs += std::max(r2[b], 0.0);
+  }
+  *res = std::sqrt(es);
+  *rhs = std::sqrt(rs);
 }
 
 namespace {

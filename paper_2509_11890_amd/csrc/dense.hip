@@ -458,8 +458,8 @@ __global__ __launch_bounds__(DT) void cholesky_lds_kernel(double* A, int n, int*
   extern __shared__ double S[];
   __shared__ int s_bad;
   const int ld = n | 1;
-  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
-  for (int t = tid; t < n * n; t += DT) S[(t / n) * ld + t % n] = A[t];
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5, nt = blockDim.x;
+  for (int t = tid; t < n * n; t += nt) S[(t / n) * ld + t % n] = A[t];
   if (tid == 0) { status[0] = 0; s_bad = 0; }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
@@ -471,15 +471,15 @@ __global__ __launch_bounds__(DT) void cholesky_lds_kernel(double* A, int n, int*
     __syncthreads();
     if (s_bad) return;
     const double inv = 1.0 / S[j * ld + j];
-    for (int i = j + 1 + tid; i < n; i += DT) S[i * ld + j] *= inv;
+    for (int i = j + 1 + tid; i < n; i += nt) S[i * ld + j] *= inv;
     __syncthreads();
-    for (int i = j + 1 + ty; i < n; i += DT / 32) {
+    for (int i = j + 1 + ty; i < n; i += nt / 32) {
       const double a = S[i * ld + j];
       for (int c = j + 1 + tx; c <= i; c += 32) S[i * ld + c] -= a * S[c * ld + j];
     }
     __syncthreads();
   }
-  for (int t = tid; t < n * n; t += DT) {
+  for (int t = tid; t < n * n; t += nt) {
     const int i = t / n, c = t % n;
     A[t] = (c <= i) ? S[i * ld + c] : 0.0;
   }
@@ -490,25 +490,26 @@ __global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, doub
   extern __shared__ double S[];
   __shared__ double rv[DT];
   __shared__ int ri[DT];
-  __shared__ int s_piv;
   const int ld = n | 1;
   double* Bs = S + (size_t)n * ld;
-  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
-  for (int t = tid; t < n * n; t += DT) S[(t / n) * ld + t % n] = A[t];
-  for (int t = tid; t < n * nrhs; t += DT) Bs[t] = B[t];
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5, nt = blockDim.x;
+  for (int t = tid; t < n * n; t += nt) S[(t / n) * ld + t % n] = A[t];
+  for (int t = tid; t < n * nrhs; t += nt) Bs[t] = B[t];
   if (tid == 0) status[0] = 0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
+    // pivot: the largest |entry| of column j from row j on, ties to the
+    // smallest row
     double best = -1.0;
     int bi = j;
-    for (int i = j + tid; i < n; i += DT) {
+    for (int i = j + tid; i < n; i += nt) {
       const double v = fabs(S[i * ld + j]);
       if (v > best) { best = v; bi = i; }
     }
     rv[tid] = best;
     ri[tid] = bi;
     __syncthreads();
-    for (int o = DT / 2; o > 0; o >>= 1) {
+    for (int o = nt / 2; o > 0; o >>= 1) {
       if (tid < o) {
         const double a = rv[tid], b = rv[tid + o];
         const int ia = ri[tid], ib = ri[tid + o];
@@ -516,14 +517,12 @@ __global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, doub
       }
       __syncthreads();
     }
-    if (tid == 0) s_piv = ri[0];
-    __syncthreads();
-    const int piv = s_piv;
+    const int piv = ri[0];
     if (piv != j) {
-      for (int c = tid; c < n; c += DT) {
+      for (int c = tid; c < n; c += nt) {
         const double t = S[j * ld + c]; S[j * ld + c] = S[piv * ld + c]; S[piv * ld + c] = t;
       }
-      for (int c = tid; c < nrhs; c += DT) {
+      for (int c = tid; c < nrhs; c += nt) {
         const double t = Bs[j * nrhs + c]; Bs[j * nrhs + c] = Bs[piv * nrhs + c]; Bs[piv * nrhs + c] = t;
       }
     }
@@ -534,9 +533,9 @@ __global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, doub
       return;
     }
     const double inv = 1.0 / d;
-    for (int i = j + 1 + tid; i < n; i += DT) S[i * ld + j] *= inv;
+    for (int i = j + 1 + tid; i < n; i += nt) S[i * ld + j] *= inv;
     __syncthreads();
-    for (int i = j + 1 + ty; i < n; i += DT / 32) {
+    for (int i = j + 1 + ty; i < n; i += nt / 32) {
       const double a = S[i * ld + j];
       for (int c = j + 1 + tx; c < n; c += 32) S[i * ld + c] -= a * S[j * ld + c];
       for (int c = tx; c < nrhs; c += 32) Bs[i * nrhs + c] -= a * Bs[j * nrhs + c];
@@ -545,54 +544,67 @@ __global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, doub
   }
   for (int j = n - 1; j >= 0; --j) {
     const double inv = 1.0 / S[j * ld + j];
-    for (int c = tid; c < nrhs; c += DT) Bs[j * nrhs + c] *= inv;
+    for (int c = tid; c < nrhs; c += nt) Bs[j * nrhs + c] *= inv;
     __syncthreads();
-    for (int i = ty; i < j; i += DT / 32) {
+    for (int i = ty; i < j; i += nt / 32) {
       const double a = S[i * ld + j];
       for (int c = tx; c < nrhs; c += 32) Bs[i * nrhs + c] -= a * Bs[j * nrhs + c];
     }
     __syncthreads();
   }
-  for (int t = tid; t < n * n; t += DT) A[t] = S[(t / n) * ld + t % n];
-  for (int t = tid; t < n * nrhs; t += DT) B[t] = Bs[t];
+  for (int t = tid; t < n * n; t += nt) A[t] = S[(t / n) * ld + t % n];
+  for (int t = tid; t < n * nrhs; t += nt) B[t] = Bs[t];
 }
 
-// Triangular solve L X = B (or L^T X = B) for a slab of right-hand sides per
-// workgroup: workgroup g takes columns [g cb, g cb + cb) of B into LDS; L is
-// read through the caches (every workgroup reads all of it).
-template <bool TRANS>
-__global__ __launch_bounds__(DT) void trsm_slab_kernel(const double* L, int n, double* B, int nrhs, int cb) {
-  extern __shared__ double Bs[];
+// Triangular solves with L (MODE 0: L X = B; 1: L^T X = B; 2: both, L^T L X
+// = B, the solve with a Cholesky factor) for a slab of right-hand sides per
+// workgroup: workgroup g takes columns [g cb, g cb + cb) of B into LDS.  With
+// stage_l the factor is staged into LDS as well (row stride n | 1), so the n
+// dependent column steps read LDS instead of waiting on L2; otherwise L is read
+// through the caches (every workgroup reads all of it).  The operation order
+// per right-hand side is that of the separate forward and backward sweeps.
+template <int MODE>
+__global__ __launch_bounds__(DT) void trsm_slab_kernel(const double* L, int n, double* B, int nrhs, int cb,
+                                                       int stage_l) {
+  extern __shared__ double smem[];
+  const int ld = n | 1;
+  double* Ls = smem;
+  double* Bs = smem + (stage_l ? (size_t)n * ld : 0);
   const int c0 = blockIdx.x * cb;
   const int w = min(cb, nrhs - c0);
   const int tid = threadIdx.x;
-  const int c = tid % cb, rg = tid / cb, nrg = DT / cb;
-  for (int t = tid; t < n * w; t += DT) Bs[(t / w) * cb + t % w] = B[(long)(t / w) * nrhs + c0 + t % w];
+  const int nt = blockDim.x;
+  const int c = tid % cb, rg = tid / cb, nrg = nt / cb;
+  if (stage_l)
+    for (int t = tid; t < n * n; t += nt) Ls[(t / n) * ld + t % n] = L[t];
+  for (int t = tid; t < n * w; t += nt) Bs[(t / w) * cb + t % w] = B[(long)(t / w) * nrhs + c0 + t % w];
   __syncthreads();
-  // threads beyond nrg full row groups (cb not dividing DT) stay idle
+  auto l_at = [&](int i, int j) { return stage_l ? Ls[i * ld + j] : L[(long)i * n + j]; };
+  // threads beyond nrg full row groups (cb not dividing the thread count) stay idle
   const bool active = c < w && rg < nrg;
-  if (!TRANS) {
+  if (MODE != 1) {
     for (int j = 0; j < n; ++j) {
-      if (rg == 0 && active) Bs[j * cb + c] /= L[(long)j * n + j];
+      if (rg == 0 && active) Bs[j * cb + c] /= l_at(j, j);
       __syncthreads();
       if (active) {
         const double bj = Bs[j * cb + c];
-        for (int i = j + 1 + rg; i < n; i += nrg) Bs[i * cb + c] -= L[(long)i * n + j] * bj;
-      }
-      __syncthreads();
-    }
-  } else {
-    for (int j = n - 1; j >= 0; --j) {
-      if (rg == 0 && active) Bs[j * cb + c] /= L[(long)j * n + j];
-      __syncthreads();
-      if (active) {
-        const double bj = Bs[j * cb + c];
-        for (int i = rg; i < j; i += nrg) Bs[i * cb + c] -= L[(long)j * n + i] * bj;
+        for (int i = j + 1 + rg; i < n; i += nrg) Bs[i * cb + c] -= l_at(i, j) * bj;
       }
       __syncthreads();
     }
   }
-  for (int t = tid; t < n * w; t += DT) B[(long)(t / w) * nrhs + c0 + t % w] = Bs[(t / w) * cb + t % w];
+  if (MODE != 0) {
+    for (int j = n - 1; j >= 0; --j) {
+      if (rg == 0 && active) Bs[j * cb + c] /= l_at(j, j);
+      __syncthreads();
+      if (active) {
+        const double bj = Bs[j * cb + c];
+        for (int i = rg; i < j; i += nrg) Bs[i * cb + c] -= l_at(j, i) * bj;
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = tid; t < n * w; t += nt) B[(long)(t / w) * nrhs + c0 + t % w] = Bs[(t / w) * cb + t % w];
 }
 
 __global__ void symmetrize_kernel(double* A, int n) {
@@ -953,8 +965,9 @@ static size_t small_lds_limit() {
     size_t lim = (size_t)v - (size_t)DT * 12 - 256;
     const void* ks[] = {reinterpret_cast<const void*>(&cholesky_lds_kernel),
                         reinterpret_cast<const void*>(&lu_solve_lds_kernel),
-                        reinterpret_cast<const void*>(&trsm_slab_kernel<false>),
-                        reinterpret_cast<const void*>(&trsm_slab_kernel<true>)};
+                        reinterpret_cast<const void*>(&trsm_slab_kernel<0>),
+                        reinterpret_cast<const void*>(&trsm_slab_kernel<1>),
+                        reinterpret_cast<const void*>(&trsm_slab_kernel<2>)};
     if (lim > 65536 - (size_t)DT * 12 - 256)
       for (const void* k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
@@ -996,24 +1009,40 @@ void dense_cholesky(double* A, int n, int* status, hipStream_t s) {
   TT_HIP(hipGetLastError());
 }
 
-void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s) {
+// mode 0: L X = B, 1: L^T X = B, 2: L^T L X = B
+static void trsm_modes(const double* L, int n, double* B, int nrhs, int mode, hipStream_t s) {
   const double nn = n;
-  const double fl = nn * nn * nrhs, by = 8.0 * (0.5 * nn * nn + 2.0 * nn * nrhs);
-  // slabs of up to 16 right-hand sides, one workgroup each
+  const double fl = (mode == 2 ? 2.0 : 1.0) * nn * nn * nrhs, by = 8.0 * (0.5 * nn * nn + 2.0 * nn * nrhs);
+  // slabs of up to 16 right-hand sides, one workgroup each; the factor is
+  // staged into LDS with them when both fit
   const int cb = std::min(16, std::max(1, nrhs));
-  const size_t lds = sizeof(double) * (size_t)n * cb;
-  if (lds <= small_lds_limit()) {
+  const size_t lds_b = sizeof(double) * (size_t)n * cb;
+  const size_t lds_l = sizeof(double) * (size_t)n * (n | 1);
+  if (lds_b <= small_lds_limit()) {
+    const int stage = (lds_b + lds_l <= small_lds_limit()) ? 1 : 0;
+    const unsigned lds = (unsigned)(lds_b + (stage ? lds_l : 0));
     const dim3 grid((nrhs + cb - 1) / cb);
-    if (transpose)
-      launch_prof(PK_DENSE_1WG, fl, by, trsm_slab_kernel<true>, grid, dim3(DT), (unsigned)lds, s, L, n, B, nrhs, cb);
+    // about two threads per row of each right-hand side of the slab
+    const dim3 blk(std::max(64, std::min(DT, ((2 * n * cb + 63) / 64) * 64)));
+    if (mode == 0)
+      launch_prof(PK_DENSE_1WG, fl, by, trsm_slab_kernel<0>, grid, blk, lds, s, L, n, B, nrhs, cb, stage);
+    else if (mode == 1)
+      launch_prof(PK_DENSE_1WG, fl, by, trsm_slab_kernel<1>, grid, blk, lds, s, L, n, B, nrhs, cb, stage);
     else
-      launch_prof(PK_DENSE_1WG, fl, by, trsm_slab_kernel<false>, grid, dim3(DT), (unsigned)lds, s, L, n, B, nrhs, cb);
-  } else if (transpose) {
-    launch_prof(PK_DENSE_1WG, fl, by, trsm_lower_t_kernel, dim3(1), dim3(DT), 0u, s, L, n, B, nrhs);
+      launch_prof(PK_DENSE_1WG, fl, by, trsm_slab_kernel<2>, grid, blk, lds, s, L, n, B, nrhs, cb, stage);
   } else {
-    launch_prof(PK_DENSE_1WG, fl, by, trsm_lower_kernel, dim3(1), dim3(DT), 0u, s, L, n, B, nrhs);
+    if (mode != 1) launch_prof(PK_DENSE_1WG, fl, by, trsm_lower_kernel, dim3(1), dim3(DT), 0u, s, L, n, B, nrhs);
+    if (mode != 0) launch_prof(PK_DENSE_1WG, fl, by, trsm_lower_t_kernel, dim3(1), dim3(DT), 0u, s, L, n, B, nrhs);
   }
   TT_HIP(hipGetLastError());
+}
+
+void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s) {
+  trsm_modes(L, n, B, nrhs, transpose ? 1 : 0, s);
+}
+
+void dense_chol_solve(const double* L, int n, double* B, int nrhs, hipStream_t s) {
+  trsm_modes(L, n, B, nrhs, 2, s);
 }
 
 }  // namespace ttipm

@@ -44,5 +44,7 @@ void dense_cholesky(double* A, int n, int* status, hipStream_t s);
 void dense_symmetrize(double* A, int n, hipStream_t s);
 // Solve L X = B (or L^T X = B) in place; L lower triangular row-major.
 void dense_trsm_lower(const double* L, int n, double* B, int nrhs, bool transpose, hipStream_t s);
+// Solve L^T L X = B in place (both sweeps in one launch where the slab fits LDS).
+void dense_chol_solve(const double* L, int n, double* B, int nrhs, hipStream_t s);
 
 }  // namespace ttipm

@@ -247,6 +247,83 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   gemm_f64_tile<WM, WN, AKC, BKC>(ga.g[q.i], q.tm, q.tn, q.bidx, q.slice);
 }
 
+// Small products (both output dimensions <= 64, short K: the frames of rank
+// <= 16): one wave per 16 x 16 output block, operands loaded from global
+// memory (L2) straight into the MFMA operand registers, no LDS and no
+// barrier.  Lane l supplies row l%16 of A and column l%16 of B at k = 4u +
+// l/16 of each group of 16 k, exactly as the tiled kernel reads them from LDS,
+// so the MFMA sequence of every accumulator (k ascending in steps of 4, a
+// ragged tail padded with zeros) and hence every result is bit-identical to
+// the tiled kernel without split-K.  Two groups of 16 k (eight loads per
+// operand) are issued before their MFMAs.
+__device__ __forceinline__ void gemm_f64_block16(const KArgs& g, int bm, int bn, int bidx) {
+  const int lane = threadIdx.x % 64, q = lane / 16, r16 = lane % 16;
+  const int m0 = bm * 16, n0 = bn * 16;
+  const int row = min(m0 + r16, g.M - 1), col = min(n0 + r16, g.N - 1);
+  const double* Ar = g.A + (long)bidx * g.sA + (long)row * g.am;
+  const double* Bc = g.B + (long)bidx * g.sB + (long)col * g.bn;
+  const long ak = g.ak, bk = g.bk;
+  f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+  int k0 = 0;
+  for (; k0 + 32 <= g.K; k0 += 32) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = Ar[(long)(k0 + 4 * u + q) * ak];
+      b[u] = Bc[(long)(k0 + 4 * u + q) * bk];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  }
+  // the rest (< 32 k): all loads first (k clamped, zeros past K), then one
+  // MFMA per group of four k that holds any k < K (a group of the tiled
+  // kernel whose MFMAs see only zeros leaves the accumulator unchanged)
+  if (k0 < g.K) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + 4 * u + q;
+      const bool in = k < g.K;
+      const int kc = in ? k : g.K - 1;
+      const double av = Ar[(long)kc * ak], bv = Bc[(long)kc * bk];
+      a[u] = in ? av : 0.0;
+      b[u] = in ? bv : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + 4 * u < g.K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int rr = m0 + q + 4 * e, cc = n0 + r16;
+    if (rr < g.M && cc < g.N) {
+      double* c = g.C + (long)bidx * g.sC + (long)rr * g.cm + (long)cc * g.cn;
+      *c = (g.beta == 0.0) ? g.alpha * acc[e] : g.alpha * acc[e] + g.beta * (*c);
+    }
+  }
+}
+
+// blocks: 16 x 16 output blocks of one batch entry (gn columns of them); one
+// wave each, four waves per workgroup
+__global__ __launch_bounds__(256) void gemm_f64_small_kernel(KArgs g, int gn, int blocks, long total) {
+  const long w = (long)blockIdx.x * 4 + threadIdx.x / 64;
+  if (w >= total) return;
+  const int t = (int)(w % blocks), bidx = (int)(w / blocks);
+  gemm_f64_block16(g, t / gn, t % gn, bidx);
+}
+
+// Grouped small products: problem i owns the waves [end[i-1], end[i]),
+// tiles[i] 16 x 16 blocks (gn[i] columns of them) per batch entry.
+__global__ __launch_bounds__(256) void gemm_f64_small_grouped_kernel(GroupArgs ga) {
+  const int w = blockIdx.x * 4 + threadIdx.x / 64;
+  if (w >= ga.end[ga.n - 1]) return;
+  int i = 0;
+  while (i + 1 < ga.n && w >= ga.end[i]) ++i;
+  const int local = w - (i ? ga.end[i - 1] : 0);
+  const int t = local % ga.tiles[i], bidx = local / ga.tiles[i];
+  gemm_f64_block16(ga.g[i], t / ga.gn[i], t % ga.gn[i], bidx);
+}
+
 // BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16): lane l supplies
 // row l%16 and the eight k-values 8(l/16)..8(l/16)+7 of each operand, so the
 // LDS tiles are stored with k contiguous ([m][k], row pitch 40 values = 80
@@ -483,6 +560,13 @@ size_t gemm_splitk_need(const Gemm& q, GemmPrec prec) {
   return need;
 }
 
+// Products small enough for the register-direct kernel: both output
+// dimensions within one 64 x 64 tile and K short enough that the tiled kernel
+// would not split it.
+static bool small_gemm(const Gemm& q, GemmPrec prec) {
+  return prec == GemmPrec::F64 && q.M <= 64 && q.N <= 64 && q.K < 16 * BK;
+}
+
 template <int WM, int WN>
 void launch_bf16(dim3 grid, hipStream_t stream, const KArgs& g, double flops, double bytes) {
   const bool akc = (g.ak == 1), bkc = (g.bk == 1 && g.bn != 1);
@@ -533,6 +617,20 @@ void gemm(const Gemm& q, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   g.B = q.B; g.bk = q.bk; g.bn = q.bn; g.sB = q.sB;
   g.C = q.C; g.cm = q.cm; g.cn = q.cn; g.sC = q.sC;
   g.alpha = q.alpha; g.beta = q.beta;
+  if (small_gemm(q, prec)) {
+    g.kslices = 1;
+    g.kchunk = q.K;
+    g.P = nullptr;
+    const int gm = (q.M + 15) / 16, gn = (q.N + 15) / 16;
+    const long total = (long)gm * gn * q.batch;
+    const double flops = 2.0 * q.M * q.N * (double)q.K * q.batch;
+    const double bytes =
+        8.0 * q.batch * ((double)q.M * q.K + (double)q.K * q.N + (double)q.M * q.N * (q.beta != 0.0 ? 2 : 1));
+    launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_small_kernel, dim3((unsigned)((total + 3) / 4)), dim3(256), 0u,
+                stream, g, gn, gm * gn, total);
+    TT_HIP(hipGetLastError());
+    return;
+  }
   // Tile shape (both precisions): 128 x 128 for large outputs, 128 x 64 /
   // 64 x 128 for skinny ones, 64 x 64 otherwise.
   // The largest tile that still gives the chip enough workgroups (min_tiles,
@@ -636,13 +734,16 @@ void launch_f64_grouped(int blocks, hipStream_t stream, const GroupArgs& ga, boo
 // One grouped launch of up to kMaxGroup problems of one operand layout.
 static void gemm_group_launch(const std::vector<const Gemm*>& take, bool akc0, bool bkc0, hipStream_t stream,
                               Workspace* ws, GemmPrec prec);
+// One grouped launch of up to kMaxGroup small FP64 problems.
+static void gemm_small_group_launch(const std::vector<const Gemm*>& take, hipStream_t stream);
 
 void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws, GemmPrec prec) {
   // Problems are sorted into the four operand layouts (which index of A and
   // of B is unit stride) and launched in groups of up to kMaxGroup per
   // layout; problems outside the 32-bit offset range or with K = 0 go
   // through gemm() one by one.
-  std::vector<const Gemm*> cls[4];
+  // Small problems (register-direct kernel, any layout) form a fifth class.
+  std::vector<const Gemm*> cls[5];
   for (int i = 0; i < count; ++i) {
     const Gemm& q = qs[i];
     if (q.M <= 0 || q.N <= 0 || q.batch <= 0) continue;
@@ -654,15 +755,54 @@ void gemm_grouped(const Gemm* qs, int count, hipStream_t stream, Workspace* ws, 
       gemm(q, stream, ws, prec);
       continue;
     }
-    std::vector<const Gemm*>& c = cls[(akc ? 2 : 0) + (bkc ? 1 : 0)];
+    const int l = small_gemm(q, prec) ? 4 : (akc ? 2 : 0) + (bkc ? 1 : 0);
+    std::vector<const Gemm*>& c = cls[l];
     c.push_back(&q);
     if ((int)c.size() == kMaxGroup) {
-      gemm_group_launch(c, akc, bkc, stream, ws, prec);
+      if (l == 4)
+        gemm_small_group_launch(c, stream);
+      else
+        gemm_group_launch(c, akc, bkc, stream, ws, prec);
       c.clear();
     }
   }
   for (int l = 0; l < 4; ++l)
     if (!cls[l].empty()) gemm_group_launch(cls[l], l >= 2, l % 2 == 1, stream, ws, prec);
+  if (!cls[4].empty()) gemm_small_group_launch(cls[4], stream);
+}
+
+static void gemm_small_group_launch(const std::vector<const Gemm*>& take, hipStream_t stream) {
+  if (take.size() == 1) {
+    gemm(*take[0], stream, nullptr, GemmPrec::F64);
+    return;
+  }
+  GroupArgs ga{};
+  ga.n = (int)take.size();
+  long waves = 0;
+  double flops = 0.0, bytes = 0.0;
+  for (int i = 0; i < ga.n; ++i) {
+    const Gemm& q = *take[i];
+    KArgs& g = ga.g[i];
+    g.M = q.M; g.N = q.N; g.K = q.K;
+    g.A = q.A; g.am = q.am; g.ak = q.ak; g.sA = q.sA;
+    g.B = q.B; g.bk = q.bk; g.bn = q.bn; g.sB = q.sB;
+    g.C = q.C; g.cm = q.cm; g.cn = q.cn; g.sC = q.sC;
+    g.alpha = q.alpha; g.beta = q.beta;
+    g.kslices = 1;
+    g.kchunk = q.K;
+    g.P = nullptr;
+    const int gm = (q.M + 15) / 16, gn = (q.N + 15) / 16;
+    ga.gn[i] = gn;
+    ga.tiles[i] = gm * gn;
+    waves += (long)gm * gn * q.batch;
+    if (waves > (1L << 30)) throw Error(TT_ERR_ARG, "gemm_grouped: grid too large");
+    ga.end[i] = (int)waves;
+    flops += 2.0 * q.M * q.N * (double)q.K * q.batch;
+    bytes += 8.0 * q.batch * ((double)q.M * q.K + (double)q.K * q.N + (double)q.M * q.N * (q.beta != 0.0 ? 2 : 1));
+  }
+  launch_prof(PK_GEMM_F64, flops, bytes, gemm_f64_small_grouped_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256),
+              0u, stream, ga);
+  TT_HIP(hipGetLastError());
 }
 
 static void gemm_group_launch(const std::vector<const Gemm*>& take, bool akc0, bool bkc0, hipStream_t stream,

@@ -310,62 +310,171 @@ double tt_sandwich(const TT& u, const TT& A, const TT& v, Ctx& c) {
 // E[a][alpha][beta][c] (a, c: ranks of vi, vj; alpha, beta: ranks of Oi, Oj),
 // four GEMM stages per core: vj, then Oj over its input mode, then Oi over the
 // shared output mode, then vi over Oi's input mode.
-double tt_op_dot(const TT& vi, const TT* Oi, const TT& vj, const TT* Oj, Ctx& c) {
-  const int d = vi.d, m = vi.mo;
-  TT_REQUIRE(vj.d == d && vj.mo == m && vi.mi == 1 && vj.mi == 1, "op_dot vector shapes");
-  for (const TT* O : {Oi, Oj})
-    if (O) TT_REQUIRE(O->d == d && O->mo == m && O->mi == m, "op_dot operator shapes");
+namespace {
+// gathers the scalars at the given device addresses into out[0..n)
+constexpr int kGather = 64;
+struct GatherArgs {
+  const double* p[kGather];
+  int n;
+};
+__global__ void gather_scalars_kernel(GatherArgs g, double* out) {
+  const int t = threadIdx.x;
+  if (t < g.n) out[t] = *g.p[t];
+}
+}  // namespace
+
+std::vector<double> tt_op_dots(const std::vector<OpDotPair>& pairs, Ctx& c) {
+  const int np = (int)pairs.size();
+  std::vector<double> out(np, 0.0);
+  if (np == 0) return out;
+  const TT& v0 = *pairs[0].vi;
+  const int d = v0.d, m = v0.mo;
+  for (const OpDotPair& q : pairs) {
+    TT_REQUIRE(q.vi->d == d && q.vj->d == d && q.vi->mo == m && q.vj->mo == m && q.vi->mi == 1 && q.vj->mi == 1,
+               "op_dot vector shapes");
+    for (const TT* O : {q.Oi, q.Oj})
+      if (O) TT_REQUIRE(O->d == d && O->mo == m && O->mi == m, "op_dot operator shapes");
+  }
   std::vector<double> eye((size_t)m * m, 0.0);
   for (int i = 0; i < m; ++i) eye[(size_t)i * m + i] = 1.0;
-  TT Id;
-  if (!Oi || !Oj) Id = tt_rank1(d, m, m, eye, c);
-  const TT& A = Oi ? *Oi : Id;
-  const TT& B = Oj ? *Oj : Id;
-  size_t emax = 1, tmax = 1;
-  for (int k = 0; k <= d; ++k)
-    emax = std::max(emax, (size_t)vi.r[k] * A.r[k] * B.r[k] * vj.r[k]);
-  for (int k = 0; k < d; ++k) {
-    const size_t a = vi.r[k], al = A.r[k], be = B.r[k], cc = vj.r[k];
-    const size_t a2 = vi.r[k + 1], al2 = A.r[k + 1], be2 = B.r[k + 1], c2 = vj.r[k + 1];
-    tmax = std::max({tmax, a * al * be * m * c2, a * al * c2 * m * be2, a * c2 * be2 * m * al2});
+  TT Id = tt_rank1(d, m, m, eye, c);
+  std::vector<const TT*> A(np), B(np);
+  for (int p = 0; p < np; ++p) {
+    A[p] = pairs[p].Oi ? pairs[p].Oi : &Id;
+    B[p] = pairs[p].Oj ? pairs[p].Oj : &Id;
   }
-  DevBuf e0(emax), e1(emax), t1(tmax), t2(tmax), pB((size_t)B.max_rank() * B.max_rank() * m * m);
-  fill(1, 1.0, e0.get(), c.s);
+  // per pair: environments e0, e1 and stage buffers t1, t2, carved from one slab
+  std::vector<size_t> emax(np, 1), tmax(np, 1);
+  size_t total = 0;
+  for (int p = 0; p < np; ++p) {
+    const TT &vi = *pairs[p].vi, &vj = *pairs[p].vj, &a = *A[p], &bb = *B[p];
+    for (int k = 0; k <= d; ++k) emax[p] = std::max(emax[p], (size_t)vi.r[k] * a.r[k] * bb.r[k] * vj.r[k]);
+    for (int k = 0; k < d; ++k) {
+      const size_t ra = vi.r[k], al = a.r[k], be = bb.r[k];
+      const size_t a2 = vi.r[k + 1], al2 = a.r[k + 1], be2 = bb.r[k + 1], c2 = vj.r[k + 1];
+      tmax[p] = std::max({tmax[p], ra * al * be * m * c2, ra * al * c2 * m * be2, ra * c2 * be2 * m * al2});
+    }
+    total += 2 * ((emax[p] + 31) & ~size_t(31)) + 2 * ((tmax[p] + 31) & ~size_t(31));
+  }
+  // the permuted core of each distinct right operator, per core
+  std::vector<const TT*> ops;
+  std::vector<int> op_of(np);
+  for (int p = 0; p < np; ++p) {
+    int f = -1;
+    for (int i = 0; i < (int)ops.size(); ++i)
+      if (ops[i] == B[p]) f = i;
+    if (f < 0) {
+      f = (int)ops.size();
+      ops.push_back(B[p]);
+    }
+    op_of[p] = f;
+  }
+  std::vector<size_t> pmax(ops.size());
+  for (size_t i = 0; i < ops.size(); ++i) {
+    pmax[i] = (size_t)ops[i]->max_rank() * ops[i]->max_rank() * m * m;
+    total += (pmax[i] + 31) & ~size_t(31);
+  }
+  DevBuf slab(total), res(np);
+  std::vector<double*> e0(np), e1(np), t1(np), t2(np), pB(ops.size());
+  {
+    double* q = slab.get();
+    auto take = [&](size_t n) {
+      double* r = q;
+      q += (n + 31) & ~size_t(31);
+      return r;
+    };
+    for (int p = 0; p < np; ++p) {
+      e0[p] = take(emax[p]);
+      e1[p] = take(emax[p]);
+      t1[p] = take(tmax[p]);
+      t2[p] = take(tmax[p]);
+    }
+    for (size_t i = 0; i < ops.size(); ++i) pB[i] = take(pmax[i]);
+  }
+  for (int p = 0; p < np; ++p) fill(1, 1.0, e0[p], c.s);
+  std::vector<Gemm> g(np);
+  std::vector<PermJob> pj;
   for (int k = 0; k < d; ++k) {
-    const int a = vi.r[k], al = A.r[k], be = B.r[k], cc = vj.r[k];
-    const int a2 = vi.r[k + 1], al2 = A.r[k + 1], be2 = B.r[k + 1], c2 = vj.r[k + 1];
+    // Oj [be][i][j][be2] -> [(be,j)][(i,be2)], once per distinct operator
+    pj.clear();
+    for (size_t i = 0; i < ops.size(); ++i)
+      pj.push_back({ops[i]->core(k), pB[i], {ops[i]->r[k], m, m, ops[i]->r[k + 1]}, {0, 2, 1, 3}});
+    permute_many(pj, c.s);
     // T1[(a,al,be)][(j,c2)] = E[(a,al,be)][c] vj[c][(j,c2)]
-    gemm(gemm_nn(a * al * be, m * c2, cc, e0.get(), cc, vj.core(k), (long)m * c2, t1.get(), (long)m * c2), c.s,
-         &c.ws, GemmPrec::F64);
+    for (int p = 0; p < np; ++p) {
+      const TT &vi = *pairs[p].vi, &vj = *pairs[p].vj;
+      const int a = vi.r[k], al = A[p]->r[k], be = B[p]->r[k], cc = vj.r[k], c2 = vj.r[k + 1];
+      g[p] = gemm_nn(a * al * be, m * c2, cc, e0[p], cc, vj.core(k), (long)m * c2, t1[p], (long)m * c2);
+    }
+    gemm_grouped(g.data(), np, c.s, &c.ws, GemmPrec::F64);
     // [a][al][be][j][c2] -> [a][al][c2][be][j]
-    permute(t1.get(), t2.get(), {a, al, be, m, c2}, {0, 1, 4, 2, 3}, c.s);
-    // Oj [be][i][j][be2] -> [(be,j)][(i,be2)]
-    permute(B.core(k), pB.get(), {be, m, m, be2}, {0, 2, 1, 3}, c.s);
+    pj.clear();
+    for (int p = 0; p < np; ++p) {
+      const int a = pairs[p].vi->r[k], al = A[p]->r[k], be = B[p]->r[k], c2 = pairs[p].vj->r[k + 1];
+      pj.push_back({t1[p], t2[p], {a, al, be, m, c2}, {0, 1, 4, 2, 3}});
+    }
+    permute_many(pj, c.s);
     // T2[(a,al,c2)][(i,be2)] = T1'[(a,al,c2)][(be,j)] Oj'[(be,j)][(i,be2)]
-    gemm(gemm_nn(a * al * c2, m * be2, be * m, t2.get(), (long)be * m, pB.get(), (long)m * be2, t1.get(),
-                 (long)m * be2),
-         c.s, &c.ws, GemmPrec::F64);
+    for (int p = 0; p < np; ++p) {
+      const int a = pairs[p].vi->r[k], al = A[p]->r[k], be = B[p]->r[k], c2 = pairs[p].vj->r[k + 1];
+      const int be2 = B[p]->r[k + 1];
+      g[p] = gemm_nn(a * al * c2, m * be2, be * m, t2[p], (long)be * m, pB[op_of[p]], (long)m * be2, t1[p],
+                     (long)m * be2);
+    }
+    gemm_grouped(g.data(), np, c.s, &c.ws, GemmPrec::F64);
     // [a][al][c2][i][be2] -> [a][c2][be2][al][i]
-    permute(t1.get(), t2.get(), {a, al, c2, m, be2}, {0, 2, 4, 1, 3}, c.s);
+    pj.clear();
+    for (int p = 0; p < np; ++p) {
+      const int a = pairs[p].vi->r[k], al = A[p]->r[k], c2 = pairs[p].vj->r[k + 1], be2 = B[p]->r[k + 1];
+      pj.push_back({t1[p], t2[p], {a, al, c2, m, be2}, {0, 2, 4, 1, 3}});
+    }
+    permute_many(pj, c.s);
     // T3[(a,c2,be2)][(j,al2)] = T2'[(a,c2,be2)][(al,i)] Oi[(al,i)][(j,al2)]
-    gemm(gemm_nn(a * c2 * be2, m * al2, al * m, t2.get(), (long)al * m, A.core(k), (long)m * al2, t1.get(),
-                 (long)m * al2),
-         c.s, &c.ws, GemmPrec::F64);
+    for (int p = 0; p < np; ++p) {
+      const int a = pairs[p].vi->r[k], al = A[p]->r[k], c2 = pairs[p].vj->r[k + 1], be2 = B[p]->r[k + 1];
+      const int al2 = A[p]->r[k + 1];
+      g[p] = gemm_nn(a * c2 * be2, m * al2, al * m, t2[p], (long)al * m, A[p]->core(k), (long)m * al2, t1[p],
+                     (long)m * al2);
+    }
+    gemm_grouped(g.data(), np, c.s, &c.ws, GemmPrec::F64);
     // [a][c2][be2][j][al2] -> [a][j][al2][be2][c2]
-    permute(t1.get(), t2.get(), {a, c2, be2, m, al2}, {0, 3, 4, 2, 1}, c.s);
+    pj.clear();
+    for (int p = 0; p < np; ++p) {
+      const int a = pairs[p].vi->r[k], c2 = pairs[p].vj->r[k + 1], be2 = B[p]->r[k + 1], al2 = A[p]->r[k + 1];
+      pj.push_back({t1[p], t2[p], {a, c2, be2, m, al2}, {0, 3, 4, 2, 1}});
+    }
+    permute_many(pj, c.s);
     // E'[a2][(al2,be2,c2)] = sum_(a,j) vi[(a,j)][a2] T3'[(a,j)][(al2,be2,c2)]
-    Gemm g;
-    g.M = a2; g.N = al2 * be2 * c2; g.K = a * m;
-    g.A = vi.core(k); g.am = 1; g.ak = a2;
-    g.B = t2.get(); g.bk = (long)al2 * be2 * c2; g.bn = 1;
-    g.C = e1.get(); g.cm = (long)al2 * be2 * c2; g.cn = 1;
-    gemm(g, c.s, &c.ws, GemmPrec::F64);
+    for (int p = 0; p < np; ++p) {
+      const TT& vi = *pairs[p].vi;
+      const int a = vi.r[k], a2 = vi.r[k + 1], al2 = A[p]->r[k + 1], be2 = B[p]->r[k + 1];
+      const int c2 = pairs[p].vj->r[k + 1];
+      Gemm q;
+      q.M = a2; q.N = al2 * be2 * c2; q.K = a * m;
+      q.A = vi.core(k); q.am = 1; q.ak = a2;
+      q.B = t2[p]; q.bk = (long)al2 * be2 * c2; q.bn = 1;
+      q.C = e1[p]; q.cm = (long)al2 * be2 * c2; q.cn = 1;
+      g[p] = q;
+    }
+    gemm_grouped(g.data(), np, c.s, &c.ws, GemmPrec::F64);
     std::swap(e0, e1);
   }
-  double* h = c.host(1);
-  TT_HIP(hipMemcpyAsync(h, e0.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
+  for (int p0 = 0; p0 < np; p0 += kGather) {
+    GatherArgs ga{};
+    ga.n = std::min(kGather, np - p0);
+    for (int i = 0; i < ga.n; ++i) ga.p[i] = e0[p0 + i];
+    hipLaunchKernelGGL(gather_scalars_kernel, dim3(1), dim3(kGather), 0, c.s, ga, res.get() + p0);
+    TT_HIP(hipGetLastError());
+  }
+  double* h = c.host(np);
+  TT_HIP(hipMemcpyAsync(h, res.get(), sizeof(double) * np, hipMemcpyDeviceToHost, c.s));
   c.sync();
-  return h[0];
+  for (int p = 0; p < np; ++p) out[p] = h[p];
+  return out;
+}
+
+double tt_op_dot(const TT& vi, const TT* Oi, const TT& vj, const TT* Oj, Ctx& c) {
+  return tt_op_dots({OpDotPair{&vi, Oi, &vj, Oj}}, c)[0];
 }
 
 // ---------------------------------------------------------------------------

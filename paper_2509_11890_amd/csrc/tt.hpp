@@ -84,6 +84,15 @@ double tt_sandwich(const TT& u, const TT& A, const TT& v, Ctx& c);  // u^T A v
 // identity), never forming Oi vi: the norm of a sum of operator images is a
 // sum of these (synchronises)
 double tt_op_dot(const TT& vi, const TT* Oi, const TT& vj, const TT* Oj, Ctx& c);
+// Several such inner products at once: the k-th stage of every pair runs in
+// grouped launches (one sweep over the cores for all pairs, one synchronisation).
+struct OpDotPair {
+  const TT* vi;
+  const TT* Oi;
+  const TT* vj;
+  const TT* Oj;
+};
+std::vector<double> tt_op_dots(const std::vector<OpDotPair>& pairs, Ctx& c);
 
 // ---- environments and projected local products (Sec. 3.3) ---------------------
 // phi_in/phi_out layouts as in tt_contract_interfaces; O == nullptr is the identity.

@@ -52,6 +52,72 @@ void permute(const double* in, double* out, const std::vector<long>& dims, const
   TT_HIP(hipGetLastError());
 }
 
+// Several independent permutations in one launch: problem i owns the
+// threads [end[i-1], end[i]) of a 1-D grid, one per input element.
+constexpr int kPermMany = 16;
+struct PermProb {
+  const double* in;
+  double* out;
+  int nd;
+  int dims[6];
+  long ostr[6];
+};
+struct PermManyArgs {
+  PermProb p[kPermMany];
+  long end[kPermMany];
+  int n;
+};
+
+__global__ void permute_many_kernel(PermManyArgs a) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.end[a.n - 1]) return;
+  int i = 0;
+  while (i + 1 < a.n && t >= a.end[i]) ++i;
+  const PermProb& q = a.p[i];
+  long rem = t - (i ? a.end[i - 1] : 0), off = 0;
+  const long local = rem;
+  for (int j = q.nd - 1; j >= 0; --j) {
+    const long v = rem % q.dims[j];
+    rem /= q.dims[j];
+    off += v * q.ostr[j];
+  }
+  q.out[off] = q.in[local];
+}
+
+void permute_many(const std::vector<PermJob>& jobs, hipStream_t s) {
+  PermManyArgs a{};
+  auto flush = [&]() {
+    if (a.n == 0) return;
+    hipLaunchKernelGGL(permute_many_kernel, dim3(nblocks(a.end[a.n - 1], TB)), dim3(TB), 0, s, a);
+    TT_HIP(hipGetLastError());
+    a = PermManyArgs{};
+  };
+  for (const PermJob& j : jobs) {
+    const int nd = (int)j.dims.size();
+    TT_REQUIRE(nd >= 1 && nd <= 6 && (int)j.perm.size() == nd, "permute rank");
+    PermProb& q = a.p[a.n];
+    q.in = j.in;
+    q.out = j.out;
+    q.nd = nd;
+    long total = 1;
+    for (int i = 0; i < nd; ++i) {
+      TT_REQUIRE(j.dims[i] >= 0 && j.dims[i] <= 2147483647L, "permute dimension");
+      q.dims[i] = (int)j.dims[i];
+      total *= j.dims[i];
+    }
+    if (total == 0) continue;
+    long st = 1;
+    for (int k = nd - 1; k >= 0; --k) {
+      q.ostr[j.perm[k]] = st;
+      st *= j.dims[j.perm[k]];
+    }
+    a.end[a.n] = (a.n ? a.end[a.n - 1] : 0) + total;
+    ++a.n;
+    if (a.n == kPermMany) flush();
+  }
+  flush();
+}
+
 // ---------------------------------------------------------------------------
 // dst[(o0 + i) * dst_s0 + mid * ... ] : place a [n0][mid][n1] block into a
 // [N0][mid][N1] tensor at offsets (o0, o1), scaled by alpha.

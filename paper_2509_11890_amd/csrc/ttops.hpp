@@ -7,6 +7,14 @@
 
 namespace ttipm {
 
+// Independent permutations (as permute, alpha = 1), up to 16 per launch.
+struct PermJob {
+  const double* in;
+  double* out;
+  std::vector<long> dims;
+  std::vector<int> perm;
+};
+void permute_many(const std::vector<PermJob>& jobs, hipStream_t s);
 // out = alpha * permute(in): input row-major with dims; output dims are dims[perm[0]], dims[perm[1]], ...
 void permute(const double* in, double* out, const std::vector<long>& dims, const std::vector<int>& perm,
              hipStream_t s, double alpha = 1.0);
