@@ -171,7 +171,7 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
   // 16-lane groups rotate one column pair each (64 pairs in flight per step);
   // a group is active or idle as a whole, so its shuffles stay inside it.
   const int gl = threadIdx.x % 16, gid = threadIdx.x / 16;
-  constexpr int NG = DT / 16;
+  const int NG = blockDim.x / 16, nw = blockDim.x / 64;
   int sweep = 0;
   for (; sweep < max_sweeps && N > 1; ++sweep) {
     if (threadIdx.x == 0) { s_rot[0] = 0; s_rot[1] = 0; }
@@ -231,7 +231,7 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
     __syncthreads();
   }
   // column norms
-  for (int c = w; c < n; c += NW) {
+  for (int c = w; c < n; c += nw) {
     const double* ac = A + (long)c * m;
     double s = 0.0;
     for (int i = lane; i < m; i += 64) s += ac[i] * ac[i];
@@ -675,7 +675,7 @@ __device__ int lz_sturm(const double* a, const double* b, int k, double x) {
 // left in *s_theta, y in shared memory; h is scratch.
 __device__ void lz_ritz_min(const double* al, const double* be, int k, double* y, double* h, double* s_lo,
                             double* s_hi, double* s_theta, int* s_first) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) {
     double lo = 1e300, hi = -1e300;
     for (int i = 0; i < k; ++i) {
@@ -690,15 +690,15 @@ __device__ void lz_ritz_min(const double* al, const double* be, int k, double* y
   for (int round = 0; round < 8; ++round) {
     const double lo = *s_lo, hi = *s_hi;
     if (!(hi - lo > 1e-15 * (fabs(lo) + fabs(hi)) + 1e-300)) break;
-    if (tid == 0) *s_first = DT;
+    if (tid == 0) *s_first = nt;
     __syncthreads();
-    const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(DT + 1);
+    const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(nt + 1);
     if (lz_sturm(al, be, k, x) >= 1) atomicMin(s_first, tid);
     __syncthreads();
     if (tid == 0) {
       const int f = *s_first;
-      const double xf = (f < DT) ? lo + (hi - lo) * (double)(f + 1) / (double)(DT + 1) : hi;
-      const double xp = (f > 0) ? lo + (hi - lo) * (double)f / (double)(DT + 1) : lo;
+      const double xf = (f < nt) ? lo + (hi - lo) * (double)(f + 1) / (double)(nt + 1) : hi;
+      const double xp = (f > 0) ? lo + (hi - lo) * (double)f / (double)(nt + 1) : lo;
       *s_lo = xp;
       *s_hi = xf;
     }
@@ -740,21 +740,21 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
   __shared__ double red[NW];
   __shared__ double s_theta, s_lo, s_hi, s_bnorm;
   __shared__ int s_first;
-  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64, nt = blockDim.x, nw = nt / 64;
   // start vector: the caller's (a warm start) unless it is absent or zero
   if (v_init) {
     double part = 0.0;
-    for (int i = tid; i < p; i += DT) part += v[i] * v[i];
+    for (int i = tid; i < p; i += nt) part += v[i] * v[i];
     const double nv = block_sum(part, red);
     v_init = (nv > 0.0 && nv < 1e300) ? 1 : 0;
   }
   if (!v_init)
-    for (int i = tid; i < p; i += DT) v[i] = 1.0 + 0.25 * lz_pseudo(i, 0);
+    for (int i = tid; i < p; i += nt) v[i] = 1.0 + 0.25 * lz_pseudo(i, 0);
   __syncthreads();
   // Frobenius norm of B (scale for tolerances)
   {
     double part = 0.0;
-    for (long t = tid; t < (long)p * p; t += DT) part += B[t] * B[t];
+    for (long t = tid; t < (long)p * p; t += nt) part += B[t] * B[t];
     const double f = block_sum(part, red);
     if (tid == 0) s_bnorm = sqrt(f) + 1e-300;
   }
@@ -763,16 +763,16 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
   for (int rs = 0; rs <= restarts; ++rs) {
     // q_0 = v / |v|
     double part = 0.0;
-    for (int i = tid; i < p; i += DT) part += v[i] * v[i];
+    for (int i = tid; i < p; i += nt) part += v[i] * v[i];
     const double nv = sqrt(block_sum(part, red));
-    for (int i = tid; i < p; i += DT) Q[i] = v[i] / nv;
+    for (int i = tid; i < p; i += nt) Q[i] = v[i] / nv;
     __syncthreads();
     int k = 0;
     for (int j = 0; j < kmax; ++j) {
       double* qj = Q + (long)j * p;
       double* wv = Q + (long)(j + 1) * p;
       // w = B q_j, one wave per row
-      for (int i = w; i < p; i += NW) {
+      for (int i = w; i < p; i += nw) {
         const double* row = B + (long)i * p;
         double acc = 0.0;
         for (int c = lane; c < p; c += 64) acc += row[c] * qj[c];
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
       __syncthreads();
       // two passes of classical Gram-Schmidt against q_0 .. q_j
       for (int pass = 0; pass < 2; ++pass) {
-        for (int t = w; t <= j; t += NW) {
+        for (int t = w; t <= j; t += nw) {
           const double* qt = Q + (long)t * p;
           double acc = 0.0;
           for (int i = lane; i < p; i += 64) acc += qt[i] * wv[i];
@@ -791,7 +791,7 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
         }
         __syncthreads();
         if (pass == 0 && tid == 0) al[j] = h[j];
-        for (int i = tid; i < p; i += DT) {
+        for (int i = tid; i < p; i += nt) {
           double acc = wv[i];
           for (int t = 0; t <= j; ++t) acc -= Q[(long)t * p + i] * h[t];
           wv[i] = acc;
@@ -799,16 +799,16 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
         __syncthreads();
       }
       part = 0.0;
-      for (int i = tid; i < p; i += DT) part += wv[i] * wv[i];
+      for (int i = tid; i < p; i += nt) part += wv[i] * wv[i];
       double bj = sqrt(block_sum(part, red));
       k = j + 1;
       if (k >= p) { if (tid == 0) be[j] = 0.0; __syncthreads(); break; }
       if (bj <= 1e-13 * s_bnorm) {
         // invariant subspace: continue with a pseudo-random vector orthogonal to the basis
-        for (int i = tid; i < p; i += DT) wv[i] = lz_pseudo(i, j + 1 + 7919 * rs);
+        for (int i = tid; i < p; i += nt) wv[i] = lz_pseudo(i, j + 1 + 7919 * rs);
         __syncthreads();
         for (int pass = 0; pass < 2; ++pass) {
-          for (int t = w; t <= j; t += NW) {
+          for (int t = w; t <= j; t += nw) {
             const double* qt = Q + (long)t * p;
             double acc = 0.0;
             for (int i = lane; i < p; i += 64) acc += qt[i] * wv[i];
@@ -816,7 +816,7 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
             if (lane == 0) h[t] = acc;
           }
           __syncthreads();
-          for (int i = tid; i < p; i += DT) {
+          for (int i = tid; i < p; i += nt) {
             double acc = wv[i];
             for (int t = 0; t <= j; ++t) acc -= Q[(long)t * p + i] * h[t];
             wv[i] = acc;
@@ -824,12 +824,12 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
           __syncthreads();
         }
         part = 0.0;
-        for (int i = tid; i < p; i += DT) part += wv[i] * wv[i];
+        for (int i = tid; i < p; i += nt) part += wv[i] * wv[i];
         const double nr = sqrt(block_sum(part, red));
-        for (int i = tid; i < p; i += DT) wv[i] /= nr;
+        for (int i = tid; i < p; i += nt) wv[i] /= nr;
         if (tid == 0) be[j] = 0.0;
       } else {
-        for (int i = tid; i < p; i += DT) wv[i] /= bj;
+        for (int i = tid; i < p; i += nt) wv[i] /= bj;
         if (tid == 0) be[j] = bj;
       }
       __syncthreads();
@@ -845,14 +845,14 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
     __syncthreads();
     theta = s_theta;
     // Ritz vector v = Q_k y and its residual |B v - theta v|
-    for (int i = tid; i < p; i += DT) {
+    for (int i = tid; i < p; i += nt) {
       double acc = 0.0;
       for (int t = 0; t < k; ++t) acc += Q[(long)t * p + i] * y[t];
       v[i] = acc;
     }
     __syncthreads();
     part = 0.0;
-    for (int i = w; i < p; i += NW) {
+    for (int i = w; i < p; i += nw) {
       const double* row = B + (long)i * p;
       double acc = 0.0;
       for (int c = lane; c < p; c += 64) acc += row[c] * v[c];
@@ -909,8 +909,8 @@ void dense_svd(double* A, int m, int n, double* U, double* sigma, double* V, dou
   const size_t lds_bytes = sizeof(double) * ((size_t)m * n + (size_t)n * n);
   const size_t lds_a_bytes = sizeof(double) * (size_t)m * n;
   if (lds_bytes <= jacobi_lds_limit()) {
-    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_kernel, dim3(1), dim3(DT), (unsigned)lds_bytes, s,
-                (const double*)A, m, n, U, sigma, V, iwork, max_sweeps, tol, iwork + n, 1);
+    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_kernel, dim3(1), dim3(DT),
+                (unsigned)lds_bytes, s, (const double*)A, m, n, U, sigma, V, iwork, max_sweeps, tol, iwork + n, 1);
   } else if (lds_a_bytes <= jacobi_lds_limit()) {
     launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_a_kernel, dim3(1), dim3(DT), (unsigned)lds_a_bytes, s,
                 (const double*)A, m, n, work, U, sigma, V, iwork, max_sweeps, tol, iwork + n);
@@ -932,8 +932,9 @@ void dense_svd_left(double* A, int m, int n, double* U, double* sigma, int* iwor
   const double bytes = 8.0 * ((double)m * n * 2 + n);
   const size_t lds_bytes = sizeof(double) * (size_t)m * n;
   if (lds_bytes <= jacobi_lds_limit())
-    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_kernel, dim3(1), dim3(DT), (unsigned)lds_bytes, s,
-                (const double*)A, m, n, U, sigma, (double*)nullptr, iwork, max_sweeps, tol, iwork + n, 0);
+    launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_lds_kernel, dim3(1), dim3(DT),
+                (unsigned)lds_bytes, s, (const double*)A, m, n, U, sigma, (double*)nullptr, iwork, max_sweeps, tol,
+                iwork + n, 0);
   else
     launch_prof(PK_JACOBI_SVD, 0.0, bytes, jacobi_svd_kernel, dim3(1), dim3(DT), 0u, s, A, m, n, (double*)nullptr, U,
                 sigma, (double*)nullptr, iwork, max_sweeps, tol, iwork + n);

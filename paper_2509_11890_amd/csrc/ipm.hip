@@ -437,8 +437,11 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
   for (int k = d - 1; k > 0; --k) upd_right(k);
   double lam_best = 1e300;
   DevBuf M2, D2, Ml, Dl, e, e0, sg;
-  // one sweep = left-to-right then right-to-left over the pairs (k, k+1)
+  // one sweep = left-to-right then right-to-left over the pairs (k, k+1);
+  // further sweeps are skipped once the two passes of a sweep agree on the
+  // smallest eigenvalue to 1e-9 (relative): the frame has converged
   for (int sw = 0; sw < sweeps; ++sw) {
+    double lam_pass[2] = {1e300, 1e300};
     for (int pass = 0; pass < 2; ++pass) {
       const bool lr = (pass == 0);
       for (int step = 0; step < d - 1; ++step) {
@@ -461,6 +464,7 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
              &c.ws, GemmPrec::F64);
         const double lam = pencil_min(Ml.get(), Dl.get(), p, e.get(), c, e0.get());
         lam_best = std::min(lam_best, lam);
+        lam_pass[pass] = std::min(lam_pass[pass], lam);
         // split the supercore [(r,i)][(i',s)] by a truncated SVD
         SvdOut sv;
         svd_rowmajor(e.get(), 2 * r, 2 * s, sv, c);
@@ -518,6 +522,8 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
         c.sync();
       }
     }
+    if (std::fabs(lam_pass[1] - lam_pass[0]) <= 1e-9 * std::max(std::fabs(lam_pass[0]), std::fabs(lam_pass[1])))
+      break;
   }
   // leave E right-orthogonal with the block at 0 (core 0 is not orthogonal)
   E.pos = 0;
