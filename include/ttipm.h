@@ -429,6 +429,11 @@ typedef struct {
                            ((I - K_Y)(I - K_T) = 0), Y and T updates share one padded block
                            dL of the Newton system (Sec. 3.5, Combined Multiplier Storage):
                            two block rows and columns instead of three (1)               */
+  int32_t amen_global_stop; /* 1: an AMEn solve whose frame the rank cap has truncated stops
+                           after the half-sweep at which the global FP64 residual ratio
+                           ||K dU + R|| / ||R|| meets eta or improves on the previous
+                           half-sweep's by less than 10 % (evaluated after every half-sweep
+                           of such a solve) (1)                                            */
   int32_t finish;       /* 1: finishing phase (Sec. 3.5, Relaxing the Positive Definiteness
                            Barrier): once the relative stopping criteria hold, ttipm_solve
                            goes on until ||R_p||_F, ||R_d||_F, <X, Z> < finish_abs; in that

@@ -97,7 +97,8 @@ class ttipm_params(C.Structure):
                 ("kick_sweeps", C.c_int32), ("collect_probes", C.c_int32), ("collect_cap", C.c_int64),
                 ("xz_fallback", C.c_int32), ("eig_kick", C.c_int32), ("g4_window", C.c_int32),
                 ("g4_retries", C.c_int32), ("shift_mode", C.c_int32), ("newton_check", C.c_int32),
-                ("refine_sweeps", C.c_int32), ("combine_multipliers", C.c_int32), ("finish", C.c_int32),
+                ("refine_sweeps", C.c_int32), ("combine_multipliers", C.c_int32), ("amen_global_stop", C.c_int32),
+                ("finish", C.c_int32),
                 ("finish_abs", C.c_double), ("finish_nu_max", C.c_double), ("enrich", C.c_int32)]
 
 

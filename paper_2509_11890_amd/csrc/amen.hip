@@ -1083,6 +1083,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   DevBuf f, u, Ku, dz;
   std::vector<int> bj_ref(d, 0);   // block-Jacobi Krylov counts per core (MLP fallback budget)
   std::vector<double> res_hist;   // max_res of each sweep
+  std::vector<double> glob_hist;  // global Newton residual ratio of each half-sweep (-1: not evaluated)
   for (int sweep = 0; sweep < prm.max_sweeps; ++sweep) {
     double max_res = 0.0;
     const bool enrich_now = resid && sweep < prm.kick_sweeps;
@@ -1236,6 +1237,30 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
     // than 10 %.
     res_hist.push_back(max_res);
     if (info.capped && sweep >= 2 && max_res > 0.9 * res_hist[sweep - 2]) break;
+    // Capped solves, measured globally: once the cap binds, further
+    // half-sweeps mostly cycle between truncated frames.  After every
+    // half-sweep of such a solve the FP64 residual ||K dU + R|| / ||R|| of
+    // the whole Newton system is evaluated (batched operator-image inner
+    // products); the solve stops when it meets the forcing bound eta = 2 tol
+    // (Lemma "AMEn Directions as Inexact Newton Directions"), or when it is
+    // below 1 and improves on the half-sweep two back (same direction) by
+    // less than 10 %.
+    if (prm.global_stop && info.capped) {
+      const double tg = now();
+      double res = 0.0, rhs = 0.0;
+      newton_residual(sys, W, &res, &rhs, c);
+      info.t_check += now() - tg;
+      if (res >= 0.0 && rhs > 0.0) {
+        const double ratio = res / rhs;
+        glob_hist.resize(sweep + 1, -1.0);
+        glob_hist[sweep] = ratio;
+        info.newton_res = ratio;
+        const bool met = ratio <= 2.0 * prm.tol;
+        const bool flat = sweep >= 2 && glob_hist[sweep - 2] >= 0.0 && ratio < 1.0 &&
+                          ratio > 0.9 * glob_hist[sweep - 2];
+        if (met || flat) break;
+      }
+    }
   }
   // The block stays where the last sweep left it (an end core): moving it back
   // without truncation would only merge the components into the shared frame

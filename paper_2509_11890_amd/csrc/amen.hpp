@@ -90,6 +90,7 @@ struct AmenParams {
   int collect_probes = 0;    // > 0: add every local system's blocks to mlp's dataset
   long collect_cap = 0;
   double mu = 1.0;           // barrier parameter (a context feature of the MLP)
+  int global_stop = 1;       // capped solves: stop once the global Newton residual stagnates
 };
 
 struct AmenInfo {
@@ -99,7 +100,8 @@ struct AmenInfo {
   double last_max_res = 0.0;
   bool capped = false;      // some split was limited by the rank cap (not by the tolerance)
   int mlp_used = 0, mlp_fallbacks = 0;
-  double t_env = 0, t_solve = 0, t_svd = 0;
+  double t_env = 0, t_solve = 0, t_svd = 0, t_check = 0;
+  double newton_res = -1.0;  // last global ratio ||K dU + R|| / ||R|| evaluated by the stopping rule
 };
 
 // Solve the Newton system starting from W, whose block sits at an end core

@@ -503,6 +503,7 @@ void ttipm_params_default(ttipm_params* p) {
   p->refine_sweeps = 2;
   p->enrich = 1;
   p->combine_multipliers = 1;
+  p->amen_global_stop = 1;
   p->finish = 0;
   p->finish_abs = 1e-3;
   p->finish_nu_max = 1e-3;

@@ -904,6 +904,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   // the cap, where they would only perturb the truncated solve; residual
   // directions stay on wherever a split leaves capacity.
   ap.enrich = prm.enrich;
+  ap.global_stop = prm.amen_global_stop;
   ap.kick = (prm.enrich == 0 && S.frame_capped) ? 0 : std::max(0, prm.kick);
   ap.verbose = prm.verbose;
   ap.kick_sweeps = std::max(0, prm.kick_sweeps);
@@ -1229,6 +1230,7 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   info.mlp_used = ai_p.mlp_used + ai_c.mlp_used;
   info.mlp_fallbacks = ai_p.mlp_fallbacks + ai_c.mlp_fallbacks;
   info.rank_w = std::max(ai_p.max_rank, ai_c.max_rank);
+  info.t_check += ai_p.t_check + ai_c.t_check;
   info.t_env = ai_p.t_env + ai_c.t_env;
   info.t_solve = ai_p.t_solve + ai_c.t_solve;
   info.t_svd = ai_p.t_svd + ai_c.t_svd;
