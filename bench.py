@@ -45,6 +45,11 @@ PEAK = {"f64": 78.6e12, "bf16": 2.5e15}
 HBM = 8.0e12
 MARK = dict(stop_gap=1e-4, eps_gap=1e-4)
 
+# HIP kernels timed and counted together under each instrumented name
+FAMILY = {"gemm_f64_kernel": ["gemm_f64_kernel<WM,WN,AKC,BKC>", "gemm_f64_grouped_kernel<2,2,AKC,BKC>",
+                              "gemm_f64_small_kernel", "gemm_f64_small_grouped_kernel"],
+          "gemm_bf16_kernel": ["gemm_bf16_kernel<WM,WN,AKC,BKC>", "gemm_bf16_grouped_kernel<2,2,AKC,BKC>"]}
+
 WORKLOADS = {
     # name: (instance config, frame rank cap, iterate rank cap)
     "maxcut_grid_d5": ("maxcut_grid_d5", 8, 8),
@@ -68,6 +73,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the precision variants, the configuration records and the n = 1024 closed forms")
+    ap.add_argument("--no-contraction", action="store_true",
+                    help="skip the local-contraction microbenchmarks after the timed solves (counter runs)")
     ap.add_argument("--contraction-only", action="store_true",
                     help="only the local-contraction microbenchmarks (and a 256 MiB device copy used to calibrate "
                          "the HBM byte counters)")
@@ -337,7 +344,8 @@ def roofline_of(kstats, period, workload):
     if dom["timed"] <= 0 or dom["time_ms"] <= 0:
         return None
     t_avg = dom["time_ms"] / 1e3 / dom["timed"]
-    common = {"kernel": dom_name, "avg_launch_us": t_avg * 1e6, "launches": dom["launches"],
+    common = {"kernel": dom_name, "hip_kernels": FAMILY.get(dom_name, [dom_name]),
+              "avg_launch_us": t_avg * 1e6, "launches": dom["launches"],
               "timed_launches": dom["timed"], "traffic": stored_traffic(dom_name, workload)}
     if dom["flops"] > 0:
         prec = "bf16" if "bf16" in dom_name else "f64"
@@ -412,7 +420,8 @@ def main():
     kernel_share = {k: round(v["time_ms"] * (args.profile_period if v["timed"] else 0) / 1e3 / args.steps, 5)
                     for k, v in kstats.items()}
 
-    contraction = [contraction_rate(P, torch, r, 2 * r, bf16=b) for r in (32, 64, 128) for b in (False, True)]
+    contraction = None if args.no_contraction else \
+        [contraction_rate(P, torch, r, 2 * r, bf16=b) for r in (32, 64, 128) for b in (False, True)]
 
     cpu = None
     if not args.no_cpu and graph.dense is not None:
