@@ -118,12 +118,15 @@ struct LocalKKT {
     s = W->r[k + 1];
     p = 4 * r * s;
     L = sys->L();
+    // the cores of all operators, permuted for the local products in one launch
+    std::vector<PermJob> jobs;
     for (int o = 0; o < OP_COUNT; ++o) {
       if (key_of_op[o] < 0) continue;
       const TT* op = sys->ops[o];
       operm[o].reserve((size_t)op->core_size(k));
-      permute_op_core(op->core(k), op->r[k], 4, op->r[k + 1], operm[o].get(), c.s);
+      jobs.push_back({op->core(k), operm[o].get(), {op->r[k], 4, 4, op->r[k + 1]}, {1, 3, 0, 2}});
     }
+    permute_many(jobs, c.s);
     tmp.reserve(p);
     tmp2.reserve(p);
   }
@@ -1079,7 +1082,8 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   int dir = from_right ? -1 : +1;
   info.sweeps = 0;
   info.krylov_iters = 0;
-  std::vector<DevBuf> Rhat(4);
+  DevBuf Rall;                  // the four projected residuals, contiguous (one fill)
+  double* Rhat_p[4] = {nullptr, nullptr, nullptr, nullptr};
   DevBuf f, u, Ku, dz;
   std::vector<int> bj_ref(d, 0);   // block-Jacobi Krylov counts per core (MLP fallback budget)
   std::vector<double> res_hist;   // max_res of each sweep
@@ -1111,38 +1115,50 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       const int p = K.p, r = K.r, s = K.s;
       const long n = (long)L * p;
       // projected residuals
-      for (int q = 0; q < 4; ++q) {
-        Rhat[q].reserve(p);
-        fill(p, 0.0, Rhat[q].get(), c.s);
-      }
+      Rall.reserve((size_t)4 * p);
+      fill(4L * p, 0.0, Rall.get(), c.s);
+      for (int q = 0; q < 4; ++q) Rhat_p[q] = Rall.get() + (size_t)q * p;
       // the terms' projections in grouped stage launches (terms of one block
       // residual keep their order)
+      // a term's operator is one of the system's (already permuted by
+      // K.setup) or a further one, permuted here (all in one launch)
       std::vector<DevBuf> operms(sys.terms.size());
       std::vector<LocalApplyArgs> proj;
+      std::vector<const double*> term_op(sys.terms.size(), nullptr);
+      {
+        std::vector<PermJob> jobs;
+        for (size_t t = 0; t < sys.terms.size(); ++t) {
+          const EnvKey& e = envs.keys[key_of_term[t]];
+          if (!e.op) continue;
+          for (int o = 0; o < OP_COUNT && !term_op[t]; ++o)
+            if (K.key_of_op[o] >= 0 && sys.ops[o] == e.op) term_op[t] = K.operm[o].get();
+          if (term_op[t]) continue;
+          operms[t].reserve((size_t)e.op->core_size(k));
+          jobs.push_back({e.op->core(k), operms[t].get(), {envs.op_rank(e, k), 4, 4, envs.op_rank(e, k + 1)},
+                          {1, 3, 0, 2}});
+          term_op[t] = operms[t].get();
+        }
+        permute_many(jobs, c.s);
+      }
       for (size_t t = 0; t < sys.terms.size(); ++t) {
         const Term& tm = sys.terms[t];
         const int key = key_of_term[t];
         const EnvKey& e = envs.keys[key];
         const int R0 = envs.op_rank(e, k), R1 = envs.op_rank(e, k + 1);
         const int rc = e.trial->r[k], rd = e.trial->r[k + 1];
-        const double* Op = nullptr;
-        if (e.op) {
-          operms[t].reserve((size_t)e.op->core_size(k));
-          permute_op_core(e.op->core(k), R0, 4, R1, operms[t].get(), c.s);
-          Op = operms[t].get();
-        }
+        const double* Op = e.op ? term_op[t] : nullptr;
         proj.push_back({envs.L[key][k].get(), r, R0, rc, Op, 4, envs.R[key][k].get(), s, R1, rd, e.trial->core(k),
-                        Rhat[tm.res].get(), tm.coef, 1.0});
+                        Rhat_p[tm.res], tm.coef, 1.0});
       }
       local_apply_many(proj, c);
       c.sync();   // the permuted cores are released at scope end
       // local right-hand side f = [-Rp; (-Rt;) -Rc + LX^ Rd]
       f.reserve(n);
-      axpby(p, -1.0, Rhat[RES_P].get(), 0.0, f.get(), c.s);
-      if (sys.ineq) axpby(p, -1.0, Rhat[RES_T].get(), 0.0, f.get() + p, c.s);
+      axpby(p, -1.0, Rhat_p[RES_P], 0.0, f.get(), c.s);
+      if (sys.ineq) axpby(p, -1.0, Rhat_p[RES_T], 0.0, f.get() + p, c.s);
       double* fc = f.get() + (size_t)(L - 1) * p;
-      K.apply(OP_LX, Rhat[RES_D].get(), fc, 1.0, 0.0, c);
-      axpby(p, -1.0, Rhat[RES_C].get(), 1.0, fc, c.s);
+      K.apply(OP_LX, Rhat_p[RES_D], fc, 1.0, 0.0, c);
+      axpby(p, -1.0, Rhat_p[RES_C], 1.0, fc, c.s);
       // initial guess: current block components
       u.reserve(n);
       TT_HIP(hipMemcpyAsync(u.get(), W.blk.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
@@ -1172,7 +1188,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       } else if (n <= prm.direct_max) {
         // the paper's block elimination; LU of the whole block system when
         // inequalities are present or L_Z^ is numerically singular
-        const bool ok = !sys.ineq && solve_elim(K, Rhat[RES_D].get(), Rhat[RES_P].get(), Rhat[RES_C].get(), u.get(), c);
+        const bool ok = !sys.ineq && solve_elim(K, Rhat_p[RES_D], Rhat_p[RES_P], Rhat_p[RES_C], u.get(), c);
         if (!ok) solve_direct(K, f.get(), u.get(), c);
       } else {
         double rel = 0.0;
@@ -1187,7 +1203,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       W.blk.reserve((size_t)(L + 1) * p);
       TT_HIP(hipMemcpyAsync(W.blk.get(), u.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, c.s));
       hipLaunchKernelGGL(stack_dz_kernel, dim3(nblocks(p, 256)), dim3(256), 0, c.s, W.blk.get() + n, K.tmp.get(),
-                         Rhat[RES_D].get(), (long)p);
+                         Rhat_p[RES_D], (long)p);
       TT_HIP(hipGetLastError());
       c.sync();
       info.t_solve += now() - ts;

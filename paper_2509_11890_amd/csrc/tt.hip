@@ -590,11 +590,13 @@ EnvPlan plan_right(const double* phi, int ra2, int Rp, int rc2, const double* V,
 void run_plans(std::vector<EnvPlan>& plans, Ctx& c) {
   for (int lv = 0; lv < 3; ++lv) {
     std::vector<Gemm> gs;
+    std::vector<PermJob> jobs;   // operator cores the second GEMMs read permuted, in one launch
     for (EnvPlan& P : plans) {
       if (lv >= P.ng) continue;
-      if (lv == 1 && P.permute_core) permute(P.O, P.perm, {P.R, P.mo, P.mi, P.Rp}, {1, 3, 0, 2}, c.s);
+      if (lv == 1 && P.permute_core) jobs.push_back({P.O, P.perm, {P.R, P.mo, P.mi, P.Rp}, {1, 3, 0, 2}});
       gs.push_back(P.g[lv]);
     }
+    if (!jobs.empty()) permute_many(jobs, c.s);
     if (!gs.empty()) gemm_grouped(gs.data(), (int)gs.size(), c.s, &c.ws, c.prec);
   }
 }
