@@ -633,7 +633,7 @@ int ttipm_solve(ttipm_problem* p, ttipm_state* s, const ttipm_params* prm, ttipm
       }
       ttipm_step_info inf{};
       try {
-        ipm_step(p->P, s->S, *prm, inf, c);
+        ipm_step(p->P, s->S, *prm, inf, c, &m);
       } catch (const Error& e) {
         if (e.code != TT_ERR_NOT_PD) throw;
         r.status = TT_ERR_NOT_PD;

@@ -777,11 +777,12 @@ NewtonSys combined_system(const NewtonSys& s0, const Problem& P, const CombinedO
 
 }  // namespace
 
-void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c) {
+void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c,
+              const ttipm_step_info* entry) {
   const double t_begin = now();
-  info = ttipm_step_info{};
+  info = entry ? *entry : ttipm_step_info{};
   info.iter = S.iter;
-  ipm_measures(P, S, info, c);
+  if (!entry) ipm_measures(P, S, info, c);
   const double mu = info.mu;
   // Finishing phase (Sec. 3.5, Relaxing the Positive Definiteness Barrier):
   // once the relative stopping criteria hold, the iteration goes on towards

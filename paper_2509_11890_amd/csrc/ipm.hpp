@@ -55,7 +55,11 @@ struct GenericSdp {
 Problem build_problem_generic(const GenericSdp& g, Ctx& c);
 void init_state(const Problem& P, const ttipm_params& prm, State& S, Ctx& c);
 // One IPM iteration; fills info (measures at entry + the step taken).
-void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c);
+// entry (optional): the measures of the current iterate, already computed by
+// ipm_measures (the solve loop's stopping test), so that the step does not
+// evaluate them again.
+void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_info& info, Ctx& c,
+              const ttipm_step_info* entry = nullptr);
 // Measures of the current iterate (mu, objectives, relative errors, gap).
 void ipm_measures(const Problem& P, const State& S, ttipm_step_info& info, Ctx& c);
 // The relative stopping criteria rel_gap <= stop_gap, eps_p, eps_d <= 2 stop_gap,
