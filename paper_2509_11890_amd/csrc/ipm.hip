@@ -557,11 +557,29 @@ void tt_full_device(const TT& v, DevBuf& out, DevBuf& tmp, Ctx& c) {
   }
 }
 
-__global__ void ratio_min_kernel(const double* v, const double* dv, const double* mask, long n, double* part) {
+// largest |v| on the mask (per block)
+__global__ void masked_absmax_kernel(const double* v, const double* mask, long n, double* part) {
+  __shared__ double red[256];
+  double best = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    if (mask[i] > 0.5) best = fmax(best, fabs(v[i]));
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// smallest ratio max(v, 0) / -dv over the masked entries with dv < 0 whose
+// |v| is above the floor (per block)
+__global__ void ratio_min_kernel(const double* v, const double* dv, const double* mask, long n, double floor_v,
+                                 double* part) {
   __shared__ double red[256];
   double best = 1e300;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    if (mask[i] > 0.5 && dv[i] < 0.0) best = fmin(best, fmax(v[i], 0.0) / -dv[i]);
+    if (mask[i] > 0.5 && dv[i] < 0.0 && fabs(v[i]) > floor_v) best = fmin(best, fmax(v[i], 0.0) / -dv[i]);
   red[threadIdx.x] = best;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -572,7 +590,11 @@ __global__ void ratio_min_kernel(const double* v, const double* dv, const double
 }
 
 // largest alpha with v + alpha dv >= 0 on the entries where mask = 1 (Sec. 3.4:
-// the smallest eigenvalue of the diagonal pencil is the smallest entry ratio)
+// the smallest eigenvalue of the diagonal pencil is the smallest entry ratio).
+// Precision floor (Sec. 3.4, last paragraph): an entry whose value is below
+// the precision of the TT arithmetic (64 eps of the largest masked |v|) is
+// indistinguishable from the zero entries that no inequality involves, so it
+// does not limit the step.
 double ratio_step(const TT& v, const TT& dv, const TT& mask, Ctx& c) {
   DevBuf a, b, m, tmp;
   tt_full_device(v, a, tmp, c);
@@ -582,9 +604,17 @@ double ratio_step(const TT& v, const TT& dv, const TT& mask, Ctx& c) {
   for (int k = 0; k < v.d; ++k) n *= (long)v.mo * v.mi;
   const int nb = 256;
   DevBuf part(nb);
-  hipLaunchKernelGGL(ratio_min_kernel, dim3(nb), dim3(256), 0, c.s, a.get(), b.get(), m.get(), n, part.get());
-  TT_HIP(hipGetLastError());
   std::vector<double> h(nb);
+  hipLaunchKernelGGL(masked_absmax_kernel, dim3(nb), dim3(256), 0, c.s, a.get(), m.get(), n, part.get());
+  TT_HIP(hipGetLastError());
+  TT_HIP(hipMemcpyAsync(h.data(), part.get(), sizeof(double) * nb, hipMemcpyDeviceToHost, c.s));
+  c.sync();
+  double vmax = 0.0;
+  for (double x : h) vmax = std::max(vmax, x);
+  const double floor_v = 64.0 * 2.220446049250313e-16 * vmax;
+  hipLaunchKernelGGL(ratio_min_kernel, dim3(nb), dim3(256), 0, c.s, a.get(), b.get(), m.get(), n, floor_v,
+                     part.get());
+  TT_HIP(hipGetLastError());
   TT_HIP(hipMemcpyAsync(h.data(), part.get(), sizeof(double) * nb, hipMemcpyDeviceToHost, c.s));
   c.sync();
   double best = 1e300;
