@@ -466,7 +466,7 @@ def main():
                   "max_rank_w": max((l["rank_w"] for l in last_log), default=0),
                   "max_rank_x": max((l["rank_x"] for l in last_log), default=0),
                   "phase_s": {k: round(sum(l[k] for l in last_log), 4)
-                              for k in ("t_env", "t_solve", "t_svd", "t_step", "t_round")}},
+                              for k in ("t_env", "t_solve", "t_svd", "t_step", "t_round", "t_check")}},
         "error_vs_oracle": err,
         "kernel_time_s_per_step": kernel_share,
         "roofline": roof,

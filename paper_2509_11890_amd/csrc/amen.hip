@@ -1088,6 +1088,20 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   std::vector<int> bj_ref(d, 0);   // block-Jacobi Krylov counts per core (MLP fallback budget)
   std::vector<double> res_hist;   // max_res of each sweep
   std::vector<double> glob_hist;  // global Newton residual ratio of each half-sweep (-1: not evaluated)
+  // The global rule pays one residual evaluation per half-sweep: it is used
+  // only while that is cheap next to a half-sweep, i.e. while the four-layer
+  // environments of the operator-image products stay small (frame rank r,
+  // operator ranks R: r^2 R^2 per core below 2^20 doubles; at r = 32, R = 64
+  // one evaluation cost as much as a quarter of the iteration).
+  bool glob_cheap = true;
+  {
+    size_t rmax = 1, Rmax = 1;
+    for (int x : W.r) rmax = std::max(rmax, (size_t)std::max(x, 1));
+    rmax = std::max(rmax, (size_t)prm.rank_cap);
+    for (const TT* op : sys.ops)
+      if (op) Rmax = std::max(Rmax, (size_t)op->max_rank());
+    glob_cheap = rmax * rmax * Rmax * Rmax <= (size_t(1) << 20);
+  }
   for (int sweep = 0; sweep < prm.max_sweeps; ++sweep) {
     double max_res = 0.0;
     const bool enrich_now = resid && sweep < prm.kick_sweeps;
@@ -1261,7 +1275,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
     // (Lemma "AMEn Directions as Inexact Newton Directions"), or when it is
     // below 1 and improves on the half-sweep two back (same direction) by
     // less than 10 %.
-    if (prm.global_stop && info.capped) {
+    if (prm.global_stop && info.capped && glob_cheap) {
       const double tg = now();
       double res = 0.0, rhs = 0.0;
       newton_residual(sys, W, &res, &rhs, c);

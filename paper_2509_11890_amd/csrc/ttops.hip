@@ -25,11 +25,22 @@ struct PermArgs {
 __global__ void permute_kernel(const double* in, double* out, PermArgs a, double alpha) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.total) return;
-  long rem = t, off = 0;
-  for (int i = a.nd - 1; i >= 0; --i) {
-    long v = rem % a.in_dims[i];
-    rem /= a.in_dims[i];
-    off += v * a.out_stride_for_in[i];
+  long off = 0;
+  if (a.total < 2147483648L) {   // 32-bit index decomposition (see permute_many_kernel)
+    unsigned rem = (unsigned)t;
+    for (int i = a.nd - 1; i >= 0; --i) {
+      const unsigned di = (unsigned)a.in_dims[i];
+      const unsigned v = rem % di;
+      rem /= di;
+      off += (long)v * a.out_stride_for_in[i];
+    }
+  } else {
+    long rem = t;
+    for (int i = a.nd - 1; i >= 0; --i) {
+      long v = rem % a.in_dims[i];
+      rem /= a.in_dims[i];
+      off += v * a.out_stride_for_in[i];
+    }
   }
   out[off] = alpha * in[t];
 }
@@ -68,18 +79,23 @@ struct PermManyArgs {
   int n;
 };
 
+// Index arithmetic in 32 bits (every problem holds fewer than 2^31 elements):
+// the 64-bit divisions of a generic index decomposition cost more than the
+// element's load and store.
 __global__ void permute_many_kernel(PermManyArgs a) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.end[a.n - 1]) return;
   int i = 0;
   while (i + 1 < a.n && t >= a.end[i]) ++i;
   const PermProb& q = a.p[i];
-  long rem = t - (i ? a.end[i - 1] : 0), off = 0;
-  const long local = rem;
+  const unsigned local = (unsigned)(t - (i ? a.end[i - 1] : 0));
+  unsigned rem = local;
+  long off = 0;
   for (int j = q.nd - 1; j >= 0; --j) {
-    const long v = rem % q.dims[j];
-    rem /= q.dims[j];
-    off += v * q.ostr[j];
+    const unsigned dj = (unsigned)q.dims[j];
+    const unsigned v = rem % dj;
+    rem /= dj;
+    off += (long)v * q.ostr[j];
   }
   q.out[off] = q.in[local];
 }
@@ -106,6 +122,7 @@ void permute_many(const std::vector<PermJob>& jobs, hipStream_t s) {
       total *= j.dims[i];
     }
     if (total == 0) continue;
+    TT_REQUIRE(total < 2147483648L, "permute_many: more than 2^31 elements in one problem");
     long st = 1;
     for (int k = nd - 1; k >= 0; --k) {
       q.ostr[j.perm[k]] = st;
