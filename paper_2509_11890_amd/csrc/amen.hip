@@ -388,7 +388,7 @@ void principal_orth_rows(const double* B, int q0, long bj, long bi, int len, con
 // Move the block index from W.pos to W.pos + 1 (dir > 0) or W.pos - 1 (dir < 0).
 
 bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick, unsigned long long seed,
-                 const double* cand, int ncand) {
+                 const CandidateFn* cand_fn) {
   bool capped = false;
   const int k = W.pos, Lp = W.Lp, r = W.r[k], s = W.r[k + 1], md = W.m;
   const long n1 = (long)r * md * s;
@@ -423,13 +423,16 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     capped = rk_tol > cap;
     const int q = std::max(0, std::min({kick, rows - rk0, cap - rk0}));
     const int rk = rk0 + q;
+    const double* cand = nullptr;
+    int ncand = 0;
+    if (q > 0 && cand_fn) ncand = (*cand_fn)(&cand);
     // W_k = [U[:, :rk0] | kick]  ([r][4][rk])
     W.cores[k].reserve((size_t)rows * rk);
     copy2d(sv.U.get(), sv.k, W.cores[k].get(), rk, rows, rk0, c.s);
     if (q > 0) {
       // enrichment columns orthonormalised against U (the columns of W_k)
       DevBuf G((size_t)q * rows);                                // G^T: q x rows
-      if (cand)
+      if (ncand > 0)
         principal_orth_rows(W.cores[k].get(), rk0, 1, rk, rows, cand, ncand, G.get(), q, seed, c);
       else
         random_orth_rows(W.cores[k].get(), rk0, 1, rk, rows, G.get(), q, seed, c);
@@ -470,12 +473,15 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     capped = rk_tol > cap;
     const int q = std::max(0, std::min({kick, cols - rk0, cap - rk0}));
     const int rk = rk0 + q;
+    const double* cand = nullptr;
+    int ncand = 0;
+    if (q > 0 && cand_fn) ncand = (*cand_fn)(&cand);
     // W_k = [Vt[:rk0]; kick]  ([rk][4][s])
     W.cores[k].reserve((size_t)rk * cols);
     TT_HIP(hipMemcpyAsync(W.cores[k].get(), sv.Vt.get(), sizeof(double) * (size_t)rk0 * cols, hipMemcpyDeviceToDevice,
                           c.s));
     if (q > 0) {   // enrichment rows orthonormalised against those of Vt
-      if (cand)
+      if (ncand > 0)
         principal_orth_rows(W.cores[k].get(), rk0, cols, 1, cols, cand, ncand, W.cores[k].get() + (size_t)rk0 * cols,
                             q, seed, c);
       else
@@ -1221,20 +1227,21 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       TT_HIP(hipGetLastError());
       c.sync();
       info.t_solve += now() - ts;
-      // sketched residual of the local system: candidate enrichment rows
+      // sketched residual of the local system: candidate enrichment rows,
+      // computed by the split only when the cap leaves room for them
       DevBuf cand;
-      int ncand = 0;
-      if (enrich_now && ((dir > 0 && k < d - 1) || (dir < 0 && k > 0))) {
-        const double te = now();
-        ncand = residual_candidates(sys, envs, sk, W, k, dir, key_of_op, key_of_term, key_id, rho, cand, c);
-        info.t_svd += now() - te;
-      }
+      const CandidateFn cand_fn = [&](const double** rows) {
+        const int nc = residual_candidates(sys, envs, sk, W, k, dir, key_of_op, key_of_term, key_id, rho, cand, c);
+        *rows = cand.get();
+        return nc;
+      };
+      const CandidateFn* cand_use =
+          (enrich_now && ((dir > 0 && k < d - 1) || (dir < 0 && k > 0))) ? &cand_fn : nullptr;
       // move the block index and extend the environments
       if (dir > 0 && k < d - 1) {
         double t1 = now();
         info.capped |= split_block(W, +1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
-                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k), ncand ? cand.get() : nullptr,
-                    ncand);
+                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k), cand_use);
         info.t_svd += now() - t1;
         t1 = now();
         envs.update_left(W, k, c);
@@ -1243,8 +1250,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       } else if (dir < 0 && k > 0) {
         double t1 = now();
         info.capped |= split_block(W, -1, tol_svd, prm.rank_cap, c, sweep < prm.kick_sweeps ? prm.kick : 0,
-                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k) + 7777ull,
-                    ncand ? cand.get() : nullptr, ncand);
+                    prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k) + 7777ull, cand_use);
         info.t_svd += now() - t1;
         t1 = now();
         envs.update_right(W, k, c);

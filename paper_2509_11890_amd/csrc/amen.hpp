@@ -6,6 +6,8 @@
 // cached and updated incrementally.
 #pragma once
 
+#include <functional>
+
 #include <string>
 #include <vector>
 
@@ -62,12 +64,14 @@ struct BlockTT {
 // passes) and against each other (QR): the random enrichment of a TT core.
 void random_orth_rows(const double* B, int q0, long bj, long bi, int len, double* G, int q, unsigned long long seed,
                       Ctx& c);
-// With candidate rows cand (ncand rows of the kept factor's length: the
-// sketched residual of the local system, see amen_solve) the kick directions
-// are their leading principal directions.  Either kind fills only capacity
-// left under the cap.
+// With a candidate provider (it writes candidate rows of the kept factor's
+// length, the sketched residual of the local system (see amen_solve), and
+// returns their pointer and count) the kick directions are their leading
+// principal directions.  Either kind fills only capacity left under the cap;
+// the provider is called only when there is such capacity.
+using CandidateFn = std::function<int(const double** rows)>;
 bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick = 0,
-                 unsigned long long seed = 0, const double* cand = nullptr, int ncand = 0);
+                 unsigned long long seed = 0, const CandidateFn* cand = nullptr);
 // Norm of a device vector (deterministic; synchronises).
 double dev_norm(const double* x, long n, Ctx& c);
 
