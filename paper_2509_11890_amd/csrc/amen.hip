@@ -1111,17 +1111,22 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   for (int sweep = 0; sweep < prm.max_sweeps; ++sweep) {
     double max_res = 0.0;
     const bool enrich_now = resid && sweep < prm.kick_sweeps;
-    if (enrich_now) {
-      // sketch environments on the side ahead of the block (its frame cores
-      // stay fixed until the sweep reaches them)
+    // sketch environments on the side ahead of the block (its frame cores
+    // stay fixed until the sweep reaches them), built at the first request
+    // for candidates in this half-sweep (core k0): the side ahead of k0 is
+    // all that this and every later request of the half-sweep reads
+    bool sk_fresh = false;
+    auto ensure_sketch = [&](int k0) {
+      if (sk_fresh) return;
       const double te = now();
       if (dir > 0)
-        for (int k = d - 1; k > 0; --k) sk.update_right(W, k, c);
+        for (int k = d - 1; k > k0; --k) sk.update_right(W, k, c);
       else
-        for (int k = 0; k < d - 1; ++k) sk.update_left(W, k, c);
+        for (int k = 0; k < k0; ++k) sk.update_left(W, k, c);
       c.sync();
       info.t_env += now() - te;
-    }
+      sk_fresh = true;
+    };
     for (int step = 0; step < d; ++step) {
       const int k = (dir > 0) ? step : d - 1 - step;
       TT_REQUIRE(W.pos == k, "block position");
@@ -1231,6 +1236,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       // computed by the split only when the cap leaves room for them
       DevBuf cand;
       const CandidateFn cand_fn = [&](const double** rows) {
+        ensure_sketch(k);
         const int nc = residual_candidates(sys, envs, sk, W, k, dir, key_of_op, key_of_term, key_id, rho, cand, c);
         *rows = cand.get();
         return nc;
