@@ -1110,6 +1110,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   }
   for (int sweep = 0; sweep < prm.max_sweeps; ++sweep) {
     double max_res = 0.0;
+    info.newton_res_final = false;   // the direction changes in this half-sweep
     const bool enrich_now = resid && sweep < prm.kick_sweeps;
     // sketch environments on the side ahead of the block (its frame cores
     // stay fixed until the sweep reaches them), built at the first request
@@ -1297,6 +1298,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
         glob_hist.resize(sweep + 1, -1.0);
         glob_hist[sweep] = ratio;
         info.newton_res = ratio;
+        info.newton_res_final = true;
         const bool met = ratio <= 2.0 * prm.tol;
         const bool flat = sweep >= 2 && glob_hist[sweep - 2] >= 0.0 && ratio < 1.0 &&
                           ratio > 0.9 * glob_hist[sweep - 2];

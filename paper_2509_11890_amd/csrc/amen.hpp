@@ -106,6 +106,7 @@ struct AmenInfo {
   int mlp_used = 0, mlp_fallbacks = 0;
   double t_env = 0, t_solve = 0, t_svd = 0, t_check = 0;
   double newton_res = -1.0;  // last global ratio ||K dU + R|| / ||R|| evaluated by the stopping rule
+  bool newton_res_final = false;  // ... and it is that of the returned direction
 };
 
 // Solve the Newton system starting from W, whose block sits at an end core

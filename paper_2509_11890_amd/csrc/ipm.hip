@@ -1050,8 +1050,12 @@ void ipm_step(const Problem& P, State& S, const ttipm_params& prm, ttipm_step_in
   if (prm.newton_check) {
     const double t0 = now();
     double res = 0.0, rhs = 0.0;
-    newton_residual(sys_c, S.W, &res, &rhs, c);
-    info.newton_res = rhs > 0 ? res / rhs : (res < 0 ? -1.0 : 0.0);
+    if (ai_c.newton_res_final) {
+      info.newton_res = ai_c.newton_res;   // the AMEn stopping rule evaluated this direction already
+    } else {
+      newton_residual(sys_c, S.W, &res, &rhs, c);
+      info.newton_res = rhs > 0 ? res / rhs : (res < 0 ? -1.0 : 0.0);
+    }
     if (ap.mixed && info.newton_res > S.eta) {
       AmenParams ar = ap;
       ar.mixed = false;
