@@ -66,8 +66,10 @@ def parse():
     ap.add_argument("--rank-cap", type=int, default=None, help="override the frame rank cap")
     ap.add_argument("--iter-rank-cap", type=int, default=None, help="override the iterate rank cap")
     ap.add_argument("--max-iter", type=int, default=100, help="IPM iteration limit of a step")
-    ap.add_argument("--profile-period", type=int, default=8,
-                    help="event-time every n-th launch of the instrumented kernels")
+    ap.add_argument("--profile-period", type=int, default=61,
+                    help="event-time every n-th launch of each instrumented kernel class (a timed launch costs "
+                         "about 20 us of host time, so a sparse, prime period keeps the timing from inflating "
+                         "the measured solves and from aliasing with their launch patterns)")
     ap.add_argument("--record-wall", type=float, default=30.0,
                     help="wall-time cap (s) of each configuration record")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
