@@ -843,7 +843,7 @@ BlockTT block_from_frame(const TT& frame, int Lp, Ctx& c) {
   return W;
 }
 
-void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double* rhs, Ctx& c) {
+void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double* rhs, Ctx& c, ResidualRhs* rr) {
   struct Img {
     double coef;
     const TT* op;   // nullptr: identity
@@ -891,14 +891,17 @@ void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double
     bool in_r;   // also a pair of ||R||^2
   };
   std::vector<PairUse> use;
+  const bool cached = rr && rr->have;
   for (int b = 0; b < 4; ++b) {
     const int nk = (int)KU[b].size();
     std::vector<Img> all = KU[b];
     all.insert(all.end(), R[b].begin(), R[b].end());
     for (size_t i = 0; i < all.size(); ++i)
       for (size_t j = i; j < all.size(); ++j) {
+        const bool in_r = (int)i >= nk && (int)j >= nk;
+        if (in_r && cached) continue;   // ||R_b||^2 is known
         pairs.push_back({all[i].vec, all[i].op, all[j].vec, all[j].op});
-        use.push_back({b, (i == j ? 1.0 : 2.0) * all[i].coef * all[j].coef, (int)i >= nk && (int)j >= nk});
+        use.push_back({b, (i == j ? 1.0 : 2.0) * all[i].coef * all[j].coef, in_r});
       }
   }
   const std::vector<double> ip = tt_op_dots(pairs, c);
@@ -906,6 +909,15 @@ void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double
   for (size_t q = 0; q < ip.size(); ++q) {
     e2[use[q].b] += use[q].w * ip[q];
     if (use[q].in_r) r2[use[q].b] += use[q].w * ip[q];
+  }
+  if (cached) {
+    for (int b = 0; b < 4; ++b) {
+      r2[b] = rr->r2[b];
+      e2[b] += r2[b];
+    }
+  } else if (rr) {
+    for (int b = 0; b < 4; ++b) rr->r2[b] = r2[b];
+    rr->have = true;
   }
   double es = 0.0, rs = 0.0;
   for (int b = 0; b < 4; ++b) {
@@ -1100,6 +1112,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
   // operator ranks R: r^2 R^2 per core below 2^20 doubles; at r = 32, R = 64
   // one evaluation cost as much as a quarter of the iteration).
   bool glob_cheap = true;
+  ResidualRhs rhs_cache;   // ||R||^2 of the block rows, the same for every half-sweep
   {
     size_t rmax = 1, Rmax = 1;
     for (int x : W.r) rmax = std::max(rmax, (size_t)std::max(x, 1));
@@ -1291,7 +1304,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
     if (prm.global_stop && info.capped && glob_cheap) {
       const double tg = now();
       double res = 0.0, rhs = 0.0;
-      newton_residual(sys, W, &res, &rhs, c);
+      newton_residual(sys, W, &res, &rhs, c, &rhs_cache);
       info.t_check += now() - tg;
       if (res >= 0.0 && rhs > 0.0) {
         const double ratio = res / rhs;

@@ -120,7 +120,15 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
 // block rows, each norm exact from operator-image inner products (no image is
 // formed).  The forcing condition of Sec. 3.3 (Lemma "AMEn Directions as
 // Inexact Newton Directions") asks res <= eta rhs.
-void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double* rhs, Ctx& c);
+// rr (optional): the right-hand-side part ||R_b||^2 of every block row, which
+// does not depend on the direction; filled by the first call that gets it
+// and reused by later calls for the same system.
+struct ResidualRhs {
+  bool have = false;
+  double r2[4] = {0.0, 0.0, 0.0, 0.0};
+};
+void newton_residual(const NewtonSys& sys, const BlockTT& W, double* res, double* rhs, Ctx& c,
+                     ResidualRhs* rr = nullptr);
 
 // Build an initial block TT (block at 0) from a frame TT (e.g. the identity).
 BlockTT block_from_frame(const TT& frame, int Lp, Ctx& c);

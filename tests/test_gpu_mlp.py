@@ -135,7 +135,11 @@ def test_training_lowers_heldout_loss_and_fallback_rule():
         torch.cuda.synchronize()
         x_ref = np.linalg.solve(Kd, b)
         assert ib["converged"] and im["converged"]
-        assert np.linalg.norm(xm.cpu().numpy() - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
+        # forward error of a solve stopped at relative residual rtol: at most
+        # cond(K) rtol (||x - x*|| / ||x*|| <= cond(K) ||r|| / ||b||), with a
+        # factor 2 for the rounding of the final residual evaluation
+        bound = 2.0 * np.linalg.cond(Kd) * 1e-10
+        assert np.linalg.norm(xm.cpu().numpy() - x_ref) <= bound * np.linalg.norm(x_ref)
         assert im["iters"] <= ib["iters"]
         kept += im["precond"] == P.TT_PREC_MLP
         print("bjacobi", ib["iters"], "mlp", im["iters"], "used", im["precond"])
