@@ -19,12 +19,6 @@ namespace ttipm {
 
 constexpr int BT = 1024;
 
-__device__ __forceinline__ double wave_sum64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 constexpr int kTriMax = 32;
 
 // Cholesky of an n x n (n <= 32) diagonal block (row-major, leading dimension

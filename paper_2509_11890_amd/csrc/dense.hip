@@ -11,6 +11,7 @@
 // steps of the algorithm.  Reductions use a fixed order, so results are
 // reproducible run to run.
 #include "dense.hpp"
+#include "xlane.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -20,11 +21,7 @@ namespace ttipm {
 constexpr int DT = 1024;        // threads per dense workgroup
 constexpr int NW = DT / 64;     // waves per workgroup
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return xlane::wave_sum(v); }
 
 // Block-wide sum with a fixed reduction order (result broadcast to all threads).
 __device__ double block_sum(double v, double* red) {
@@ -190,12 +187,9 @@ __device__ __forceinline__ void jacobi_svd_body(double* A, int m, int n, double*
           double x = ap[i], y = aq[i];
           al += x * x; be += y * y; ga += x * y;
         }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o);
-          be += __shfl_xor(be, o);
-          ga += __shfl_xor(ga, o);
-        }
+        al = xlane::row16_sum(al);
+        be = xlane::row16_sum(be);
+        ga = xlane::row16_sum(ga);
         if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
         if (fabs(ga) <= tol * sqrt(al * be)) continue;
         double zeta = (be - al) / (2.0 * ga);

@@ -6,6 +6,7 @@
 // stores coalesce, and the reductions use a fixed two-level order (per-block
 // partials, then one block) so that repeated runs are bit-identical.
 #include "ttops.hpp"
+#include "xlane.hpp"
 
 namespace ttipm {
 
@@ -336,8 +337,7 @@ __global__ void mdot_stage1(long n, int k, const double* V, long ld, const doubl
   double acc = 0.0;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
     acc += v[t] * w[t];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  acc = xlane::wave_sum(acc);
   if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -384,8 +384,7 @@ __global__ void mdot_single(long n, const double* V, long ld, const double* w, d
     for (int u = 0; u < U; ++u)
       if (t0 + (long)u * blockDim.x < n) acc += vs[u] * ws[u];
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  acc = xlane::wave_sum(acc);
   if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
