@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "ttops.hpp"
+#include "xlane.hpp"
 
 namespace ttipm {
 
@@ -106,9 +107,8 @@ __global__ __launch_bounds__(64) void trinv_upper_kernel(const double* U, int n,
 // piv[t] receives the absolute row chosen at step t (row_base + local index).
 __global__ __launch_bounds__(BT) void panel_lu_kernel(double* A, int m, int nb, long lda, int* piv, int row_base,
                                                       int* status) {
-  __shared__ double rv[BT];
-  __shared__ int ri[BT];
-  __shared__ int s_piv;
+  __shared__ double rv[BT / 64];
+  __shared__ int ri[BT / 64];
   for (int j = 0; j < nb && j < m; ++j) {
     double best = -1.0;
     int bi = j;
@@ -116,23 +116,9 @@ __global__ __launch_bounds__(BT) void panel_lu_kernel(double* A, int m, int nb, 
       double v = fabs(A[(long)i * lda + j]);
       if (v > best) { best = v; bi = i; }
     }
-    rv[threadIdx.x] = best;
-    ri[threadIdx.x] = bi;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) {
-        double a = rv[threadIdx.x], b = rv[threadIdx.x + o];
-        int ia = ri[threadIdx.x], ib = ri[threadIdx.x + o];
-        if (b > a || (b == a && ib < ia)) { rv[threadIdx.x] = b; ri[threadIdx.x] = ib; }
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      s_piv = ri[0];
-      piv[j] = row_base + ri[0];
-    }
-    __syncthreads();
-    const int p = s_piv;
+    xlane::block_argmax<BT / 64>(best, bi, min(BT / 64, (m - j + 63) / 64), rv, ri);
+    if (threadIdx.x == 0) piv[j] = row_base + bi;
+    const int p = bi;
     if (p != j)
       for (int c = threadIdx.x; c < nb; c += blockDim.x) {
         double t = A[(long)j * lda + c];
@@ -163,9 +149,8 @@ __global__ __launch_bounds__(BT) void panel_lu_kernel(double* A, int m, int nb, 
 __global__ __launch_bounds__(BT) void panel_lu_lds_kernel(double* A, int m, int nb, long lda, int* piv, int row_base,
                                                           int* status) {
   extern __shared__ double P[];
-  __shared__ double rv[BT];
-  __shared__ int ri[BT];
-  __shared__ int s_piv;
+  __shared__ double rv[BT / 64];
+  __shared__ int ri[BT / 64];
   const int ld = nb + 1;
   const int tid = threadIdx.x;
   for (int t = tid; t < m * nb; t += BT) P[(t / nb) * ld + t % nb] = A[(long)(t / nb) * lda + t % nb];
@@ -177,23 +162,9 @@ __global__ __launch_bounds__(BT) void panel_lu_lds_kernel(double* A, int m, int 
       const double v = fabs(P[i * ld + j]);
       if (v > best) { best = v; bi = i; }
     }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int o = BT / 2; o > 0; o >>= 1) {
-      if (tid < o) {
-        const double a = rv[tid], b = rv[tid + o];
-        const int ia = ri[tid], ib = ri[tid + o];
-        if (b > a || (b == a && ib < ia)) { rv[tid] = b; ri[tid] = ib; }
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      s_piv = ri[0];
-      piv[j] = row_base + ri[0];
-    }
-    __syncthreads();
-    const int pv = s_piv;
+    xlane::block_argmax<BT / 64>(best, bi, min(BT / 64, (m - j + 63) / 64), rv, ri);
+    if (tid == 0) piv[j] = row_base + bi;
+    const int pv = bi;
     if (pv != j)
       for (int c = tid; c < nb; c += BT) {
         const double t = P[j * ld + c];

@@ -314,9 +314,8 @@ __global__ __launch_bounds__(DT) void jacobi_svd_lds_a_kernel(const double* Ag, 
 // status[0] = 0 on success, j+1 if the pivot of column j is exactly zero.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(DT) void lu_solve_kernel(double* A, int n, double* B, int nrhs, int* status) {
-  __shared__ double rv[DT];
-  __shared__ int ri[DT];
-  __shared__ int s_piv;
+  __shared__ double rv[DT / 64];
+  __shared__ int ri[DT / 64];
   if (threadIdx.x == 0) status[0] = 0;
   for (int j = 0; j < n; ++j) {
     // pivot search (max |A[i][j]|, lowest index on ties)
@@ -325,19 +324,8 @@ __global__ __launch_bounds__(DT) void lu_solve_kernel(double* A, int n, double* 
       double v = fabs(A[(long)i * n + j]);
       if (v > best) { best = v; bi = i; }
     }
-    rv[threadIdx.x] = best; ri[threadIdx.x] = bi;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) {
-        double a = rv[threadIdx.x], b = rv[threadIdx.x + o];
-        int ia = ri[threadIdx.x], ib = ri[threadIdx.x + o];
-        if (b > a || (b == a && ib < ia)) { rv[threadIdx.x] = b; ri[threadIdx.x] = ib; }
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) s_piv = ri[0];
-    __syncthreads();
-    const int piv = s_piv;
+    xlane::block_argmax<DT / 64>(best, bi, min(DT / 64, (n - j + 63) / 64), rv, ri);
+    const int piv = bi;
     if (piv != j) {
       for (int c = threadIdx.x; c < n; c += blockDim.x) {
         double t = A[(long)j * n + c]; A[(long)j * n + c] = A[(long)piv * n + c]; A[(long)piv * n + c] = t;
@@ -482,8 +470,8 @@ __global__ __launch_bounds__(DT) void cholesky_lds_kernel(double* A, int n, int*
 // LU with partial pivoting and solve, as lu_solve_kernel, with A and B in LDS.
 __global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, double* B, int nrhs, int* status) {
   extern __shared__ double S[];
-  __shared__ double rv[DT];
-  __shared__ int ri[DT];
+  __shared__ double rv[DT / 64];
+  __shared__ int ri[DT / 64];
   const int ld = n | 1;
   double* Bs = S + (size_t)n * ld;
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5, nt = blockDim.x;
@@ -500,18 +488,8 @@ __global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, doub
       const double v = fabs(S[i * ld + j]);
       if (v > best) { best = v; bi = i; }
     }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int o = nt / 2; o > 0; o >>= 1) {
-      if (tid < o) {
-        const double a = rv[tid], b = rv[tid + o];
-        const int ia = ri[tid], ib = ri[tid + o];
-        if (b > a || (b == a && ib < ia)) { rv[tid] = b; ri[tid] = ib; }
-      }
-      __syncthreads();
-    }
-    const int piv = ri[0];
+    xlane::block_argmax<DT / 64>(best, bi, min(DT / 64, (n - j + 63) / 64), rv, ri);
+    const int piv = bi;
     if (piv != j) {
       for (int c = tid; c < n; c += nt) {
         const double t = S[j * ld + c]; S[j * ld + c] = S[piv * ld + c]; S[piv * ld + c] = t;
