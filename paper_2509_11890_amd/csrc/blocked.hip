@@ -38,15 +38,16 @@ __global__ __launch_bounds__(BT) void chol_block_kernel(double* A, int n, long l
       s_bad = 1;
       break;
     }
-    const double dj = sqrt(d);
     __syncthreads();   // every thread has read As[j][j]
-    if (threadIdx.x == 0) As[j][j] = dj;
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) As[i][j] /= dj;
+    if (threadIdx.x == 0 || j + 1 + (int)threadIdx.x < n) {   // the threads that use the root
+      const double dj = sqrt(d);
+      if (threadIdx.x == 0) As[j][j] = dj;
+      for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) As[i][j] /= dj;
+    }
     __syncthreads();
-    const int rows = n - j - 1;
-    for (int t = threadIdx.x; t < rows * rows; t += blockDim.x) {
-      const int i = j + 1 + t / rows, c = j + 1 + t % rows;
-      if (c <= i) As[i][c] -= As[i][j] * As[c][j];
+    {   // thread (t / 32, t % 32) updates entry (j + 1 + t / 32, j + 1 + t % 32)
+      const int i = j + 1 + (int)(threadIdx.x >> 5), c = j + 1 + (int)(threadIdx.x & 31);
+      if (i < n && c <= i) As[i][c] -= As[i][j] * As[c][j];
     }
     __syncthreads();
   }
@@ -134,10 +135,11 @@ __global__ __launch_bounds__(BT) void panel_lu_kernel(double* A, int m, int nb, 
     }
     for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) A[(long)i * lda + j] /= d;
     __syncthreads();
-    const int rows = m - j - 1, cols = nb - j - 1;
-    for (long t = threadIdx.x; t < (long)rows * cols; t += blockDim.x) {
-      int i = j + 1 + (int)(t / cols), c = j + 1 + (int)(t % cols);
-      A[(long)i * lda + c] -= A[(long)i * lda + j] * A[(long)j * lda + c];
+    {   // thread t updates column j + 1 + t % 32 of rows j + 1 + t / 32 + 32 k (nb <= 32)
+      const int c = j + 1 + (int)(threadIdx.x & 31);
+      if (c < nb)
+        for (int i = j + 1 + (int)(threadIdx.x >> 5); i < m; i += BT / 32)
+          A[(long)i * lda + c] -= A[(long)i * lda + j] * A[(long)j * lda + c];
     }
     __syncthreads();
   }
@@ -180,12 +182,11 @@ __global__ __launch_bounds__(BT) void panel_lu_lds_kernel(double* A, int m, int 
     }
     for (int i = j + 1 + tid; i < m; i += BT) P[i * ld + j] /= d;
     __syncthreads();
-    const int cols = nb - j - 1;
-    if (cols > 0)
-      for (int t = tid; t < (m - j - 1) * cols; t += BT) {
-        const int i = j + 1 + t / cols, c = j + 1 + t % cols;
-        P[i * ld + c] -= P[i * ld + j] * P[j * ld + c];
-      }
+    {   // thread t updates column j + 1 + t % 32 of rows j + 1 + t / 32 + 32 k (nb <= 32)
+      const int c = j + 1 + (tid & 31);
+      if (c < nb)
+        for (int i = j + 1 + (tid >> 5); i < m; i += BT / 32) P[i * ld + c] -= P[i * ld + j] * P[j * ld + c];
+    }
     __syncthreads();
   }
   for (int t = tid; t < m * nb; t += BT) A[(long)(t / nb) * lda + t % nb] = P[(t / nb) * ld + t % nb];
@@ -376,6 +377,7 @@ void chol_rec(double* A, int n, BlockedFactors& f, int j0, int len, int* st, Dev
 void lu_rec(double* A, int n, BlockedFactors& f, int* piv, int j0, int w, int* st, DevBuf& tmp, Ctx& c) {
   const int nb = f.nb;
   if (w <= nb) {
+    TT_REQUIRE(w <= kTriMax, "diagonal block above 32");   // the panel kernels take at most 32 columns
     const double pm = n - j0;
     const size_t lds = sizeof(double) * (size_t)(n - j0) * (w + 1);
     if (lds <= panel_lds_limit())
@@ -385,7 +387,6 @@ void lu_rec(double* A, int n, BlockedFactors& f, int* piv, int j0, int w, int* s
       launch_prof(PK_PANEL_LU, pm * w * (double)w, 16.0 * pm * w, panel_lu_kernel, dim3(1), dim3(BT), 0, c.s,
                   A + (long)j0 * n + j0, n - j0, w, (long)n, piv + j0, j0, st);
     double* Ajj = A + (long)j0 * n + j0;
-    TT_REQUIRE(w <= kTriMax, "diagonal block above 32");
     hipLaunchKernelGGL(trinv_lower_kernel, dim3(1), dim3(64), 0, c.s, Ajj, w, (long)n,
                        const_cast<double*>(dblock(f.dinv, j0, nb)), 1);
     hipLaunchKernelGGL(trinv_upper_kernel, dim3(1), dim3(64), 0, c.s, Ajj, w, (long)n,

@@ -23,15 +23,26 @@ constexpr int NW = DT / 64;     // waves per workgroup
 
 __device__ __forceinline__ double wave_sum(double v) { return xlane::wave_sum(v); }
 
-// Block-wide sum with a fixed reduction order (result broadcast to all threads).
-__device__ double block_sum(double v, double* red) {
+// Block-wide sum of nonnegative partials (sums of squares) over a workgroup of
+// DT threads with a fixed reduction order (result broadcast to all threads).
+// Only the first `active` threads may hold nonzero partials: the wavefronts
+// beyond them hold +0 and are left out, which leaves the sum unchanged, and
+// do no reduction work (they share the SIMDs with the ones that do).
+__device__ double block_sum(double v, double* red, int active = DT) {
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  v = wave_sum(v);
+  const int nwa = min(NW, (active + 63) / 64);
+  if (w < nwa) v = wave_sum(v);
   __syncthreads();
-  if (lane == 0) red[w] = v;
+  if (lane == 0 && w < nwa) red[w] = v;
   __syncthreads();
+  double r[NW];
+#pragma unroll
+  for (int i = 0; i < NW; ++i)
+    if (i < nwa) r[i] = red[i];
   double s = 0.0;
-  for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += red[i];
+#pragma unroll
+  for (int i = 0; i < NW; ++i)
+    if (i < nwa) s += r[i];
   __syncthreads();
   return s;
 }
@@ -87,7 +98,7 @@ __global__ __launch_bounds__(DT) void qr_kernel(double* A, int m, int n, int lda
     double* col = A + (long)j * lda;
     double part = 0.0;
     for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) part += col[i] * col[i];
-    double sig = block_sum(part, red);
+    double sig = block_sum(part, red, m - j - 1);
     if (threadIdx.x == 0) {
       double alpha = col[j];
       if (sig == 0.0) {
@@ -452,8 +463,10 @@ __global__ __launch_bounds__(DT) void cholesky_lds_kernel(double* A, int n, int*
     }
     __syncthreads();
     if (s_bad) return;
-    const double inv = 1.0 / S[j * ld + j];
-    for (int i = j + 1 + tid; i < n; i += nt) S[i * ld + j] *= inv;
+    if (j + 1 + tid < n) {   // only the threads that scale take the reciprocal
+      const double inv = 1.0 / S[j * ld + j];
+      for (int i = j + 1 + tid; i < n; i += nt) S[i * ld + j] *= inv;
+    }
     __syncthreads();
     for (int i = j + 1 + ty; i < n; i += nt / 32) {
       const double a = S[i * ld + j];
@@ -504,8 +517,10 @@ __global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, doub
       if (tid == 0) status[0] = j + 1;
       return;
     }
-    const double inv = 1.0 / d;
-    for (int i = j + 1 + tid; i < n; i += nt) S[i * ld + j] *= inv;
+    if (j + 1 + tid < n) {   // only the threads that scale take the reciprocal
+      const double inv = 1.0 / d;
+      for (int i = j + 1 + tid; i < n; i += nt) S[i * ld + j] *= inv;
+    }
     __syncthreads();
     for (int i = j + 1 + ty; i < n; i += nt / 32) {
       const double a = S[i * ld + j];
@@ -515,8 +530,10 @@ __global__ __launch_bounds__(DT) void lu_solve_lds_kernel(double* A, int n, doub
     __syncthreads();
   }
   for (int j = n - 1; j >= 0; --j) {
-    const double inv = 1.0 / S[j * ld + j];
-    for (int c = tid; c < nrhs; c += nt) Bs[j * nrhs + c] *= inv;
+    if (tid < nrhs) {
+      const double inv = 1.0 / S[j * ld + j];
+      for (int c = tid; c < nrhs; c += nt) Bs[j * nrhs + c] *= inv;
+    }
     __syncthreads();
     for (int i = ty; i < j; i += nt / 32) {
       const double a = S[i * ld + j];
@@ -717,7 +734,7 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
   if (v_init) {
     double part = 0.0;
     for (int i = tid; i < p; i += nt) part += v[i] * v[i];
-    const double nv = block_sum(part, red);
+    const double nv = block_sum(part, red, p);
     v_init = (nv > 0.0 && nv < 1e300) ? 1 : 0;
   }
   if (!v_init)
@@ -736,7 +753,7 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
     // q_0 = v / |v|
     double part = 0.0;
     for (int i = tid; i < p; i += nt) part += v[i] * v[i];
-    const double nv = sqrt(block_sum(part, red));
+    const double nv = sqrt(block_sum(part, red, p));
     for (int i = tid; i < p; i += nt) Q[i] = v[i] / nv;
     __syncthreads();
     int k = 0;
@@ -772,7 +789,7 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
       }
       part = 0.0;
       for (int i = tid; i < p; i += nt) part += wv[i] * wv[i];
-      double bj = sqrt(block_sum(part, red));
+      double bj = sqrt(block_sum(part, red, p));
       k = j + 1;
       if (k >= p) { if (tid == 0) be[j] = 0.0; __syncthreads(); break; }
       if (bj <= 1e-13 * s_bnorm) {
@@ -797,7 +814,7 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
         }
         part = 0.0;
         for (int i = tid; i < p; i += nt) part += wv[i] * wv[i];
-        const double nr = sqrt(block_sum(part, red));
+        const double nr = sqrt(block_sum(part, red, p));
         for (int i = tid; i < p; i += nt) wv[i] /= nr;
         if (tid == 0) be[j] = 0.0;
       } else {
@@ -834,7 +851,7 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
         part += r * r;
       }
     }
-    const double res = sqrt(block_sum(part, red));
+    const double res = sqrt(block_sum(part, red));   // partials in lane 0 of every wavefront
     if (res <= tol * s_bnorm || k >= p) break;
   }
   if (tid == 0) lam_out[0] = theta;
