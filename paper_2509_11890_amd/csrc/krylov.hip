@@ -56,6 +56,30 @@ __global__ void set_first_kernel(double* g, int len, double beta) {
   if (i < len) g[i] = (i == 0) ? beta : 0.0;
 }
 
+// Back substitution of the cycle's least-squares problem: y solves the upper
+// triangular H[0:len, 0:len] y = g[0:len] (H row-major with row stride m), a
+// zero diagonal entry giving y_i = 0.  With staged != 0 the wavefront first
+// copies the len x len block into LDS (dynamic, len * len doubles); one lane
+// then runs the substitution row by row, each row's sum left to right with
+// separately rounded products and differences (no contraction), the
+// arithmetic of the textbook loop.
+__global__ __launch_bounds__(64) void backsub_kernel(const double* H, int m, const double* g, int len, double* y,
+                                                     int staged) {
+#pragma clang fp contract(off)
+  extern __shared__ double Hs[];
+  if (staged)
+    for (int t = threadIdx.x; t < len * len; t += 64) Hs[t] = H[(long)(t / len) * m + t % len];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double* R = staged ? Hs : H;
+  const long ld = staged ? len : m;
+  for (int i = len - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int l = i + 1; l < len; ++l) acc -= R[i * ld + l] * y[l];
+    y[i] = (R[i * ld + i] != 0.0) ? acc / R[i * ld + i] : 0.0;
+  }
+}
+
 }  // namespace
 
 // Arnoldi steps run without host round trips: the Givens rotations are applied
@@ -78,7 +102,6 @@ void gmres_solve(long n, const KrylovOps& ops, const double* f, double* u, const
     c.sync();
     return;
   }
-  std::vector<double> H((size_t)(m + 1) * m), g(m + 1);
   double best = std::numeric_limits<double>::infinity();
   int stall = 0;
   while (true) {
@@ -143,20 +166,13 @@ void gmres_solve(long n, const KrylovOps& ops, const double* f, double* u, const
     } else {
       info.iters -= (j + 1) - jend;   // steps computed past the converged one are not part of the solve
     }
-    // back substitution on the host with the final rotated columns 0 .. jend-1
+    // back substitution on the device with the final rotated columns 0 .. jend-1
     if (jend > 0) {
-      TT_HIP(hipMemcpyAsync(H.data(), Hd.get(), sizeof(double) * (size_t)jend * m, hipMemcpyDeviceToHost, c.s));
-      TT_HIP(hipMemcpyAsync(g.data(), gd.get(), sizeof(double) * (size_t)jend, hipMemcpyDeviceToHost, c.s));
-      c.sync();
-    }
-    std::vector<double> y(jend, 0.0);
-    for (int i = jend - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int l = i + 1; l < jend; ++l) acc -= H[(size_t)i * m + l] * y[l];
-      y[i] = (H[(size_t)i * m + i] != 0.0) ? acc / H[(size_t)i * m + i] : 0.0;
-    }
-    if (jend > 0) {
-      TT_HIP(hipMemcpyAsync(yv.get(), y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, c.s));
+      const size_t lds = sizeof(double) * (size_t)jend * jend;
+      const int staged = lds <= 65536 ? 1 : 0;
+      hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(64), staged ? (unsigned)lds : 0u, c.s, Hd.get(), m, gd.get(),
+                         jend, yv.get(), staged);
+      TT_HIP(hipGetLastError());
       fill(n, 0.0, z.get(), c.s);
       gemv_update(n, jend, V.get(), n, yv.get(), 1.0, z.get(), c.s);      // z = V y
       if (ops.precond) {
@@ -165,7 +181,6 @@ void gmres_solve(long n, const KrylovOps& ops, const double* f, double* u, const
       } else {
         axpby(n, 1.0, z.get(), 1.0, u, c.s);
       }
-      c.sync();   // y (host) is released at scope end
     }
     ++info.cycles;
   }
