@@ -661,8 +661,8 @@ __device__ int lz_sturm(const double* a, const double* b, int k, double x) {
 // Smallest eigenvalue theta of the Lanczos tridiagonal T_k (diagonal al,
 // off-diagonal be[0..k-2]) by multisection of the Sturm count, and its unit
 // eigenvector y by inverse iteration.  Called by the whole workgroup; theta is
-// left in *s_theta, y in shared memory; h is scratch.
-__device__ void lz_ritz_min(const double* al, const double* be, int k, double* y, double* h, double* s_lo,
+// left in *s_theta, y in shared memory; h and lq (k entries each) are scratch.
+__device__ void lz_ritz_min(const double* al, const double* be, int k, double* y, double* h, double* lq, double* s_lo,
                             double* s_hi, double* s_theta, int* s_first) {
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) {
@@ -700,20 +700,23 @@ __device__ void lz_ritz_min(const double* al, const double* be, int k, double* y
     double tn = 0.0;
     for (int i = 0; i < k; ++i) tn = fmax(tn, fabs(al[i]) + ((i > 0) ? fabs(be[i - 1]) : 0.0) + ((i + 1 < k) ? fabs(be[i]) : 0.0));
     const double sh = theta - (1e-12 * tn + 1e-300);
+    // LDL^T of the tridiagonal T - sh I (h holds D, lq the multipliers
+    // be[i-1] / h[i-1]), factored once for the three passes
+    double dprev = al[0] - sh;
+    h[0] = dprev;
+    for (int i = 1; i < k; ++i) {
+      const double l = be[i - 1] / dprev;
+      lq[i] = l;
+      dprev = al[i] - sh - l * be[i - 1];
+      if (dprev == 0.0) dprev = 1e-300;
+      h[i] = dprev;
+    }
     for (int i = 0; i < k; ++i) y[i] = 1.0;
     for (int it = 0; it < 3; ++it) {
-      // LDL^T of the tridiagonal T - sh I, then solve in place (h holds D)
-      double dprev = al[0] - sh;
-      h[0] = dprev;
-      for (int i = 1; i < k; ++i) {
-        const double l = be[i - 1] / dprev;
-        dprev = al[i] - sh - l * be[i - 1];
-        if (dprev == 0.0) dprev = 1e-300;
-        h[i] = dprev;
-      }
-      for (int i = 1; i < k; ++i) y[i] -= (be[i - 1] / h[i - 1]) * y[i - 1];
+      // solve (T - sh I) y_new = y in place
+      for (int i = 1; i < k; ++i) y[i] -= lq[i] * y[i - 1];
       for (int i = 0; i < k; ++i) y[i] /= h[i];
-      for (int i = k - 2; i >= 0; --i) y[i] -= (be[i] / h[i]) * y[i + 1];
+      for (int i = k - 2; i >= 0; --i) y[i] -= lq[i + 1] * y[i + 1];
       double nn = 0.0;
       for (int i = 0; i < k; ++i) nn += y[i] * y[i];
       nn = sqrt(nn) + 1e-300;
@@ -725,7 +728,7 @@ __device__ void lz_ritz_min(const double* al, const double* be, int k, double* y
 
 __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p, int kmax, int restarts, double tol,
                                                          double* Q, double* v, double* lam_out, int v_init) {
-  __shared__ double al[LZ_MAX], be[LZ_MAX], y[LZ_MAX], h[LZ_MAX];
+  __shared__ double al[LZ_MAX], be[LZ_MAX], y[LZ_MAX], h[LZ_MAX], lq[LZ_MAX];
   __shared__ double red[NW];
   __shared__ double s_theta, s_lo, s_hi, s_bnorm;
   __shared__ int s_first;
@@ -826,11 +829,11 @@ __global__ __launch_bounds__(DT) void lanczos_min_kernel(const double* B, int p,
       // T_k has converged (its residual norm is |beta_k y_k|, exact under full
       // reorthogonalisation); a warm start often converges within the first checks
       if ((k == 4 || (k >= 8 && k % 8 == 0)) && k < kmax) {
-        lz_ritz_min(al, be, k, y, h, &s_lo, &s_hi, &s_theta, &s_first);
+        lz_ritz_min(al, be, k, y, h, lq, &s_lo, &s_hi, &s_theta, &s_first);
         if (be[k - 1] != 0.0 && fabs(be[k - 1] * y[k - 1]) <= 0.5 * tol * s_bnorm) break;
       }
     }
-    lz_ritz_min(al, be, k, y, h, &s_lo, &s_hi, &s_theta, &s_first);
+    lz_ritz_min(al, be, k, y, h, lq, &s_lo, &s_hi, &s_theta, &s_first);
     __syncthreads();
     theta = s_theta;
     // Ritz vector v = Q_k y and its residual |B v - theta v|
