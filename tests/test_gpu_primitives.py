@@ -322,6 +322,40 @@ def test_local_solve_matches_dense_lu(method):
     assert _rel(x.cpu().numpy(), x_ref) < 1e-10
 
 
+def test_local_solve_gmres_long_cycle():
+    """One GMRES cycle of more than 90 steps (restart 200, no preconditioner,
+    spectrum spread over 1 .. 3e4): the cycle's back substitution then reads
+    the Hessenberg triangle in place instead of staging it in LDS.  The
+    solution matches the dense solve of the same operator."""
+    P = _lib()
+    rng = np.random.default_rng(41)
+    r, rp, m = 6, 6, 4
+    p = r * m * rp
+    # a diagonal operator (diagonal environments and core) plus a small coupling
+    dL, dR, dc = (np.exp(rng.uniform(0.0, np.log(30.0), k)) for k in (r, rp, m))
+    phiL = np.zeros((r, 1, r))
+    phiL[np.arange(r), 0, np.arange(r)] = dL
+    phiR = np.zeros((rp, 1, rp))
+    phiR[np.arange(rp), 0, np.arange(rp)] = dR
+    core = np.zeros((1, m, m, 1))
+    core[0, np.arange(m), np.arange(m), 0] = dc
+    cpl = (rng.standard_normal((r, 2, r)) * 0.05, rng.standard_normal((2, m, m, 2)), rng.standard_normal((rp, 2, rp)) * 0.05)
+    blocks = [(0, 0, 1.0, [(phiL, core, phiR)]), (0, 0, 1.0, [cpl])]
+    Kd = ott.local_dense(phiL, core, phiR) + ott.local_dense(*cpl)
+    b = rng.standard_normal(p)
+    x_ref = np.linalg.solve(Kd, b)
+    pblocks = [P.LocalBlock(row, col, coef, [P.ProjOp(_cuda(a), _cuda(c), _cuda(bb)) for a, c, bb in chain])
+               for row, col, coef, chain in blocks]
+    K = P.LocalOp(r, rp, 1, pblocks)
+    x = torch.zeros(p, dtype=torch.float64, device="cuda")
+    info = P.local_solve(K, _cuda(b), x, method=P.TT_SOLVE_GMRES, rtol=1e-13, restart=200, maxit=400,
+                         precond=P.TT_PREC_NONE)
+    torch.cuda.synchronize()
+    assert info["iters"] > 90, info
+    assert info["rel_res"] < 1e-12
+    assert _rel(x.cpu().numpy(), x_ref) < 1e-8
+
+
 @pytest.mark.parametrize("precond", ["none", "bjacobi"])
 def test_local_solve_gmres_at_frame_rank_32(precond):
     """GMRES on a local system of the n = 2^10 frame size (r = r' = 32, two
