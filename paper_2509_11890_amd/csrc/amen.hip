@@ -625,19 +625,30 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
       dense_chol_solve(LZ.get(), p, B, nrhs, c.s);
     }
   };
-  // G = L_Z^{-1} L_X^ Aeq^T^ ; S = Aeq^ G + K_Y^
-  T1.reserve((size_t)p * p);
-  gemm(gemm_nn(p, p, p, LX.get(), p, AT.get(), p, T1.get(), p), c.s, &c.ws, GemmPrec::F64);
-  solve_LZ(T1.get(), p);
-  S.reserve((size_t)p * p);
-  TT_HIP(hipMemcpyAsync(S.get(), KY.get(), sizeof(double) * (size_t)p * p, hipMemcpyDeviceToDevice, c.s));
-  gemm(gemm_nn(p, p, p, A.get(), p, T1.get(), p, S.get(), p, 1.0, 1.0), c.s, &c.ws, GemmPrec::F64);
-  // rhs_y = Aeq^ L_Z^{-1}(L_X^ R_d^ - R_c^) - R_p^
+  // G = L_Z^{-1} L_X^ Aeq^T^ ; S = Aeq^ G + K_Y^ ;
+  // rhs_y = Aeq^ L_Z^{-1}(L_X^ R_d^ - R_c^) - R_p^.
+  // With the single-workgroup solves, the p columns of L_X^ Aeq^T^ and the
+  // vector L_X^ R_d^ - R_c^ go through one triangular-solve launch as the
+  // independent columns of one p x (p + 1) buffer (the solve's latency does
+  // not depend on the number of columns; each column's arithmetic is the same).
+  const int tw = blocked ? p : p + 1;
+  T1.reserve((size_t)p * tw);
   v1.reserve(p);
   v2.reserve(p);
+  gemm(gemm_nn(p, p, p, LX.get(), p, AT.get(), p, T1.get(), tw), c.s, &c.ws, GemmPrec::F64);
+  if (blocked) solve_LZ(T1.get(), p);
   gemm(gemm_nn(p, 1, p, LX.get(), p, Rd, 1, v1.get(), 1), c.s, &c.ws, GemmPrec::F64);
   axpby(p, -1.0, Rc, 1.0, v1.get(), c.s);
-  solve_LZ(v1.get(), 1);
+  if (blocked) {
+    solve_LZ(v1.get(), 1);
+  } else {
+    copy2d(v1.get(), 1, T1.get() + p, tw, p, 1, c.s);
+    solve_LZ(T1.get(), p + 1);
+    copy2d(T1.get() + p, tw, v1.get(), 1, p, 1, c.s);
+  }
+  S.reserve((size_t)p * p);
+  TT_HIP(hipMemcpyAsync(S.get(), KY.get(), sizeof(double) * (size_t)p * p, hipMemcpyDeviceToDevice, c.s));
+  gemm(gemm_nn(p, p, p, A.get(), p, T1.get(), tw, S.get(), p, 1.0, 1.0), c.s, &c.ws, GemmPrec::F64);
   ry.reserve(p);
   gemm(gemm_nn(p, 1, p, A.get(), p, v1.get(), 1, ry.get(), 1), c.s, &c.ws, GemmPrec::F64);
   axpby(p, -1.0, Rp, 1.0, ry.get(), c.s);
