@@ -607,12 +607,13 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
   int hst = 0;
   if (blocked) {
     hst = chol_blocked(LZ.get(), p, fz, c);
+    if (hst != 0) return false;
   } else {
+    // The status (st[0]) is read back with the LU's (st[1]) at the end, so the
+    // stream does not stop here: a failed factorisation only wastes the work
+    // queued after it, and the caller then solves the whole block system.
     dense_cholesky(LZ.get(), p, st, c.s);
-    TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
-    c.sync();
   }
-  if (hst != 0) return false;
   dense(OP_AEQ, A);
   dense(OP_AEQT, AT);
   dense(OP_KY, KY);
@@ -656,9 +657,7 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
     hst = lu_blocked(S.get(), p, fs, c);
     if (hst == 0) lu_solve_blocked(S.get(), p, fs, ry.get(), 1, c);
   } else {
-    dense_lu_solve(S.get(), p, ry.get(), 1, st, c.s);
-    TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
-    c.sync();
+    dense_lu_solve(S.get(), p, ry.get(), 1, st + 1, c.s);
   }
   if (hst != 0) throw Error(TT_ERR_NUMERIC, "singular Schur complement in the local block elimination");
   // dZ = Aeq^T^ y - R_d^ ; dX = -L_Z^{-1}(R_c^ + L_X^ dZ)
@@ -669,6 +668,13 @@ bool solve_elim(LocalKKT& K, const double* Rd, const double* Rp, const double* R
   solve_LZ(v2.get(), 1);
   axpby(p, -1.0, v2.get(), 0.0, u, c.s);
   TT_HIP(hipMemcpyAsync(u + p, ry.get(), sizeof(double) * p, hipMemcpyDeviceToDevice, c.s));
+  if (!blocked) {
+    int hs[2] = {0, 0};
+    TT_HIP(hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, c.s));
+    c.sync();
+    if (hs[0] != 0) return false;
+    if (hs[1] != 0) throw Error(TT_ERR_NUMERIC, "singular Schur complement in the local block elimination");
+  }
   c.sync();
   return true;
 }
