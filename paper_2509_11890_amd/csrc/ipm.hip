@@ -339,17 +339,17 @@ double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c, const double*
   // triangular solves; the single-workgroup kernels win only for small ones.
   const bool blocked = p >= kPencilBlocked || !dense_small_fits_lds(p);
   BlockedFactors f;
-  int hst = 0;
+  int* st = nullptr;
   if (blocked) {
-    hst = chol_blocked(Mm, p, f, c);
+    if (chol_blocked(Mm, p, f, c) != 0)
+      throw Error(TT_ERR_NOT_PD, "projected iterate is not positive definite (step length)");
   } else {
+    // the status is read back with the eigenvalue at the end: a failed
+    // factorisation only wastes the work queued after it
     c.ired.reserve((size_t)p + 8);
-    int* st = reinterpret_cast<int*>(c.ired.get());
+    st = reinterpret_cast<int*>(c.ired.get());
     dense_cholesky(Mm, p, st, c.s);
-    TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
-    c.sync();
   }
-  if (hst != 0) throw Error(TT_ERR_NOT_PD, "projected iterate is not positive definite (step length)");
   auto solve_L = [&](double* B, int nrhs, bool trans) {
     if (blocked)
       trsm_blocked(Mm, p, f, B, nrhs, trans, c);
@@ -371,8 +371,11 @@ double pencil_min(double* Mm, double* D, int p, double* e, Ctx& c, const double*
   dense_sym_min_eig(Bt.get(), p, e, lam.get(), work.get(), c.s, 128, 8, 1e-12, e0 != nullptr);
   solve_L(e, 1, true);
   double lmin = 0.0;
+  int hst = 0;
   TT_HIP(hipMemcpyAsync(&lmin, lam.get(), sizeof(double), hipMemcpyDeviceToHost, c.s));
+  if (st) TT_HIP(hipMemcpyAsync(&hst, st, sizeof(int), hipMemcpyDeviceToHost, c.s));
   c.sync();
+  if (hst != 0) throw Error(TT_ERR_NOT_PD, "projected iterate is not positive definite (step length)");
   return lmin;
 }
 
