@@ -825,7 +825,8 @@ void local_dense_ops(const std::vector<DenseOpArgs>& v, Ctx& c) {
     const DenseOpArgs& a = v[q];
     permute(T2[q].get(), a.out, {a.r, a.r, a.m, a.m, a.s, a.s}, {0, 2, 4, 1, 3, 5}, c.s);
   }
-  c.sync();   // the stage buffers are released at scope end
+  // no sync: the stage buffers go back to this stream's free list, whose
+  // blocks later work on the same stream reuses only after these kernels
 }
 
 void local_dense_op(const double* phiL, int r, int R, const double* O, int m, const double* phiR, int s, int Rp,
@@ -1206,8 +1207,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
         proj.push_back({envs.L[key][k].get(), r, R0, rc, Op, 4, envs.R[key][k].get(), s, R1, rd, e.trial->core(k),
                         Rhat_p[tm.res], tm.coef, 1.0});
       }
-      local_apply_many(proj, c);
-      c.sync();   // the permuted cores are released at scope end
+      local_apply_many(proj, c);   // the permuted cores are recycled in stream order
       // local right-hand side f = [-Rp; (-Rt;) -Rc + LX^ Rd]
       f.reserve(n);
       axpby(p, -1.0, Rhat_p[RES_P], 0.0, f.get(), c.s);
