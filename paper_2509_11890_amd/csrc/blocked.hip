@@ -434,7 +434,8 @@ int chol_blocked(double* A, int n, BlockedFactors& f, Ctx& c) {
 void trsm_blocked(const double* L, int n, const BlockedFactors& f, double* B, int nrhs, bool trans, Ctx& c) {
   DevBuf tmp;
   trsm_left_rec(L, n, f.dinv, f.nb, 0, n, B, nrhs, nrhs, trans, tmp, c);
-  c.sync();   // tmp is released at return
+  // tmp goes back to this stream's free list: later work on the stream
+  // reuses it only after these kernels
 }
 
 int lu_blocked(double* A, int n, BlockedFactors& f, Ctx& c) {

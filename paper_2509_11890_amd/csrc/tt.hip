@@ -907,7 +907,7 @@ void orth_rows(double* G, int q, int len, Ctx& c) {
   DevBuf Q((size_t)len * q), R((size_t)q * q);
   qr_colmajor(G, len, q, Q.get(), R.get(), c);
   TT_HIP(hipMemcpyAsync(G, Q.get(), sizeof(double) * (size_t)len * q, hipMemcpyDeviceToDevice, c.s));
-  c.sync();
+  // Q and R are recycled in stream order (no sync needed to release them)
 }
 
 void tt_orth_right(TT& t, int downto, Ctx& c) {
@@ -936,7 +936,7 @@ void tt_orth_right(TT& t, int downto, Ctx& c) {
     t.r[k] = kk;
     t.cores[k - 1].reserve((size_t)rows * kk);
     TT_HIP(hipMemcpyAsync(t.core(k - 1), nc.get(), sizeof(double) * (size_t)rows * kk, hipMemcpyDeviceToDevice, c.s));
-    c.sync();   // temporaries are released at scope end
+    // the temporaries (and replaced cores) are recycled in stream order
   }
 }
 
@@ -989,7 +989,8 @@ double tt_round_abs(TT& t, double eps, int max_rank, Ctx& c, bool* capped, doubl
     TT_HIP(hipMemcpyAsync(t.core(k), nc.get(), sizeof(double) * (size_t)rows * rk, hipMemcpyDeviceToDevice, c.s));
     t.cores[k + 1].reserve((size_t)rk * ncols);
     TT_HIP(hipMemcpyAsync(t.core(k + 1), nn.get(), sizeof(double) * (size_t)rk * ncols, hipMemcpyDeviceToDevice, c.s));
-    c.sync();
+    // no sync: the temporaries are recycled in stream order, and the next
+    // core's SVD synchronises when it reads its singular values
   }
   if (zeta_tol) *zeta_tol = std::sqrt(zeta_tol2);
   return std::sqrt(zeta2);
