@@ -505,7 +505,8 @@ bool split_block(BlockTT& W, int dir, double tol_rel, int cap, Ctx& c, int kick,
     W.r[k] = rk;
     W.pos = k - 1;
   }
-  c.sync();
+  // no sync: the temporaries are recycled in stream order, and everything the
+  // host decides on (ranks, the cap) is already on the host
   return capped;
 }
 
@@ -1281,8 +1282,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
                     prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k), cand_use);
         info.t_svd += now() - t1;
         t1 = now();
-        envs.update_left(W, k, c);
-        c.sync();
+        envs.update_left(W, k, c);   // its kernels finish under the next local solve
         info.t_env += now() - t1;
       } else if (dir < 0 && k > 0) {
         double t1 = now();
@@ -1290,8 +1290,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
                     prm.seed * 1000003ull + (unsigned long long)(sweep * 131 + k) + 7777ull, cand_use);
         info.t_svd += now() - t1;
         t1 = now();
-        envs.update_right(W, k, c);
-        c.sync();
+        envs.update_right(W, k, c);   // its kernels finish under the next local solve
         info.t_env += now() - t1;
       }
     }
