@@ -486,7 +486,10 @@ typedef struct {
   int32_t finishing;                /* 1 in the finishing phase */
   int32_t finish_rejected;          /* 1 when the finishing phase kept the iterate (no acceptable step) */
   double nu;                        /* barrier relaxation nu of this iteration (finishing phase) */
-  double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration */
+  double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration: host time
+                                    between synchronisation points, so GPU work a phase queues without
+                                    waiting for it (environment updates, the end of a split) is counted
+                                    in the phase that next waits (the local solve) */
 } ttipm_step_info;
 
 /*
