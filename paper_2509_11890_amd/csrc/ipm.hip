@@ -440,6 +440,9 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
   for (int k = d - 1; k > 0; --k) upd_right(k);
   double lam_best = 1e300;
   DevBuf M2, D2, Ml, Dl, e, e0, sg;
+  // host copies of the singular values sent to the device, kept until the
+  // synchronisation at the end (the pair steps do not wait for their copies)
+  std::vector<std::vector<double>> sig_keep;
   // one sweep = left-to-right then right-to-left over the pairs (k, k+1);
   // further sweeps are skipped once the two passes of a sweep agree on the
   // smallest eigenvalue to 1e-9 (relative): the frame has converged
@@ -522,7 +525,7 @@ double min_gen_eig(const TT& Mv, const TT& dMv, BlockTT& E, bool& have_E, int ra
           E.r[k + 1] = rq;
           upd_right(k + 1);
         }
-        c.sync();
+        sig_keep.push_back(std::move(sv.sigma));   // device temporaries are recycled in stream order
       }
     }
     if (std::fabs(lam_pass[1] - lam_pass[0]) <= 1e-9 * std::max(std::fabs(lam_pass[0]), std::fabs(lam_pass[1])))
