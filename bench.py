@@ -364,7 +364,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: --gpus {args.gpus} requested, but this build runs the TT-IPM hot path on a single GPU; "
+        print(f"bench.py: --gpus {args.gpus} requested, but this implementation runs the TT-IPM hot path on a single GPU; "
               "multi-GPU runs are not supported (see the sharding design note).", file=sys.stderr)
         sys.exit(2)
 

@@ -15,5 +15,5 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # a GPU test on a machine without a GPU is a configuration error, not a skip:
-    # the full test run selects -m gpu only on the GPU machine.
+    # GPU tests are selected with -m gpu on machines that have a GPU.
     pass
