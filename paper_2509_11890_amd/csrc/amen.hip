@@ -1262,8 +1262,7 @@ void amen_solve(const NewtonSys& sys, BlockTT& W, const AmenParams& prm, AmenInf
       hipLaunchKernelGGL(stack_dz_kernel, dim3(nblocks(p, 256)), dim3(256), 0, c.s, W.blk.get() + n, K.tmp.get(),
                          Rhat_p[RES_D], (long)p);
       TT_HIP(hipGetLastError());
-      c.sync();
-      info.t_solve += now() - ts;
+      info.t_solve += now() - ts;   // the block core's last kernels finish under the split
       // sketched residual of the local system: candidate enrichment rows,
       // computed by the split only when the cap leaves room for them
       DevBuf cand;
