@@ -488,8 +488,8 @@ typedef struct {
   double nu;                        /* barrier relaxation nu of this iteration (finishing phase) */
   double t_env, t_solve, t_svd, t_step, t_round, t_total;  /* seconds, this iteration: host time
                                     between synchronisation points, so GPU work a phase queues without
-                                    waiting for it (environment updates, the end of a split) is counted
-                                    in the phase that next waits (the local solve) */
+                                    waiting for it (the end of a local solve or of a split, environment
+                                    updates) is counted in the phase that next waits */
 } ttipm_step_info;
 
 /*
